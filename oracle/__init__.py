@@ -81,6 +81,9 @@ def _load():
         "or_neighbor_table": (None, [_I, _P]),
         "or_gamma_matrices": (None, [_P]),
         "or_dslash": (None, [_I, _P, _P, _P, C.c_int, C.c_int]),
+        "or_dslash_sites": (None, [_I, _P, _P, _P, C.c_long, C.c_int, _P]),
+        "or_weak_field_sites": (None, [_I, C.c_uint64, C.c_double, _P, C.c_long, _P]),
+        "or_gauss_source_sites": (None, [C.c_uint64, C.c_uint64, _P, C.c_long, _P]),
         "or_wilson_m": (None, [_I, _P, C.c_double, _P, _P, C.c_int]),
         "or_mhat": (None, [_I, _P, C.c_double, _P, _P, C.c_int]),
         "or_norm2": (C.c_double, [C.c_long, _P]),
@@ -186,6 +189,27 @@ def dslash(L, U, psi, out_parity=-1, dagger=False):
     out = spinor_zeros(L)
     _load().or_dslash(_dims(L), _ptr(U), _ptr(psi), _ptr(out), int(out_parity), int(bool(dagger)))
     return out
+
+
+def dslash_sites(L, U, psi, sites, dagger=False):
+    """Hopping term at the listed lexicographic sites only -> (n, 4, 3)."""
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.zeros((sites.size, 4, 3), np.complex128)
+    _load().or_dslash_sites(_dims(L), _ptr(U), _ptr(psi), _ptr(sites), sites.size, int(bool(dagger)), _ptr(out))
+    return out
+
+
+def weak_field_sites(L, seed, eps, sites, U):
+    """Fill the links of the listed sites of the full-size array U in place."""
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    assert U.flags.c_contiguous and U.dtype == np.complex128
+    _load().or_weak_field_sites(_dims(L), seed, float(eps), _ptr(sites), sites.size, _ptr(U))
+
+
+def gauss_source_sites(seed, epoch, sites, b):
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    assert b.flags.c_contiguous and b.dtype == np.complex128
+    _load().or_gauss_source_sites(seed, epoch, _ptr(sites), sites.size, _ptr(b))
 
 
 def wilson_m(L, U, kappa, psi, dagger=False):

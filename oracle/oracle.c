@@ -198,48 +198,66 @@ void or_gamma_matrices(cplx *out)
 /* -1 writes every site.                                               */
 /* ------------------------------------------------------------------ */
 
+/* The hopping term at one site i, written to out_site[12]. */
+static void dslash_site(const int *L, const cplx *U, const cplx *in, long i, int dagger, cplx *out_site)
+{
+    int s_fwd = dagger ? +1 : -1; /* forward hop carries (1 + s_fwd*gamma) */
+    int c[4];
+    coords_of(L, i, c);
+    cplx acc[4][3];
+    memset(acc, 0, sizeof acc);
+    for (int mu = 0; mu < 4; ++mu) {
+        for (int dir = +1; dir >= -1; dir -= 2) {
+            int wraps;
+            long j = hop(L, c, mu, dir, &wraps);
+            double bc = wraps ? -1.0 : 1.0;
+            /* colour matrix: U_mu(x) forward, U_mu(x-mu)^dag backward */
+            cplx Um[9];
+            if (dir > 0)
+                memcpy(Um, &U[(i * 4 + mu) * 9], sizeof Um);
+            else
+                mat_dag(&U[(j * 4 + mu) * 9], Um);
+            cplx Upsi[4][3];
+            for (int sp = 0; sp < 4; ++sp)
+                for (int a = 0; a < 3; ++a) {
+                    cplx s = 0;
+                    for (int b = 0; b < 3; ++b) s += Um[3 * a + b] * in[(j * 4 + sp) * 3 + b];
+                    Upsi[sp][a] = s;
+                }
+            int sgn = (dir > 0) ? s_fwd : -s_fwd;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    cplx pr = proj_el(mu, sgn, a, b);
+                    if (pr == 0) continue;
+                    for (int col = 0; col < 3; ++col) acc[a][col] += bc * pr * Upsi[b][col];
+                }
+        }
+    }
+    for (int sp = 0; sp < 4; ++sp)
+        for (int a = 0; a < 3; ++a) out_site[sp * 3 + a] = acc[sp][a];
+}
+
 void or_dslash(const int *L, const cplx *U, const cplx *in, cplx *out, int out_parity, int dagger)
 {
     long V = vol4(L);
-    int s_fwd = dagger ? +1 : -1; /* forward hop carries (1 + s_fwd*gamma) */
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < V; ++i) {
         int c[4];
         coords_of(L, i, c);
-        cplx acc[4][3];
-        memset(acc, 0, sizeof acc);
-        if (out_parity < 0 || parity_of(c) == out_parity) {
-            for (int mu = 0; mu < 4; ++mu) {
-                for (int dir = +1; dir >= -1; dir -= 2) {
-                    int wraps;
-                    long j = hop(L, c, mu, dir, &wraps);
-                    double bc = wraps ? -1.0 : 1.0;
-                    /* colour matrix: U_mu(x) forward, U_mu(x-mu)^dag backward */
-                    cplx Um[9];
-                    if (dir > 0)
-                        memcpy(Um, &U[(i * 4 + mu) * 9], sizeof Um);
-                    else
-                        mat_dag(&U[(j * 4 + mu) * 9], Um);
-                    cplx Upsi[4][3];
-                    for (int sp = 0; sp < 4; ++sp)
-                        for (int a = 0; a < 3; ++a) {
-                            cplx s = 0;
-                            for (int b = 0; b < 3; ++b) s += Um[3 * a + b] * in[(j * 4 + sp) * 3 + b];
-                            Upsi[sp][a] = s;
-                        }
-                    int sgn = (dir > 0) ? s_fwd : -s_fwd;
-                    for (int a = 0; a < 4; ++a)
-                        for (int b = 0; b < 4; ++b) {
-                            cplx pr = proj_el(mu, sgn, a, b);
-                            if (pr == 0) continue;
-                            for (int col = 0; col < 3; ++col) acc[a][col] += bc * pr * Upsi[b][col];
-                        }
-                }
-            }
-        }
-        for (int sp = 0; sp < 4; ++sp)
-            for (int a = 0; a < 3; ++a) out[(i * 4 + sp) * 3 + a] = acc[sp][a];
+        if (out_parity < 0 || parity_of(c) == out_parity)
+            dslash_site(L, U, in, i, dagger, &out[i * 12]);
+        else
+            for (int k = 0; k < 12; ++k) out[i * 12 + k] = 0;
     }
+}
+
+/* The hopping term at the n listed sites only: out[k*12..] for sites[k].
+ * U and in are full-size canonical arrays of which only the links and
+ * spinors touching the listed sites are read. */
+void or_dslash_sites(const int *L, const cplx *U, const cplx *in, const long *sites, long n, int dagger, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) dslash_site(L, U, in, sites[k], dagger, &out[k * 12]);
 }
 
 /* Full Wilson matrix M = 1 - kappa D (or M^dagger with dagger=1). */
@@ -648,7 +666,7 @@ void or_weak_field(const int *L, uint64_t seed, double eps, cplx *U)
 void or_eta(const int *L, uint64_t seed, uint64_t traj, int parity, cplx *eta)
 {
     long V = vol4(L);
-    const double s = 1.0 / sqrt(2.0);
+    const double s = sqrt(0.5); /* 1/sqrt2, correctly rounded */
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < V; ++i) {
         int c[4];
@@ -667,7 +685,7 @@ void or_eta(const int *L, uint64_t seed, uint64_t traj, int parity, cplx *eta)
 void or_source(const int *L, int kind, uint64_t seed, uint64_t epoch, cplx *b)
 {
     long V = vol4(L);
-    const double s = 1.0 / sqrt(2.0);
+    const double s = sqrt(0.5); /* 1/sqrt2, correctly rounded */
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < V; ++i) {
         if (kind == 0) {
@@ -685,6 +703,37 @@ void or_source(const int *L, int kind, uint64_t seed, uint64_t epoch, cplx *b)
         } else {
             for (int k = 0; k < 12; ++k) b[i * 12 + k] = (i == 0 && k == 0) ? 1.0 : 0.0;
         }
+    }
+}
+
+/* Site-list variants of the weak-field start and the sources: fill only the
+ * listed sites (and the 4 links of each) of full-size canonical arrays. */
+void or_weak_field_sites(const int *L, uint64_t seed, double eps, const long *sites, long n, cplx *U)
+{
+    (void)L;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        long i = sites[k];
+        double g[32];
+        or_site_gaussians(seed, i, ST_WEAKFIELD, 0, 32, g);
+        for (int mu = 0; mu < 4; ++mu) {
+            cplx H[9], A[9];
+            or_algebra_matrix(&g[mu * 8], H);
+            for (int m = 0; m < 9; ++m) A[m] = I * eps * H[m];
+            or_mat_exp(A, &U[(i * 4 + mu) * 9]);
+            or_reunit(&U[(i * 4 + mu) * 9]);
+        }
+    }
+}
+
+void or_gauss_source_sites(uint64_t seed, uint64_t epoch, const long *sites, long n, cplx *b)
+{
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        long i = sites[k];
+        double g[24];
+        or_site_gaussians(seed, i, ST_SOURCE, epoch, 24, g);
+        for (int m = 0; m < 12; ++m) b[i * 12 + m] = g[2 * m] + I * g[2 * m + 1];
     }
 }
 
