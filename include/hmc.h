@@ -1,0 +1,341 @@
+/*
+ * libhmc: the data-parallel hot path of Nf=2 Wilson-fermion Hybrid Monte
+ * Carlo on one AMD MI355X (gfx950), as a C ABI.
+ *
+ * The operations are the ones the paper (Winter, "Gauge Field Generation on
+ * Large-Scale GPU-Enabled Systems", Lattice 2012) lists for an HMC that runs
+ * entirely on the accelerator (Sec. 1): pseudofermion refresh, momentum
+ * update, force terms, projection of fields, reunitarisation of SU(3)
+ * matrices, random numbers, exponentiation of SU(3) matrices, the fermion
+ * matrix inversion, and the global sums sum/sumMulti.  The paper prints no
+ * formula for any of them; each entry below states the textbook definition
+ * it computes.
+ *
+ * Conventions (shared by every entry point):
+ *   - Lattice L = {Lx, Ly, Lz, Lt}, every extent even and >= 2.  Site
+ *     i = x + Lx*(y + Ly*(z + Lz*t)), parity (x+y+z+t) mod 2, checkerboard
+ *     index s = i >> 1 within its parity; Vh = V/2 sites per parity.
+ *   - Wilson operator M = 1 - kappa*D with the hopping term
+ *       (D psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                           + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)],
+ *     gamma matrices in the DeGrand-Rossi basis (mu = 0..3 <-> x,y,z,t), and
+ *     a factor -1 on every hop across the t = Lt-1 <-> 0 boundary
+ *     (antiperiodic fermions; links are periodic).  D^dag = gamma5 D gamma5.
+ *     Even/odd: Mhat = 1 - kappa^2 D_eo D_oe on even sites, det M = det Mhat.
+ *   - Gauge action S_g = beta * sum_{x,mu<nu} (1 - Re Tr U_munu(x)/3);
+ *     plaquette = sum Re Tr U_munu / (18 V).
+ *   - Momenta P_mu(x) traceless Hermitian, T^a = lambda^a/2, kinetic term
+ *     sum Tr P^2, equations of motion U' = i P U, P' = -F with
+ *     F = sum_a T^a d/dt S(exp(i t T^a) U)|_0.
+ *   - Fermion action S_f = phi_e^dag (Mhat^dag Mhat)^-1 phi_e.
+ *   - Random numbers: Philox4x64-10 with counter (block, site i, stream,
+ *     epoch) and key (seed, 0); uniform u = ((w >> 11) + 0.5) * 2^-53;
+ *     Box-Muller on consecutive word pairs.  Streams: 0 weak-field start,
+ *     1 momenta, 2 pseudofermion noise, 3 Metropolis, 4 sources.
+ *
+ * Memory: the caller owns every byte of device memory.  Device pointers are
+ * plain addresses (e.g. torch tensors' data_ptr()); the library never calls
+ * hipMalloc.  A fields object lives in one caller-provided device arena of
+ * hmc_fields_bytes() bytes; its host metadata is freed by hmc_free_fields.
+ *
+ * Device field layouts (structure of arrays, component-major so that
+ * consecutive sites are consecutive addresses):
+ *   half spinor  [12 = spin*3+colour][Vh] complex, element type per prec:
+ *                F64 double2, F32 float2, BF16 2 x bfloat16, F16 __half2
+ *                followed by one float scale per site (components divided
+ *                by the site's largest |re|,|im|)
+ *   full spinor  two half spinors, even parity first
+ *   gauge        [mu][parity][9 = row*3+col][Vh] complex
+ *   momenta      [mu][parity][8][Vh] double: (P00, P11, Re P01, Im P01,
+ *                Re P02, Im P02, Re P12, Im P12), P22 = -P00-P11
+ * Canonical layouts (import/export; complex128, device memory):
+ *   gauge / momenta [V][4][3][3], spinor [V][4][3].
+ *
+ * Streams: `stream` is a hipStream_t (0 = null stream).  Calls are
+ * asynchronous on it, except those that return host values (stated per
+ * entry), which synchronise that stream before returning.
+ *
+ * Errors: every entry returns an hmc_status; on failure
+ * hmc_last_error() (thread-local) describes it.  No C++ exception crosses
+ * this interface.
+ */
+#ifndef HMC_H
+#define HMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hmc_status;
+#define HMC_OK 0
+#define HMC_E_ARG (-1)    /* invalid argument (null pointer, odd extent, size) */
+#define HMC_E_OOM (-2)    /* arena too small, or a request can never fit */
+#define HMC_E_HIP (-3)    /* a HIP runtime call failed */
+#define HMC_E_NOCONV (-4) /* solver reached maxiter before the tolerance */
+#define HMC_E_BUSY (-5)   /* poll: request not finished yet */
+#define HMC_E_NAN (-6)    /* non-finite energy change; trajectory rejected */
+
+typedef enum { HMC_F64 = 0, HMC_F32 = 1, HMC_F16 = 2, HMC_BF16 = 3 } hmc_prec;
+
+typedef enum {
+  HMC_KIND_HALF_SPINOR = 0,
+  HMC_KIND_FULL_SPINOR = 1,
+  HMC_KIND_GAUGE = 2,
+  HMC_KIND_MOMENTA = 3
+} hmc_kind;
+
+typedef struct {
+  int32_t L[4];
+} hmc_geom;
+
+typedef struct {
+  double beta;  /* gauge coupling */
+  double kappa; /* hopping parameter */
+} hmc_action;
+
+typedef struct hmc_fields hmc_fields;
+
+/* Thread-local description of the last failure on this thread. */
+const char* hmc_last_error(void);
+/* Library version (major, minor). */
+hmc_status hmc_get_version(int32_t* major, int32_t* minor);
+
+/* Bytes of one device field of the given kind and storage precision
+ * (momenta exist in F64 only).  HMC_E_ARG on bad geometry. */
+hmc_status hmc_field_bytes(const hmc_geom* geom, hmc_prec prec, hmc_kind kind, size_t* bytes);
+
+/* Flags of hmc_alloc_fields. */
+#define HMC_FIELDS_LOWPREC 1u /* also hold F32/F16/BF16 link copies and inner solver vectors */
+
+/* Arena bytes hmc_alloc_fields needs for this geometry and flags. */
+hmc_status hmc_fields_bytes(const hmc_geom* geom, uint32_t flags, size_t* bytes);
+
+/* Create a fields object inside the caller's device arena (at least
+ * hmc_fields_bytes bytes, 256-byte aligned).  It holds: the gauge field U,
+ * its backup, the momenta P, the pseudofermion noise eta_e and phi_e, the
+ * solution X_e, the force vectors and the solver work space.  Nothing is
+ * initialised: import or generate U before use.  The arena must outlive
+ * the object.  HMC_E_ARG on bad geometry or null pointers, HMC_E_OOM when
+ * arena_bytes is too small. */
+hmc_status hmc_alloc_fields(const hmc_geom* geom, const hmc_action* action, uint32_t flags, void* arena,
+                            size_t arena_bytes, hmc_fields** out);
+/* Release the host metadata (the arena stays the caller's). */
+hmc_status hmc_free_fields(hmc_fields* f);
+/* Change beta and kappa of an existing fields object. */
+hmc_status hmc_set_action(hmc_fields* f, const hmc_action* action);
+
+/* Internal fields a caller may read or write directly (device pointers in
+ * the layouts above, F64). */
+typedef enum {
+  HMC_FIELD_GAUGE = 0,
+  HMC_FIELD_MOMENTA = 1,
+  HMC_FIELD_ETA = 2, /* even half spinor */
+  HMC_FIELD_PHI = 3, /* even half spinor */
+  HMC_FIELD_XE = 4   /* even half spinor: last solve of the fermion force */
+} hmc_field_id;
+hmc_status hmc_field_pointer(hmc_fields* f, hmc_field_id which, void** ptr);
+
+/* Canonical <-> device layout conversion (both buffers in device memory).
+ * Spinors: `parity` 0 or 1 converts one half spinor (export writes zeros on
+ * the other parity's sites of the canonical buffer); -1 converts a full
+ * spinor.  Gauge/momenta act on the fields object's U / P.  The canonical
+ * momenta must be traceless Hermitian (the compact form keeps P00, P11 and
+ * the upper triangle). */
+hmc_status hmc_import_gauge(hmc_fields* f, const void* canon, void* stream);
+hmc_status hmc_export_gauge(hmc_fields* f, void* canon, void* stream);
+hmc_status hmc_import_momenta(hmc_fields* f, const void* canon, void* stream);
+hmc_status hmc_export_momenta(hmc_fields* f, void* canon, void* stream);
+hmc_status hmc_import_spinor(hmc_fields* f, void* dst, const void* canon, int32_t parity, void* stream);
+hmc_status hmc_export_spinor(hmc_fields* f, void* canon, const void* src, int32_t parity, void* stream);
+
+/* Convert a half spinor between storage precisions (F64 <-> F32/F16/BF16). */
+hmc_status hmc_convert_spinor(hmc_fields* f, void* dst, hmc_prec dst_prec, const void* src, hmc_prec src_prec,
+                              void* stream);
+/* Refresh the F32/F16/BF16 link copies from U (needs HMC_FIELDS_LOWPREC).
+ * hmc_cg_solve calls it itself when U changed since the last refresh. */
+hmc_status hmc_sync_lowprec(hmc_fields* f, void* stream);
+
+/* One half-lattice hop: out = D_{p <- 1-p} in (dagger: D^dag), p =
+ * out_parity.  in/out are half spinors of storage `prec`; links come from U
+ * (F64) or its low-precision copy.  Arithmetic is FP64 for F64, else FP32. */
+hmc_status hmc_wilson_dslash(hmc_fields* f, void* out, const void* in, int32_t out_parity, int32_t dagger,
+                             hmc_prec prec, void* stream);
+/* out_e = Mhat in_e (dagger: Mhat^dag), half spinors of storage `prec`. */
+hmc_status hmc_mhat(hmc_fields* f, void* out, const void* in, int32_t dagger, hmc_prec prec, void* stream);
+/* Full Wilson matrix on full F64 spinors: out = M in (dagger: M^dag). */
+hmc_status hmc_wilson_m(hmc_fields* f, void* out, const void* in, int32_t dagger, void* stream);
+
+/* Global sums (QDP++ sum / innerProduct / sumMulti, Sec. 1), deterministic:
+ * per-block partials in a fixed order, then one fixed-order pass.  Each
+ * synchronises the stream and returns host values.  `nhalves` = 1 (half
+ * spinor) or 2 (full spinor).
+ *   hmc_norm2: sum |x|^2 (x of storage prec).
+ *   hmc_inner: <a, b> = sum conj(a) b (F64), out[0] = Re, out[1] = Im.
+ *   hmc_sum_multi: out[k] = sum of |x(site)|^2 over the sites with
+ *     subset[site] == k; subset is an int32 device array in the field's own
+ *     site order ([parity][Vh]; for nhalves = 1 only the first Vh entries),
+ *     values in [0, nsub) (other values are ignored).  nsub <= 1024. */
+hmc_status hmc_norm2(hmc_fields* f, const void* x, int32_t nhalves, hmc_prec prec, double* out, void* stream);
+hmc_status hmc_inner(hmc_fields* f, const void* a, const void* b, int32_t nhalves, double* out, void* stream);
+hmc_status hmc_sum_multi(hmc_fields* f, const void* x, int32_t nhalves, const int32_t* subset, int32_t nsub,
+                         double* out, void* stream);
+
+/* Plaquette (1/18V) sum Re Tr U_munu, gauge action S_g and kinetic term
+ * sum Tr P^2 of the fields object; synchronise and return host values. */
+hmc_status hmc_plaquette(hmc_fields* f, double* out, void* stream);
+hmc_status hmc_gauge_action(hmc_fields* f, double* out, void* stream);
+hmc_status hmc_kinetic_energy(hmc_fields* f, double* out, void* stream);
+
+/* Momentum update with the gauge force (Sec. 1 "force term", "momentum
+ * update"): P <- P - coef * F_g with
+ *   F_g = -(i beta/12) [(W - W^dag) - Tr(W - W^dag)/3],  W = U_mu(x) A_mu(x),
+ * A_mu the sum of the six staples. */
+hmc_status hmc_gauge_force(hmc_fields* f, double coef, void* stream);
+
+/* Momentum update with the fermion force of S_f for the solution X_e =
+ * (Mhat^dag Mhat)^-1 phi_e (even half spinor, F64): the library forms
+ * X_o = D_oe X_e, Y_e = Mhat X_e, Y_o = (D^dag)_oe Y_e and applies
+ *   P <- P - coef * (i kappa^2/2) [(W - W^dag) - Tr(W - W^dag)/3],
+ *   W = U_mu(x) M1 - M2 U_mu(x)^dag,
+ *   M1 = s tr_spin[(1 - gamma_mu) X(x+mu) Y(x)^dag],
+ *   M2 = s tr_spin[(1 + gamma_mu) X(x) Y(x+mu)^dag],
+ * s the time-boundary sign of the hop x -> x+mu. */
+hmc_status hmc_fermion_force(hmc_fields* f, const void* X_e, double coef, void* stream);
+
+/* Link update of the integrator with exponentiation and reunitarisation
+ * (Sec. 1): U_mu(x) <- reunit(exp(i eps P_mu(x)) U_mu(x)); reunit is the
+ * row Gram-Schmidt projection (row 2 = conj(row0 x row1)). */
+hmc_status hmc_exp_update_reunit(hmc_fields* f, double eps, void* stream);
+
+/* Refresh (Sec. 1 "pseudofermion refresh", "random number generator"):
+ *   HMC_REFRESH_MOM: P_mu(x) = sum_a w_a T^a, w ~ N(0,1) from stream 1 at
+ *     epoch traj; Gaussian index mu*8 + (a-1).
+ *   HMC_REFRESH_PF: eta_e complex Gaussian with E|eta|^2 = 1 (stream 2,
+ *     epoch traj, components (spin, colour, re/im)), phi_e = Mhat^dag eta_e. */
+#define HMC_REFRESH_MOM 1u
+#define HMC_REFRESH_PF 2u
+hmc_status hmc_refresh(hmc_fields* f, uint64_t seed, uint64_t traj, uint32_t what, void* stream);
+
+/* Weak-field start U_mu(x) = reunit(exp(i eps H_mu(x))), H = sum_a h_a T^a,
+ * h ~ N(0,1) from stream 0, epoch 0. */
+hmc_status hmc_weak_field_start(hmc_fields* f, uint64_t seed, double eps, void* stream);
+
+/* Solver source on a full F64 spinor b (stream 4, epoch = source index):
+ * HMC_SOURCE_GAUSS unit-variance Gaussian per real component;
+ * HMC_SOURCE_Z2 (+-1 +-i)/sqrt2 with signs from bit 63 of successive words;
+ * HMC_SOURCE_POINT 1 at site 0, spin 0, colour 0. */
+#define HMC_SOURCE_GAUSS 0
+#define HMC_SOURCE_Z2 1
+#define HMC_SOURCE_POINT 2
+hmc_status hmc_make_source(hmc_fields* f, void* b, int32_t kind, uint64_t seed, uint64_t epoch, void* stream);
+
+/* Raw generator access for bit-exactness checks: for each lexicographic
+ * site in sites[0..nsites) (int64, device) write nblocks Philox blocks
+ * (4 words each) to out[site_k][nblocks*4] (device, uint64), or n
+ * Box-Muller Gaussians to out[site_k][n] (device, double, n even <= 32). */
+hmc_status hmc_random_words(uint64_t seed, uint64_t rng_stream, uint64_t epoch, const int64_t* sites,
+                            int32_t nsites, int32_t nblocks, uint64_t* out, void* stream);
+hmc_status hmc_random_gaussians(uint64_t seed, uint64_t rng_stream, uint64_t epoch, const int64_t* sites,
+                                int32_t nsites, int32_t n, double* out, void* stream);
+
+/* Krylov solve (the "fermion matrix inversion" of Sec. 1).
+ *   HMC_CG_NORMAL_MHAT: x_e = (Mhat^dag Mhat)^-1 b_e by conjugate gradient
+ *     from x = 0, stopping at the first k with |r_k| <= tol |b| (recursive
+ *     residual).  x, b: even half spinors F64.
+ *   HMC_CG_WILSON_SOLVE: M x = b for full F64 spinors through the Schur
+ *     complement: bhat_e = b_e + kappa D_eo b_o, CGLS on Mhat x_e = bhat_e
+ *     until |bhat_e - Mhat x_e| <= tol |b|, x_o = b_o + kappa D_oe x_e.
+ * prec = HMC_F64 runs FP64 throughout.  F32 / F16 / BF16 run the inner
+ * iteration on vectors and links stored in that format with FP32
+ * arithmetic and FP64 global sums, and replace the residual by the FP64
+ * true residual b - A x whenever the inner residual fell by
+ * reliable_delta (Clark et al., Comput. Phys. Commun. 181 (2010) 1517);
+ * the exit test is always on the FP64 true residual.  Needs
+ * HMC_FIELDS_LOWPREC.  fixed_iters > 0 runs exactly that many (outer
+ * FP64) iterations and ignores tol.  Synchronises the stream; fills
+ * stats.  HMC_E_NOCONV when maxiter is reached (x holds the last iterate). */
+typedef enum { HMC_CG_NORMAL_MHAT = 0, HMC_CG_WILSON_SOLVE = 1 } hmc_cg_mode;
+typedef struct {
+  double tol;
+  int32_t maxiter;
+  int32_t mode;   /* hmc_cg_mode */
+  int32_t prec;   /* hmc_prec of the inner iteration */
+  int32_t fixed_iters;
+  double reliable_delta; /* <= 0 selects 0.1 */
+} hmc_cg_params;
+typedef struct {
+  int32_t iters;            /* total (inner) iterations */
+  int32_t reliable_updates; /* FP64 residual replacements */
+  double rel_res;           /* last recursive residual / |b| */
+  double true_rel_res;      /* FP64 |b - A x| / |b| (full M for Wilson solves) */
+  double seconds;           /* wall time of the solve */
+} hmc_cg_stats;
+hmc_status hmc_cg_solve(hmc_fields* f, void* x, const void* b, const hmc_cg_params* params, hmc_cg_stats* stats,
+                        void* stream);
+
+/* Leapfrog molecular dynamics (PQP): with eps = tau/nsteps,
+ *   P -= (eps/2) F(U); then nsteps times { U <- reunit(exp(i eps P) U);
+ *   P -= eps_k F(U) } with eps_k = eps except eps/2 for the last step;
+ * F = F_g + F_f, the fermion force from a CG solve of phi_e (FP64).
+ * tau may be negative.  X_e holds the last solve.  Synchronises. */
+typedef struct {
+  int32_t solves;
+  int32_t iters_total;
+  int32_t iters_max;
+  int32_t nonconverged;
+} hmc_md_stats;
+hmc_status hmc_md_leapfrog(hmc_fields* f, double tau, int32_t nsteps, const hmc_cg_params* cg, hmc_md_stats* stats,
+                           void* stream);
+
+/* One HMC trajectory with index traj (Sec. 1's HMC; Sec. 7's gauge field
+ * generation): backup U; refresh momenta and pseudofermions; H_old = sum
+ * Tr P^2 + S_g + eta^dag eta; leapfrog; H_new = sum Tr P^2 + S_g +
+ * phi^dag X_e; accept iff dH <= 0 or u < exp(-dH), u from stream 3 at epoch
+ * traj (site 0, block 0, word 0); restore U on reject.  A non-converged
+ * solve or a non-finite dH forces a reject and returns HMC_E_NOCONV /
+ * HMC_E_NAN with the result filled.  Synchronises. */
+typedef struct {
+  double tau;
+  int32_t nsteps;
+  int32_t pad;
+  hmc_cg_params cg;
+} hmc_traj_params;
+typedef struct {
+  double H_old, H_new, dH;
+  double S_g_old, S_g_new, S_f_old, S_f_new, KE_old, KE_new;
+  double plaquette; /* after accept/reject */
+  double u;         /* Metropolis uniform */
+  int32_t accepted;
+  int32_t cg_iters_total;
+  int32_t cg_iters_max;
+  int32_t nonconverged;
+  double seconds;
+} hmc_traj_result;
+hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_traj_params* params,
+                          hmc_traj_result* result, void* stream);
+
+/* Kernel timing with HIP events on the launch streams.  With sample_every =
+ * n > 0 every n-th launch of each kernel family is bracketed by a pair of
+ * events (up to a fixed pool; later launches go untimed); 0 disables.
+ * hmc_timing_read synchronises the recorded events and returns, per family,
+ * the number of timed launches, their summed milliseconds and summed
+ * algorithmic bytes.  Process-wide, not thread-safe against concurrent
+ * launches. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} hmc_timing_entry;
+hmc_status hmc_timing_enable(int32_t sample_every);
+hmc_status hmc_timing_reset(void);
+hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* n_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMC_H */

@@ -1,0 +1,406 @@
+// Global sums (the QDP++ sum / innerProduct / sumMulti functions named in
+// the paper's QDP-JIT feature list, Sec. 1) and the fused vector updates
+// of the Krylov solvers.
+//
+// Every reduction is deterministic and independent of other work in the
+// same launch: a work-item accumulates its sites in a fixed grid-stride
+// order, a wave64 butterfly and a fixed wave order give one partial per
+// block, and consumers sum the partials in index order.  The solver
+// kernels re-sum the partials they need in every block (the same bits in
+// every block), which removes the separate finalisation launches from the
+// iteration.
+#include <climits>
+
+#include "device.h"
+#include "internal.h"
+
+namespace hmc {
+
+static Lat to_lat(const LatArg& a) {
+  Lat g;
+  for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
+  g.Vh = a.Vh;
+  g.stride = a.stride;
+  return g;
+}
+
+// ------------------------------------------------------------- sums
+
+template <class SP>
+__global__ void __launch_bounds__(kBlock) k_norm2_partials(Lat g, const void* x, double* part) {
+  double v[1] = {0.0};
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
+    cx<typename SP::R> a[12];
+    SP::load(x, g.stride, s, a);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[0] += (double)a[k].re * a[k].re + (double)a[k].im * a[k].im;
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_inner_partials(Lat g, const double2* a, const double2* b, double* part) {
+  double v[2] = {0.0, 0.0};
+  const size_t n = (size_t)12 * g.stride;
+  for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)gridDim.x * kBlock) {
+    if ((int)(j % g.stride) >= g.Vh) continue;
+    double2 x = a[j], y = b[j];
+    v[0] += x.x * y.x + x.y * y.y;  // Re conj(x) y
+    v[1] += x.x * y.y - x.y * y.x;  // Im conj(x) y
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v[0];
+    part[gridDim.x + blockIdx.x] = v[1];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* part, int n, int nvals, double* out, double scale,
+                                                     int accumulate) {
+  for (int v = 0; v < nvals; ++v) {
+    double s = sum_partials(part + (size_t)v * n, n);
+    if (threadIdx.x == 0) out[v] = (accumulate ? out[v] : 0.0) + scale * s;
+  }
+}
+
+// sumMulti: per-block histogram of |x|^2 over subsets, accumulated in
+// site order by one work-item per block (deterministic), then summed over
+// blocks in block order.
+constexpr int kMaxSub = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_sum_multi_partials(Lat g, const double2* x, const int* subset, int nsub,
+                                                               double* part) {
+  __shared__ double bins[kMaxSub];
+  __shared__ double vals[kBlock];
+  __shared__ int subs[kBlock];
+  for (int k = threadIdx.x; k < nsub; k += kBlock) bins[k] = 0.0;
+  const int half = blockIdx.y;
+  const double2* xh = x + (size_t)half * 12 * g.stride;
+  const int* sh = subset + (size_t)half * g.Vh;
+  for (int base = blockIdx.x * kBlock; base < g.Vh; base += gridDim.x * kBlock) {
+    int s = base + threadIdx.x;
+    double v = 0.0;
+    int sub = 0;
+    if (s < g.Vh) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        double2 a = xh[(size_t)k * g.stride + s];
+        v += a.x * a.x + a.y * a.y;
+      }
+      sub = sh[s];
+    }
+    __syncthreads();
+    vals[threadIdx.x] = v;
+    subs[threadIdx.x] = sub;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int n = min(kBlock, g.Vh - base);
+      for (int k = 0; k < n; ++k)
+        if (subs[k] >= 0 && subs[k] < nsub) bins[subs[k]] += vals[k];  // ids outside [0, nsub) are ignored
+    }
+  }
+  __syncthreads();
+  double* out = part + ((size_t)half * gridDim.x + blockIdx.x) * nsub;
+  for (int k = threadIdx.x; k < nsub; k += kBlock) out[k] = bins[k];
+}
+
+__global__ void k_sum_multi_final(const double* part, int nrows, int nsub, double* out) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nsub) return;
+  double s = 0.0;
+  for (int r = 0; r < nrows; ++r) s += part[(size_t)r * nsub + k];
+  out[k] = s;
+}
+
+// ------------------------------------------------------- element-wise
+
+__global__ void k_axpby(Lat g, double a, const double2* x, double b, double2* y) {
+  const size_t n = (size_t)12 * g.stride;
+  for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)gridDim.x * kBlock) {
+    double2 u = x[j], v = y[j];
+    y[j] = make_double2(fma(a, u.x, b * v.x), fma(a, u.y, b * v.y));
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_xmy_norm(Lat g, const double2* b, const double2* q, double2* r,
+                                                    double* part) {
+  double v[1] = {0.0};
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      size_t j = (size_t)k * g.stride + s;
+      double2 d = make_double2(b[j].x - q[j].x, b[j].y - q[j].y);
+      r[j] = d;
+      v[0] += d.x * d.x + d.y * d.y;
+    }
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void k_gamma5(Lat g, const double2* in, double2* out) {
+  int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.Vh) return;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double2 a = in[(size_t)k * g.stride + s];
+    double sg = k < 6 ? 1.0 : -1.0;  // gamma5 = diag(1, 1, -1, -1)
+    out[(size_t)k * g.stride + s] = make_double2(sg * a.x, sg * a.y);
+  }
+}
+
+__global__ void k_zero(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
+  for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n16; j += (size_t)gridDim.x * kBlock)
+    p[j] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ void k_copy(uint4* d, const uint4* s, size_t n16, unsigned char* dt, const unsigned char* st,
+                       size_t ntail) {
+  for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n16; j += (size_t)gridDim.x * kBlock) d[j] = s[j];
+  if (blockIdx.x == 0 && threadIdx.x < ntail) dt[threadIdx.x] = st[threadIdx.x];
+}
+
+// ------------------------------------------------------------ solvers
+
+// x = 0, r = p = b, partials of |b|^2 (FP64 vectors).
+__global__ void __launch_bounds__(kBlock) k_cg_init(Lat g, const double2* b, double2* x, double2* r, double2* p,
+                                                    double* part) {
+  double v[1] = {0.0};
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      size_t j = (size_t)k * g.stride + s;
+      double2 a = b[j];
+      x[j] = make_double2(0.0, 0.0);
+      r[j] = a;
+      p[j] = a;
+      v[0] += a.x * a.x + a.y * a.y;
+    }
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// alpha = sum(part_a) / sum(part_b);  x += alpha p;  r -= alpha q;
+// part_out = per-block |r|^2.  (CG: part_a = |r|^2, part_b = <p, A p>;
+// CGLS: part_a = |s|^2, part_b = |q|^2.)
+template <class SP, class SX>
+__global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table, CgArgs one) {
+  const CgArgs a = table ? table[blockIdx.y] : one;
+  if (a.iter >= a.state->stop_at) return;
+  using R = typename SP::R;
+  const double num = sum_partials(a.part_a, a.n_a);
+  const double den = sum_partials(a.part_b, a.n_b);
+  const double alpha = num / den;
+  const R al = (R)alpha;
+  double v[1] = {0.0};
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
+    cx<R> p[12], q[12], r[12];
+    cx<typename SX::R> x[12];
+    SP::load(a.p, g.stride, s, p);
+    SP::load(a.q, g.stride, s, q);
+    SP::load(a.r, g.stride, s, r);
+    SX::load(a.x, g.stride, s, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      x[k].re = fma((typename SX::R)alpha, (typename SX::R)p[k].re, x[k].re);
+      x[k].im = fma((typename SX::R)alpha, (typename SX::R)p[k].im, x[k].im);
+      r[k].re = fma(-al, q[k].re, r[k].re);
+      r[k].im = fma(-al, q[k].im, r[k].im);
+      v[0] += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
+    }
+    SX::store(a.x, g.stride, s, x);
+    SP::store(a.r, g.stride, s, r);
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) a.part_out[blockIdx.x] = v[0];
+}
+
+// beta = sum(part_a) / sum(part_b);  p = src + beta p, src = r (CG) or s
+// (CGLS).  The convergence measure |r|^2 = sum(part_c).  Block 0 records
+// the iteration and, when |r|^2 <= thr (or, in mixed precision, when the
+// inner residual fell by delta since the last FP64 update), sets
+// stop_at = iter + 1; no other block reads that value in this launch.
+template <class SP>
+__global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, int cgls, const CgArgs* table, CgArgs one) {
+  const CgArgs a = table ? table[blockIdx.y] : one;
+  SolverState* stt = a.state;
+  if (a.iter >= stt->stop_at) return;
+  using R = typename SP::R;
+  const double nw = sum_partials(a.part_a, a.n_a);
+  const double old = sum_partials(a.part_b, a.n_b);
+  const double rr = cgls ? sum_partials(a.part_c, a.n_c) : nw;
+  bool conv = rr <= a.thr;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    stt->iter = a.iter + 1;
+    stt->rr = rr;
+    if (a.mixed) {
+      double mx = fmax(stt->maxrr, rr);
+      stt->maxrr = mx;
+      if (conv || rr < a.delta2 * mx || !(rr == rr)) {
+        stt->reason = 2;
+        stt->stop_at = a.iter + 1;
+      }
+    } else if (conv || !(rr == rr)) {
+      stt->reason = conv ? 1 : 3;
+      stt->stop_at = a.iter + 1;
+    }
+  }
+  if (conv && !a.mixed) return;
+  const R beta = (R)(nw / old);
+  const void* src = cgls ? a.s : a.r;
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
+    cx<R> p[12], q[12];
+    SP::load(a.p, g.stride, s, p);
+    SP::load(src, g.stride, s, q);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      p[k].re = fma(beta, p[k].re, q[k].re);
+      p[k].im = fma(beta, p[k].im, q[k].im);
+    }
+    SP::store(a.p, g.stride, s, p);
+  }
+}
+
+// Resume/initialise solver control: stop_at = INT_MAX, iter given, maxrr
+// from a device slot (may be null -> 0).
+__global__ void k_state_reset(SolverState* st, int iter, const double* maxrr, int nbatch) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nbatch) return;
+  st[k].stop_at = INT_MAX;
+  st[k].reason = 0;
+  st[k].iter = iter;
+  st[k].maxrr = maxrr ? maxrr[k] : 0.0;
+}
+
+// x64 += x32; x32 = 0 (mixed precision accumulator hand-over).
+__global__ void k_add_low_to_f64(Lat g, double2* x64, float2* x32) {
+  const size_t n = (size_t)12 * g.stride;
+  for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)gridDim.x * kBlock) {
+    float2 l = x32[j];
+    double2 h = x64[j];
+    x64[j] = make_double2(h.x + (double)l.x, h.y + (double)l.y);
+    x32[j] = make_float2(0.f, 0.f);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_norm2_partials(const LatArg& g, hmc_prec prec, const void* x, double* part, int nb,
+                                 hipStream_t st) {
+  TimedScope ts(TK_REDUCE, st, 0);
+  switch (prec) {
+    case HMC_F64: hipLaunchKernelGGL(k_norm2_partials<SpF64>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
+    case HMC_F32: hipLaunchKernelGGL(k_norm2_partials<SpF32>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
+    case HMC_F16: hipLaunchKernelGGL(k_norm2_partials<SpF16>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
+    case HMC_BF16: hipLaunchKernelGGL(k_norm2_partials<SpBF16>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_partials(const LatArg& g, const void* a, const void* b, double* part, int nb,
+                                 hipStream_t st) {
+  TimedScope ts(TK_REDUCE, st, 0);
+  hipLaunchKernelGGL(k_inner_partials, dim3(nb), dim3(kBlock), 0, st, to_lat(g), (const double2*)a,
+                     (const double2*)b, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* part, int n, int nvals, double* out, double scale, int accumulate,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, part, n, nvals, out, scale, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_multi(const LatArg& g, const void* x, int nhalves, const int* subset, int nsub, double* part,
+                            int nb, double* out, hipStream_t st) {
+  if (nsub > kMaxSub || nsub < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sum_multi_partials, dim3(nb, nhalves), dim3(kBlock), 0, st, to_lat(g), (const double2*)x,
+                     subset, nsub, part);
+  hipLaunchKernelGGL(k_sum_multi_final, dim3(ceil_div(nsub, kBlock)), dim3(kBlock), 0, st, part, nb * nhalves, nsub,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(const LatArg& g, double a, const void* x, double b, void* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(blas_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), a, (const double2*)x, b,
+                     (double2*)y);
+  return hipGetLastError();
+}
+
+hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* r, double* part, int nb,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_xmy_norm, dim3(nb), dim3(kBlock), 0, st, to_lat(g), (const double2*)b, (const double2*)q,
+                     (double2*)r, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma5(const LatArg& g, const void* in, void* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gamma5, dim3(site_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), (const double2*)in,
+                     (double2*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  size_t n16 = bytes / 16, nt = bytes % 16;
+  int nb = (int)std::min<size_t>(std::max<size_t>((n16 + kBlock - 1) / kBlock, 1), 4096);
+  hipLaunchKernelGGL(k_zero, dim3(nb), dim3(kBlock), 0, st, (uint4*)p, n16, (unsigned char*)p + n16 * 16, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  size_t n16 = bytes / 16, nt = bytes % 16;
+  int nb = (int)std::min<size_t>(std::max<size_t>((n16 + kBlock - 1) / kBlock, 1), 4096);
+  hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kBlock), 0, st, (uint4*)dst, (const uint4*)src, n16,
+                     (unsigned char*)dst + n16 * 16, (const unsigned char*)src + n16 * 16, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x, void* r, void* p, double* part,
+                          int nb, hipStream_t st) {
+  if (prec != HMC_F64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kBlock), 0, st, to_lat(g), (const double2*)b, (double2*)x,
+                     (double2*)r, (double2*)p, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
+                            int nbatch, hipStream_t st) {
+  TimedScope ts(TK_CG_BLAS, st, 0);
+  dim3 grid(nb, nbatch), block(kBlock);
+  switch (prec) {
+    case HMC_F64: hipLaunchKernelGGL((k_cg_update<SpF64, SpF64>), grid, block, 0, st, to_lat(g), table, a); break;
+    case HMC_F32: hipLaunchKernelGGL((k_cg_update<SpF32, SpF32>), grid, block, 0, st, to_lat(g), table, a); break;
+    case HMC_F16: hipLaunchKernelGGL((k_cg_update<SpF16, SpF32>), grid, block, 0, st, to_lat(g), table, a); break;
+    case HMC_BF16: hipLaunchKernelGGL((k_cg_update<SpBF16, SpF32>), grid, block, 0, st, to_lat(g), table, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, int cgls, const CgArgs& a, int nb,
+                             const CgArgs* table, int nbatch, hipStream_t st) {
+  TimedScope ts(TK_CG_BLAS, st, 0);
+  dim3 grid(nb, nbatch), block(kBlock);
+  switch (prec) {
+    case HMC_F64: hipLaunchKernelGGL(k_cg_pupdate<SpF64>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
+    case HMC_F32: hipLaunchKernelGGL(k_cg_pupdate<SpF32>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
+    case HMC_F16: hipLaunchKernelGGL(k_cg_pupdate<SpF16>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
+    case HMC_BF16: hipLaunchKernelGGL(k_cg_pupdate<SpBF16>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_state_reset(SolverState* st_dev, int iter, const double* maxrr, int nbatch, hipStream_t st) {
+  hipLaunchKernelGGL(k_state_reset, dim3(ceil_div(nbatch, kBlock)), dim3(kBlock), 0, st, st_dev, iter, maxrr,
+                     nbatch);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_low_to_f64, dim3(blas_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), (double2*)x64,
+                     (float2*)xlow);
+  return hipGetLastError();
+}
+
+}  // namespace hmc

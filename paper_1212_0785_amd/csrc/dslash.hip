@@ -1,0 +1,184 @@
+// Wilson hopping term on one checkerboard (the dominant kernel of the
+// fermion-matrix inversion that the paper's introduction singles out as
+// the bulk of the floating-point work):
+//   (D psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+//                      + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)]
+// with -1 on hops across the time boundary; the dagger swaps the
+// projectors.  One work-item per output site (Sec. 3's site-per-thread
+// mapping); the 4x4 spin structure is applied through the rank-2
+// projections (1 +- gamma_mu), so each hop multiplies only two colour
+// vectors by the link.
+//
+// The kernel is HBM-bound (about 0.86 flop per byte in FP64).  Fields are
+// stored component-major so every load instruction of a wave covers one
+// contiguous 1 KiB (FP64) span; neighbour spinors are re-read through L2,
+// and the XCD-aware block order keeps the +-y/+-z neighbours of a block on
+// the XCD that owns it.
+#include "device.h"
+#include "internal.h"
+
+namespace hmc {
+
+#ifndef HMC_DSLASH_WAVES
+#define HMC_DSLASH_WAVES
+#endif
+#ifndef HMC_HOP_CHAIN
+#define HMC_HOP_CHAIN 1
+#endif
+
+// Makes `idx` depend on every accumulator without changing either.  The
+// loads of a hop use indices chained to the accumulators left by the
+// previous hop, so the compiler cannot issue all sixteen hops' loads up
+// front (that needs ~600 registers and spills); a wave keeps one hop
+// (HMC_HOP_CHAIN = 1) or one direction (= 2) of loads in flight and
+// occupancy supplies the memory parallelism.
+template <typename R>
+__device__ __forceinline__ int chain(int idx, cx<R>* acc) {
+#if HMC_HOP_CHAIN
+#pragma unroll
+  for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
+  asm volatile("" : "+v"(idx));
+#endif
+  return idx;
+}
+
+template <class SP, class LK, int MU, bool DAG>
+__device__ __forceinline__ void hop_dir(const Lat& g, const Site& st, int out_par, int s, const void* U,
+                                        const void* in, cx<typename SP::R>* acc) {
+  using R = typename SP::R;
+  constexpr int SF = DAG ? +1 : -1;  // forward hop carries (1 + SF gamma_mu)
+  constexpr int SB = -SF;
+  bool wf, wb;
+  const int lf = neighbour_lex<MU, +1>(g, st, &wf);
+  const int lb = neighbour_lex<MU, -1>(g, st, &wb);
+  {
+    cx<R> psi[12], h[6], uh[6];
+    const int sn = chain(lf >> 1, acc), sl = chain(s, acc);
+    SP::load(in, g.stride, sn, psi);
+    spin_project<MU, SF>(psi, h);
+    if (MU == 3) {  // antiperiodic time boundary
+      const R sg = wf ? R(-1) : R(1);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k] = sg * h[k];
+    }
+    const mat3<R> u = LK::load(U, g.stride, MU, out_par, sl);
+    mv(u, h, uh);
+    mv(u, h + 3, uh + 3);
+    spin_accum<MU, SF>(acc, uh);
+  }
+  {
+    cx<R> psi[12], h[6], uh[6];
+    const int sn = HMC_HOP_CHAIN == 1 ? chain(lb >> 1, acc) : lb >> 1;
+    SP::load(in, g.stride, sn, psi);
+    spin_project<MU, SB>(psi, h);
+    if (MU == 3) {
+      const R sg = wb ? R(-1) : R(1);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k] = sg * h[k];
+    }
+    const mat3<R> u = LK::load(U, g.stride, MU, out_par ^ 1, sn);
+    mdv(u, h, uh);
+    mdv(u, h + 3, uh + 3);
+    spin_accum<MU, SB>(acc, uh);
+  }
+}
+
+// BATCH: blockIdx.y selects an entry of `table` (same-volume requests share
+// one launch); otherwise the single entry `one` is read from the kernel
+// arguments.
+template <class SP, class LK, bool DAG, int EPI, bool BATCH>
+__global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int out_par,
+                                                                    const DslashArgs* __restrict__ table,
+                                                                    DslashArgs one) {
+  using R = typename SP::R;
+  const DslashArgs* ep;
+  if constexpr (BATCH)
+    ep = table + blockIdx.y;
+  else
+    ep = &one;
+  const DslashArgs& e = *ep;
+  if (e.stop_at && e.iter >= *(const HMC_GLOBAL int*)e.stop_at) return;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = b * kBlock + threadIdx.x;
+  double nrm[1] = {0.0};
+  if (s < g.Vh) {
+    const Site st = cb_site(g, out_par, s);
+    cx<R> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+    hop_dir<SP, LK, 0, DAG>(g, st, out_par, s, e.U, e.in, acc);
+    hop_dir<SP, LK, 1, DAG>(g, st, out_par, s, e.U, e.in, acc);
+    hop_dir<SP, LK, 2, DAG>(g, st, out_par, s, e.U, e.in, acc);
+    hop_dir<SP, LK, 3, DAG>(g, st, out_par, s, e.U, e.in, acc);
+    if (EPI != EPI_PLAIN) {
+      const R a = (R)e.a, bb = (R)e.b;
+      if (e.y) {
+        cx<R> y[12];
+        SP::load(e.y, g.stride, s, y);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {fma(bb, acc[k].re, a * y[k].re), fma(bb, acc[k].im, a * y[k].im)};
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = bb * acc[k];
+      }
+    }
+    if (EPI == EPI_AXPY_NORM)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) nrm[0] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+    SP::store(e.out, g.stride, s, acc);
+  }
+  if (EPI == EPI_AXPY_NORM) {
+    block_sum<1>(nrm);
+    if (threadIdx.x == 0) ((HMC_GLOBAL double*)e.partial)[b] = nrm[0];
+  }
+}
+
+template <class SP, class LK>
+static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_par, const DslashArgs* table,
+                               int nbatch, const DslashArgs& one, hipStream_t st) {
+  Lat g;
+  for (int k = 0; k < 4; ++k) g.L[k] = ga.L[k];
+  g.Vh = ga.Vh;
+  g.stride = ga.stride;
+  dim3 grid(site_blocks(ga.Vh), nbatch), block(kBlock);
+#define HMC_DS(D, E)                                                                                    \
+  do {                                                                                                 \
+    if (table)                                                                                         \
+      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one);  \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one); \
+  } while (0)
+  if (dagger) {
+    if (epi == EPI_PLAIN) HMC_DS(true, EPI_PLAIN);
+    else if (epi == EPI_AXPY) HMC_DS(true, EPI_AXPY);
+    else HMC_DS(true, EPI_AXPY_NORM);
+  } else {
+    if (epi == EPI_PLAIN) HMC_DS(false, EPI_PLAIN);
+    else if (epi == EPI_AXPY) HMC_DS(false, EPI_AXPY);
+    else HMC_DS(false, EPI_AXPY_NORM);
+  }
+#undef HMC_DS
+  return hipGetLastError();
+}
+
+hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,
+                         int nbatch, const DslashArgs& one, hipStream_t st) {
+  // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for y)
+  double site_bytes = 0;
+  switch (prec) {
+    case HMC_F64: site_bytes = 8 * LkF64::kBytes + 2 * SpF64::kBytes + (epi ? SpF64::kBytes : 0); break;
+    case HMC_F32: site_bytes = 8 * LkF32::kBytes + 2 * SpF32::kBytes + (epi ? SpF32::kBytes : 0); break;
+    case HMC_F16: site_bytes = 8 * LkF16::kBytes + 2 * SpF16::kBytes + (epi ? SpF16::kBytes : 0); break;
+    default: site_bytes = 8 * LkBF16::kBytes + 2 * SpBF16::kBytes + (epi ? SpBF16::kBytes : 0); break;
+  }
+  TimedScope ts(TK_DSLASH, st, site_bytes * g.Vh * nbatch);
+  switch (prec) {
+    case HMC_F64: return launch_typed<SpF64, LkF64>(dagger, epi, g, out_par, table, nbatch, one, st);
+    case HMC_F32: return launch_typed<SpF32, LkF32>(dagger, epi, g, out_par, table, nbatch, one, st);
+    case HMC_F16: return launch_typed<SpF16, LkF16>(dagger, epi, g, out_par, table, nbatch, one, st);
+    case HMC_BF16: return launch_typed<SpBF16, LkBF16>(dagger, epi, g, out_par, table, nbatch, one, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace hmc

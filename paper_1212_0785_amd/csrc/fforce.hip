@@ -1,0 +1,103 @@
+// Wilson fermion force fused with the momentum update (the "force term
+// calculation" and "projection of fields" of the paper's Sec. 1 step list).
+// For S_f = phi^dag (Mhat^dag Mhat)^-1 phi with X = (X_e, D_oe X_e) and
+// Y = (Mhat X_e, (D^dag)_oe Mhat X_e) on the full lattice:
+//   M1 = s tr_spin[(1 - gamma_mu) X(x+mu) Y(x)^dag]
+//   M2 = s tr_spin[(1 + gamma_mu) X(x) Y(x+mu)^dag]
+//   F  = (i kappa^2/2) TA(U_mu(x) M1 - M2 U_mu(x)^dag).
+// Because P = 1 +- gamma_mu is Hermitian with P^2 = 2P, the spin trace
+// tr[P a b^dag] equals sum over the two projected components h_j(a)
+// h_j(b)^dag, so each trace is two colour outer products.
+#include "device.h"
+#include "internal.h"
+
+namespace hmc {
+
+static Lat to_lat(const LatArg& a) {
+  Lat g;
+  for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
+  g.Vh = a.Vh;
+  g.stride = a.stride;
+  return g;
+}
+
+struct ForceVecs {
+  const void* X[2];  // by parity
+  const void* Y[2];
+};
+
+// sg * sum_{j=0,1} h_j(a) h_j(b)^dag for projected half spinors ha, hb.
+__device__ __forceinline__ mat3<double> proj_outer(const cx<double>* ha, const cx<double>* hb, double sg) {
+  mat3<double> m;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cx<double> v = ha[r] * conj(hb[c]);
+      v = cmadd(v, ha[3 + r], conj(hb[3 + c]));
+      m.m[3 * r + c] = sg * v;
+    }
+  return m;
+}
+
+template <int MU>
+__device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, const ForceVecs& v, double* P,
+                                                   double c_ta, int par, int s) {
+  Site x = cb_site(g, par, s);
+  bool w;
+  const int sf = neighbour_lex<MU, +1>(g, x, &w) >> 1;
+  const double sg = (MU == 3 && w) ? -1.0 : 1.0;
+  cx<double> a[12], b[12], ha[6], hb[6];
+  // M1 from X(x+mu) and Y(x), projector (1 - gamma_mu)
+  SpF64::load(v.X[par ^ 1], g.stride, sf, a);
+  SpF64::load(v.Y[par], g.stride, s, b);
+  spin_project<MU, -1>(a, ha);
+  spin_project<MU, -1>(b, hb);
+  mat3<double> M1 = proj_outer(ha, hb, sg);
+  // M2 from X(x) and Y(x+mu), projector (1 + gamma_mu)
+  SpF64::load(v.X[par], g.stride, s, a);
+  SpF64::load(v.Y[par ^ 1], g.stride, sf, b);
+  spin_project<MU, +1>(a, ha);
+  spin_project<MU, +1>(b, hb);
+  mat3<double> M2 = proj_outer(ha, hb, sg);
+  mat3<double> u = LkF64::load(U, g.stride, MU, par, s);
+  mat3<double> W = msub(mmul(u, M1), mmul_nd(M2, u));
+  double f[8], c[8];
+  i_ta_compact(W, c_ta, f);
+  load_compact(P, g.stride, MU, par, s, c);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c[k] += f[k];
+  store_compact(P, g.stride, MU, par, s, c);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, ForceVecs v, double* P,
+                                                          double c_ta) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= 2 * g.Vh) return;
+  int par = j >= g.Vh, s = j - par * g.Vh;
+  switch (blockIdx.y) {
+    case 0: fermion_force_link<0>(g, U, v, P, c_ta, par, s); break;
+    case 1: fermion_force_link<1>(g, U, v, P, c_ta, par, s); break;
+    case 2: fermion_force_link<2>(g, U, v, P, c_ta, par, s); break;
+    default: fermion_force_link<3>(g, U, v, P, c_ta, par, s); break;
+  }
+}
+
+// P <- P - coef * F_f with F_f = (i kappa^2 / 2) TA(W): the kernel adds
+// i c_ta TA(W) with c_ta = -coef kappa^2 / 2 (coef passed already times
+// kappa^2 by the caller as `coef`).
+hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
+                                const void* Yo, double* P, double coef, hipStream_t st) {
+  // algorithmic: 4 links, X and Y (both read once), momenta read + written
+  TimedScope ts(TK_FERMION_FORCE, st, 2.0 * g.Vh * (4 * LkF64::kBytes + 2 * SpF64::kBytes + 2 * 4 * 64));
+  ForceVecs v;
+  v.X[0] = Xe;
+  v.X[1] = Xo;
+  v.Y[0] = Ye;
+  v.Y[1] = Yo;
+  hipLaunchKernelGGL(k_fermion_force, dim3(ceil_div(2LL * g.Vh, kBlock), 4), dim3(kBlock), 0, st, to_lat(g), U, v, P,
+                     -0.5 * coef);
+  return hipGetLastError();
+}
+
+}  // namespace hmc

@@ -1,0 +1,184 @@
+// Gauge-field kernels of the HMC step list (Sec. 1): the plaquette / gauge
+// action sum, the staple force fused with the momentum update, the link
+// update exp(i eps P) U with SU(3) reunitarisation, and the kinetic sum.
+// One work-item per (site, direction) for the force and the link update
+// (direction from blockIdx.y, so the direction is uniform in a block and
+// resolved at compile time), one per site for the sums.
+#include "device.h"
+#include "internal.h"
+
+namespace hmc {
+
+static Lat to_lat(const LatArg& a) {
+  Lat g;
+  for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
+  g.Vh = a.Vh;
+  g.stride = a.stride;
+  return g;
+}
+
+// The site one step along +-MU, with coordinates.
+template <int MU, int DIR>
+__device__ __forceinline__ Site shift(const Lat& g, const Site& st) {
+  Site n = st;
+  bool w;
+  n.lex = neighbour_lex<MU, DIR>(g, st, &w);
+  int c = st.c[MU] + DIR;
+  n.c[MU] = w ? (DIR > 0 ? 0 : g.L[MU] - 1) : c;
+  return n;
+}
+
+__device__ __forceinline__ int site_parity(const Site& st) { return (st.c[0] + st.c[1] + st.c[2] + st.c[3]) & 1; }
+
+__device__ __forceinline__ mat3<double> link(const Lat& g, const void* U, int mu, const Site& st) {
+  return LkF64::load(U, g.stride, mu, site_parity(st), st.lex >> 1);
+}
+
+// Re Tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+template <int MU, int NU>
+__device__ __forceinline__ double plaq(const Lat& g, const void* U, const Site& x) {
+  Site xm = shift<MU, +1>(g, x), xn = shift<NU, +1>(g, x);
+  mat3<double> a = mmul(link(g, U, MU, x), link(g, U, NU, xm));
+  // U_mu(x+nu)^dag U_nu(x)^dag = b^dag with b = U_nu(x) U_mu(x+nu)
+  mat3<double> b = mmul(link(g, U, NU, x), link(g, U, MU, xn));
+  // Re Tr(a b^dag) = sum_ij Re(a_ij conj(b_ij))
+  double s = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s += a.m[k].re * b.m[k].re + a.m[k].im * b.m[k].im;
+  return s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_plaquette_partials(Lat g, const void* U, double* part) {
+  double v[1] = {0.0};
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < 2 * g.Vh; j += gridDim.x * kBlock) {
+    int par = j >= g.Vh, s = j - par * g.Vh;
+    Site x = cb_site(g, par, s);
+    v[0] += plaq<0, 1>(g, U, x) + plaq<0, 2>(g, U, x) + plaq<0, 3>(g, U, x) + plaq<1, 2>(g, U, x) +
+            plaq<1, 3>(g, U, x) + plaq<2, 3>(g, U, x);
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_kinetic_partials(Lat g, const double* P, double* part) {
+  double v[1] = {0.0};
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < 2 * g.Vh; j += gridDim.x * kBlock) {
+    int par = j >= g.Vh, s = j - par * g.Vh;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      double c[8];
+      load_compact(P, g.stride, mu, par, s, c);
+      double p22 = -c[0] - c[1];
+      v[0] += c[0] * c[0] + c[1] * c[1] + p22 * p22 +
+              2.0 * (c[2] * c[2] + c[3] * c[3] + c[4] * c[4] + c[5] * c[5] + c[6] * c[6] + c[7] * c[7]);
+    }
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Orders the loads of successive staples after the accumulation of the
+// previous one (see the same device in the Dslash): without it all 19 link
+// loads of a (site, direction) are issued at once and the kernel spills.
+__device__ __forceinline__ void chain_sites(Site& x, Site& xm, mat3<double>& A) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(A.m[k].re), "+v"(A.m[k].im));
+  asm volatile("" : "+v"(x.lex), "+v"(xm.lex));
+}
+
+// Staple pair of plane (MU, NU) for the link U_mu(x):
+//   U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+template <int MU, int NU>
+__device__ __forceinline__ void add_staples(const Lat& g, const void* U, Site x, Site xm, mat3<double>& A) {
+  chain_sites(x, xm, A);
+  {
+    Site xn = shift<NU, +1>(g, x);
+    mat3<double> t = mmul_nd(link(g, U, NU, xm), link(g, U, MU, xn));
+    A = madd(A, mmul_nd(t, link(g, U, NU, x)));
+  }
+  chain_sites(x, xm, A);
+  {
+    Site xmn = shift<NU, -1>(g, xm), xn = shift<NU, -1>(g, x);
+    // U_nu(x+mu-nu)^dag U_mu(x-nu)^dag = (U_mu(x-nu) U_nu(x+mu-nu))^dag
+    mat3<double> ba = mmul(link(g, U, MU, xn), link(g, U, NU, xmn));
+    A = madd(A, mmul_dn(ba, link(g, U, NU, xn)));
+  }
+}
+
+template <int MU>
+__device__ __forceinline__ void gauge_force_link(const Lat& g, const void* U, double* P, double coef_beta, int par,
+                                                 int s) {
+  Site x = cb_site(g, par, s);
+  Site xm = shift<MU, +1>(g, x);
+  mat3<double> A;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) A.m[k] = {0.0, 0.0};
+  if (MU != 0) add_staples<MU, 0>(g, U, x, xm, A);
+  if (MU != 1) add_staples<MU, 1>(g, U, x, xm, A);
+  if (MU != 2) add_staples<MU, 2>(g, U, x, xm, A);
+  if (MU != 3) add_staples<MU, 3>(g, U, x, xm, A);
+  mat3<double> W = mmul(LkF64::load(U, g.stride, MU, par, s), A);
+  // F = -(i beta / 12) TA(W);  P <- P - coef F = P + (i coef beta / 12) TA(W)
+  double f[8], c[8];
+  i_ta_compact(W, coef_beta / 12.0, f);
+  load_compact(P, g.stride, MU, par, s, c);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c[k] += f[k];
+  store_compact(P, g.stride, MU, par, s, c);
+}
+
+__global__ void __launch_bounds__(kBlock) k_gauge_force(Lat g, const void* U, double* P, double coef_beta) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= 2 * g.Vh) return;
+  int par = j >= g.Vh, s = j - par * g.Vh;
+  switch (blockIdx.y) {
+    case 0: gauge_force_link<0>(g, U, P, coef_beta, par, s); break;
+    case 1: gauge_force_link<1>(g, U, P, coef_beta, par, s); break;
+    case 2: gauge_force_link<2>(g, U, P, coef_beta, par, s); break;
+    default: gauge_force_link<3>(g, U, P, coef_beta, par, s); break;
+  }
+}
+
+// U <- reunit(exp(i eps P) U), one link per work-item.
+__global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const double* P, double eps) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= 2 * g.Vh) return;
+  int par = j >= g.Vh, s = j - par * g.Vh;
+  int mu = blockIdx.y;
+  double c[8];
+  load_compact(P, g.stride, mu, par, s, c);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c[k] *= eps;
+  mat3<double> E = exp_iQ(herm_from_compact(c));
+  mat3<double> u = mmul(E, LkF64::load(U, g.stride, mu, par, s));
+  reunitarise(u);
+  LkF64::store(U, g.stride, mu, par, s, u);
+}
+
+hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st) {
+  TimedScope ts(TK_PLAQUETTE, st, 2.0 * g.Vh * 4 * LkF64::kBytes);
+  hipLaunchKernelGGL(k_plaquette_partials, dim3(nb), dim3(kBlock), 0, st, to_lat(g), U, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* part, int nb, hipStream_t st) {
+  TimedScope ts(TK_REDUCE, st, 2.0 * g.Vh * 4 * 64);
+  hipLaunchKernelGGL(k_kinetic_partials, dim3(nb), dim3(kBlock), 0, st, to_lat(g), P, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st) {
+  // algorithmic: 4 links read, momenta read + written, per site
+  TimedScope ts(TK_GAUGE_FORCE, st, 2.0 * g.Vh * (4 * LkF64::kBytes + 2 * 4 * 64));
+  hipLaunchKernelGGL(k_gauge_force, dim3(ceil_div(2LL * g.Vh, kBlock), 4), dim3(kBlock), 0, st, to_lat(g), U, P,
+                     coef_beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st) {
+  TimedScope ts(TK_EXP_UPDATE, st, 2.0 * g.Vh * 4 * (2 * LkF64::kBytes + 64));
+  hipLaunchKernelGGL(k_exp_update, dim3(ceil_div(2LL * g.Vh, kBlock), 4), dim3(kBlock), 0, st, to_lat(g), U, P, eps);
+  return hipGetLastError();
+}
+
+}  // namespace hmc

@@ -1,0 +1,807 @@
+// C-ABI entry points of libhmc: fields objects in caller-owned arenas,
+// layout conversion, the Dslash / Mhat / M operators, global sums, forces,
+// the link update, refresh, the leapfrog integrator and the HMC trajectory
+// (the HMC step list of the paper's Sec. 1, run entirely on the device).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fields.h"
+
+namespace hmc {
+
+// ------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+const char* last_error() { return g_err.c_str(); }
+
+// ------------------------------------------------------------ timing
+
+namespace {
+struct TimingRec {
+  int kernel;
+  int pair;
+  double bytes;
+};
+struct Timing {
+  std::mutex mu;
+  int sample_every = 0;
+  std::vector<hipEvent_t> events;  // 2 per pair
+  std::vector<TimingRec> recs;
+  long long counter[TK_COUNT] = {};
+  long long launches[TK_COUNT] = {};
+  double ms[TK_COUNT] = {};
+  double bytes[TK_COUNT] = {};
+  int open_pair = -1;
+};
+Timing& timing() {
+  static Timing t;
+  return t;
+}
+constexpr int kMaxPairs = 8192;
+}  // namespace
+
+const char* timed_kernel_name(int k) {
+  static const char* names[TK_COUNT] = {"dslash", "cg_blas", "reduce", "gauge_force", "fermion_force",
+                                        "exp_update", "refresh", "plaquette", "other"};
+  return (k >= 0 && k < TK_COUNT) ? names[k] : "?";
+}
+
+bool timing_begin(int kernel, hipStream_t st, double bytes) {
+  Timing& T = timing();
+  if (T.sample_every <= 0) return false;
+  std::lock_guard<std::mutex> lk(T.mu);
+  if (T.counter[kernel]++ % T.sample_every) return false;
+  int pair = (int)T.recs.size();
+  if (pair >= kMaxPairs) return false;
+  while ((int)T.events.size() < 2 * (pair + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return false;
+    T.events.push_back(e);
+  }
+  if (hipEventRecord(T.events[2 * pair], st) != hipSuccess) return false;
+  T.recs.push_back({kernel, pair, bytes});
+  T.open_pair = pair;
+  return true;
+}
+
+void timing_end(int kernel, hipStream_t st) {
+  (void)kernel;
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  if (T.open_pair >= 0) hipEventRecord(T.events[2 * T.open_pair + 1], st);
+  T.open_pair = -1;
+}
+
+// --------------------------------------------------------- geometry
+
+static hmc_status check_geom(const hmc_geom* geom, LatArg* g, long long* V) {
+  HMC_REQUIRE(geom, "null geometry");
+  long long v = 1;
+  for (int k = 0; k < 4; ++k) {
+    int L = geom->L[k];
+    HMC_REQUIRE(L >= 2 && L % 2 == 0, "lattice extent L[%d] = %d must be even and >= 2", k, L);
+    v *= L;
+  }
+  HMC_REQUIRE(v / 2 < (1LL << 31) / 12, "lattice too large for 32-bit component indexing");
+  for (int k = 0; k < 4; ++k) g->L[k] = geom->L[k];
+  g->Vh = (int)(v / 2);
+  g->stride = g->Vh;
+  *V = v;
+  return HMC_OK;
+}
+
+static size_t half_bytes(int Vh, hmc_prec p) {
+  switch (p) {
+    case HMC_F64: return (size_t)Vh * 192;
+    case HMC_F32: return (size_t)Vh * 96;
+    case HMC_F16: return (size_t)Vh * 52;
+    case HMC_BF16: return (size_t)Vh * 48;
+  }
+  return 0;
+}
+static size_t gauge_bytes(int Vh, hmc_prec p) {
+  switch (p) {
+    case HMC_F64: return (size_t)Vh * 8 * 144;
+    case HMC_F32: return (size_t)Vh * 8 * 72;
+    case HMC_F16:
+    case HMC_BF16: return (size_t)Vh * 8 * 36;
+  }
+  return 0;
+}
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Arena plan; with base == nullptr only the size is computed.
+static size_t plan_fields(Fields* F, char* base, const LatArg& g, uint32_t flags) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  const int Vh = g.Vh;
+  const size_t h64 = half_bytes(Vh, HMC_F64);
+  const int nbD = site_blocks(Vh), nbR = blas_blocks(Vh);
+  const int npart = 2 * std::max(nbD, nbR);
+  const int nb_multi = std::min(nbR, 1024);
+  const size_t multi = (size_t)nb_multi * 2 * 1024 + 1024;
+  Fields tmp;
+  Fields* f = F ? F : &tmp;
+  f->half64 = h64;
+  f->halflow = half_bytes(Vh, HMC_F32);
+  f->nbD = nbD;
+  f->nbR = nbR;
+  f->npart = npart;
+  f->multi_doubles = multi;
+  f->U = take(gauge_bytes(Vh, HMC_F64));
+  f->U_old = take(gauge_bytes(Vh, HMC_F64));
+  f->P = (double*)take((size_t)Vh * 8 * 8 * 8);
+  f->eta = take(h64);
+  f->phi = take(h64);
+  f->Xe = take(h64);
+  f->Xo = take(h64);
+  f->Ye = take(h64);
+  f->Yo = take(h64);
+  f->r = take(h64);
+  f->p = take(h64);
+  f->q = take(h64);
+  f->s = take(h64);
+  f->t = take(h64);
+  f->bhat = take(h64);
+  f->tmp = take(2 * h64);
+  for (int k = 0; k < kNumPart; ++k) f->part[k] = (double*)take((size_t)npart * 8);
+  f->multi = (double*)take(multi * 8);
+  f->state = (SolverState*)take(sizeof(SolverState) * 4);
+  f->slots = (double*)take(SL_COUNT * 8);
+  for (int k = 0; k < 4; ++k) f->Ulow[k] = nullptr;
+  f->lr = f->lp = f->lq = f->ls = f->lt = f->lx = nullptr;
+  if (flags & HMC_FIELDS_LOWPREC) {
+    f->Ulow[HMC_F32] = take(gauge_bytes(Vh, HMC_F32));
+    f->Ulow[HMC_F16] = take(gauge_bytes(Vh, HMC_F16));
+    f->Ulow[HMC_BF16] = take(gauge_bytes(Vh, HMC_BF16));
+    const size_t hl = f->halflow;
+    f->lr = take(hl);
+    f->lp = take(hl);
+    f->lq = take(hl);
+    f->ls = take(hl);
+    f->lt = take(hl);
+    f->lx = take(half_bytes(Vh, HMC_F32));
+  }
+  return off;
+}
+
+hipError_t read_slots(Fields* F, int first, int n, double* out, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(F->pinned, F->slots + first, n * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < n; ++k) out[k] = F->pinned[k];
+  return hipSuccess;
+}
+
+hipError_t dslash_f64(Fields* F, void* out, const void* in, int out_par, int dag, int epi, const void* y, double a,
+                      double b, double* partial, const int* stop_at, int iter, hipStream_t st) {
+  DslashArgs d;
+  d.U = F->U;
+  d.in = in;
+  d.out = out;
+  d.y = y;
+  d.a = a;
+  d.b = b;
+  d.partial = partial;
+  d.stop_at = stop_at;
+  d.iter = iter;
+  return launch_dslash(HMC_F64, dag, epi, F->g, out_par, nullptr, 1, d, st);
+}
+
+void* low_links(Fields* F, hmc_prec prec) { return (prec == HMC_F64) ? F->U : F->Ulow[prec]; }
+
+hipError_t ensure_lowprec(Fields* F, hmc_prec prec, hipStream_t st) {
+  if (prec == HMC_F64) return hipSuccess;
+  if (!F->Ulow[prec]) return hipErrorInvalidValue;
+  if (F->low_version[prec] == F->u_version) return hipSuccess;
+  hipError_t e = launch_convert_gauge(F->g, F->U, F->Ulow[prec], prec, st);
+  if (e == hipSuccess) F->low_version[prec] = F->u_version;
+  return e;
+}
+
+// Mhat (dag) on F64 half spinors: out = in - kappa^2 D_eo D_oe in.
+hipError_t mhat_f64(Fields* F, void* out, const void* in, int dag, double* partial, hipStream_t st) {
+  hipError_t e = dslash_f64(F, F->t, in, 1, dag, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st);
+  if (e != hipSuccess) return e;
+  return dslash_f64(F, out, F->t, 0, dag, partial ? EPI_AXPY_NORM : EPI_AXPY, in, 1.0, -F->kappa * F->kappa, partial,
+                    nullptr, 0, st);
+}
+
+static hipError_t finalize_to_slot(Fields* F, const double* part, int n, int nvals, int slot, hipStream_t st) {
+  return launch_finalize(part, n, nvals, F->slots + slot, 1.0, 0, st);
+}
+
+}  // namespace hmc
+
+using namespace hmc;
+
+#define ST(s) reinterpret_cast<hipStream_t>(s)
+#define FIELDS(f)                                 \
+  HMC_REQUIRE((f) != nullptr, "null fields");     \
+  Fields* F = as_fields(f);
+
+extern "C" {
+
+const char* hmc_last_error(void) { return last_error(); }
+
+hmc_status hmc_get_version(int32_t* major, int32_t* minor) {
+  HMC_REQUIRE(major && minor, "null output");
+  *major = 1;
+  *minor = 0;
+  return HMC_OK;
+}
+
+hmc_status hmc_field_bytes(const hmc_geom* geom, hmc_prec prec, hmc_kind kind, size_t* bytes) {
+  LatArg g;
+  long long V;
+  hmc_status s = check_geom(geom, &g, &V);
+  if (s) return s;
+  HMC_REQUIRE(bytes, "null output");
+  HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision %d", (int)prec);
+  switch (kind) {
+    case HMC_KIND_HALF_SPINOR: *bytes = half_bytes(g.Vh, prec); break;
+    case HMC_KIND_FULL_SPINOR: *bytes = 2 * half_bytes(g.Vh, prec); break;
+    case HMC_KIND_GAUGE: *bytes = gauge_bytes(g.Vh, prec); break;
+    case HMC_KIND_MOMENTA:
+      HMC_REQUIRE(prec == HMC_F64, "momenta are stored in F64 only");
+      *bytes = (size_t)g.Vh * 8 * 8 * 8;
+      break;
+    default: HMC_REQUIRE(false, "bad field kind %d", (int)kind);
+  }
+  return HMC_OK;
+}
+
+hmc_status hmc_fields_bytes(const hmc_geom* geom, uint32_t flags, size_t* bytes) {
+  LatArg g;
+  long long V;
+  hmc_status s = check_geom(geom, &g, &V);
+  if (s) return s;
+  HMC_REQUIRE(bytes, "null output");
+  *bytes = plan_fields(nullptr, nullptr, g, flags);
+  return HMC_OK;
+}
+
+hmc_status hmc_alloc_fields(const hmc_geom* geom, const hmc_action* action, uint32_t flags, void* arena,
+                            size_t arena_bytes, hmc_fields** out) {
+  LatArg g;
+  long long V;
+  hmc_status s = check_geom(geom, &g, &V);
+  if (s) return s;
+  HMC_REQUIRE(action && arena && out, "null argument");
+  HMC_REQUIRE(((uintptr_t)arena & 255) == 0, "arena must be 256-byte aligned");
+  size_t need = plan_fields(nullptr, nullptr, g, flags);
+  if (arena_bytes < need) {
+    set_error("arena of %zu bytes is smaller than the %zu bytes needed", arena_bytes, need);
+    return HMC_E_OOM;
+  }
+  Fields* F = new Fields();
+  F->g = g;
+  F->V = V;
+  F->beta = action->beta;
+  F->kappa = action->kappa;
+  F->flags = flags;
+  F->arena = (char*)arena;
+  F->arena_bytes = arena_bytes;
+  plan_fields(F, (char*)arena, g, flags);
+  F->u_version = 1;
+  for (int k = 0; k < 4; ++k) F->low_version[k] = 0;
+  if (hipHostMalloc((void**)&F->pinned, (SL_COUNT + 64) * sizeof(double)) != hipSuccess) {
+    delete F;
+    set_error("hipHostMalloc of the scalar read-back buffer failed");
+    return HMC_E_HIP;
+  }
+  *out = reinterpret_cast<hmc_fields*>(F);
+  return HMC_OK;
+}
+
+hmc_status hmc_free_fields(hmc_fields* f) {
+  FIELDS(f);
+  if (F->pinned) hipHostFree(F->pinned);
+  delete F;
+  return HMC_OK;
+}
+
+hmc_status hmc_set_action(hmc_fields* f, const hmc_action* action) {
+  FIELDS(f);
+  HMC_REQUIRE(action, "null action");
+  F->beta = action->beta;
+  F->kappa = action->kappa;
+  return HMC_OK;
+}
+
+hmc_status hmc_field_pointer(hmc_fields* f, hmc_field_id which, void** ptr) {
+  FIELDS(f);
+  HMC_REQUIRE(ptr, "null output");
+  switch (which) {
+    case HMC_FIELD_GAUGE: *ptr = F->U; break;
+    case HMC_FIELD_MOMENTA: *ptr = F->P; break;
+    case HMC_FIELD_ETA: *ptr = F->eta; break;
+    case HMC_FIELD_PHI: *ptr = F->phi; break;
+    case HMC_FIELD_XE: *ptr = F->Xe; break;
+    default: HMC_REQUIRE(false, "bad field id %d", (int)which);
+  }
+  return HMC_OK;
+}
+
+hmc_status hmc_import_gauge(hmc_fields* f, const void* canon, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(canon, "null buffer");
+  HMC_CHECK_HIP(launch_pack_gauge(F->g, canon, F->U, ST(stream)));
+  F->u_version++;
+  return HMC_OK;
+}
+
+hmc_status hmc_export_gauge(hmc_fields* f, void* canon, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(canon, "null buffer");
+  HMC_CHECK_HIP(launch_unpack_gauge(F->g, F->U, canon, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_import_momenta(hmc_fields* f, const void* canon, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(canon, "null buffer");
+  HMC_CHECK_HIP(launch_pack_momenta(F->g, canon, F->P, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_export_momenta(hmc_fields* f, void* canon, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(canon, "null buffer");
+  HMC_CHECK_HIP(launch_unpack_momenta(F->g, F->P, canon, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_import_spinor(hmc_fields* f, void* dst, const void* canon, int32_t parity, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(dst && canon, "null buffer");
+  HMC_REQUIRE(parity >= -1 && parity <= 1, "parity must be -1, 0 or 1");
+  HMC_CHECK_HIP(launch_pack_spinor(F->g, canon, dst, parity, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_export_spinor(hmc_fields* f, void* canon, const void* src, int32_t parity, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(src && canon, "null buffer");
+  HMC_REQUIRE(parity >= -1 && parity <= 1, "parity must be -1, 0 or 1");
+  HMC_CHECK_HIP(launch_unpack_spinor(F->g, src, canon, parity, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_convert_spinor(hmc_fields* f, void* dst, hmc_prec dst_prec, const void* src, hmc_prec src_prec,
+                              void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(dst && src, "null buffer");
+  HMC_REQUIRE(dst_prec >= HMC_F64 && dst_prec <= HMC_BF16 && src_prec >= HMC_F64 && src_prec <= HMC_BF16,
+              "bad precision");
+  HMC_CHECK_HIP(launch_convert_spinor(F->g, src, src_prec, dst, dst_prec, 1, nullptr, nullptr, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_sync_lowprec(hmc_fields* f, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(F->flags & HMC_FIELDS_LOWPREC, "fields were allocated without HMC_FIELDS_LOWPREC");
+  for (int p = HMC_F32; p <= HMC_BF16; ++p) HMC_CHECK_HIP(ensure_lowprec(F, (hmc_prec)p, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_wilson_dslash(hmc_fields* f, void* out, const void* in, int32_t out_parity, int32_t dagger,
+                             hmc_prec prec, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(out && in, "null buffer");
+  HMC_REQUIRE(out != in, "out and in must not alias");
+  HMC_REQUIRE(out_parity == 0 || out_parity == 1, "out_parity must be 0 or 1");
+  HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision");
+  HMC_REQUIRE(prec == HMC_F64 || (F->flags & HMC_FIELDS_LOWPREC), "low precision needs HMC_FIELDS_LOWPREC");
+  HMC_CHECK_HIP(ensure_lowprec(F, prec, ST(stream)));
+  DslashArgs d{};
+  d.U = low_links(F, prec);
+  d.in = in;
+  d.out = out;
+  d.b = 1.0;
+  HMC_CHECK_HIP(launch_dslash(prec, dagger ? 1 : 0, EPI_PLAIN, F->g, out_parity, nullptr, 1, d, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_mhat(hmc_fields* f, void* out, const void* in, int32_t dagger, hmc_prec prec, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(out && in, "null buffer");
+  HMC_REQUIRE(out != in, "out and in must not alias");
+  HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision");
+  HMC_REQUIRE(prec == HMC_F64 || (F->flags & HMC_FIELDS_LOWPREC), "low precision needs HMC_FIELDS_LOWPREC");
+  hipStream_t st = ST(stream);
+  if (prec == HMC_F64) {
+    HMC_CHECK_HIP(mhat_f64(F, out, in, dagger ? 1 : 0, nullptr, st));
+    return HMC_OK;
+  }
+  HMC_CHECK_HIP(ensure_lowprec(F, prec, st));
+  DslashArgs d{};
+  d.U = low_links(F, prec);
+  d.in = in;
+  d.out = F->lt;
+  d.b = 1.0;
+  HMC_CHECK_HIP(launch_dslash(prec, dagger ? 1 : 0, EPI_PLAIN, F->g, 1, nullptr, 1, d, st));
+  d.in = F->lt;
+  d.out = out;
+  d.y = in;
+  d.a = 1.0;
+  d.b = -F->kappa * F->kappa;
+  HMC_CHECK_HIP(launch_dslash(prec, dagger ? 1 : 0, EPI_AXPY, F->g, 0, nullptr, 1, d, st));
+  return HMC_OK;
+}
+
+hmc_status hmc_wilson_m(hmc_fields* f, void* out, const void* in, int32_t dagger, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(out && in, "null buffer");
+  HMC_REQUIRE(out != in, "out and in must not alias");
+  hipStream_t st = ST(stream);
+  const char* ie = (const char*)in;
+  char* oe = (char*)out;
+  const int dag = dagger ? 1 : 0;
+  // out_e = in_e - kappa D_eo in_o ; out_o = in_o - kappa D_oe in_e
+  HMC_CHECK_HIP(dslash_f64(F, oe, ie + F->half64, 0, dag, EPI_AXPY, ie, 1.0, -F->kappa, nullptr, nullptr, 0, st));
+  HMC_CHECK_HIP(dslash_f64(F, oe + F->half64, ie, 1, dag, EPI_AXPY, ie + F->half64, 1.0, -F->kappa, nullptr, nullptr,
+                           0, st));
+  return HMC_OK;
+}
+
+hmc_status hmc_norm2(hmc_fields* f, const void* x, int32_t nhalves, hmc_prec prec, double* out, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(x && out, "null argument");
+  HMC_REQUIRE(nhalves == 1 || nhalves == 2, "nhalves must be 1 or 2");
+  HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision");
+  hipStream_t st = ST(stream);
+  const int nb = F->nbR;
+  size_t hb = half_bytes(F->g.Vh, prec);
+  for (int h = 0; h < nhalves; ++h)
+    HMC_CHECK_HIP(launch_norm2_partials(F->g, prec, (const char*)x + h * hb, F->part[0] + h * nb, nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb * nhalves, 1, SL_RED, st));
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 1, out, st));
+  return HMC_OK;
+}
+
+hmc_status hmc_inner(hmc_fields* f, const void* a, const void* b, int32_t nhalves, double* out, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(a && b && out, "null argument");
+  HMC_REQUIRE(nhalves == 1 || nhalves == 2, "nhalves must be 1 or 2");
+  hipStream_t st = ST(stream);
+  const int nb = F->nbR;
+  // partial layout per half: [re: nb][im: nb]; rearranged by two finalisations
+  for (int h = 0; h < nhalves; ++h)
+    HMC_CHECK_HIP(launch_inner_partials(F->g, (const char*)a + h * F->half64, (const char*)b + h * F->half64,
+                                        F->part[1 + h], nb, st));
+  double res[2] = {0, 0};
+  for (int h = 0; h < nhalves; ++h) {
+    HMC_CHECK_HIP(launch_finalize(F->part[1 + h], nb, 2, F->slots + SL_RED, 1.0, h > 0, st));
+  }
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 2, res, st));
+  out[0] = res[0];
+  out[1] = res[1];
+  return HMC_OK;
+}
+
+hmc_status hmc_sum_multi(hmc_fields* f, const void* x, int32_t nhalves, const int32_t* subset, int32_t nsub,
+                         double* out, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(x && subset && out, "null argument");
+  HMC_REQUIRE(nhalves == 1 || nhalves == 2, "nhalves must be 1 or 2");
+  HMC_REQUIRE(nsub >= 1 && nsub <= 1024, "nsub must be in [1, 1024]");
+  hipStream_t st = ST(stream);
+  const int nb = std::min(F->nbR, 1024);
+  std::vector<double> host(nsub);
+  // rows of partials first, the nsub results in the last 1024 doubles
+  double* res = F->multi + F->multi_doubles - 1024;
+  HMC_CHECK_HIP(launch_sum_multi(F->g, x, nhalves, subset, nsub, F->multi, nb, res, st));
+  HMC_CHECK_HIP(hipMemcpyAsync(host.data(), res, nsub * sizeof(double), hipMemcpyDeviceToHost, st));
+  HMC_CHECK_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < nsub; ++k) out[k] = host[k];
+  return HMC_OK;
+}
+
+hmc_status hmc_plaquette(hmc_fields* f, double* out, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(out, "null output");
+  hipStream_t st = ST(stream);
+  double sum;
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], F->nbR, 1, SL_RED, st));
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &sum, st));
+  *out = sum / (18.0 * F->V);
+  return HMC_OK;
+}
+
+hmc_status hmc_gauge_action(hmc_fields* f, double* out, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(out, "null output");
+  hipStream_t st = ST(stream);
+  double sum;
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], F->nbR, 1, SL_RED, st));
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &sum, st));
+  *out = F->beta * (6.0 * F->V - sum / 3.0);
+  return HMC_OK;
+}
+
+hmc_status hmc_kinetic_energy(hmc_fields* f, double* out, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(out, "null output");
+  hipStream_t st = ST(stream);
+  HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], F->nbR, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], F->nbR, 1, SL_RED, st));
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 1, out, st));
+  return HMC_OK;
+}
+
+hmc_status hmc_gauge_force(hmc_fields* f, double coef, void* stream) {
+  FIELDS(f);
+  HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, coef * F->beta, ST(stream)));
+  return HMC_OK;
+}
+
+static hipError_t fermion_force_impl(Fields* F, const void* Xe, double coef, hipStream_t st) {
+  const double k2 = F->kappa * F->kappa;
+  hipError_t e;
+  // X_o = D_oe X_e ; Y_e = X_e - kappa^2 D_eo X_o ; Y_o = (D^dag)_oe Y_e
+  if ((e = dslash_f64(F, F->Xo, Xe, 1, 0, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st))) return e;
+  if ((e = dslash_f64(F, F->Ye, F->Xo, 0, 0, EPI_AXPY, Xe, 1.0, -k2, nullptr, nullptr, 0, st))) return e;
+  if ((e = dslash_f64(F, F->Yo, F->Ye, 1, 1, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st))) return e;
+  return launch_fermion_force(F->g, F->U, Xe, F->Xo, F->Ye, F->Yo, F->P, coef * k2, st);
+}
+
+hmc_status hmc_fermion_force(hmc_fields* f, const void* X_e, double coef, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(X_e, "null X_e");
+  HMC_CHECK_HIP(fermion_force_impl(F, X_e, coef, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_exp_update_reunit(hmc_fields* f, double eps, void* stream) {
+  FIELDS(f);
+  HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, ST(stream)));
+  F->u_version++;
+  return HMC_OK;
+}
+
+static hipError_t refresh_pf(Fields* F, uint64_t seed, uint64_t traj, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_eta(F->g, seed, traj, 0, F->eta, st))) return e;
+  return mhat_f64(F, F->phi, F->eta, 1, nullptr, st);
+}
+
+hmc_status hmc_refresh(hmc_fields* f, uint64_t seed, uint64_t traj, uint32_t what, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE((what & ~(HMC_REFRESH_MOM | HMC_REFRESH_PF)) == 0 && what, "bad refresh flags");
+  hipStream_t st = ST(stream);
+  if (what & HMC_REFRESH_MOM) HMC_CHECK_HIP(launch_refresh_momenta(F->g, seed, traj, F->P, st));
+  if (what & HMC_REFRESH_PF) HMC_CHECK_HIP(refresh_pf(F, seed, traj, st));
+  return HMC_OK;
+}
+
+hmc_status hmc_weak_field_start(hmc_fields* f, uint64_t seed, double eps, void* stream) {
+  FIELDS(f);
+  HMC_CHECK_HIP(launch_weak_field(F->g, seed, eps, F->U, ST(stream)));
+  F->u_version++;
+  return HMC_OK;
+}
+
+hmc_status hmc_make_source(hmc_fields* f, void* b, int32_t kind, uint64_t seed, uint64_t epoch, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(b, "null buffer");
+  HMC_REQUIRE(kind >= 0 && kind <= 2, "bad source kind %d", kind);
+  HMC_CHECK_HIP(launch_source(F->g, kind, seed, epoch, b, (char*)b + F->half64, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_random_words(uint64_t seed, uint64_t rng_stream, uint64_t epoch, const int64_t* sites,
+                            int32_t nsites, int32_t nblocks, uint64_t* out, void* stream) {
+  HMC_REQUIRE(sites && out, "null buffer");
+  HMC_REQUIRE(nsites >= 0 && nblocks >= 1 && nblocks <= 64, "bad sizes");
+  if (nsites == 0) return HMC_OK;
+  HMC_CHECK_HIP(launch_site_words(seed, rng_stream, epoch, (const long long*)sites, nsites, nblocks, out, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_random_gaussians(uint64_t seed, uint64_t rng_stream, uint64_t epoch, const int64_t* sites,
+                                int32_t nsites, int32_t n, double* out, void* stream) {
+  HMC_REQUIRE(sites && out, "null buffer");
+  HMC_REQUIRE(nsites >= 0 && n >= 2 && n <= 32 && n % 4 == 0, "n must be a multiple of 4 in [4, 32]");
+  if (nsites == 0) return HMC_OK;
+  HMC_CHECK_HIP(launch_site_gaussians(seed, rng_stream, epoch, (const long long*)sites, nsites, n, out, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_cg_solve(hmc_fields* f, void* x, const void* b, const hmc_cg_params* params, hmc_cg_stats* stats,
+                        void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(x && b && params, "null argument");
+  return cg_solve_impl(F, x, b, params, stats, ST(stream));
+}
+
+// One force evaluation: P -= coef (F_g + F_f) with the fermion force from a
+// fresh solve of phi_e into X_e.
+static hmc_status force_kick(Fields* F, double coef, const hmc_cg_params* cg, hmc_md_stats* ms, hipStream_t st) {
+  HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, coef * F->beta, st));
+  hmc_cg_params p = *cg;
+  p.mode = HMC_CG_NORMAL_MHAT;
+  hmc_cg_stats cs;
+  hmc_status s = cg_solve_impl(F, F->Xe, F->phi, &p, &cs, st);
+  if (s != HMC_OK && s != HMC_E_NOCONV) return s;
+  ms->solves++;
+  ms->iters_total += cs.iters;
+  ms->iters_max = std::max(ms->iters_max, cs.iters);
+  if (s == HMC_E_NOCONV) ms->nonconverged++;
+  HMC_CHECK_HIP(fermion_force_impl(F, F->Xe, coef, st));
+  return HMC_OK;
+}
+
+static hmc_status leapfrog_impl(Fields* F, double tau, int nsteps, const hmc_cg_params* cg, hmc_md_stats* ms,
+                                hipStream_t st) {
+  const double eps = tau / nsteps;
+  *ms = hmc_md_stats{0, 0, 0, 0};
+  hmc_status s = force_kick(F, 0.5 * eps, cg, ms, st);
+  if (s) return s;
+  for (int k = 1; k <= nsteps; ++k) {
+    HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, st));
+    F->u_version++;
+    s = force_kick(F, k < nsteps ? eps : 0.5 * eps, cg, ms, st);
+    if (s) return s;
+  }
+  return HMC_OK;
+}
+
+hmc_status hmc_md_leapfrog(hmc_fields* f, double tau, int32_t nsteps, const hmc_cg_params* cg, hmc_md_stats* stats,
+                           void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(cg && stats, "null argument");
+  HMC_REQUIRE(nsteps >= 1, "nsteps must be >= 1");
+  hipStream_t st = ST(stream);
+  hmc_status s = leapfrog_impl(F, tau, nsteps, cg, stats, st);
+  if (s) return s;
+  HMC_CHECK_HIP(hipStreamSynchronize(st));
+  return stats->nonconverged ? HMC_E_NOCONV : HMC_OK;
+}
+
+hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_traj_params* params,
+                          hmc_traj_result* res, void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(params && res, "null argument");
+  HMC_REQUIRE(params->nsteps >= 1, "nsteps must be >= 1");
+  hipStream_t st = ST(stream);
+  auto t0 = std::chrono::steady_clock::now();
+  const size_t ub = gauge_bytes(F->g.Vh, HMC_F64);
+  HMC_CHECK_HIP(launch_copy(F->U_old, F->U, ub, st));
+  HMC_CHECK_HIP(launch_refresh_momenta(F->g, seed, traj, F->P, st));
+  HMC_CHECK_HIP(refresh_pf(F, seed, traj, st));
+  const int nb = F->nbR;
+  HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_OLD, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_OLD, st));
+  HMC_CHECK_HIP(launch_norm2_partials(F->g, HMC_F64, F->eta, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_ETA2, st));
+
+  hmc_md_stats ms;
+  hmc_status s = leapfrog_impl(F, params->tau, params->nsteps, &params->cg, &ms, st);
+  if (s) return s;
+
+  HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_NEW, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_NEW, st));
+  HMC_CHECK_HIP(launch_inner_partials(F->g, F->phi, F->Xe, F->part[1], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_PHIX, st));
+  HMC_CHECK_HIP(launch_metropolis(seed, traj, F->beta, (double)F->V, F->slots, st));
+  double sl[13];
+  HMC_CHECK_HIP(read_slots(F, 0, 13, sl, st));
+
+  bool accepted = sl[SL_ACC] != 0.0 && ms.nonconverged == 0;
+  if (!accepted) {
+    HMC_CHECK_HIP(launch_copy(F->U, F->U_old, ub, st));
+    F->u_version++;
+  }
+  double plaq_sum;
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED, st));
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &plaq_sum, st));
+
+  res->KE_old = sl[SL_KE_OLD];
+  res->KE_new = sl[SL_KE_NEW];
+  res->S_f_old = sl[SL_ETA2];
+  res->S_g_old = sl[SL_SG_OLD];
+  res->S_g_new = sl[SL_SG_NEW];
+  res->H_old = sl[SL_H_OLD];
+  res->H_new = sl[SL_H_NEW];
+  res->dH = sl[SL_DH];
+  res->u = sl[SL_U];
+  res->S_f_new = sl[SL_PHIX];
+  res->accepted = accepted ? 1 : 0;
+  res->plaquette = plaq_sum / (18.0 * F->V);
+  res->cg_iters_total = ms.iters_total;
+  res->cg_iters_max = ms.iters_max;
+  res->nonconverged = ms.nonconverged;
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (ms.nonconverged) {
+    set_error("%d of %d solves did not converge; trajectory rejected", ms.nonconverged, ms.solves);
+    return HMC_E_NOCONV;
+  }
+  if (!(res->dH == res->dH) || std::isinf(res->dH)) {
+    set_error("non-finite energy change; trajectory rejected");
+    return HMC_E_NAN;
+  }
+  return HMC_OK;
+}
+
+hmc_status hmc_timing_enable(int32_t sample_every) {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.sample_every = sample_every > 0 ? sample_every : 0;
+  return HMC_OK;
+}
+
+hmc_status hmc_timing_reset(void) {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.recs.clear();
+  T.open_pair = -1;
+  for (int k = 0; k < TK_COUNT; ++k) {
+    T.counter[k] = 0;
+    T.launches[k] = 0;
+    T.ms[k] = 0;
+    T.bytes[k] = 0;
+  }
+  return HMC_OK;
+}
+
+hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* n_entries) {
+  HMC_REQUIRE(n_entries, "null output");
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  for (const TimingRec& r : T.recs) {
+    hipEvent_t a = T.events[2 * r.pair], b = T.events[2 * r.pair + 1];
+    HMC_CHECK_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    HMC_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
+    T.launches[r.kernel]++;
+    T.ms[r.kernel] += ms;
+    T.bytes[r.kernel] += r.bytes;
+  }
+  T.recs.clear();
+  int n = 0;
+  for (int k = 0; k < TK_COUNT; ++k) {
+    if (!T.launches[k]) continue;
+    if (out && n < max_entries) {
+      std::snprintf(out[n].name, sizeof out[n].name, "%s", timed_kernel_name(k));
+      out[n].launches = T.launches[k];
+      out[n].total_ms = T.ms[k];
+      out[n].bytes = T.bytes[k];
+    }
+    ++n;
+  }
+  *n_entries = n;
+  return HMC_OK;
+}
+
+}  // extern "C"

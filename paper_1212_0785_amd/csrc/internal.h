@@ -1,0 +1,199 @@
+// Host-side internals of libhmc: device-argument structs shared by the
+// kernel files and the host runtime, kernel launchers, error plumbing and
+// the timing registry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "hmc.h"
+
+namespace hmc {
+
+constexpr int kThreads = 256;
+
+// Lattice description passed by value to every kernel (mirrors the device
+// struct in device.h; kept layout-identical).
+struct LatArg {
+  int L[4];
+  int Vh;
+  int stride;
+};
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Number of blocks of the grid-stride BLAS kernels (and of their partial
+// sums): enough to fill 256 CUs several times over, never more than needed.
+inline int blas_blocks(int Vh) {
+  int nb = ceil_div(Vh, kThreads);
+  return nb < 2048 ? nb : 2048;
+}
+inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
+
+// Iteration control of the Krylov solvers, resident in device memory.
+// Kernels of iteration k do nothing once k >= stop_at.  Only block 0 of the
+// p-update kernel writes it, and only with a value > k, so blocks of the
+// same launch never observe a change that concerns them.
+struct SolverState {
+  int stop_at;   // INT_MAX while running
+  int reason;    // 1 converged, 2 reliable update requested
+  int iter;      // iterations completed
+  int pad;
+  double rr;     // last residual norm^2 seen by the p-update
+  double maxrr;  // mixed precision: max inner |r|^2 since the last update
+};
+
+// One Dslash application (one batch entry).
+struct DslashArgs {
+  const void* U;        // links in the storage format of the launch
+  const void* in;       // input half-field (parity 1 - out_parity)
+  void* out;            // output half-field
+  const void* y;        // epilogue addend on the output parity (may be null)
+  double a, b;          // out = a*y + b*(D in) for the AXPY epilogues
+  double* partial;      // per-block |out|^2 for the NORM epilogue
+  const int* stop_at;   // solver control (may be null)
+  int iter;             // iteration index compared with *stop_at
+};
+
+enum Epilogue { EPI_PLAIN = 0, EPI_AXPY = 1, EPI_AXPY_NORM = 2 };
+
+// Launchers (defined in the .hip files).  All return hipGetLastError().
+hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,
+                         int nbatch, const DslashArgs& one, hipStream_t st);
+
+// Layout conversion between canonical AoS complex128 (device) and SoA.
+hipError_t launch_pack_gauge(const LatArg& g, const void* canon, void* U, hipStream_t st);
+hipError_t launch_unpack_gauge(const LatArg& g, const void* U, void* canon, hipStream_t st);
+hipError_t launch_pack_spinor(const LatArg& g, const void* canon, void* half, int par, hipStream_t st);
+hipError_t launch_unpack_spinor(const LatArg& g, const void* half, void* canon, int par, hipStream_t st);
+hipError_t launch_pack_momenta(const LatArg& g, const void* canon, double* P, hipStream_t st);
+hipError_t launch_unpack_momenta(const LatArg& g, const double* P, void* canon, hipStream_t st);
+hipError_t launch_convert_gauge(const LatArg& g, const void* U64, void* Ulow, hmc_prec prec, hipStream_t st);
+hipError_t launch_convert_spinor(const LatArg& g, const void* in, hmc_prec pin, void* out, hmc_prec pout,
+                                 int nbatch, const void* const* tab_in, void* const* tab_out, hipStream_t st);
+
+// Reductions: per-block partials of one half-field (or several), then a
+// fixed-order finalisation into a device slot.
+hipError_t launch_norm2_partials(const LatArg& g, hmc_prec prec, const void* x, double* part, int nb,
+                                 hipStream_t st);
+hipError_t launch_inner_partials(const LatArg& g, const void* a, const void* b, double* part, int nb,
+                                 hipStream_t st);  // FP64 only; part holds [re..., im...]
+hipError_t launch_finalize(const double* part, int n, int nvals, double* out, double scale, int accumulate,
+                           hipStream_t st);
+hipError_t launch_sum_multi(const LatArg& g, const void* x, int nhalves, const int* subset, int nsub, double* part,
+                            int nb, double* out, hipStream_t st);
+
+// Element-wise FP64 helpers.
+hipError_t launch_axpby(const LatArg& g, double a, const void* x, double b, void* y, hipStream_t st);  // y=a x+b y
+hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* r, double* part, int nb,
+                           hipStream_t st);  // r = b - q, partials of |r|^2
+hipError_t launch_gamma5(const LatArg& g, const void* in, void* out, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+// Krylov solver kernels.  `prec` is the storage of p/r/q/s; x is FP64 for
+// HMC_F64 and FP32 (inner accumulator) otherwise.
+struct CgArgs {
+  void* x;
+  void* p;
+  void* r;
+  const void* q;   // operator applied to p
+  const void* s;   // CGLS: Mhat^dag r
+  const double* part_a;  // partial sums read (see kernels)
+  const double* part_b;
+  const double* part_c;
+  double* part_out;
+  int n_a, n_b, n_c;
+  SolverState* state;
+  int iter;
+  double thr;      // convergence threshold on |r|^2
+  double delta2;   // mixed precision: reliable-update trigger (delta^2)
+  int mixed;       // 1: never declare convergence, pause instead
+};
+hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x, void* r, void* p, double* part,
+                          int nb, hipStream_t st);
+hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
+                            int nbatch, hipStream_t st);
+hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, int cgls, const CgArgs& a, int nb,
+                             const CgArgs* table, int nbatch, hipStream_t st);
+hipError_t launch_state_reset(SolverState* st_dev, int iter, const double* maxrr, int nbatch, hipStream_t st);
+hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st);  // x += xl; xl = 0
+
+// Gauge-field kernels.
+hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st);
+hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* part, int nb, hipStream_t st);
+hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st);
+hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st);
+hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
+                                const void* Yo, double* P, double coef, hipStream_t st);
+
+// Random fields (Philox4x64-10, counter = (block, lex site, stream, epoch),
+// key = (seed, 0)).
+hipError_t launch_refresh_momenta(const LatArg& g, uint64_t seed, uint64_t epoch, double* P, hipStream_t st);
+hipError_t launch_weak_field(const LatArg& g, uint64_t seed, double eps, void* U, hipStream_t st);
+hipError_t launch_eta(const LatArg& g, uint64_t seed, uint64_t epoch, int par, void* half, hipStream_t st);
+hipError_t launch_source(const LatArg& g, int kind, uint64_t seed, uint64_t epoch, void* even, void* odd,
+                         hipStream_t st);
+hipError_t launch_site_words(uint64_t seed, uint64_t stream, uint64_t epoch, const long long* sites, int nsites,
+                             int nblocks, uint64_t* out, hipStream_t st);
+hipError_t launch_site_gaussians(uint64_t seed, uint64_t stream, uint64_t epoch, const long long* sites,
+                                 int nsites, int n, double* out, hipStream_t st);
+// Metropolis on device: slots[0..] hold the action pieces (see hmc.cpp).
+hipError_t launch_metropolis(uint64_t seed, uint64_t traj, double beta, double V, double* slots, hipStream_t st);
+
+// ----------------------------------------------------------- errors
+
+void set_error(const char* fmt, ...);
+const char* last_error();
+
+#define HMC_CHECK_HIP(expr)                                                                     \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      ::hmc::set_error("%s:%d: %s: %s", __FILE__, __LINE__, #expr, hipGetErrorString(e_));       \
+      return HMC_E_HIP;                                                                          \
+    }                                                                                            \
+  } while (0)
+
+#define HMC_REQUIRE(cond, ...)        \
+  do {                                \
+    if (!(cond)) {                    \
+      ::hmc::set_error(__VA_ARGS__);  \
+      return HMC_E_ARG;               \
+    }                                 \
+  } while (0)
+
+// ----------------------------------------------------------- timing
+
+// Kernel families timed with HIP events when sampling is on.
+enum TimedKernel {
+  TK_DSLASH = 0,
+  TK_CG_BLAS,
+  TK_REDUCE,
+  TK_GAUGE_FORCE,
+  TK_FERMION_FORCE,
+  TK_EXP_UPDATE,
+  TK_REFRESH,
+  TK_PLAQUETTE,
+  TK_OTHER,
+  TK_COUNT
+};
+const char* timed_kernel_name(int k);
+// Returns true and records a start event when this launch is sampled.
+bool timing_begin(int kernel, hipStream_t st, double bytes);
+void timing_end(int kernel, hipStream_t st);
+
+struct TimedScope {
+  int k;
+  hipStream_t st;
+  bool on;
+  TimedScope(int kernel, hipStream_t s, double bytes) : k(kernel), st(s), on(timing_begin(kernel, s, bytes)) {}
+  ~TimedScope() {
+    if (on) timing_end(k, st);
+  }
+};
+
+}  // namespace hmc

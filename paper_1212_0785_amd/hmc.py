@@ -1,0 +1,426 @@
+"""ctypes binding of libhmc (include/hmc.h): argument marshalling only.
+
+Every ``hmc_*`` function here calls the C entry point of the same name;
+all work runs in the library's HIP kernels.  Device memory comes from
+PyTorch tensors (passed as raw pointers) and streams from
+``torch.cuda.current_stream()``.  The module refuses to run without the
+built library: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmc.so")
+
+HMC_OK, HMC_E_ARG, HMC_E_OOM, HMC_E_HIP, HMC_E_NOCONV, HMC_E_BUSY, HMC_E_NAN = 0, -1, -2, -3, -4, -5, -6
+F64, F32, F16, BF16 = 0, 1, 2, 3
+KIND_HALF_SPINOR, KIND_FULL_SPINOR, KIND_GAUGE, KIND_MOMENTA = 0, 1, 2, 3
+FIELDS_LOWPREC = 1
+FIELD_GAUGE, FIELD_MOMENTA, FIELD_ETA, FIELD_PHI, FIELD_XE = 0, 1, 2, 3, 4
+REFRESH_MOM, REFRESH_PF = 1, 2
+SOURCE_GAUSS, SOURCE_Z2, SOURCE_POINT = 0, 1, 2
+CG_NORMAL_MHAT, CG_WILSON_SOLVE = 0, 1
+
+PREC_NAMES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+
+
+class HmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libhmc status {status}: {msg}")
+        self.status = status
+
+
+class Geom(C.Structure):
+    _fields_ = [("L", C.c_int32 * 4)]
+
+
+class Action(C.Structure):
+    _fields_ = [("beta", C.c_double), ("kappa", C.c_double)]
+
+
+class CgParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("mode", C.c_int32), ("prec", C.c_int32),
+                ("fixed_iters", C.c_int32), ("reliable_delta", C.c_double)]
+
+
+class CgStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("reliable_updates", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("seconds", C.c_double)]
+
+
+class MdStats(C.Structure):
+    _fields_ = [("solves", C.c_int32), ("iters_total", C.c_int32), ("iters_max", C.c_int32),
+                ("nonconverged", C.c_int32)]
+
+
+class TrajParams(C.Structure):
+    _fields_ = [("tau", C.c_double), ("nsteps", C.c_int32), ("pad", C.c_int32), ("cg", CgParams)]
+
+
+class TrajResult(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("H_old", "H_new", "dH", "S_g_old", "S_g_new", "S_f_old", "S_f_new",
+                                          "KE_old", "KE_new", "plaquette", "u")] + \
+               [(n, C.c_int32) for n in ("accepted", "cg_iters_total", "cg_iters_max", "nonconverged")] + \
+               [("seconds", C.c_double)]
+
+
+class TimingEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double)]
+
+
+def struct_dict(s) -> dict:
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        out[name] = struct_dict(v) if isinstance(v, C.Structure) else v
+    return out
+
+
+_lib = None
+_P, _I32, _U32, _U64, _D = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_double
+
+_SIGNATURES = {
+    "hmc_last_error": (C.c_char_p, []),
+    "hmc_get_version": (_I32, [C.POINTER(_I32), C.POINTER(_I32)]),
+    "hmc_field_bytes": (_I32, [C.POINTER(Geom), _I32, _I32, C.POINTER(C.c_size_t)]),
+    "hmc_fields_bytes": (_I32, [C.POINTER(Geom), _U32, C.POINTER(C.c_size_t)]),
+    "hmc_alloc_fields": (_I32, [C.POINTER(Geom), C.POINTER(Action), _U32, _P, C.c_size_t, C.POINTER(_P)]),
+    "hmc_free_fields": (_I32, [_P]),
+    "hmc_set_action": (_I32, [_P, C.POINTER(Action)]),
+    "hmc_field_pointer": (_I32, [_P, _I32, C.POINTER(_P)]),
+    "hmc_import_gauge": (_I32, [_P, _P, _P]),
+    "hmc_export_gauge": (_I32, [_P, _P, _P]),
+    "hmc_import_momenta": (_I32, [_P, _P, _P]),
+    "hmc_export_momenta": (_I32, [_P, _P, _P]),
+    "hmc_import_spinor": (_I32, [_P, _P, _P, _I32, _P]),
+    "hmc_export_spinor": (_I32, [_P, _P, _P, _I32, _P]),
+    "hmc_convert_spinor": (_I32, [_P, _P, _I32, _P, _I32, _P]),
+    "hmc_sync_lowprec": (_I32, [_P, _P]),
+    "hmc_wilson_dslash": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P]),
+    "hmc_mhat": (_I32, [_P, _P, _P, _I32, _I32, _P]),
+    "hmc_wilson_m": (_I32, [_P, _P, _P, _I32, _P]),
+    "hmc_norm2": (_I32, [_P, _P, _I32, _I32, C.POINTER(_D), _P]),
+    "hmc_inner": (_I32, [_P, _P, _P, _I32, C.POINTER(_D), _P]),
+    "hmc_sum_multi": (_I32, [_P, _P, _I32, _P, _I32, C.POINTER(_D), _P]),
+    "hmc_plaquette": (_I32, [_P, C.POINTER(_D), _P]),
+    "hmc_gauge_action": (_I32, [_P, C.POINTER(_D), _P]),
+    "hmc_kinetic_energy": (_I32, [_P, C.POINTER(_D), _P]),
+    "hmc_gauge_force": (_I32, [_P, _D, _P]),
+    "hmc_fermion_force": (_I32, [_P, _P, _D, _P]),
+    "hmc_exp_update_reunit": (_I32, [_P, _D, _P]),
+    "hmc_refresh": (_I32, [_P, _U64, _U64, _U32, _P]),
+    "hmc_weak_field_start": (_I32, [_P, _U64, _D, _P]),
+    "hmc_make_source": (_I32, [_P, _P, _I32, _U64, _U64, _P]),
+    "hmc_random_words": (_I32, [_U64, _U64, _U64, _P, _I32, _I32, _P, _P]),
+    "hmc_random_gaussians": (_I32, [_U64, _U64, _U64, _P, _I32, _I32, _P, _P]),
+    "hmc_cg_solve": (_I32, [_P, _P, _P, C.POINTER(CgParams), C.POINTER(CgStats), _P]),
+    "hmc_md_leapfrog": (_I32, [_P, _D, _I32, C.POINTER(CgParams), C.POINTER(MdStats), _P]),
+    "hmc_trajectory": (_I32, [_P, _U64, _U64, C.POINTER(TrajParams), C.POINTER(TrajResult), _P]),
+    "hmc_timing_enable": (_I32, [_I32]),
+    "hmc_timing_reset": (_I32, []),
+    "hmc_timing_read": (_I32, [C.POINTER(TimingEntry), _I32, C.POINTER(_I32)]),
+}
+
+
+def lib():
+    """Load libhmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().hmc_last_error().decode()
+
+
+def check(status: int, allow=()) -> int:
+    if status != HMC_OK and status not in allow:
+        raise HmcError(status, last_error())
+    return status
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def geom(L) -> Geom:
+    g = Geom()
+    for k in range(4):
+        g.L[k] = int(L[k])
+    return g
+
+
+# ------------------------------------------------------------------ sizes
+
+
+def hmc_field_bytes(L, prec: int, kind: int) -> int:
+    n = C.c_size_t()
+    check(lib().hmc_field_bytes(C.byref(geom(L)), prec, kind, C.byref(n)))
+    return n.value
+
+
+def hmc_fields_bytes(L, flags: int = 0) -> int:
+    n = C.c_size_t()
+    check(lib().hmc_fields_bytes(C.byref(geom(L)), flags, C.byref(n)))
+    return n.value
+
+
+# ------------------------------------------------------------- fields
+
+
+class Fields:
+    """A fields object in a torch-allocated device arena."""
+
+    def __init__(self, L, beta: float, kappa: float, flags: int = 0, device="cuda"):
+        self.L = tuple(int(v) for v in L)
+        self.V = 1
+        for v in self.L:
+            self.V *= v
+        self.flags = flags
+        nbytes = hmc_fields_bytes(self.L, flags)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        a = Action(beta, kappa)
+        check(lib().hmc_alloc_fields(C.byref(geom(self.L)), C.byref(a), flags, self.arena.data_ptr(), nbytes,
+                                     C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().hmc_free_fields(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # device buffers in the library's layouts
+    def spinor(self, prec=F64, full=False, device="cuda"):
+        n = hmc_field_bytes(self.L, prec, KIND_FULL_SPINOR if full else KIND_HALF_SPINOR)
+        return torch.zeros(n, dtype=torch.uint8, device=device)
+
+    def pointer(self, which: int) -> int:
+        p = C.c_void_p()
+        check(lib().hmc_field_pointer(self.handle, which, C.byref(p)))
+        return p.value
+
+
+def _h(f):
+    return f.handle if isinstance(f, Fields) else f
+
+
+def hmc_set_action(f, beta, kappa):
+    a = Action(beta, kappa)
+    check(lib().hmc_set_action(_h(f), C.byref(a)))
+
+
+def hmc_import_gauge(f, canon, stream=None):
+    check(lib().hmc_import_gauge(_h(f), _ptr(canon), _stream(stream)))
+
+
+def hmc_export_gauge(f, canon, stream=None):
+    check(lib().hmc_export_gauge(_h(f), _ptr(canon), _stream(stream)))
+
+
+def hmc_import_momenta(f, canon, stream=None):
+    check(lib().hmc_import_momenta(_h(f), _ptr(canon), _stream(stream)))
+
+
+def hmc_export_momenta(f, canon, stream=None):
+    check(lib().hmc_export_momenta(_h(f), _ptr(canon), _stream(stream)))
+
+
+def hmc_import_spinor(f, dst, canon, parity, stream=None):
+    check(lib().hmc_import_spinor(_h(f), _ptr(dst), _ptr(canon), parity, _stream(stream)))
+
+
+def hmc_export_spinor(f, canon, src, parity, stream=None):
+    check(lib().hmc_export_spinor(_h(f), _ptr(canon), _ptr(src), parity, _stream(stream)))
+
+
+def hmc_convert_spinor(f, dst, dst_prec, src, src_prec, stream=None):
+    check(lib().hmc_convert_spinor(_h(f), _ptr(dst), dst_prec, _ptr(src), src_prec, _stream(stream)))
+
+
+def hmc_sync_lowprec(f, stream=None):
+    check(lib().hmc_sync_lowprec(_h(f), _stream(stream)))
+
+
+def hmc_wilson_dslash(f, out, inp, out_parity, dagger=0, prec=F64, stream=None):
+    check(lib().hmc_wilson_dslash(_h(f), _ptr(out), _ptr(inp), out_parity, int(dagger), prec, _stream(stream)))
+
+
+def hmc_mhat(f, out, inp, dagger=0, prec=F64, stream=None):
+    check(lib().hmc_mhat(_h(f), _ptr(out), _ptr(inp), int(dagger), prec, _stream(stream)))
+
+
+def hmc_wilson_m(f, out, inp, dagger=0, stream=None):
+    check(lib().hmc_wilson_m(_h(f), _ptr(out), _ptr(inp), int(dagger), _stream(stream)))
+
+
+def hmc_norm2(f, x, nhalves=1, prec=F64, stream=None) -> float:
+    out = C.c_double()
+    check(lib().hmc_norm2(_h(f), _ptr(x), nhalves, prec, C.byref(out), _stream(stream)))
+    return out.value
+
+
+def hmc_inner(f, a, b, nhalves=1, stream=None) -> complex:
+    out = (C.c_double * 2)()
+    check(lib().hmc_inner(_h(f), _ptr(a), _ptr(b), nhalves, out, _stream(stream)))
+    return complex(out[0], out[1])
+
+
+def hmc_sum_multi(f, x, nhalves, subset, nsub, stream=None):
+    out = (C.c_double * nsub)()
+    check(lib().hmc_sum_multi(_h(f), _ptr(x), nhalves, _ptr(subset), nsub, out, _stream(stream)))
+    return list(out)
+
+
+def hmc_plaquette(f, stream=None) -> float:
+    out = C.c_double()
+    check(lib().hmc_plaquette(_h(f), C.byref(out), _stream(stream)))
+    return out.value
+
+
+def hmc_gauge_action(f, stream=None) -> float:
+    out = C.c_double()
+    check(lib().hmc_gauge_action(_h(f), C.byref(out), _stream(stream)))
+    return out.value
+
+
+def hmc_kinetic_energy(f, stream=None) -> float:
+    out = C.c_double()
+    check(lib().hmc_kinetic_energy(_h(f), C.byref(out), _stream(stream)))
+    return out.value
+
+
+def hmc_gauge_force(f, coef, stream=None):
+    check(lib().hmc_gauge_force(_h(f), float(coef), _stream(stream)))
+
+
+def hmc_fermion_force(f, X_e, coef, stream=None):
+    check(lib().hmc_fermion_force(_h(f), _ptr(X_e), float(coef), _stream(stream)))
+
+
+def hmc_exp_update_reunit(f, eps, stream=None):
+    check(lib().hmc_exp_update_reunit(_h(f), float(eps), _stream(stream)))
+
+
+def hmc_refresh(f, seed, traj, what=REFRESH_MOM | REFRESH_PF, stream=None):
+    check(lib().hmc_refresh(_h(f), seed, traj, what, _stream(stream)))
+
+
+def hmc_weak_field_start(f, seed, eps, stream=None):
+    check(lib().hmc_weak_field_start(_h(f), seed, float(eps), _stream(stream)))
+
+
+def hmc_make_source(f, b, kind, seed, epoch, stream=None):
+    check(lib().hmc_make_source(_h(f), _ptr(b), kind, seed, epoch, _stream(stream)))
+
+
+def hmc_random_words(seed, rng_stream, epoch, sites, nblocks, stream=None):
+    """sites: int64 cuda tensor of lexicographic sites -> uint64 words (as int64 tensor)."""
+    out = torch.empty((sites.numel(), nblocks * 4), dtype=torch.int64, device=sites.device)
+    check(lib().hmc_random_words(seed, rng_stream, epoch, _ptr(sites), sites.numel(), nblocks, _ptr(out),
+                                 _stream(stream)))
+    return out
+
+
+def hmc_random_gaussians(seed, rng_stream, epoch, sites, n, stream=None):
+    out = torch.empty((sites.numel(), n), dtype=torch.float64, device=sites.device)
+    check(lib().hmc_random_gaussians(seed, rng_stream, epoch, _ptr(sites), sites.numel(), n, _ptr(out),
+                                     _stream(stream)))
+    return out
+
+
+def cg_params(tol=1e-10, maxiter=10000, mode=CG_NORMAL_MHAT, prec=F64, fixed_iters=0, reliable_delta=0.1):
+    return CgParams(tol, maxiter, mode, prec, fixed_iters, reliable_delta)
+
+
+def hmc_cg_solve(f, x, b, params: CgParams, stream=None, allow_noconv=False):
+    st = CgStats()
+    status = lib().hmc_cg_solve(_h(f), _ptr(x), _ptr(b), C.byref(params), C.byref(st), _stream(stream))
+    check(status, allow=(HMC_E_NOCONV,) if allow_noconv else ())
+    d = struct_dict(st)
+    d["status"] = status
+    return d
+
+
+def hmc_md_leapfrog(f, tau, nsteps, params: CgParams, stream=None, allow_noconv=False):
+    st = MdStats()
+    status = lib().hmc_md_leapfrog(_h(f), float(tau), int(nsteps), C.byref(params), C.byref(st), _stream(stream))
+    check(status, allow=(HMC_E_NOCONV,) if allow_noconv else ())
+    d = struct_dict(st)
+    d["status"] = status
+    return d
+
+
+def hmc_trajectory(f, seed, traj, tau, nsteps, params: CgParams, stream=None):
+    tp = TrajParams(float(tau), int(nsteps), 0, params)
+    r = TrajResult()
+    status = lib().hmc_trajectory(_h(f), seed, traj, C.byref(tp), C.byref(r), _stream(stream))
+    check(status, allow=(HMC_E_NOCONV, HMC_E_NAN))
+    d = struct_dict(r)
+    d["status"] = status
+    return d
+
+
+def hmc_timing_enable(sample_every: int):
+    check(lib().hmc_timing_enable(int(sample_every)))
+
+
+def hmc_timing_reset():
+    check(lib().hmc_timing_reset())
+
+
+def hmc_timing_read() -> dict:
+    n = C.c_int32()
+    buf = (TimingEntry * 16)()
+    check(lib().hmc_timing_read(buf, 16, C.byref(n)))
+    return {buf[k].name.decode(): {"launches": buf[k].launches, "total_ms": buf[k].total_ms,
+                                   "bytes": buf[k].bytes} for k in range(min(n.value, 16))}
+
+
+# --------------------------------------------------- canonical helpers
+
+
+def to_device_c128(a, device="cuda"):
+    """numpy complex128 array -> contiguous complex128 cuda tensor."""
+    return torch.from_numpy(a).to(device).contiguous()
+
+
+def canon_gauge_zeros(L, device="cuda"):
+    V = L[0] * L[1] * L[2] * L[3]
+    return torch.zeros((V, 4, 3, 3), dtype=torch.complex128, device=device)
+
+
+def canon_spinor_zeros(L, device="cuda"):
+    V = L[0] * L[1] * L[2] * L[3]
+    return torch.zeros((V, 4, 3), dtype=torch.complex128, device=device)

@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI (no GPU needed): every symbol declared in
+include/hmc.h is exported by libhmc.so, and argument validation reports
+HMC_E_ARG / HMC_E_OOM with a message."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hmc_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1212_0785_amd import hmc
+    hmc.lib()
+    return hmc
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("hmc_alloc_fields", "hmc_wilson_dslash", "hmc_cg_solve", "hmc_gauge_force", "hmc_fermion_force",
+                 "hmc_md_leapfrog", "hmc_exp_update_reunit", "hmc_refresh", "hmc_plaquette", "hmc_trajectory",
+                 "hmc_norm2", "hmc_inner", "hmc_sum_multi"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(H):
+    lib = C.CDLL(H.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding wraps every one of them
+    assert set(declared_functions()) <= set(H._SIGNATURES)
+
+
+def test_version(H):
+    a, b = C.c_int32(), C.c_int32()
+    assert H.lib().hmc_get_version(C.byref(a), C.byref(b)) == 0 and a.value == 1
+
+
+@pytest.mark.parametrize("L", [(3, 4, 4, 4), (4, 4, 4, 5), (4, 0, 4, 4), (4, 4, -2, 4)])
+def test_bad_geometry_rejected(H, L):
+    n = C.c_size_t()
+    st = H.lib().hmc_fields_bytes(C.byref(H.geom(L)), 0, C.byref(n))
+    assert st == H.HMC_E_ARG
+    assert "even" in H.last_error()
+
+
+def test_field_sizes(H):
+    L = (4, 4, 4, 4)
+    Vh = 128
+    assert H.hmc_field_bytes(L, H.F64, H.KIND_HALF_SPINOR) == Vh * 192
+    assert H.hmc_field_bytes(L, H.F32, H.KIND_FULL_SPINOR) == 2 * Vh * 96
+    assert H.hmc_field_bytes(L, H.F16, H.KIND_HALF_SPINOR) == Vh * 52
+    assert H.hmc_field_bytes(L, H.F64, H.KIND_GAUGE) == Vh * 8 * 144
+    with pytest.raises(H.HmcError):
+        H.hmc_field_bytes(L, H.F32, H.KIND_MOMENTA)
+    assert H.hmc_fields_bytes(L, H.FIELDS_LOWPREC) > H.hmc_fields_bytes(L, 0)
+
+
+def test_arena_too_small_is_oom(H):
+    L = (4, 4, 4, 4)
+    need = H.hmc_fields_bytes(L, 0)
+    buf = C.create_string_buffer(need + 512)
+    base = (C.addressof(buf) + 255) & ~255
+    h = C.c_void_p()
+    a = H.Action(5.6, 0.15)
+    st = H.lib().hmc_alloc_fields(C.byref(H.geom(L)), C.byref(a), 0, base, need - 1, C.byref(h))
+    assert st == H.HMC_E_OOM and "smaller" in H.last_error()
+    st = H.lib().hmc_alloc_fields(C.byref(H.geom(L)), C.byref(a), 0, base + 8, need, C.byref(h))
+    assert st == H.HMC_E_ARG
+
+
+def test_null_arguments_rejected(H):
+    assert H.lib().hmc_free_fields(None) == H.HMC_E_ARG
+    assert H.lib().hmc_plaquette(None, None, None) == H.HMC_E_ARG

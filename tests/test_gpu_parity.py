@@ -1,0 +1,482 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle.
+
+Inputs are seeded synthetic fields from tests/synth.py (or each side's own
+Philox draws from the same seed).  All calls go through the C ABI
+(libhmc.so via the ctypes binding).  Tolerances: bit-exact for indexing,
+layout conversion and random words; relative 1e-12 on FP64 fields
+(observed ~1e-15 per kernel); solver and trajectory tolerances as noted.
+Lattices: 4^4 (one partial block), 8x6x6x10 (Vh = 1440: several blocks and
+a ragged tail) and 16^3x32 (the HMC benchmark volume).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SMALL = [(4, 4, 4, 4), (8, 6, 6, 10)]
+ALL = SMALL + [(16, 16, 16, 32)]
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1212_0785_amd import hmc
+    hmc.lib()
+    return hmc
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def put_gauge(H, F, U):
+    H.hmc_import_gauge(F, H.to_device_c128(np.ascontiguousarray(U)))
+
+
+def get_gauge(H, F):
+    c = H.canon_gauge_zeros(F.L)
+    H.hmc_export_gauge(F, c)
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+def put_spinor(H, F, psi, parity, prec=0):
+    buf = F.spinor(full=(parity < 0))
+    H.hmc_import_spinor(F, buf, H.to_device_c128(np.ascontiguousarray(psi)), parity)
+    if prec:
+        low = F.spinor(prec=prec, full=False)
+        H.hmc_convert_spinor(F, low, prec, buf, 0)
+        return low
+    return buf
+
+
+def get_spinor(H, F, buf, parity, prec=0):
+    if prec:
+        b64 = F.spinor()
+        H.hmc_convert_spinor(F, b64, 0, buf, prec)
+        buf = b64
+    c = H.canon_spinor_zeros(F.L)
+    H.hmc_export_spinor(F, c, buf, parity)
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+def put_momenta(H, F, P):
+    H.hmc_import_momenta(F, H.to_device_c128(np.ascontiguousarray(P)))
+
+
+def get_momenta(H, F):
+    c = H.canon_gauge_zeros(F.L)
+    H.hmc_export_momenta(F, c)
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+def odd_mask(L):
+    return synth.site_coords(L).sum(1) % 2 == 1
+
+
+# ------------------------------------------------------- layout and RNG
+
+
+@pytest.mark.parametrize("L", SMALL)
+def test_layout_roundtrip_bit_exact(H, L):
+    F = H.Fields(L, 5.6, 0.15)
+    U = synth.gauge_field(1, L)
+    put_gauge(H, F, U)
+    assert np.array_equal(get_gauge(H, F), U)
+    psi = synth.spinor(2, L)
+    odd = odd_mask(L)
+    for par in (0, 1):
+        b = put_spinor(H, F, psi, par)
+        want = psi.copy()
+        want[odd != bool(par)] = 0
+        assert np.array_equal(get_spinor(H, F, b, par), want)
+    b = put_spinor(H, F, psi, -1)
+    assert np.array_equal(get_spinor(H, F, b, -1), psi)
+    P = synth.hermitian_traceless(3, L)
+    put_momenta(H, F, P)
+    back = get_momenta(H, F)
+    assert np.array_equal(back[..., 0, 1], P[..., 0, 1]) and np.array_equal(back[..., 1, 2], P[..., 1, 2])
+    assert rel(back, P) < 1e-15
+
+
+@pytest.mark.parametrize("stream,epoch", [(0, 0), (1, 3), (2, 7), (4, 1)])
+def test_random_words_bit_exact(H, stream, epoch):
+    seed = 12120785
+    sites = np.array([0, 1, 2, 255, 4096, 131071, 10616831, 123456789], dtype=np.int64)
+    got = H.hmc_random_words(seed, stream, epoch, torch.from_numpy(sites).cuda(), 8).cpu().numpy().view(np.uint64)
+    for k, i in enumerate(sites):
+        assert np.array_equal(got[k], O.site_words(seed, int(i), stream, epoch, 8))
+
+
+def test_random_gaussians_match(H):
+    seed = 99
+    sites = np.arange(0, 5000, 7, dtype=np.int64)
+    got = H.hmc_random_gaussians(seed, 1, 2, torch.from_numpy(sites).cuda(), 32).cpu().numpy()
+    want = np.array([O.site_gaussians(seed, int(i), 1, 2, 32) for i in sites])
+    # uniforms are bit-exact; log/sin/cos of host libm and device math may
+    # differ by an ulp or two
+    assert np.abs(got - want).max() <= 8 * np.finfo(float).eps * np.abs(want).max()
+
+
+# ----------------------------------------------------------- operators
+
+
+def test_dslash_indexing_bit_exact(H):
+    # unit links and small-integer spinors: every hop is exact in FP64, so
+    # any indexing, shift or boundary-sign difference shows as a bit change
+    L = (8, 6, 6, 10)
+    F = H.Fields(L, 5.6, 0.15)
+    put_gauge(H, F, O.unit_gauge(L))
+    psi = synth.integer_spinor(5, L)
+    for dag in (0, 1):
+        for par in (0, 1):
+            b = put_spinor(H, F, psi, 1 - par)
+            out = F.spinor()
+            H.hmc_wilson_dslash(F, out, b, par, dag)
+            got = get_spinor(H, F, out, par)
+            want = O.dslash(L, O.unit_gauge(L), psi, par, dag)
+            assert np.array_equal(got, want), (dag, par)
+
+
+@pytest.mark.parametrize("L", ALL)
+def test_dslash_parity(H, L):
+    F = H.Fields(L, 5.6, 0.15)
+    U = synth.gauge_field(7, L)
+    put_gauge(H, F, U)
+    psi = synth.spinor(8, L)
+    for dag in (0, 1):
+        for par in (0, 1):
+            b = put_spinor(H, F, psi, 1 - par)
+            out = F.spinor()
+            H.hmc_wilson_dslash(F, out, b, par, dag)
+            got = get_spinor(H, F, out, par)
+            assert rel(got, O.dslash(L, U, psi, par, dag)) < 1e-14
+
+
+@pytest.mark.parametrize("L", SMALL)
+def test_mhat_and_wilson_m_parity(H, L):
+    k = 0.156
+    F = H.Fields(L, 5.6, k)
+    U = synth.gauge_field(9, L, eps=0.6)
+    put_gauge(H, F, U)
+    psi = synth.spinor(10, L)
+    for dag in (0, 1):
+        b = put_spinor(H, F, psi, 0)
+        out = F.spinor()
+        H.hmc_mhat(F, out, b, dag)
+        assert rel(get_spinor(H, F, out, 0), O.mhat(L, U, k, psi, dag)) < 1e-14
+        bf = put_spinor(H, F, psi, -1)
+        of = F.spinor(full=True)
+        H.hmc_wilson_m(F, of, bf, dag)
+        assert rel(get_spinor(H, F, of, -1), O.wilson_m(L, U, k, psi, dag)) < 1e-14
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-6), (2, 3e-3), (3, 2e-2)])
+def test_low_precision_dslash(H, prec, tol):
+    L = (8, 6, 6, 10)
+    F = H.Fields(L, 5.6, 0.15, flags=H.FIELDS_LOWPREC)
+    U = synth.gauge_field(11, L, eps=0.5)
+    put_gauge(H, F, U)
+    psi = synth.spinor(12, L)
+    b = put_spinor(H, F, psi, 1, prec=prec)
+    out = F.spinor(prec=prec)
+    H.hmc_wilson_dslash(F, out, b, 0, 0, prec)
+    got = get_spinor(H, F, out, 0, prec=prec)
+    assert rel(got, O.dslash(L, U, psi, 0, 0)) < tol
+
+
+# ---------------------------------------------------------- global sums
+
+
+def test_reductions_exact_on_integers(H):
+    L = (8, 6, 6, 10)
+    F = H.Fields(L, 5.6, 0.15)
+    a = synth.integer_spinor(1, L)
+    b = synth.integer_spinor(2, L)
+    ba, bb = put_spinor(H, F, a, -1), put_spinor(H, F, b, -1)
+    assert H.hmc_norm2(F, ba, 2) == O.norm2(a)
+    assert H.hmc_inner(F, ba, bb, 2) == O.inner(a, b)
+    # sumMulti over time slices in the field's own site order ([parity][Vh])
+    t = synth.site_coords(L)[:, 3]
+    odd = odd_mask(L)
+    sub = np.concatenate([t[~odd], t[odd]]).astype(np.int32)  # cb order = lex order within a parity
+    got = H.hmc_sum_multi(F, ba, 2, torch.from_numpy(sub).cuda(), L[3])
+    dens = (np.abs(a) ** 2).reshape(synth.volume(L), -1)
+    assert got == list(O.sum_multi(dens, t, L[3]))
+
+
+def test_reductions_random(H):
+    L = (16, 16, 16, 32)
+    F = H.Fields(L, 5.6, 0.15)
+    a, b = synth.spinor(3, L), synth.spinor(4, L)
+    ba, bb = put_spinor(H, F, a, -1), put_spinor(H, F, b, -1)
+    assert abs(H.hmc_norm2(F, ba, 2) - O.norm2(a)) < 1e-13 * O.norm2(a)
+    ip, want = H.hmc_inner(F, ba, bb, 2), O.inner(a, b)
+    assert abs(ip - want) < 1e-13 * np.sqrt(O.norm2(a) * O.norm2(b))
+    # deterministic: same bits twice
+    assert H.hmc_norm2(F, ba, 2) == H.hmc_norm2(F, ba, 2)
+
+
+# ------------------------------------------------ gauge-field kernels
+
+
+@pytest.mark.parametrize("L", ALL)
+def test_plaquette_and_action(H, L):
+    F = H.Fields(L, 5.6, 0.15)
+    put_gauge(H, F, O.unit_gauge(L))
+    assert H.hmc_plaquette(F) == 1.0
+    U = synth.gauge_field(13, L, eps=0.7)
+    put_gauge(H, F, U)
+    assert abs(H.hmc_plaquette(F) - O.plaquette(L, U)) < 1e-14
+    sg = O.gauge_action(L, U, 5.6)
+    assert abs(H.hmc_gauge_action(F) - sg) < 1e-13 * sg
+
+
+@pytest.mark.parametrize("L", ALL)
+def test_gauge_force_parity(H, L):
+    F = H.Fields(L, 5.7, 0.15)
+    U = synth.gauge_field(14, L, eps=0.6)
+    P = synth.hermitian_traceless(15, L)
+    put_gauge(H, F, U)
+    put_momenta(H, F, P)
+    H.hmc_gauge_force(F, 0.05)
+    want = P - 0.05 * O.gauge_force(L, U, 5.7)
+    assert rel(get_momenta(H, F), want) < 1e-14
+
+
+@pytest.mark.parametrize("L", ALL)
+def test_fermion_force_parity(H, L):
+    k = 0.156
+    F = H.Fields(L, 5.6, k)
+    U = synth.gauge_field(16, L, eps=0.6)
+    P = synth.hermitian_traceless(17, L)
+    odd = odd_mask(L)
+    Xe = synth.spinor(18, L, odd, 0)
+    put_gauge(H, F, U)
+    put_momenta(H, F, P)
+    bx = put_spinor(H, F, Xe, 0)
+    H.hmc_fermion_force(F, bx, 0.05)
+    X = Xe.copy()
+    X[odd] = O.dslash(L, U, Xe, 1)[odd]
+    Y = O.mhat(L, U, k, Xe)
+    Y[odd] = O.dslash(L, U, Y, 1, dagger=True)[odd]
+    want = P - 0.05 * O.fermion_force(L, U, k * k, X, Y)
+    assert rel(get_momenta(H, F), want) < 1e-13
+
+
+@pytest.mark.parametrize("L", ALL)
+def test_exp_update_reunit_parity(H, L):
+    F = H.Fields(L, 5.6, 0.15)
+    U = synth.gauge_field(19, L)
+    P = synth.hermitian_traceless(20, L, scale=2.0)
+    put_gauge(H, F, U)
+    put_momenta(H, F, P)
+    H.hmc_exp_update_reunit(F, 0.1)
+    got = get_gauge(H, F)
+    assert rel(got, O.update_links(L, U, P, 0.1)) < 1e-14
+    g = got.reshape(-1, 3, 3)
+    assert np.abs(g @ np.conj(np.swapaxes(g, 1, 2)) - np.eye(3)).max() < 1e-14
+
+
+# ------------------------------------------------------- random fields
+
+
+@pytest.mark.parametrize("L", ALL)
+def test_refresh_and_weak_field_parity(H, L):
+    seed, traj, k = 12120785, 3, 0.15
+    F = H.Fields(L, 5.6, k)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    U = O.weak_field(L, seed, 0.3)
+    assert rel(get_gauge(H, F), U) < 1e-14
+    H.hmc_refresh(F, seed, traj)
+    assert rel(get_momenta(H, F), O.refresh_momenta(L, seed, traj)) < 1e-14
+    eta = O.eta(L, seed, traj, 0)
+    assert rel(get_spinor(H, F, F.pointer(H.FIELD_ETA), 0), eta) < 1e-15
+    assert rel(get_spinor(H, F, F.pointer(H.FIELD_PHI), 0), O.mhat(L, U, k, eta, dagger=True)) < 1e-14
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_sources(H, kind):
+    L = (8, 6, 6, 10)
+    F = H.Fields(L, 5.6, 0.15)
+    b = F.spinor(full=True)
+    H.hmc_make_source(F, b, kind, 77, 5)
+    got = get_spinor(H, F, b, -1)
+    want = O.source(L, kind, 77, 5)
+    if kind == 0:
+        assert rel(got, want) < 1e-15
+    else:
+        assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------- solvers
+
+
+@pytest.mark.parametrize("L", ALL)
+def test_cg_fixed_iterations_parity(H, L):
+    k = 0.156
+    F = H.Fields(L, 5.6, k)
+    U = synth.gauge_field(21, L, eps=0.4)
+    put_gauge(H, F, U)
+    b = synth.spinor(22, L, odd_mask(L), 0)
+    bb = put_spinor(H, F, b, 0)
+    x = F.spinor()
+    n = 20
+    st = H.hmc_cg_solve(F, x, bb, H.cg_params(fixed_iters=n))
+    assert st["iters"] == n
+    want, ost = O.cg_mhat(L, U, k, b, fixed_iters=n)
+    assert rel(get_spinor(H, F, x, 0), want) < 1e-12
+    assert abs(st["true_rel_res"] - ost["true_rel_res"]) < 1e-10
+
+
+@pytest.mark.parametrize("L", SMALL)
+def test_cg_converged_parity(H, L):
+    k = 0.15
+    F = H.Fields(L, 5.6, k)
+    U = O.weak_field(L, 5, 0.3)
+    put_gauge(H, F, U)
+    b = synth.spinor(23, L, odd_mask(L), 0)
+    bb = put_spinor(H, F, b, 0)
+    x = F.spinor()
+    st = H.hmc_cg_solve(F, x, bb, H.cg_params(tol=1e-10))
+    want, ost = O.cg_mhat(L, U, k, b, tol=1e-10)
+    assert st["status"] == 0 and st["true_rel_res"] < 2e-10
+    assert abs(st["iters"] - ost["iters"]) <= 1
+    assert rel(get_spinor(H, F, x, 0), want) < 1e-8
+
+
+def test_cg_nonconvergence_reported(H):
+    L = (4, 4, 4, 4)
+    F = H.Fields(L, 5.6, 0.15)
+    put_gauge(H, F, O.weak_field(L, 5, 0.3))
+    bb = put_spinor(H, F, synth.spinor(24, L, odd_mask(L), 0), 0)
+    x = F.spinor()
+    st = H.hmc_cg_solve(F, x, bb, H.cg_params(tol=1e-10, maxiter=3), allow_noconv=True)
+    assert st["status"] == H.HMC_E_NOCONV and st["iters"] == 3
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_wilson_solve_parity(H, prec):
+    L = (8, 6, 6, 10)
+    k = 0.157
+    F = H.Fields(L, 5.6, k, flags=H.FIELDS_LOWPREC)
+    U = O.weak_field(L, 1, 0.5)
+    put_gauge(H, F, U)
+    b = O.source(L, 0, 3, 0)
+    bb = put_spinor(H, F, b, -1)
+    x = F.spinor(full=True)
+    st = H.hmc_cg_solve(F, x, bb, H.cg_params(tol=1e-10, mode=H.CG_WILSON_SOLVE, prec=prec, maxiter=20000))
+    assert st["status"] == 0 and st["true_rel_res"] <= 1e-10
+    want, ost = O.wilson_solve(L, U, k, b, tol=1e-10)
+    assert ost["true_rel_res"] <= 1e-10
+    got = get_spinor(H, F, x, -1)
+    # both solutions satisfy |b - M x| <= 1e-10 |b|; they agree to ~cond * 1e-10
+    assert rel(got, want) < 1e-7
+    if prec:
+        assert st["reliable_updates"] >= 1
+
+
+# ------------------------------------------------------------------ HMC
+
+
+def test_leapfrog_parity_c1(H):
+    L = (4, 4, 4, 4)
+    seed, beta, k = 12120785, 5.6, 0.15
+    F = H.Fields(L, beta, k)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    H.hmc_refresh(F, seed, 0)
+    U0 = O.weak_field(L, seed, 0.3)
+    P0 = O.refresh_momenta(L, seed, 0)
+    phi = O.mhat(L, U0, k, O.eta(L, seed, 0, 0), dagger=True)
+    st = H.hmc_md_leapfrog(F, 1.0, 10, H.cg_params(tol=1e-10))
+    U1, P1, Xe, ost = O.leapfrog(L, U0, P0, phi, beta, k, 1.0, 10, tol=1e-10)
+    assert st["solves"] == ost["solves"] == 11
+    assert rel(get_gauge(H, F), U1) < 1e-12
+    assert rel(get_momenta(H, F), P1) < 1e-12
+
+
+def test_trajectory_parity_c1(H):
+    L = (4, 4, 4, 4)
+    seed, beta, k = 12120785, 5.6, 0.15
+    F = H.Fields(L, beta, k)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    U = O.weak_field(L, seed, 0.3)
+    for traj in range(3):
+        r = H.hmc_trajectory(F, seed, traj, 1.0, 10, H.cg_params(tol=1e-10))
+        U, o = O.hmc_trajectory(L, U, beta, k, seed, traj, 1.0, 10, tol=1e-10)
+        assert r["status"] == 0
+        assert r["u"] == o["u"]  # bit-exact uniform
+        assert r["accepted"] == o["accepted"]
+        for key in ("H_old", "H_new", "KE_old", "KE_new", "S_g_old", "S_g_new", "S_f_old", "S_f_new"):
+            assert abs(r[key] - o[key]) < 1e-12 * abs(o[key]), key
+        assert abs(r["dH"] - o["dH"]) < 1e-12 * abs(o["H_old"])
+        assert abs(r["plaquette"] - o["plaquette"]) < 1e-12
+        assert rel(get_gauge(H, F), U) < 1e-12
+
+
+def test_trajectory_accepts_at_small_step(H):
+    # a finer integration gives |dH| small enough to accept; both sides agree
+    L = (4, 4, 4, 4)
+    seed, beta, k = 4, 5.6, 0.15
+    F = H.Fields(L, beta, k)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    U = O.weak_field(L, seed, 0.3)
+    r = H.hmc_trajectory(F, seed, 0, 0.2, 20, H.cg_params(tol=1e-12))
+    U2, o = O.hmc_trajectory(L, U, beta, k, seed, 0, 0.2, 20, tol=1e-12)
+    assert r["accepted"] == o["accepted"] == 1
+    assert abs(r["dH"] - o["dH"]) < 1e-10
+    assert rel(get_gauge(H, F), U2) < 1e-12
+
+
+# -------------------------------------- full-size sampled check (48^3x96)
+
+
+def _coords48(lex):
+    return np.stack([lex % 48, (lex // 48) % 48, (lex // 2304) % 48, lex // 110592], 1)
+
+
+def test_dslash_sampled_at_48c96(H):
+    """The 48^3 x 96 bandwidth workload in the launch configuration the
+    benchmark times: GPU weak-field links and Gaussian spinor from their
+    seeds; ~260 even output sites recomputed by the oracle from its own
+    draws (only the links and spinors those sites touch are generated)."""
+    L = (48, 48, 48, 96)
+    V = synth.volume(L)
+    F = H.Fields(L, 5.6, 0.15)
+    H.hmc_weak_field_start(F, 2, 0.3)
+    src = F.spinor(full=True)
+    H.hmc_make_source(F, src, 0, 2, 0)
+    out = F.spinor()
+    hb = H.hmc_field_bytes(L, 0, H.KIND_HALF_SPINOR)
+    H.hmc_wilson_dslash(F, out, src[hb:], 0, 0)  # even <- odd
+    torch.cuda.synchronize()
+    cand = np.random.default_rng(1).integers(0, V, 2048)
+    lex = cand[_coords48(cand).sum(1) % 2 == 0][:256]
+    corners = [O.lex_index(L, 0, 0, 0, 0), O.lex_index(L, 47, 0, 0, 95), O.lex_index(L, 0, 47, 47, 94),
+               O.lex_index(L, 47, 47, 47, 95)]
+    lex = np.unique(np.concatenate([lex, corners])).astype(np.int64)
+    assert np.all(_coords48(lex).sum(1) % 2 == 0)
+    need = set(int(i) for i in lex)
+    for x, y, z, t in _coords48(lex):
+        for d in ((1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1)):
+            for sg in (1, -1):
+                need.add(O.lex_index(L, (x + sg * d[0]) % 48, (y + sg * d[1]) % 48, (z + sg * d[2]) % 48,
+                                     (t + sg * d[3]) % 96))
+    need = np.array(sorted(need), dtype=np.int64)
+    U = np.zeros((V, 4, 3, 3), np.complex128)  # lazily zero pages: only the needed sites are touched
+    psi = np.zeros((V, 4, 3), np.complex128)
+    O.weak_field_sites(L, 2, 0.3, need, U)
+    O.gauss_source_sites(2, 0, need, psi)
+    want = O.dslash_sites(L, U, psi, lex)
+    half = out.view(torch.float64).view(12, -1, 2)  # component-major [12][Vh] complex
+    gv = half[:, torch.from_numpy(lex // 2).cuda(), :].cpu().numpy()
+    got = (gv[..., 0] + 1j * gv[..., 1]).T.reshape(-1, 4, 3)
+    assert rel(got, want) < 1e-14
