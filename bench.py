@@ -1,0 +1,313 @@
+"""Benchmark of the MI355X Wilson-HMC hot path (one JSON line on stdout).
+
+Workloads (--workload):
+  hmc     (default) HMC seconds per trajectory on 16^3x32, beta 5.6,
+          kappa 0.156, tau 1 with 20 leapfrog steps, CG to 1e-10 (FP64),
+          trajectories 0..K-1 of the chain from the weak-field eps=0.3 start.
+          A step is one trajectory.
+  dslash  field-kernel bandwidth at 48^3x96 (FP64 and FP32 Dslash, staple
+          force, exp+reunit, norm2 / innerProduct), GB/s against HBM peak.
+  cg      24^3x48 kappa 0.157 Wilson solves of Gaussian sources to
+          |b - M x| <= 1e-10 |b|: FP64 CGLS against mixed precision
+          (FP32, FP16 and BF16 inner storage).
+
+Inputs are synthetic (weak-field gauge fields and sources drawn on the device
+from seeds) and resident in HBM when the timed region starts.  The roofline
+object reports the dominant kernel's algorithmic bytes per launch over its
+average duration, measured with HIP events on the launch stream inside the
+timed region.  The CPU baseline times the FP64 oracle on a bounded sample of
+the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "HMC s/traj @16^3x32; Dslash HBM GB/s; mixed vs FP64 CG; solve p50/p99"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dslash.hip", "device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1212_0785_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per Dslash launch from the committed rocprofv3 counter runs,
+    or None when the kernel changed since they were taken."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def timed_kernel_roofline(H, name="dslash", timing=None):
+    t = (timing if timing is not None else H.hmc_timing_read()).get(name)
+    if not t or not t["launches"]:
+        return None
+    avg_ms = t["total_ms"] / t["launches"]
+    bytes_per_launch = t["bytes"] / t["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"avg_ms": avg_ms, "bytes_per_launch": bytes_per_launch, "achieved": achieved,
+            "launches_timed": t["launches"]}
+
+
+# ------------------------------------------------------------------- HMC
+
+
+def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sample=30):
+    """Time each oracle piece of one trajectory once (the CG over a fixed
+    n_cg_sample iterations) and project seconds per trajectory with the
+    measured GPU iteration count per solve (same algorithm, same count)."""
+    import numpy as np  # noqa: F401
+
+    import oracle as O
+    t0 = time.perf_counter()
+    U = O.weak_field(L, seed, 0.3)
+    ta = time.perf_counter()
+    P = O.refresh_momenta(L, seed, 0)
+    eta = O.eta(L, seed, 0, 0)
+    phi = O.mhat(L, U, kappa, eta, dagger=True)
+    O.kinetic(L, P), O.gauge_action(L, U, beta)
+    t_refresh = time.perf_counter() - ta
+    ta = time.perf_counter()
+    F = O.gauge_force(L, U, beta)
+    t_gf = time.perf_counter() - ta
+    ta = time.perf_counter()
+    Xe, _ = O.cg_mhat(L, U, kappa, phi, fixed_iters=n_cg_sample)
+    t_cg = (time.perf_counter() - ta) / n_cg_sample
+    ta = time.perf_counter()
+    odd = O.parity_mask(L)
+    X = Xe.copy()
+    X[odd] = O.dslash(L, U, Xe, 1)[odd]
+    Y = O.mhat(L, U, kappa, Xe)
+    Y[odd] = O.dslash(L, U, Y, 1, dagger=True)[odd]
+    O.fermion_force(L, U, kappa * kappa, X, Y)
+    t_ff = time.perf_counter() - ta
+    ta = time.perf_counter()
+    O.update_links(L, U, P, 1.0 / nsteps)
+    t_up = time.perf_counter() - ta
+    sample = time.perf_counter() - t0
+    n_force = nsteps + 1
+    proj = 2 * t_refresh + n_force * (t_gf + t_ff + cg_iters_per_solve * t_cg) + nsteps * t_up
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": proj, "unit": "s/traj", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle on 16^3x32, trajectory 0 pieces timed once each: refresh + actions, "
+                       f"gauge force, fermion force, link update, and {n_cg_sample} CG iterations; "
+                       f"projected to {n_force} force evaluations x {cg_iters_per_solve:.0f} CG iterations "
+                       f"(the GPU's mean per solve) + {nsteps} link updates; sample wall {sample:.1f} s"),
+            "per_cg_iter_s": t_cg, "force_eval_s": t_gf + t_ff}
+
+
+def run_hmc(args, H, torch):
+    L = (16, 16, 16, 32)
+    seed, beta, kappa, tau, nsteps = 12120785, 5.6, 0.156, 1.0, 20
+    F = H.Fields(L, beta, kappa)
+    stream = torch.cuda.current_stream()
+    prm = H.cg_params(tol=1e-10, maxiter=10000)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    for w in range(args.warmup):
+        H.hmc_trajectory(F, seed, w, tau, nsteps, prm)
+    H.hmc_weak_field_start(F, seed, 0.3)  # timed chain starts at trajectory 0
+    torch.cuda.synchronize()
+    H.hmc_timing_reset()
+    H.hmc_timing_enable(args.sample_every)
+    t0 = time.perf_counter()
+    results = [H.hmc_trajectory(F, seed, k, tau, nsteps, prm, stream=stream) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    H.hmc_timing_enable(0)
+    timing = H.hmc_timing_read()
+    rf = timed_kernel_roofline(H, "dslash", timing)
+    iters = sum(r["cg_iters_total"] for r in results)
+    solves = args.steps * (nsteps + 1)
+    out = {
+        "metric": METRIC, "value": dt / args.steps, "unit": "s/traj", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "hmc_16c32", "lattice": list(L), "beta": beta, "kappa": kappa, "tau": tau,
+                   "nsteps": nsteps, "cg_tol": 1e-10, "start": "weak-field eps=0.3 seed 12120785",
+                   "trajectories": f"0..{args.steps - 1}", "parallelism": "1 GPU"},
+        "trajectories": [{"traj": k, "seconds": r["seconds"], "dH": r["dH"], "accepted": r["accepted"],
+                          "plaquette": r["plaquette"], "cg_iters": r["cg_iters_total"]}
+                         for k, r in enumerate(results)],
+        "cg_iters_per_solve": iters / solves,
+        "kernels_sampled": {k: {"launches_timed": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
+                                "GBps": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9 if v["bytes"] else None}
+                            for k, v in timing.items()},
+    }
+    if rf:
+        out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": rf["achieved"] / HBM_PEAK_GBS, "traffic": load_traffic("hmc_16c32"),
+                           "kernel": "k_dslash F64 (half-lattice hop, plain and axpy/norm epilogues)",
+                           "avg_launch_ms": rf["avg_ms"], "bytes_per_launch": rf["bytes_per_launch"],
+                           "launches_timed": rf["launches_timed"]}
+    return out, iters / solves, L, seed, beta, kappa, nsteps
+
+
+# ----------------------------------------------------------------- Dslash
+
+
+def run_dslash(args, H, torch):
+    L = (48, 48, 48, 96)
+    F = H.Fields(L, 5.6, 0.15, flags=H.FIELDS_LOWPREC)
+    H.hmc_weak_field_start(F, 2, 0.3)
+    H.hmc_sync_lowprec(F)
+    hb = {p: H.hmc_field_bytes(L, p, H.KIND_HALF_SPINOR) for p in (H.F64, H.F32)}
+    src = F.spinor(full=True)
+    H.hmc_make_source(F, src, 0, 2, 0)
+    inp = {H.F64: src[hb[H.F64]:]}
+    inp[H.F32] = F.spinor(prec=H.F32)
+    H.hmc_convert_spinor(F, inp[H.F32], H.F32, inp[H.F64], H.F64)
+    outb = {p: F.spinor(prec=p) for p in (H.F64, H.F32)}
+    res = {}
+    for p, name in ((H.F64, "f64"), (H.F32, "f32")):
+        for _ in range(args.warmup):
+            H.hmc_wilson_dslash(F, outb[p], inp[p], 0, 0, p)
+        torch.cuda.synchronize()
+        H.hmc_timing_reset()
+        H.hmc_timing_enable(1)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            H.hmc_wilson_dslash(F, outb[p], inp[p], 0, 0, p)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        H.hmc_timing_enable(0)
+        rf = timed_kernel_roofline(H, "dslash")
+        res[name] = {"avg_ms": rf["avg_ms"], "GBps": rf["achieved"], "frac": rf["achieved"] / HBM_PEAK_GBS,
+                     "wall_ms": 1e3 * wall, "bytes_per_launch": rf["bytes_per_launch"]}
+    # other field kernels (FP64)
+    for name, fn, kern in (
+            ("gauge_force", lambda: H.hmc_gauge_force(F, 1e-3), "gauge_force"),
+            ("exp_update", lambda: H.hmc_exp_update_reunit(F, 1e-3), "exp_update")):
+        H.hmc_refresh(F, 5, 0, H.REFRESH_MOM)
+        fn()
+        torch.cuda.synchronize()
+        H.hmc_timing_reset()
+        H.hmc_timing_enable(1)
+        for _ in range(max(3, args.steps // 4)):
+            fn()
+        torch.cuda.synchronize()
+        H.hmc_timing_enable(0)
+        rf = timed_kernel_roofline(H, kern)
+        res[name] = {"avg_ms": rf["avg_ms"], "GBps": rf["achieved"], "frac": rf["achieved"] / HBM_PEAK_GBS}
+    best = res["f64"]
+    out = {
+        "metric": METRIC, "value": best["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": best["avg_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "dslash_48c96", "lattice": list(L), "gauge": "weak-field eps=0.3 seed 2",
+                   "spinor": "Gaussian seed 2", "parallelism": "1 GPU"},
+        "kernels": res,
+        "roofline": {"bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": best["frac"], "traffic": load_traffic("dslash_48c96"),
+                     "kernel": "k_dslash F64 plain, 1536 B/site", "avg_launch_ms": best["avg_ms"]},
+    }
+    return out
+
+
+# --------------------------------------------------------------------- CG
+
+
+def run_cg(args, H, torch):
+    L = (24, 24, 24, 48)
+    kappa = 0.157
+    F = H.Fields(L, 5.6, kappa, flags=H.FIELDS_LOWPREC)
+    H.hmc_weak_field_start(F, 1, 0.5)
+    nsrc = args.steps
+    rows = {}
+    ref = {}
+    b = F.spinor(full=True)
+    x = F.spinor(full=True)
+    for prec, name in ((H.F64, "f64"), (H.F32, "f32"), (H.F16, "f16"), (H.BF16, "bf16")):
+        prm = H.cg_params(tol=1e-10, maxiter=50000, mode=H.CG_WILSON_SOLVE, prec=prec)
+        H.hmc_make_source(F, b, 0, 1, 0)
+        H.hmc_cg_solve(F, x, b, prm)  # warm-up
+        recs = []
+        for k in range(nsrc):
+            H.hmc_make_source(F, b, 0, 1, k)
+            torch.cuda.synchronize()
+            st = H.hmc_cg_solve(F, x, b, prm)
+            torch.cuda.synchronize()
+            if prec == H.F64:
+                ref[k] = x.clone()
+                err = 0.0
+            else:
+                d = (x.view(torch.float64) - ref[k].view(torch.float64)).norm() / ref[k].view(torch.float64).norm()
+                err = float(d)
+            recs.append({"src": k, "seconds": st["seconds"], "iters": st["iters"],
+                         "reliable_updates": st["reliable_updates"], "true_rel_res": st["true_rel_res"],
+                         "rel_diff_vs_f64": err})
+        t = sum(r["seconds"] for r in recs) / len(recs)
+        rows[name] = {"mean_seconds": t, "solves": recs}
+    best = min(("f32", "f16", "bf16"), key=lambda n: rows[n]["mean_seconds"])
+    out = {
+        "metric": METRIC, "value": rows["f64"]["mean_seconds"] / rows[best]["mean_seconds"],
+        "unit": "x speedup (FP64 CG time / mixed time to 1e-10)", "n_gpus": 1, "steps": nsrc,
+        "warmup": 1, "ms_per_step": 1e3 * rows[best]["mean_seconds"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": best, "data": "synthetic",
+        "config": {"workload": "wilson_solve_24c48", "lattice": list(L), "kappa": kappa,
+                   "gauge": "weak-field eps=0.5 seed 1", "sources": f"Gaussian seed 1 epochs 0..{nsrc - 1}",
+                   "tol": 1e-10, "parallelism": "1 GPU"},
+        "solvers": {k: {"mean_seconds": v["mean_seconds"],
+                        "mean_iters": sum(r["iters"] for r in v["solves"]) / len(v["solves"]),
+                        "max_true_rel_res": max(r["true_rel_res"] for r in v["solves"]),
+                        "max_rel_diff_vs_f64": max(r["rel_diff_vs_f64"] for r in v["solves"])}
+                    for k, v in rows.items()},
+        "fastest_mixed": best,
+    }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="hmc", choices=["hmc", "dslash", "cg"])
+    ap.add_argument("--sample-every", type=int, default=8, help="time every n-th kernel launch with HIP events")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (4, 1)}[args.workload]
+    args.steps = args.steps if args.steps is not None else defaults[0]
+    args.warmup = args.warmup if args.warmup is not None else defaults[1]
+
+    import torch
+
+    import paper_1212_0785_amd.hmc as H
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    H.lib()
+    torch.cuda.set_device(0)
+    if args.workload == "hmc":
+        out, iters_per_solve, L, seed, beta, kappa, nsteps = run_hmc(args, H, torch)
+        if not args.no_cpu_baseline:
+            cb = oracle_hmc_sample(L, seed, beta, kappa, nsteps, iters_per_solve)
+            out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+            out["cpu_baseline"]["gpu_speedup"] = cb["value"] / out["value"]
+    elif args.workload == "dslash":
+        out = run_dslash(args, H, torch)
+    else:
+        out = run_cg(args, H, torch)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
