@@ -74,7 +74,13 @@ def _load():
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build(force=True)
-    lib = C.CDLL(_LIB)
+    _lib = bind(_LIB)
+    return _lib
+
+
+def bind(path):
+    """Load a compiled oracle library and declare its signatures."""
+    lib = C.CDLL(path)
     sig = {
         "or_lex_index": (C.c_long, [_I, C.c_int, C.c_int, C.c_int, C.c_int]),
         "or_site_parity": (C.c_int, [_I, C.c_long]),
@@ -120,8 +126,18 @@ def _load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
     return lib
+
+
+def compile_variant(src_text: str, path: str) -> str:
+    """Compile an edited copy of oracle.c (used to check that the pins
+    detect planted mistakes)."""
+    src = path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.run(["gcc", "-O1", "-std=gnu11", "-fopenmp", "-fcx-limited-range", "-fPIC", "-shared", "-w",
+                    "-o", path, src, "-lm"], check=True)
+    return path
 
 
 def _dims(L):

@@ -1,0 +1,112 @@
+"""The oracle pins catch plausible mistakes.
+
+Each mutant is oracle.c with one planted error (a flipped projector, a
+dropped boundary sign, a missing dagger, a wrong coefficient, a transposed
+product, ...).  It is compiled to a temporary library and swapped in for the
+real oracle; at least one of the listed pin tests must then fail.  Mistakes
+are planted only in the CPU oracle.
+"""
+import os
+
+import pytest
+
+import oracle as O
+from tests import test_oracle_pins as P
+
+SRC = open(os.path.join(os.path.dirname(O.__file__), "oracle.c")).read()
+
+
+def c1():
+    L = [4, 4, 4, 4]
+    U = O.weak_field(L, 12120785, 0.3)
+    Pm = O.refresh_momenta(L, 12120785, 0)
+    eta = O.eta(L, 12120785, 0, 0)
+    phi = O.mhat(L, U, 0.15, eta, dagger=True)
+    return L, U, Pm, eta, phi
+
+
+def free_field():
+    for n in [(0, 0, 0, 0), (1, 2, 0, 3), (3, 5, 1, 7)]:
+        P.test_free_field_closed_form(n)
+
+
+MUTANTS = {
+    "forward/backward projectors swapped": (
+        "int sgn = (dir > 0) ? s_fwd : -s_fwd;", "int sgn = (dir > 0) ? -s_fwd : s_fwd;",
+        [free_field]),
+    "antiperiodic time sign dropped": (
+        "double bc = wraps ? -1.0 : 1.0;\n            /* colour matrix", "double bc = 1.0;\n            /* colour matrix",
+        [free_field]),
+    "backward link not daggered": (
+        "mat_dag(&U[(j * 4 + mu) * 9], Um);", "memcpy(Um, &U[(j * 4 + mu) * 9], sizeof Um);",
+        [P.test_gamma5_hermiticity_and_dagger, P.test_gauge_covariance]),
+    "dagger flag ignored": (
+        "int s_fwd = dagger ? +1 : -1;", "int s_fwd = -1;",
+        [P.test_gamma5_hermiticity_and_dagger]),
+    "Mhat uses kappa instead of kappa^2": (
+        "in[i * 12 + k] - kappa * kappa * u[i * 12 + k]", "in[i * 12 + k] - kappa * u[i * 12 + k]",
+        [P.test_schur_determinant_and_solvers]),
+    "gauge force coefficient beta/6": (
+        "-I * beta / 12.0 * Z[k]", "-I * beta / 6.0 * Z[k]",
+        [P.test_gauge_force_finite_difference]),
+    "lower staple orientation": (
+        "mat_mul(a, &U[(xmnu * 4 + nu) * 9], a);", "mat_mul(&U[(xmnu * 4 + nu) * 9], a, a);",
+        [P.test_gauge_force_finite_difference, P.test_forces_gauge_covariant]),
+    "fermion force boundary sign dropped": (
+        "double s = wraps ? -1.0 : 1.0;\n            cplx M1[9]", "double s = 1.0;\n            cplx M1[9]",
+        [P.test_fermion_force_finite_difference]),
+    "fermion force projectors swapped": (
+        "cplx pm = proj_el(mu, -1, a, b), pp = proj_el(mu, +1, a, b);",
+        "cplx pm = proj_el(mu, +1, a, b), pp = proj_el(mu, -1, a, b);",
+        [P.test_fermion_force_finite_difference]),
+    "fermion force W term transposed": (
+        "mat_mul(M2, Ud, t);", "mat_mul(Ud, M2, t);",
+        [P.test_fermion_force_finite_difference]),
+    "reunit third row not conjugated": (
+        "u[6] = conj(u[1] * u[5] - u[2] * u[4]);", "u[6] = (u[1] * u[5] - u[2] * u[4]);",
+        [P.test_reunit_projects_to_su3_and_fixes_su3]),
+    "Philox key increment typo": (
+        "inc1 = 0xBB67AE8584CAA73BULL", "inc1 = 0xBB67AE8584CAA73AULL",
+        [P.test_philox_known_answer_vectors]),
+    "Philox round output order": (
+        "x0 = hi1 ^ x1 ^ k0;", "x0 = hi0 ^ x1 ^ k0;",
+        [P.test_philox_known_answer_vectors, P.test_philox_matches_numpy]),
+    "CG beta inverted": (
+        "double beta = rr_new / rr;", "double beta = rr / rr_new;",
+        [P.test_schur_determinant_and_solvers]),
+    "plaquette missing dagger": (
+        "mat_dag(&U[(xnu * 4 + mu) * 9], t);\n            mat_mul(a, t, a);",
+        "memcpy(t, &U[(xnu * 4 + mu) * 9], sizeof t);\n            mat_mul(a, t, a);",
+        [P.test_plaquette_single_abelian_link, P.test_gauge_covariance]),
+    "generator normalisation lambda instead of lambda/2": (
+        "H[1] = 0.5 * (om[0] - I * om[1]);", "H[1] = (om[0] - I * om[1]);",
+        [P.test_algebra_generators]),
+    "leapfrog first kick a full step": (
+        "status |= force_kick(L, U, P, phi, a, 0.5 * eps, Xe, ms);", "status |= force_kick(L, U, P, phi, a, eps, Xe, ms);",
+        [lambda: P.test_leapfrog_reversibility(c1())]),
+    "Metropolis with exp(+dH)": (
+        "res->u < exp(-res->dH)", "res->u < exp(res->dH)",
+        [lambda: P.test_trajectory_bookkeeping(c1())]),
+    "link update right-multiplies": (
+        "mat_mul(E, &U[l * 9], &U[l * 9]);", "mat_mul(&U[l * 9], E, &U[l * 9]);",
+        [P.test_update_links_is_left_multiplication_by_exp]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new, checks = MUTANTS[name]
+    assert SRC.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
+    path = O.compile_variant(SRC.replace(old, new), str(tmp_path / "liboracle_mutant.so"))
+    real = O._load()
+    O._lib = O.bind(path)
+    try:
+        caught = []
+        for chk in checks:
+            try:
+                chk()
+            except (AssertionError, ValueError, FloatingPointError):
+                caught.append(chk)
+        assert caught, f"no pin detected the planted mistake: {name}"
+    finally:
+        O._lib = real
