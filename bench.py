@@ -10,6 +10,10 @@ Workloads (--workload):
   cg      24^3x48 kappa 0.157 Wilson solves of Gaussian sources to
           |b - M x| <= 1e-10 |b|: FP64 CGLS against mixed precision
           (FP32, FP16 and BF16 inner storage).
+  serve   Poisson stream of Wilson solves over {8^4, 16^3x32, 24^3x48}
+          through the continuous-batching service (mixed precision),
+          throughput and p50/p99 latency against a one-at-a-time FP64 FIFO
+          baseline on the same requests.
 
 Inputs are synthetic (weak-field gauge fields and sources drawn on the device
 from seeds) and resident in HBM when the timed region starts.  The roofline
@@ -273,12 +277,112 @@ def run_cg(args, H, torch):
     return out
 
 
+# ------------------------------------------------------------------ serve
+
+
+def serve_requests(n, seed=3):
+    """Request mix: volume uniform over {8^4, 16^3x32, 24^3x48}, kappa
+    U[0.150, 0.157], gauge eps U[0.2, 0.5], Z2 or point source (p = 1/2),
+    per-request seeds drawn from the master seed."""
+    import numpy as np
+    g = np.random.default_rng(seed)
+    vols = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48)]
+    out = []
+    for i in range(n):
+        out.append({"L": vols[int(g.integers(0, 3))], "kappa": float(g.uniform(0.150, 0.157)),
+                    "gauge_seed": int(g.integers(1, 2**62)), "eps": float(g.uniform(0.2, 0.5)),
+                    "kind": 1 if g.random() < 0.5 else 2, "source_seed": int(g.integers(1, 2**62))})
+    return out
+
+
+def run_serve(args, H, torch):
+    import threading
+
+    import numpy as np
+    reqs = serve_requests(args.steps)
+    # one-at-a-time FP64 baseline: measured service time of every request
+    fields = {}
+    svc_time = []
+    b, x = {}, {}
+    for r in reqs:
+        L = r["L"]
+        if L not in fields:
+            fields[L] = H.Fields(L, 5.6, r["kappa"])
+            b[L] = fields[L].spinor(full=True)
+            x[L] = fields[L].spinor(full=True)
+        F = fields[L]
+        H.hmc_set_action(F, 5.6, r["kappa"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.hmc_weak_field_start(F, r["gauge_seed"], r["eps"])
+        H.hmc_make_source(F, b[L], r["kind"], r["source_seed"], 0)
+        st = H.hmc_cg_solve(F, x[L], b[L], H.cg_params(tol=1e-10, maxiter=50000, mode=H.CG_WILSON_SOLVE),
+                            allow_noconv=True)
+        torch.cuda.synchronize()
+        svc_time.append(time.perf_counter() - t0)
+        r["f64_iters"] = st["iters"]
+    del fields, b, x
+    torch.cuda.empty_cache()
+    mu1 = 1.0 / (sum(svc_time) / len(svc_time))
+    lam = args.rho * mu1
+    arr = np.cumsum(np.random.default_rng(4).exponential(1.0 / lam, len(reqs)))
+    # FIFO single server on the measured service times
+    done, lat_base = 0.0, []
+    for a, s_ in zip(arr, svc_time):
+        start = max(a, done)
+        done = start + s_
+        lat_base.append(done - a)
+    base = {"throughput": len(reqs) / (done - arr[0]), "p50": float(np.percentile(lat_base, 50)),
+            "p99": float(np.percentile(lat_base, 99)), "mean_service_s": 1.0 / mu1}
+    # continuous-batching service, real-time Poisson submissions
+    svc = H.Service(args.arena_gb * (1 << 30), inner_prec=H.PREC_NAMES[args.inner], max_batch=64)
+    tickets = [None] * len(reqs)
+
+    def submitter():
+        t0 = time.perf_counter()
+        for i, (a, r) in enumerate(zip(arr - arr[0], reqs)):
+            dt = a - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = svc.submit(H.solve_request(r["L"], r["kappa"], r["gauge_seed"], r["eps"], r["kind"],
+                                                    r["source_seed"], 0))
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    res = [svc.wait(t) for t in tickets]
+    svc.close()
+    lat = [r["t_done"] - r["t_submit"] for r in res]
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    ok = sum(r["status"] == 0 for r in res)
+    serv = {"throughput": len(res) / span, "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            "converged": ok, "max_true_rel_res": max(r["true_rel_res"] for r in res),
+            "max_group": max(r["max_group"] for r in res)}
+    out = {
+        "metric": METRIC, "value": serv["throughput"], "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 0, "ms_per_step": 1e3 / serv["throughput"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.inner, "data": "synthetic",
+        "config": {"workload": "serve_mix", "volumes": ["8^4", "16^3x32", "24^3x48"], "kappa": [0.150, 0.157],
+                   "gauge_eps": [0.2, 0.5], "sources": "Z2 or point, p=1/2", "master_seed": 3,
+                   "rho": args.rho, "arrival_rate_per_s": lam, "tol": 1e-10, "arena_gb": args.arena_gb,
+                   "parallelism": "1 GPU"},
+        "service": serv,
+        "fifo_fp64_baseline": base,
+        "p50_ratio_vs_baseline": base["p50"] / serv["p50"],
+        "p99_ratio_vs_baseline": base["p99"] / serv["p99"],
+    }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="hmc", choices=["hmc", "dslash", "cg"])
+    ap.add_argument("--workload", default="hmc", choices=["hmc", "dslash", "cg", "serve"])
+    ap.add_argument("--rho", type=float, default=0.9, help="serve: offered load relative to FP64 FIFO capacity")
+    ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
+    ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
     ap.add_argument("--sample-every", type=int, default=8, help="time every n-th kernel launch with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -286,7 +390,7 @@ def main():
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
-    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (4, 1)}[args.workload]
+    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (4, 1), "serve": (64, 0)}[args.workload]
     args.steps = args.steps if args.steps is not None else defaults[0]
     args.warmup = args.warmup if args.warmup is not None else defaults[1]
 
@@ -304,6 +408,8 @@ def main():
             out["cpu_baseline"]["gpu_speedup"] = cb["value"] / out["value"]
     elif args.workload == "dslash":
         out = run_dslash(args, H, torch)
+    elif args.workload == "serve":
+        out = run_serve(args, H, torch)
     else:
         out = run_cg(args, H, torch)
     print(json.dumps(out))

@@ -317,6 +317,75 @@ typedef struct {
 hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_traj_params* params,
                           hmc_traj_result* result, void* stream);
 
+/* Solve service: continuous batching of Wilson solves M x = b (the
+ * fermion-matrix inversions of Sec. 1 as a request stream).  Each request
+ * brings its own lattice volume, kappa, weak-field gauge field (drawn on the
+ * device from its seed) and source.  A scheduler admits requests in FIFO
+ * order whenever their device footprint (hmc_request_bytes) fits into the
+ * free part of the caller's arena, keeps each request's gauge field and
+ * solver state resident, and advances all admitted requests of the same
+ * volume together: every solver step is one launch over the whole group
+ * (blockIdx.y = request).  Requests that arrive while others run join at
+ * the next round; finished ones leave and free their memory.  The solver is
+ * CGLS with reliable updates (HMC_CG_WILSON_SOLVE semantics) with inner
+ * storage `inner_prec`, exit on the FP64 true residual; each request's
+ * arithmetic depends only on its own data, so its result is the same alone
+ * and in any mix.
+ *
+ * With manual = 0 a scheduler thread runs rounds while work is pending;
+ * with manual = 1 progress happens only in hmc_service_step (deterministic
+ * tests).  Volume groups run on separate internal streams (default
+ * priority).  Times are seconds since hmc_service_create. */
+typedef struct {
+  void* arena;            /* device memory owned by the caller */
+  size_t arena_bytes;
+  int32_t max_batch;      /* max requests advanced together per volume (<= 256) */
+  int32_t inner_prec;     /* hmc_prec of the inner iteration */
+  double tol;             /* |b - M x| <= tol |b| */
+  int32_t maxiter;        /* inner iterations per request */
+  int32_t manual;
+  int32_t chunk;          /* iterations per round (<= 0 selects 16) */
+  int32_t pad;
+} hmc_service_params;
+typedef struct {
+  int32_t L[4];
+  double kappa;
+  uint64_t gauge_seed;
+  double gauge_eps;
+  int32_t source_kind; /* HMC_SOURCE_* */
+  int32_t pad;
+  uint64_t source_seed;
+  uint64_t source_epoch;
+  void* out; /* optional device buffer (full F64 spinor of this volume) for x */
+} hmc_solve_request;
+typedef struct {
+  int32_t status; /* HMC_OK, HMC_E_NOCONV, HMC_E_OOM */
+  int32_t iters;
+  int32_t reliable_updates;
+  int32_t max_group; /* largest group this request was advanced in */
+  double true_rel_res;
+  double t_submit, t_start, t_done;
+} hmc_solve_result;
+typedef struct hmc_service hmc_service;
+
+/* Device bytes one request occupies in the service arena. */
+hmc_status hmc_request_bytes(const hmc_solve_request* req, int32_t inner_prec, size_t* bytes);
+hmc_status hmc_service_create(const hmc_service_params* params, hmc_service** out);
+/* Non-blocking.  HMC_E_OOM if the request can never fit the arena,
+ * HMC_E_ARG on a bad request; otherwise it waits for memory. */
+hmc_status hmc_service_submit(hmc_service* svc, const hmc_solve_request* req, uint64_t* ticket);
+/* HMC_E_BUSY until the request has finished; then fills res and returns
+ * the request's status.  A finished ticket stays queryable. */
+hmc_status hmc_service_poll(hmc_service* svc, uint64_t ticket, hmc_solve_result* res);
+/* Blocks until the request has finished (runs rounds itself in manual mode). */
+hmc_status hmc_service_wait(hmc_service* svc, uint64_t ticket, hmc_solve_result* res);
+/* One scheduling round (admit, advance, retire); *pending = requests not
+ * yet finished.  Manual mode only. */
+hmc_status hmc_service_step(hmc_service* svc, int32_t* pending);
+/* Stops the scheduler (after the current round) and releases host state;
+ * unfinished requests are dropped. */
+hmc_status hmc_service_destroy(hmc_service* svc);
+
 /* Kernel timing with HIP events on the launch streams.  With sample_every =
  * n > 0 every n-th launch of each kernel family is bracketed by a pair of
  * events (up to a fixed pool; later launches go untimed); 0 disables.

@@ -182,16 +182,23 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(Lat g, const double2* b, dou
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-// alpha = sum(part_a) / sum(part_b);  x += alpha p;  r -= alpha q;
-// part_out = per-block |r|^2.  (CG: part_a = |r|^2, part_b = <p, A p>;
-// CGLS: part_a = |s|^2, part_b = |q|^2.)
+// One solver iteration with label k = iter0 + j; cur = k & 1, nxt = cur ^ 1.
+//   update:  alpha = sum(pp[cur]) / sum(pq);  x += alpha p;  r -= alpha q;
+//            per-block |r|^2 -> pp[nxt] (CG) or pr (CGLS)
+//   pupdate: beta = sum(pp[nxt]) / sum(pp[cur]);  p = src + beta p with
+//            src = r (CG) or s (CGLS); convergence measure |r|^2 =
+//            sum(pp[nxt]) (CG) or sum(pr) (CGLS).
+// (CG: pp holds |r|^2, pq = <p, A p> = |Mhat p|^2.  CGLS: pp holds
+// |s|^2 = |Mhat^dag r|^2, pq = |q|^2 = |Mhat p|^2.)
 template <class SP, class SX>
-__global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table, CgArgs one) {
+__global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table, CgArgs one, int j) {
   const CgArgs a = table ? table[blockIdx.y] : one;
-  if (a.iter >= a.state->stop_at) return;
+  const int k = a.iter0 + j;
+  if (k >= a.state->stop_at) return;
   using R = typename SP::R;
-  const double num = sum_partials(a.part_a, a.n_a);
-  const double den = sum_partials(a.part_b, a.n_b);
+  const int cur = k & 1;
+  const double num = sum_partials(a.pp[cur], a.n_pp);
+  const double den = sum_partials(a.pq, a.n_pq);
   const double alpha = num / den;
   const R al = (R)alpha;
   double v[1] = {0.0};
@@ -203,74 +210,81 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table
     SP::load(a.r, g.stride, s, r);
     SX::load(a.x, g.stride, s, x);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      x[k].re = fma((typename SX::R)alpha, (typename SX::R)p[k].re, x[k].re);
-      x[k].im = fma((typename SX::R)alpha, (typename SX::R)p[k].im, x[k].im);
-      r[k].re = fma(-al, q[k].re, r[k].re);
-      r[k].im = fma(-al, q[k].im, r[k].im);
-      v[0] += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
+    for (int m = 0; m < 12; ++m) {
+      x[m].re = fma((typename SX::R)alpha, (typename SX::R)p[m].re, x[m].re);
+      x[m].im = fma((typename SX::R)alpha, (typename SX::R)p[m].im, x[m].im);
+      r[m].re = fma(-al, q[m].re, r[m].re);
+      r[m].im = fma(-al, q[m].im, r[m].im);
+      v[0] += (double)r[m].re * r[m].re + (double)r[m].im * r[m].im;
     }
     SX::store(a.x, g.stride, s, x);
     SP::store(a.r, g.stride, s, r);
   }
   block_sum<1>(v);
-  if (threadIdx.x == 0) a.part_out[blockIdx.x] = v[0];
+  double* out = a.cgls ? a.pr : a.pp[cur ^ 1];
+  if (threadIdx.x == 0) out[blockIdx.x] = v[0];
 }
 
-// beta = sum(part_a) / sum(part_b);  p = src + beta p, src = r (CG) or s
-// (CGLS).  The convergence measure |r|^2 = sum(part_c).  Block 0 records
-// the iteration and, when |r|^2 <= thr (or, in mixed precision, when the
-// inner residual fell by delta since the last FP64 update), sets
-// stop_at = iter + 1; no other block reads that value in this launch.
+// Block 0 records the iteration and, when |r|^2 <= thr (or, in mixed
+// precision, when the inner residual fell by delta since the last FP64
+// update), sets stop_at = k + 1; blocks of this launch compare k only, so
+// none of them can observe a change that concerns it.
 template <class SP>
-__global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, int cgls, const CgArgs* table, CgArgs one) {
+__global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* table, CgArgs one, int j) {
   const CgArgs a = table ? table[blockIdx.y] : one;
   SolverState* stt = a.state;
-  if (a.iter >= stt->stop_at) return;
+  const int k = a.iter0 + j;
+  if (k >= stt->stop_at) return;
   using R = typename SP::R;
-  const double nw = sum_partials(a.part_a, a.n_a);
-  const double old = sum_partials(a.part_b, a.n_b);
-  const double rr = cgls ? sum_partials(a.part_c, a.n_c) : nw;
-  bool conv = rr <= a.thr;
+  const int cur = k & 1, nxt = cur ^ 1;
+  const double nw = sum_partials(a.pp[nxt], a.n_pp);
+  const double old = sum_partials(a.pp[cur], a.n_pp);
+  const double rr = a.cgls ? sum_partials(a.pr, a.n_pr) : nw;
+  const bool conv = rr <= a.thr;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    stt->iter = a.iter + 1;
+    stt->iters += 1;
+    stt->last = k;
     stt->rr = rr;
     if (a.mixed) {
       double mx = fmax(stt->maxrr, rr);
       stt->maxrr = mx;
       if (conv || rr < a.delta2 * mx || !(rr == rr)) {
         stt->reason = 2;
-        stt->stop_at = a.iter + 1;
+        stt->stop_at = k + 1;
       }
     } else if (conv || !(rr == rr)) {
       stt->reason = conv ? 1 : 3;
-      stt->stop_at = a.iter + 1;
+      stt->stop_at = k + 1;
     }
   }
   if (conv && !a.mixed) return;
   const R beta = (R)(nw / old);
-  const void* src = cgls ? a.s : a.r;
+  const void* src = a.cgls ? a.s : a.r;
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
     cx<R> p[12], q[12];
     SP::load(a.p, g.stride, s, p);
     SP::load(src, g.stride, s, q);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      p[k].re = fma(beta, p[k].re, q[k].re);
-      p[k].im = fma(beta, p[k].im, q[k].im);
+    for (int m = 0; m < 12; ++m) {
+      p[m].re = fma(beta, p[m].re, q[m].re);
+      p[m].im = fma(beta, p[m].im, q[m].im);
     }
     SP::store(a.p, g.stride, s, p);
   }
 }
 
-// Resume/initialise solver control: stop_at = INT_MAX, iter given, maxrr
-// from a device slot (may be null -> 0).
-__global__ void k_state_reset(SolverState* st, int iter, const double* maxrr, int nbatch) {
+// Start or resume a solve: stop_at = INT_MAX, reason = 0, maxrr from a
+// device slot (null -> 0); the iteration count is cleared on request.
+__global__ void k_state_reset(SolverState* st, const double* maxrr, int nbatch, int reset_iters) {
   int k = blockIdx.x * kBlock + threadIdx.x;
   if (k >= nbatch) return;
   st[k].stop_at = INT_MAX;
   st[k].reason = 0;
-  st[k].iter = iter;
+  if (reset_iters) {
+    st[k].iters = 0;
+    st[k].last = -1;
+    st[k].rr = 0.0;
+  }
   st[k].maxrr = maxrr ? maxrr[k] : 0.0;
 }
 
@@ -366,34 +380,34 @@ hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x
 }
 
 hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
-                            int nbatch, hipStream_t st) {
+                            int nbatch, int j, hipStream_t st) {
   TimedScope ts(TK_CG_BLAS, st, 0);
   dim3 grid(nb, nbatch), block(kBlock);
   switch (prec) {
-    case HMC_F64: hipLaunchKernelGGL((k_cg_update<SpF64, SpF64>), grid, block, 0, st, to_lat(g), table, a); break;
-    case HMC_F32: hipLaunchKernelGGL((k_cg_update<SpF32, SpF32>), grid, block, 0, st, to_lat(g), table, a); break;
-    case HMC_F16: hipLaunchKernelGGL((k_cg_update<SpF16, SpF32>), grid, block, 0, st, to_lat(g), table, a); break;
-    case HMC_BF16: hipLaunchKernelGGL((k_cg_update<SpBF16, SpF32>), grid, block, 0, st, to_lat(g), table, a); break;
+    case HMC_F64: hipLaunchKernelGGL((k_cg_update<SpF64, SpF64>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F32: hipLaunchKernelGGL((k_cg_update<SpF32, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F16: hipLaunchKernelGGL((k_cg_update<SpF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_BF16: hipLaunchKernelGGL((k_cg_update<SpBF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, int cgls, const CgArgs& a, int nb,
-                             const CgArgs* table, int nbatch, hipStream_t st) {
+hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
+                             int nbatch, int j, hipStream_t st) {
   TimedScope ts(TK_CG_BLAS, st, 0);
   dim3 grid(nb, nbatch), block(kBlock);
   switch (prec) {
-    case HMC_F64: hipLaunchKernelGGL(k_cg_pupdate<SpF64>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
-    case HMC_F32: hipLaunchKernelGGL(k_cg_pupdate<SpF32>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
-    case HMC_F16: hipLaunchKernelGGL(k_cg_pupdate<SpF16>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
-    case HMC_BF16: hipLaunchKernelGGL(k_cg_pupdate<SpBF16>, grid, block, 0, st, to_lat(g), cgls, table, a); break;
+    case HMC_F64: hipLaunchKernelGGL(k_cg_pupdate<SpF64>, grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F32: hipLaunchKernelGGL(k_cg_pupdate<SpF32>, grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F16: hipLaunchKernelGGL(k_cg_pupdate<SpF16>, grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_BF16: hipLaunchKernelGGL(k_cg_pupdate<SpBF16>, grid, block, 0, st, to_lat(g), table, a, j); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_state_reset(SolverState* st_dev, int iter, const double* maxrr, int nbatch, hipStream_t st) {
-  hipLaunchKernelGGL(k_state_reset, dim3(ceil_div(nbatch, kBlock)), dim3(kBlock), 0, st, st_dev, iter, maxrr,
-                     nbatch);
+hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, hipStream_t st) {
+  hipLaunchKernelGGL(k_state_reset, dim3(ceil_div(nbatch, kBlock)), dim3(kBlock), 0, st, st_dev, maxrr, nbatch,
+                     reset_iters);
   return hipGetLastError();
 }
 

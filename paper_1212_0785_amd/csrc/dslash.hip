@@ -89,7 +89,7 @@ __device__ __forceinline__ void hop_dir(const Lat& g, const Site& st, int out_pa
 template <class SP, class LK, bool DAG, int EPI, bool BATCH>
 __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int out_par,
                                                                     const DslashArgs* __restrict__ table,
-                                                                    DslashArgs one) {
+                                                                    DslashArgs one, int j) {
   using R = typename SP::R;
   const DslashArgs* ep;
   if constexpr (BATCH)
@@ -97,7 +97,8 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
   else
     ep = &one;
   const DslashArgs& e = *ep;
-  if (e.stop_at && e.iter >= *(const HMC_GLOBAL int*)e.stop_at) return;
+  const int label = e.iter0 + j;
+  if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int s = b * kBlock + threadIdx.x;
   double nrm[1] = {0.0};
@@ -129,13 +130,14 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
   }
   if (EPI == EPI_AXPY_NORM) {
     block_sum<1>(nrm);
-    if (threadIdx.x == 0) ((HMC_GLOBAL double*)e.partial)[b] = nrm[0];
+    double* dst = e.partial_pp[0] ? e.partial_pp[(label + 1) & 1] : e.partial;
+    if (threadIdx.x == 0) ((HMC_GLOBAL double*)dst)[b] = nrm[0];
   }
 }
 
 template <class SP, class LK>
 static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_par, const DslashArgs* table,
-                               int nbatch, const DslashArgs& one, hipStream_t st) {
+                               int nbatch, const DslashArgs& one, hipStream_t st, int j) {
   Lat g;
   for (int k = 0; k < 4; ++k) g.L[k] = ga.L[k];
   g.Vh = ga.Vh;
@@ -144,9 +146,9 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
 #define HMC_DS(D, E)                                                                                    \
   do {                                                                                                 \
     if (table)                                                                                         \
-      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one);  \
+      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one, j);  \
     else                                                                                               \
-      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one); \
+      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one, j); \
   } while (0)
   if (dagger) {
     if (epi == EPI_PLAIN) HMC_DS(true, EPI_PLAIN);
@@ -162,7 +164,7 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
 }
 
 hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,
-                         int nbatch, const DslashArgs& one, hipStream_t st) {
+                         int nbatch, const DslashArgs& one, hipStream_t st, int j) {
   // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for y)
   double site_bytes = 0;
   switch (prec) {
@@ -173,10 +175,10 @@ hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, in
   }
   TimedScope ts(TK_DSLASH, st, site_bytes * g.Vh * nbatch);
   switch (prec) {
-    case HMC_F64: return launch_typed<SpF64, LkF64>(dagger, epi, g, out_par, table, nbatch, one, st);
-    case HMC_F32: return launch_typed<SpF32, LkF32>(dagger, epi, g, out_par, table, nbatch, one, st);
-    case HMC_F16: return launch_typed<SpF16, LkF16>(dagger, epi, g, out_par, table, nbatch, one, st);
-    case HMC_BF16: return launch_typed<SpBF16, LkBF16>(dagger, epi, g, out_par, table, nbatch, one, st);
+    case HMC_F64: return launch_typed<SpF64, LkF64>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+    case HMC_F32: return launch_typed<SpF32, LkF32>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+    case HMC_F16: return launch_typed<SpF16, LkF16>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+    case HMC_BF16: return launch_typed<SpBF16, LkBF16>(dagger, epi, g, out_par, table, nbatch, one, st, j);
   }
   return hipErrorInvalidValue;
 }

@@ -198,7 +198,7 @@ hipError_t read_slots(Fields* F, int first, int n, double* out, hipStream_t st) 
 
 hipError_t dslash_f64(Fields* F, void* out, const void* in, int out_par, int dag, int epi, const void* y, double a,
                       double b, double* partial, const int* stop_at, int iter, hipStream_t st) {
-  DslashArgs d;
+  DslashArgs d{};
   d.U = F->U;
   d.in = in;
   d.out = out;
@@ -207,7 +207,7 @@ hipError_t dslash_f64(Fields* F, void* out, const void* in, int out_par, int dag
   d.b = b;
   d.partial = partial;
   d.stop_at = stop_at;
-  d.iter = iter;
+  d.iter0 = iter;
   return launch_dslash(HMC_F64, dag, epi, F->g, out_par, nullptr, 1, d, st);
 }
 

@@ -38,13 +38,17 @@ inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 // p-update kernel writes it, and only with a value > k, so blocks of the
 // same launch never observe a change that concerns them.
 struct SolverState {
-  int stop_at;   // INT_MAX while running
-  int reason;    // 1 converged, 2 reliable update requested
-  int iter;      // iterations completed
-  int pad;
+  int stop_at;   // iteration label at which kernels stop (INT_MAX while running)
+  int reason;    // 1 converged, 2 reliable update requested, 3 non-finite
+  int iters;     // iterations completed
+  int last;      // label of the last completed iteration
   double rr;     // last residual norm^2 seen by the p-update
   double maxrr;  // mixed precision: max inner |r|^2 since the last update
 };
+
+// Iteration labels: a solver iteration carries the label iter0 + j, where
+// iter0 is fixed per solve (per batch entry) and j is passed with each
+// launch.  Ping-pong partial buffers are chosen by the parity of the label.
 
 // One Dslash application (one batch entry).
 struct DslashArgs {
@@ -54,15 +58,16 @@ struct DslashArgs {
   const void* y;        // epilogue addend on the output parity (may be null)
   double a, b;          // out = a*y + b*(D in) for the AXPY epilogues
   double* partial;      // per-block |out|^2 for the NORM epilogue
+  double* partial_pp[2];  // if set: partial_pp[(label + 1) & 1] instead
   const int* stop_at;   // solver control (may be null)
-  int iter;             // iteration index compared with *stop_at
+  int iter0;            // label offset compared with *stop_at
 };
 
 enum Epilogue { EPI_PLAIN = 0, EPI_AXPY = 1, EPI_AXPY_NORM = 2 };
 
 // Launchers (defined in the .hip files).  All return hipGetLastError().
 hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,
-                         int nbatch, const DslashArgs& one, hipStream_t st);
+                         int nbatch, const DslashArgs& one, hipStream_t st, int j = 0);
 
 // Layout conversion between canonical AoS complex128 (device) and SoA.
 hipError_t launch_pack_gauge(const LatArg& g, const void* canon, void* U, hipStream_t st);
@@ -102,13 +107,13 @@ struct CgArgs {
   void* r;
   const void* q;   // operator applied to p
   const void* s;   // CGLS: Mhat^dag r
-  const double* part_a;  // partial sums read (see kernels)
-  const double* part_b;
-  const double* part_c;
-  double* part_out;
-  int n_a, n_b, n_c;
+  double* pp[2];   // ping-pong partials: CG |r|^2 (n_pp = blas blocks), CGLS |s|^2 (site blocks)
+  double* pq;      // CG <p, A p> = |Mhat p|^2, CGLS |q|^2 (site blocks, from the Dslash epilogue)
+  double* pr;      // CGLS |r|^2 written by the update (blas blocks)
+  int n_pp, n_pq, n_pr;
   SolverState* state;
-  int iter;
+  int iter0;       // label offset
+  int cgls;
   double thr;      // convergence threshold on |r|^2
   double delta2;   // mixed precision: reliable-update trigger (delta^2)
   int mixed;       // 1: never declare convergence, pause instead
@@ -116,10 +121,12 @@ struct CgArgs {
 hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x, void* r, void* p, double* part,
                           int nb, hipStream_t st);
 hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
-                            int nbatch, hipStream_t st);
-hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, int cgls, const CgArgs& a, int nb,
-                             const CgArgs* table, int nbatch, hipStream_t st);
-hipError_t launch_state_reset(SolverState* st_dev, int iter, const double* maxrr, int nbatch, hipStream_t st);
+                            int nbatch, int j, hipStream_t st);
+hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
+                             int nbatch, int j, hipStream_t st);
+// state[k].stop_at = INT_MAX, reason = 0; iters kept unless reset_iters;
+// maxrr from maxrr[k] (may be null -> 0).
+hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, hipStream_t st);
 hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st);  // x += xl; xl = 0
 
 // Gauge-field kernels.

@@ -7,14 +7,15 @@
 //    Schur complement bhat_e = b_e + kappa D_eo b_o, x_o = b_o + kappa D_oe x_e.
 //  * Mixed precision: the same iteration on FP32 / FP16 / BF16 storage with
 //    FP32 arithmetic and FP64 global sums; whenever the inner residual has
-//    fallen by reliable_delta since the last update, x is folded into the
-//    FP64 solution and the residual replaced by the FP64 true residual
-//    (reliable updates, Clark et al., Comput. Phys. Commun. 181 (2010) 1517).
+//    fallen by reliable_delta since the last update, the inner solution is
+//    folded into the FP64 solution and the residual replaced by the FP64
+//    true residual (reliable updates, Clark et al., Comput. Phys. Commun.
+//    181 (2010) 1517); the search direction is kept.
 //
-// Each iteration is a fixed sequence of kernels on one stream with every
-// scalar (alpha, beta, the stop test) computed on the device.  The host
-// enqueues chunks of iterations and reads the 32-byte solver state once per
-// chunk; iterations enqueued after the stop are no-ops (stop_at).
+// An iteration is six launches on one stream (four Dslash, two vector
+// kernels) with alpha, beta and the stop test computed on the device.  The
+// host enqueues chunks of iterations and reads the 32-byte solver state once
+// per chunk; iterations enqueued after the stop exit at once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,138 +25,179 @@
 #include <cstring>
 
 #include "fields.h"
+#include "solver.h"
 
 namespace hmc {
 
 namespace {
-
 constexpr int kChunk = 16;
 constexpr int kMaxReliable = 2000;  // a solve that needs more has stagnated
+}  // namespace
 
-struct Ctx {
-  Fields* F;
-  hipStream_t st;
-  int nbD, nbR;
-};
+void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, double delta2, IterArgs* o) {
+  const double k2 = v.kappa * v.kappa;
+  DslashArgs b{};
+  b.U = v.Ulow;
+  b.stop_at = &v.state->stop_at;
+  b.iter0 = iter0;
+  b.a = 1.0;
+  b.b = 1.0;
+  for (int i = 0; i < 4; ++i) o->d[i] = b;
+  if (!v.cgls) {
+    // t = D_oe p;  s = p - k^2 D_eo t (|s|^2 = <p, A p>);  t = D^dag_oe s;  q = s - k^2 D^dag_eo t
+    o->d[0].in = v.p, o->d[0].out = v.t;
+    o->d[1].in = v.t, o->d[1].out = v.s, o->d[1].y = v.p, o->d[1].b = -k2, o->d[1].partial = v.pq;
+    o->d[2].in = v.s, o->d[2].out = v.t;
+    o->d[3].in = v.t, o->d[3].out = v.q, o->d[3].y = v.s, o->d[3].b = -k2;
+  } else {
+    // t = D_oe p;  q = p - k^2 D_eo t (|q|^2);  [update];  t = D^dag_oe r;  s = r - k^2 D^dag_eo t (|s|^2)
+    o->d[0].in = v.p, o->d[0].out = v.t;
+    o->d[1].in = v.t, o->d[1].out = v.q, o->d[1].y = v.p, o->d[1].b = -k2, o->d[1].partial = v.pq;
+    o->d[2].in = v.r, o->d[2].out = v.t;
+    o->d[3].in = v.t, o->d[3].out = v.s, o->d[3].y = v.r, o->d[3].b = -k2;
+    o->d[3].partial_pp[0] = v.pp[0];
+    o->d[3].partial_pp[1] = v.pp[1];
+  }
+  CgArgs c{};
+  c.x = v.xl;
+  c.p = v.p;
+  c.r = v.r;
+  c.q = v.q;
+  c.s = v.s;
+  c.pp[0] = v.pp[0];
+  c.pp[1] = v.pp[1];
+  c.pq = v.pq;
+  c.pr = v.pr;
+  c.n_pp = v.cgls ? v.nbD : v.nbR;
+  c.n_pq = v.nbD;
+  c.n_pr = v.nbR;
+  c.state = v.state;
+  c.iter0 = iter0;
+  c.cgls = v.cgls;
+  c.thr = thr;
+  c.delta2 = delta2;
+  c.mixed = mixed;
+  o->c[0] = c;
+  o->c[1] = c;
+}
 
-// Vectors of one iteration family (FP64 or low precision).
-struct Vecs {
-  hmc_prec prec;
-  const void* U;
-  void *x, *r, *p, *q, *s, *t;
-};
+hipError_t launch_iteration(const LatArg& g, hmc_prec prec, int cgls, const IterTables* tab, const IterArgs& one,
+                            int nbatch, int nbD, int nbR, int j, hipStream_t st) {
+  (void)nbD;
+  hipError_t e;
+  auto D = [&](int i, int out_par, int dag, int epi) {
+    return launch_dslash(prec, dag, epi, g, out_par, tab ? tab->d[i] : nullptr, nbatch, one.d[i], st, j);
+  };
+  auto UPD = [&](int i) { return launch_cg_update(g, prec, one.c[i], nbR, tab ? tab->c[i] : nullptr, nbatch, j, st); };
+  auto PUP = [&](int i) { return launch_cg_pupdate(g, prec, one.c[i], nbR, tab ? tab->c[i] : nullptr, nbatch, j, st); };
+  if (!cgls) {
+    if ((e = D(0, 1, 0, EPI_PLAIN))) return e;
+    if ((e = D(1, 0, 0, EPI_AXPY_NORM))) return e;
+    if ((e = D(2, 1, 1, EPI_PLAIN))) return e;
+    if ((e = D(3, 0, 1, EPI_AXPY))) return e;
+    if ((e = UPD(0))) return e;
+    return PUP(1);
+  }
+  if ((e = D(0, 1, 0, EPI_PLAIN))) return e;
+  if ((e = D(1, 0, 0, EPI_AXPY_NORM))) return e;
+  if ((e = UPD(0))) return e;
+  if ((e = D(2, 1, 1, EPI_PLAIN))) return e;
+  if ((e = D(3, 0, 1, EPI_AXPY_NORM))) return e;
+  return PUP(1);
+}
 
-hipError_t ds(const Ctx& c, const Vecs& v, void* out, const void* in, int out_par, int dag, int epi, const void* y,
-              double a, double b, double* partial, int iter) {
-  DslashArgs d;
-  d.U = v.U;
+static hipError_t ds64(const SolveVecs& v, void* out, const void* in, int out_par, int dag, int epi, const void* y,
+                       double a, double b, double* partial, hipStream_t st) {
+  DslashArgs d{};
+  d.U = v.U64;
   d.in = in;
   d.out = out;
   d.y = y;
   d.a = a;
   d.b = b;
   d.partial = partial;
-  d.stop_at = &c.F->state->stop_at;
-  d.iter = iter;
-  return launch_dslash(v.prec, dag, epi, c.F->g, out_par, nullptr, 1, d, c.st);
+  return launch_dslash(HMC_F64, dag, epi, v.g, out_par, nullptr, 1, d, st, 0);
 }
 
-// out = Mhat(dag) in with |out|^2 partials when `partial` is set.
-hipError_t mhat(const Ctx& c, const Vecs& v, void* out, const void* in, int dag, double* partial, int iter) {
-  hipError_t e = ds(c, v, v.t, in, 1, dag, EPI_PLAIN, nullptr, 0.0, 1.0, nullptr, iter);
+hipError_t mhat64(const SolveVecs& v, void* out, const void* in, int dag, double* partial, hipStream_t st) {
+  hipError_t e = ds64(v, v.t64, in, 1, dag, EPI_PLAIN, nullptr, 0.0, 1.0, nullptr, st);
   if (e != hipSuccess) return e;
-  const double k2 = c.F->kappa * c.F->kappa;
-  return ds(c, v, out, v.t, 0, dag, partial ? EPI_AXPY_NORM : EPI_AXPY, in, 1.0, -k2, partial, iter);
+  return ds64(v, out, v.t64, 0, dag, partial ? EPI_AXPY_NORM : EPI_AXPY, in, 1.0, -v.kappa * v.kappa, partial, st);
 }
 
-struct Parts {
-  double* a[2];  // ping-pong: CG |r|^2 (nbR) / CGLS |s|^2 (nbD)
-  double* q;     // CG <p,Ap> = |Mhat p|^2 (nbD) / CGLS |q|^2 (nbD)
-  double* r;     // CGLS |r|^2 (nbR)
-};
-
-// One iteration (index k) of CG (cgls=0) or CGLS (cgls=1).
-hipError_t iterate(const Ctx& c, const Vecs& v, const Parts& P, int cgls, int k, double thr, int mixed,
-                   double delta2) {
+hipError_t true_residual(const SolveVecs& v, hipStream_t st) {
   hipError_t e;
-  const int cur = k & 1, nxt = cur ^ 1;
-  CgArgs u{};
-  u.state = c.F->state;
-  u.iter = k;
-  u.thr = thr;
-  u.mixed = mixed;
-  u.delta2 = delta2;
-  if (!cgls) {
-    // s = Mhat p (|s|^2 = <p, A p>), q = Mhat^dag s
-    if ((e = mhat(c, v, v.s, v.p, 0, P.q, k))) return e;
-    if ((e = mhat(c, v, v.q, v.s, 1, nullptr, k))) return e;
-    u.x = v.x;
-    u.p = v.p;
-    u.r = v.r;
-    u.q = v.q;
-    u.part_a = P.a[cur];
-    u.n_a = c.nbR;
-    u.part_b = P.q;
-    u.n_b = c.nbD;
-    u.part_out = P.a[nxt];
-    if ((e = launch_cg_update(c.F->g, v.prec, u, c.nbR, nullptr, 1, c.st))) return e;
-    u.part_a = P.a[nxt];
-    u.n_a = c.nbR;
-    u.part_b = P.a[cur];
-    u.n_b = c.nbR;
-    return launch_cg_pupdate(c.F->g, v.prec, 0, u, c.nbR, nullptr, 1, c.st);
+  if (v.cgls) {
+    if ((e = mhat64(v, v.q64, v.x, 0, nullptr, st))) return e;
+  } else {
+    if ((e = mhat64(v, v.s64, v.x, 0, nullptr, st))) return e;
+    if ((e = mhat64(v, v.q64, v.s64, 1, nullptr, st))) return e;
   }
-  // q = Mhat p, |q|^2 ; x += alpha p ; r -= alpha q ; s = Mhat^dag r ; p = s + beta p
-  if ((e = mhat(c, v, v.q, v.p, 0, P.q, k))) return e;
-  u.x = v.x;
-  u.p = v.p;
-  u.r = v.r;
-  u.q = v.q;
-  u.s = v.s;
-  u.part_a = P.a[cur];
-  u.n_a = c.nbD;
-  u.part_b = P.q;
-  u.n_b = c.nbD;
-  u.part_out = P.r;
-  if ((e = launch_cg_update(c.F->g, v.prec, u, c.nbR, nullptr, 1, c.st))) return e;
-  if ((e = mhat(c, v, v.s, v.r, 1, P.a[nxt], k))) return e;
-  u.part_a = P.a[nxt];
-  u.n_a = c.nbD;
-  u.part_b = P.a[cur];
-  u.n_b = c.nbD;
-  u.part_c = P.r;
-  u.n_c = c.nbR;
-  return launch_cg_pupdate(c.F->g, v.prec, 1, u, c.nbR, nullptr, 1, c.st);
+  if ((e = launch_xmy_norm(v.g, v.rhs, v.q64, v.r64, v.red, v.nbR, st))) return e;
+  return launch_finalize(v.red, v.nbR, 1, v.slot, 1.0, 0, st);
 }
 
-hipError_t read_state(const Ctx& c, SolverState* out) {
-  hipError_t e = hipMemcpyAsync(c.F->pinned + SL_COUNT, c.F->state, sizeof(SolverState), hipMemcpyDeviceToHost, c.st);
+hipError_t reliable_update(const SolveVecs& v, hipStream_t st) {
+  hipError_t e = launch_add_low_to_f64(v.g, v.x, v.xl, st);
   if (e != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
-  std::memcpy(out, c.F->pinned + SL_COUNT, sizeof(SolverState));
+  return true_residual(v, st);
+}
+
+hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st) {
+  hipError_t e;
+  const size_t lowbytes = (size_t)v.g.Vh * (v.prec == HMC_F32 ? 96 : v.prec == HMC_F16 ? 52 : 48);
+  if ((e = launch_convert_spinor(v.g, v.r64, HMC_F64, v.r, v.prec, 1, nullptr, nullptr, st))) return e;
+  double* part = v.pp[k & 1];
+  if (v.cgls) {
+    DslashArgs d{};
+    d.U = v.Ulow;
+    d.in = v.r;
+    d.out = v.t;
+    d.a = 1.0;
+    d.b = 1.0;
+    if ((e = launch_dslash(v.prec, 1, EPI_PLAIN, v.g, 1, nullptr, 1, d, st, 0))) return e;
+    d.in = v.t;
+    d.out = v.s;
+    d.y = v.r;
+    d.b = -v.kappa * v.kappa;
+    d.partial = part;
+    if ((e = launch_dslash(v.prec, 1, EPI_AXPY_NORM, v.g, 0, nullptr, 1, d, st, 0))) return e;
+    if (first && (e = launch_copy(v.p, v.s, lowbytes, st))) return e;
+  } else {
+    if ((e = launch_norm2_partials(v.g, v.prec, v.r, part, v.nbR, st))) return e;
+    if (first && (e = launch_copy(v.p, v.r, lowbytes, st))) return e;
+  }
+  if (first && (e = launch_zero(v.xl, (size_t)v.g.Vh * 96, st))) return e;
+  return launch_state_reset(v.state, v.slot, 1, first ? 1 : 0, st);
+}
+
+namespace {
+
+hipError_t read_state(Fields* F, SolverState* out, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(F->pinned + SL_COUNT, F->state, sizeof(SolverState), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  std::memcpy(out, F->pinned + SL_COUNT, sizeof(SolverState));
   return hipSuccess;
 }
 
-hipError_t reduce_to_host(const Ctx& c, const double* part, int n, double* out) {
-  hipError_t e = launch_finalize(part, n, 1, c.F->slots + SL_SOLVER, 1.0, 0, c.st);
-  if (e != hipSuccess) return e;
-  return read_slots(c.F, SL_SOLVER, 1, out, c.st);
-}
-
-// Runs iterations k0.. until the device stops (converged / reliable update
-// requested) or `limit` iterations in total.  Returns the state.
-hipError_t run_until_stop(const Ctx& c, const Vecs& v, const Parts& P, int cgls, int* k, int limit, double thr,
-                          int mixed, double delta2, SolverState* stt) {
+// Runs iterations with labels *k.. until the device stops or `limit` is
+// reached; leaves the next label in *k.
+hipError_t run_until_stop(Fields* F, const SolveVecs& v, const IterArgs& args, int* k, int limit, SolverState* stt,
+                          hipStream_t st) {
   while (*k < limit) {
-    int n = std::min(kChunk, limit - *k);
+    const int n = std::min(kChunk, limit - *k);
     for (int j = 0; j < n; ++j) {
-      hipError_t e = iterate(c, v, P, cgls, *k + j, thr, mixed, delta2);
+      hipError_t e = launch_iteration(v.g, v.prec, v.cgls, nullptr, args, 1, v.nbD, v.nbR, *k + j, st);
       if (e != hipSuccess) return e;
     }
-    hipError_t e = read_state(c, stt);
+    hipError_t e = read_state(F, stt, st);
     if (e != hipSuccess) return e;
-    *k = stt->iter;
-    if (stt->stop_at != INT_MAX) return hipSuccess;
+    if (stt->stop_at != INT_MAX) {
+      *k = stt->last + 1;
+      return hipSuccess;
+    }
+    *k += n;
   }
   return hipSuccess;
 }
@@ -175,93 +217,94 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   HMC_REQUIRE(x != b, "x and b must not alias");
   auto t0 = std::chrono::steady_clock::now();
   const int cgls = prm->mode == HMC_CG_WILSON_SOLVE;
-  Ctx c{F, st, F->nbD, F->nbR};
-  const double tol = prm->tol;
   const int fixed = prm->fixed_iters;
   const int limit = fixed > 0 ? fixed : prm->maxiter;
   const double delta = prm->reliable_delta > 0 ? prm->reliable_delta : 0.1;
-  Parts P{{F->part[0], F->part[1]}, F->part[2], F->part[3]};
-  Vecs v64{HMC_F64, F->U, x, F->r, F->p, F->q, F->s, F->t};
+  if (prec != HMC_F64) CHK(ensure_lowprec(F, prec, st));
+
+  SolveVecs v{};
+  v.g = F->g;
+  v.kappa = F->kappa;
+  v.cgls = cgls;
+  v.prec = prec;
+  v.U64 = F->U;
+  v.Ulow = low_links(F, prec);
+  v.x = x;
+  v.r64 = F->r;
+  v.rhs = cgls ? F->bhat : const_cast<void*>(b);
+  v.q64 = F->q;
+  v.s64 = F->s;
+  v.t64 = F->t;
+  if (prec == HMC_F64) {
+    v.r = F->r, v.p = F->p, v.q = F->q, v.s = F->s, v.t = F->t, v.xl = x;
+  } else {
+    v.r = F->lr, v.p = F->lp, v.q = F->lq, v.s = F->ls, v.t = F->lt, v.xl = F->lx;
+  }
+  v.pp[0] = F->part[0];
+  v.pp[1] = F->part[1];
+  v.pq = F->part[2];
+  v.pr = F->part[3];
+  v.red = F->part[4];
+  v.slot = F->slots + SL_SOLVER;
+  v.state = F->state;
+  v.nbD = F->nbD;
+  v.nbR = F->nbR;
   hmc_cg_stats S{};
 
-  // ---- set-up in FP64: b_norm2, the right-hand side rhs (b or bhat), x = 0, r = rhs
+  // ---- set-up in FP64: |b|^2, the even right-hand side, x = 0, r = rhs
   const char* bb = (const char*)b;
-  double bnorm2 = 0;
-  const void* rhs = b;
+  double bnorm2 = 0, rr0 = 0;
   if (cgls) {
-    CHK(launch_norm2_partials(F->g, HMC_F64, bb, F->part[4], F->nbR, st));
-    CHK(launch_norm2_partials(F->g, HMC_F64, bb + F->half64, F->part[4] + F->nbR, F->nbR, st));
-    CHK(reduce_to_host(c, F->part[4], 2 * F->nbR, &bnorm2));
+    CHK(launch_norm2_partials(F->g, HMC_F64, bb, v.red, F->nbR, st));
+    CHK(launch_norm2_partials(F->g, HMC_F64, bb + F->half64, v.red + F->nbR, F->nbR, st));
+    CHK(launch_finalize(v.red, 2 * F->nbR, 1, v.slot, 1.0, 0, st));
+    CHK(read_slots(F, SL_SOLVER, 1, &bnorm2, st));
     // bhat_e = b_e + kappa D_eo b_o
     CHK(dslash_f64(F, F->bhat, bb + F->half64, 0, 0, EPI_AXPY, bb, 1.0, F->kappa, nullptr, nullptr, 0, st));
-    rhs = F->bhat;
   }
-  double rr0 = 0;
-  CHK(launch_cg_init(F->g, HMC_F64, rhs, x, F->r, F->p, P.a[0], F->nbR, st));
-  CHK(reduce_to_host(c, P.a[0], F->nbR, &rr0));
+  CHK(launch_cg_init(F->g, HMC_F64, v.rhs, x, v.r64, prec == HMC_F64 ? v.p : v.q64, v.pp[0], F->nbR, st));
+  CHK(launch_finalize(v.pp[0], F->nbR, 1, v.slot, 1.0, 0, st));
+  CHK(read_slots(F, SL_SOLVER, 1, &rr0, st));
   if (!cgls) bnorm2 = rr0;
-  const double thr = fixed > 0 ? -1.0 : tol * tol * bnorm2;
+  const double thr = fixed > 0 ? -1.0 : prm->tol * prm->tol * bnorm2;
 
   int k = 0;
   SolverState stt{};
+  stt.rr = rr0;
   hmc_status status = HMC_OK;
-  if (bnorm2 == 0.0) {
-    // x = 0 solves it exactly
+  if (bnorm2 == 0.0 || (fixed == 0 && rr0 <= thr)) {
+    // x = 0 already meets the tolerance
   } else if (prec == HMC_F64) {
-    CHK(launch_state_reset(F->state, 0, nullptr, 1, st));
     if (cgls) {
-      // s = Mhat^dag r, p = s, |s|^2 -> P.a[0]
-      CHK(mhat(c, v64, F->s, F->r, 1, P.a[0], 0));
-      CHK(launch_copy(F->p, F->s, F->half64, st));
+      CHK(mhat64(v, v.s, v.r, 1, v.pp[0], st));  // s = Mhat^dag r, |s|^2 into pp[0]
+      CHK(launch_copy(v.p, v.s, F->half64, st));
     }
-    if (rr0 > thr) CHK(run_until_stop(c, v64, P, cgls, &k, limit, thr, 0, 0.0, &stt));
-    const double rr_last = k ? stt.rr : rr0;
-    S.rel_res = std::sqrt(rr_last / bnorm2);
-    if (fixed == 0 && !(rr_last <= thr)) status = HMC_E_NOCONV;
+    CHK(launch_state_reset(v.state, nullptr, 1, 1, st));
+    IterArgs args;
+    build_iteration(v, 0, thr, 0, 0.0, &args);
+    CHK(run_until_stop(F, v, args, &k, limit, &stt, st));
+    S.iters = stt.iters;
+    S.rel_res = std::sqrt(stt.rr / bnorm2);
+    if (fixed == 0 && !(stt.rr <= thr)) status = HMC_E_NOCONV;
   } else {
-    // ---- mixed precision with reliable updates
-    CHK(ensure_lowprec(F, prec, st));
-    Vecs vl{prec, low_links(F, prec), F->lx, F->lr, F->lp, F->lq, F->ls, F->lt};
-    // FP64 residual of the current x (x = 0): r64 = rhs, |r64|^2 = rr0
+    IterArgs args;
+    build_iteration(v, 0, thr, 1, delta * delta, &args);
+    CHK(inner_restart(v, 0, true, st));  // the slot holds |r64|^2 = rr0
     double rr64 = rr0;
-    CHK(launch_zero(F->lx, (size_t)F->g.Vh * 96, st));
-    bool first = true;
     while (true) {
-      if (rr64 <= thr) break;
-      if (k >= limit || S.reliable_updates >= kMaxReliable) {
-        status = HMC_E_NOCONV;
-        break;
-      }
-      // r_low = low(r64); CG: p = r (first time); CGLS: s = Mhat^dag r, p = s (first time)
-      CHK(launch_convert_spinor(F->g, F->r, HMC_F64, F->lr, prec, 1, nullptr, nullptr, st));
-      const int cur = k & 1;
-      if (cgls) {
-        CHK(mhat(c, vl, F->ls, F->lr, 1, P.a[cur], k));
-        if (first) CHK(launch_copy(F->lp, F->ls, F->halflow, st));
-      } else {
-        CHK(launch_norm2_partials(F->g, prec, F->lr, P.a[cur], F->nbR, st));
-        if (first) CHK(launch_copy(F->lp, F->lr, F->halflow, st));
-      }
-      first = false;
-      // the last reduction left |r64|^2 in the solver slot: it seeds maxrr
-      CHK(launch_state_reset(F->state, k, F->slots + SL_SOLVER, 1, st));
-      CHK(run_until_stop(c, vl, P, cgls, &k, limit, thr, 1, delta * delta, &stt));
-      // reliable update: x += x_low; r64 = rhs - A x
-      CHK(launch_add_low_to_f64(F->g, x, F->lx, st));
-      if (cgls) {
-        CHK(mhat_f64(F, F->q, x, 0, nullptr, st));
-      } else {
-        CHK(mhat_f64(F, F->s, x, 0, nullptr, st));
-        CHK(mhat_f64(F, F->q, F->s, 1, nullptr, st));
-      }
-      CHK(launch_xmy_norm(F->g, rhs, F->q, F->r, F->part[5], F->nbR, st));
-      CHK(reduce_to_host(c, F->part[5], F->nbR, &rr64));
+      CHK(run_until_stop(F, v, args, &k, limit, &stt, st));
+      CHK(reliable_update(v, st));
+      CHK(read_slots(F, SL_SOLVER, 1, &rr64, st));
       S.reliable_updates++;
-      if (!(rr64 == rr64)) {
+      if (rr64 <= thr) break;
+      if (!(rr64 == rr64) || k >= limit || S.reliable_updates >= kMaxReliable) {
         status = HMC_E_NOCONV;
         break;
       }
+      CHK(inner_restart(v, k, false, st));
     }
+    CHK(read_state(F, &stt, st));
+    S.iters = stt.iters;
     S.rel_res = std::sqrt(rr64 / bnorm2);
   }
 
@@ -269,26 +312,22 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   char* xx = (char*)x;
   double res2 = 0;
   if (cgls) {
-    // x_o = b_o + kappa D_oe x_e
+    // x_o = b_o + kappa D_oe x_e;  r = b - M x on both halves (into tmp)
     CHK(dslash_f64(F, xx + F->half64, xx, 1, 0, EPI_AXPY, bb + F->half64, 1.0, F->kappa, nullptr, nullptr, 0, st));
-    // r = b - M x on both halves (into tmp)
     char* tmp = (char*)F->tmp;
     CHK(dslash_f64(F, tmp, xx + F->half64, 0, 0, EPI_AXPY, xx, 1.0, -F->kappa, nullptr, nullptr, 0, st));
     CHK(dslash_f64(F, tmp + F->half64, xx, 1, 0, EPI_AXPY, xx + F->half64, 1.0, -F->kappa, nullptr, nullptr, 0, st));
-    CHK(launch_xmy_norm(F->g, bb, tmp, tmp, F->part[5], F->nbR, st));
-    CHK(launch_xmy_norm(F->g, bb + F->half64, tmp + F->half64, tmp + F->half64, F->part[5] + F->nbR, F->nbR, st));
-    CHK(reduce_to_host(c, F->part[5], 2 * F->nbR, &res2));
+    CHK(launch_xmy_norm(F->g, bb, tmp, tmp, v.red, F->nbR, st));
+    CHK(launch_xmy_norm(F->g, bb + F->half64, tmp + F->half64, tmp + F->half64, v.red + F->nbR, F->nbR, st));
+    CHK(launch_finalize(v.red, 2 * F->nbR, 1, v.slot, 1.0, 0, st));
   } else {
-    CHK(mhat_f64(F, F->s, x, 0, nullptr, st));
-    CHK(mhat_f64(F, F->q, F->s, 1, nullptr, st));
-    CHK(launch_xmy_norm(F->g, b, F->q, F->tmp, F->part[5], F->nbR, st));
-    CHK(reduce_to_host(c, F->part[5], F->nbR, &res2));
+    CHK(true_residual(v, st));
   }
-  S.iters = k;
+  CHK(read_slots(F, SL_SOLVER, 1, &res2, st));
   S.true_rel_res = bnorm2 > 0 ? std::sqrt(res2 / bnorm2) : 0.0;
   S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = S;
-  if (status == HMC_E_NOCONV) set_error("solver stopped after %d iterations at |r|/|b| = %.3e", k, S.rel_res);
+  if (status == HMC_E_NOCONV) set_error("solver stopped after %d iterations at |r|/|b| = %.3e", S.iters, S.rel_res);
   return status;
 }
 

@@ -68,6 +68,24 @@ class TrajResult(C.Structure):
                [("seconds", C.c_double)]
 
 
+class ServiceParams(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_batch", C.c_int32),
+                ("inner_prec", C.c_int32), ("tol", C.c_double), ("maxiter", C.c_int32), ("manual", C.c_int32),
+                ("chunk", C.c_int32), ("pad", C.c_int32)]
+
+
+class SolveRequest(C.Structure):
+    _fields_ = [("L", C.c_int32 * 4), ("kappa", C.c_double), ("gauge_seed", C.c_uint64), ("gauge_eps", C.c_double),
+                ("source_kind", C.c_int32), ("pad", C.c_int32), ("source_seed", C.c_uint64),
+                ("source_epoch", C.c_uint64), ("out", C.c_void_p)]
+
+
+class SolveResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("reliable_updates", C.c_int32),
+                ("max_group", C.c_int32), ("true_rel_res", C.c_double), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
 class TimingEntry(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double)]
 
@@ -120,6 +138,13 @@ _SIGNATURES = {
     "hmc_cg_solve": (_I32, [_P, _P, _P, C.POINTER(CgParams), C.POINTER(CgStats), _P]),
     "hmc_md_leapfrog": (_I32, [_P, _D, _I32, C.POINTER(CgParams), C.POINTER(MdStats), _P]),
     "hmc_trajectory": (_I32, [_P, _U64, _U64, C.POINTER(TrajParams), C.POINTER(TrajResult), _P]),
+    "hmc_request_bytes": (_I32, [C.POINTER(SolveRequest), _I32, C.POINTER(C.c_size_t)]),
+    "hmc_service_create": (_I32, [C.POINTER(ServiceParams), C.POINTER(_P)]),
+    "hmc_service_submit": (_I32, [_P, C.POINTER(SolveRequest), C.POINTER(_U64)]),
+    "hmc_service_poll": (_I32, [_P, _U64, C.POINTER(SolveResult)]),
+    "hmc_service_wait": (_I32, [_P, _U64, C.POINTER(SolveResult)]),
+    "hmc_service_step": (_I32, [_P, C.POINTER(_I32)]),
+    "hmc_service_destroy": (_I32, [_P]),
     "hmc_timing_enable": (_I32, [_I32]),
     "hmc_timing_reset": (_I32, []),
     "hmc_timing_read": (_I32, [C.POINTER(TimingEntry), _I32, C.POINTER(_I32)]),
@@ -406,6 +431,105 @@ def hmc_timing_read() -> dict:
     check(lib().hmc_timing_read(buf, 16, C.byref(n)))
     return {buf[k].name.decode(): {"launches": buf[k].launches, "total_ms": buf[k].total_ms,
                                    "bytes": buf[k].bytes} for k in range(min(n.value, 16))}
+
+
+# ------------------------------------------------------- solve service
+
+
+def solve_request(L, kappa, gauge_seed, gauge_eps, source_kind=SOURCE_Z2, source_seed=0, source_epoch=0, out=None):
+    r = SolveRequest()
+    for k in range(4):
+        r.L[k] = int(L[k])
+    r.kappa, r.gauge_seed, r.gauge_eps = float(kappa), int(gauge_seed), float(gauge_eps)
+    r.source_kind, r.source_seed, r.source_epoch = int(source_kind), int(source_seed), int(source_epoch)
+    r.out = _ptr(out)
+    return r
+
+
+def hmc_request_bytes(req: SolveRequest, inner_prec: int) -> int:
+    n = C.c_size_t()
+    check(lib().hmc_request_bytes(C.byref(req), inner_prec, C.byref(n)))
+    return n.value
+
+
+class Service:
+    """A solve service over a torch-allocated device arena."""
+
+    def __init__(self, arena_bytes, inner_prec=F32, max_batch=64, tol=1e-10, maxiter=50000, manual=False,
+                 chunk=16, device="cuda"):
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        p = ServiceParams(self.arena.data_ptr(), int(arena_bytes), int(max_batch), int(inner_prec), float(tol),
+                          int(maxiter), int(bool(manual)), int(chunk), 0)
+        h = C.c_void_p()
+        check(lib().hmc_service_create(C.byref(p), C.byref(h)))
+        self.handle = h
+        self.inner_prec = inner_prec
+
+    def submit(self, req: SolveRequest) -> int:
+        t = C.c_uint64()
+        check(lib().hmc_service_submit(self.handle, C.byref(req), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        r = SolveResult()
+        st = lib().hmc_service_poll(self.handle, ticket, C.byref(r))
+        if st == HMC_E_BUSY:
+            return None
+        check(st, allow=(HMC_E_NOCONV,))
+        return struct_dict(r)
+
+    def wait(self, ticket):
+        r = SolveResult()
+        check(lib().hmc_service_wait(self.handle, ticket, C.byref(r)), allow=(HMC_E_NOCONV,))
+        return struct_dict(r)
+
+    def step(self) -> int:
+        n = C.c_int32()
+        check(lib().hmc_service_step(self.handle, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if self.handle:
+            lib().hmc_service_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hmc_service_create(params: ServiceParams):
+    h = C.c_void_p()
+    check(lib().hmc_service_create(C.byref(params), C.byref(h)))
+    return h
+
+
+def hmc_service_submit(svc, req):
+    t = C.c_uint64()
+    check(lib().hmc_service_submit(_h(svc), C.byref(req), C.byref(t)))
+    return t.value
+
+
+def hmc_service_poll(svc, ticket):
+    r = SolveResult()
+    return lib().hmc_service_poll(_h(svc), ticket, C.byref(r)), struct_dict(r)
+
+
+def hmc_service_wait(svc, ticket):
+    r = SolveResult()
+    return lib().hmc_service_wait(_h(svc), ticket, C.byref(r)), struct_dict(r)
+
+
+def hmc_service_step(svc):
+    n = C.c_int32()
+    check(lib().hmc_service_step(_h(svc), C.byref(n)))
+    return n.value
+
+
+def hmc_service_destroy(svc):
+    check(lib().hmc_service_destroy(_h(svc)))
 
 
 # --------------------------------------------------- canonical helpers
