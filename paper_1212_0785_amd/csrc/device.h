@@ -421,6 +421,7 @@ __device__ __forceinline__ uint32_t f_to_bf16(float f) {
 // 32-bit element index, so the compiler emits global loads with a scalar
 // base and a 32-bit vector offset.
 struct SpF64 {
+  static constexpr bool kScaled = false;
   using R = double;
   static constexpr int kBytes = 192;
   __device__ static void load(const void* base, int stride, int s, cx<R>* v) {
@@ -434,9 +435,20 @@ struct SpF64 {
 #pragma unroll
     for (int k = 0; k < 12; ++k) gst<v2d>(base, k * stride + s) = v2d{v[k].re, v[k].im};
   }
+  // component k of site s
+  __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
+    v2d t = gld<v2d>(base, k * stride + s);
+    return {t.x, t.y};
+  }
+  // components 3*part .. 3*part+2 of site s
+  __device__ static void store_part(void* base, int stride, int s, int part, const cx<R>* v) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gst<v2d>(base, (3 * part + c) * stride + s) = v2d{v[c].re, v[c].im};
+  }
 };
 
 struct SpF32 {
+  static constexpr bool kScaled = false;
   using R = float;
   static constexpr int kBytes = 96;
   __device__ static void load(const void* base, int stride, int s, cx<R>* v) {
@@ -450,9 +462,18 @@ struct SpF32 {
 #pragma unroll
     for (int k = 0; k < 12; ++k) gst<v2f>(base, k * stride + s) = v2f{v[k].re, v[k].im};
   }
+  __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
+    v2f t = gld<v2f>(base, k * stride + s);
+    return {t.x, t.y};
+  }
+  __device__ static void store_part(void* base, int stride, int s, int part, const cx<R>* v) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gst<v2f>(base, (3 * part + c) * stride + s) = v2f{v[c].re, v[c].im};
+  }
 };
 
 struct SpF16 {
+  static constexpr bool kScaled = true;
   using R = float;
   static constexpr int kBytes = 52;
   __device__ static void load(const void* base, int stride, int s, cx<R>* v) {
@@ -473,9 +494,24 @@ struct SpF16 {
     for (int k = 0; k < 12; ++k)
       gst<v2h>(base, k * stride + s) = __builtin_convertvector((v2f{v[k].re * inv, v[k].im * inv}), v2h);
   }
+  __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
+    const float f = gld<float>(base, 12 * stride + s);
+    v2f t = __builtin_convertvector(gld<v2h>(base, k * stride + s), v2f);
+    return {t.x * f, t.y * f};
+  }
+  // components 3*part .. 3*part+2 of site s, with the site's max |re|,|im|
+  // m computed by the caller over all 12 components (part 0 writes it)
+  __device__ static void store_part_scaled(void* base, int stride, int s, int part, const cx<R>* v, float m) {
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    if (part == 0) gst<float>(base, 12 * stride + s) = m;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      gst<v2h>(base, (3 * part + c) * stride + s) = __builtin_convertvector((v2f{v[c].re * inv, v[c].im * inv}), v2h);
+  }
 };
 
 struct SpBF16 {
+  static constexpr bool kScaled = false;
   using R = float;
   static constexpr int kBytes = 48;
   __device__ static void load(const void* base, int stride, int s, cx<R>* v) {
@@ -488,6 +524,15 @@ struct SpBF16 {
   __device__ static void store(void* base, int stride, int s, const cx<R>* v) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) gst<uint32_t>(base, k * stride + s) = f_to_bf16(v[k].re) | (f_to_bf16(v[k].im) << 16);
+  }
+  __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
+    uint32_t w = gld<uint32_t>(base, k * stride + s);
+    return {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
+  }
+  __device__ static void store_part(void* base, int stride, int s, int part, const cx<R>* v) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      gst<uint32_t>(base, (3 * part + c) * stride + s) = f_to_bf16(v[c].re) | (f_to_bf16(v[c].im) << 16);
   }
 };
 

@@ -14,6 +14,8 @@
 // contiguous 1 KiB (FP64) span; neighbour spinors are re-read through L2,
 // and the XCD-aware block order keeps the +-y/+-z neighbours of a block on
 // the XCD that owns it.
+#include <cstdlib>
+
 #include "device.h"
 #include "internal.h"
 
@@ -135,6 +137,94 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
   }
 }
 
+// Direction-split variant: a block covers 64 sites; wave w computes the two
+// hops along direction w for those sites and parks its partial sum in LDS;
+// after a barrier each work-item combines the four partials of 3 of the 12
+// components of one site (coalesced stores).  Four times the wavefronts of
+// the one-site-per-work-item kernel at the same registers per work-item,
+// and a quarter of the serial hop chain per wavefront.
+template <class SP, class LK, bool DAG, int EPI, bool BATCH>
+__global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, const DslashArgs* __restrict__ table,
+                                                         DslashArgs one, int j) {
+  using R = typename SP::R;
+  constexpr int kSites = kBlock / 4;
+  __shared__ cx<R> part[4][12][kSites];
+  const DslashArgs* ep;
+  if constexpr (BATCH)
+    ep = table + blockIdx.y;
+  else
+    ep = &one;
+  const DslashArgs& e = *ep;
+  const int label = e.iter0 + j;
+  if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int mu = threadIdx.x >> 6;  // wave index = direction (uniform per wave)
+  const int ls = threadIdx.x & (kSites - 1);
+  const int s = b * kSites + ls;
+  {
+    cx<R> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+    if (s < g.Vh) {
+      const Site st = cb_site(g, out_par, s);
+      switch (mu) {
+        case 0: hop_dir<SP, LK, 0, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+        case 1: hop_dir<SP, LK, 1, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+        case 2: hop_dir<SP, LK, 2, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+        default: hop_dir<SP, LK, 3, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part[mu][k][ls] = acc[k];
+  }
+  __syncthreads();
+  // work-item (ls, mu) now owns components 3*mu .. 3*mu+2 of site s
+  double nrm[1] = {0.0};
+  cx<R> o[3];
+  const bool active = s < g.Vh;
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * mu + c;
+      o[c] = part[0][k][ls] + part[1][k][ls] + part[2][k][ls] + part[3][k][ls];
+    }
+    if (EPI != EPI_PLAIN) {
+      const R a = (R)e.a, bb = (R)e.b;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (e.y) {
+          const cx<R> y = SP::load_one(e.y, g.stride, s, 3 * mu + c);
+          o[c] = {fma(bb, o[c].re, a * y.re), fma(bb, o[c].im, a * y.im)};
+        } else {
+          o[c] = bb * o[c];
+        }
+      }
+    }
+    if (EPI == EPI_AXPY_NORM)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nrm[0] += (double)o[c].re * o[c].re + (double)o[c].im * o[c].im;
+  }
+  if constexpr (SP::kScaled) {
+    // the per-site scale needs the largest |re|, |im| over all 12 components
+    __shared__ float smax[4][kSites];
+    float m = 0.f;
+    if (active)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf((float)o[c].re), fabsf((float)o[c].im)));
+    smax[mu][ls] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(smax[0][ls], smax[1][ls]), fmaxf(smax[2][ls], smax[3][ls]));
+    if (active) SP::store_part_scaled(e.out, g.stride, s, mu, o, m);
+  } else {
+    if (active) SP::store_part(e.out, g.stride, s, mu, o);
+  }
+  if (EPI == EPI_AXPY_NORM) {
+    block_sum<1>(nrm);
+    double* dst = e.partial_pp[0] ? e.partial_pp[(label + 1) & 1] : e.partial;
+    if (threadIdx.x == 0) ((HMC_GLOBAL double*)dst)[b] = nrm[0];
+  }
+}
+
 template <class SP, class LK>
 static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_par, const DslashArgs* table,
                                int nbatch, const DslashArgs& one, hipStream_t st, int j) {
@@ -142,13 +232,19 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   for (int k = 0; k < 4; ++k) g.L[k] = ga.L[k];
   g.Vh = ga.Vh;
   g.stride = ga.stride;
-  dim3 grid(site_blocks(ga.Vh), nbatch), block(kBlock);
-#define HMC_DS(D, E)                                                                                    \
-  do {                                                                                                 \
-    if (table)                                                                                         \
-      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one, j);  \
-    else                                                                                               \
-      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one, j); \
+  const bool split = dslash_split(ga.Vh);
+  dim3 grid(dslash_blocks(ga.Vh), nbatch), block(kBlock);
+#define HMC_DS(D, E)                                                                                           \
+  do {                                                                                                        \
+    if (split) {                                                                                              \
+      if (table)                                                                                              \
+        hipLaunchKernelGGL((k_dslash_split<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one, j);  \
+      else                                                                                                    \
+        hipLaunchKernelGGL((k_dslash_split<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one, j); \
+    } else if (table)                                                                                         \
+      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one, j);         \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one, j);        \
   } while (0)
   if (dagger) {
     if (epi == EPI_PLAIN) HMC_DS(true, EPI_PLAIN);
@@ -161,6 +257,15 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   }
 #undef HMC_DS
   return hipGetLastError();
+}
+
+bool dslash_split(int Vh) {
+  static const int forced = [] {
+    const char* e = getenv("HMC_DSLASH_SPLIT");
+    return e ? atoi(e) : -1;
+  }();
+  if (forced >= 0) return forced != 0;
+  return Vh <= (1 << 17);  // up to 16^3x64: fewer than 2 wavefronts per SIMD otherwise
 }
 
 hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,

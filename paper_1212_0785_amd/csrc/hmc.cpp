@@ -138,7 +138,7 @@ static size_t plan_fields(Fields* F, char* base, const LatArg& g, uint32_t flags
   };
   const int Vh = g.Vh;
   const size_t h64 = half_bytes(Vh, HMC_F64);
-  const int nbD = site_blocks(Vh), nbR = blas_blocks(Vh);
+  const int nbD = dslash_blocks(Vh), nbR = blas_blocks(Vh);
   const int npart = 2 * std::max(nbD, nbR);
   const int nb_multi = std::min(nbR, 1024);
   const size_t multi = (size_t)nb_multi * 2 * 1024 + 1024;

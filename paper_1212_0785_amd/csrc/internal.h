@@ -33,6 +33,13 @@ inline int blas_blocks(int Vh) {
 }
 inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 
+// Dslash kernel shape: one site per work-item (256 sites per block) or the
+// direction-split form (64 sites per block, four wavefronts per group of
+// sites) for volumes too small to fill the GPU with one wavefront per 64
+// sites.  HMC_DSLASH_SPLIT=0/1 (read once) overrides the volume rule.
+bool dslash_split(int Vh);
+inline int dslash_blocks(int Vh) { return dslash_split(Vh) ? ceil_div(Vh, kThreads / 4) : site_blocks(Vh); }
+
 // Iteration control of the Krylov solvers, resident in device memory.
 // Kernels of iteration k do nothing once k >= stop_at.  Only block 0 of the
 // p-update kernel writes it, and only with a value > k, so blocks of the

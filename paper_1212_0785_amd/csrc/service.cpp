@@ -63,7 +63,7 @@ size_t carve_request(char* base, const LatArg& g, int prec, SolveVecs* v, void**
   Carve c(base);
   const int Vh = g.Vh;
   const size_t h64 = half_bytes(Vh, HMC_F64);
-  const int nbD = site_blocks(Vh), nbR = blas_blocks(Vh);
+  const int nbD = dslash_blocks(Vh), nbR = blas_blocks(Vh);
   SolveVecs t{};
   SolveVecs& s = v ? *v : t;
   *U64 = c.take((size_t)Vh * 8 * 144);

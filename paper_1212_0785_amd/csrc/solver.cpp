@@ -182,11 +182,20 @@ hipError_t read_state(Fields* F, SolverState* out, hipStream_t st) {
 }
 
 // Runs iterations with labels *k.. until the device stops or `limit` is
-// reached; leaves the next label in *k.
+// reached; leaves the next label in *k.  After the first chunk the chunk
+// length follows the observed convergence rate toward `target` (|r|^2 at
+// which the device will stop), so few iterations are enqueued past the stop.
+// *rate carries log(|r|^2) per iteration between calls (0 = unknown).
 hipError_t run_until_stop(Fields* F, const SolveVecs& v, const IterArgs& args, int* k, int limit, SolverState* stt,
-                          hipStream_t st) {
+                          hipStream_t st, double rr_start, double target, double* rate) {
+  double rr_now = rr_start;
   while (*k < limit) {
-    const int n = std::min(kChunk, limit - *k);
+    int n = kChunk;
+    if (*rate < 0 && rr_now > 0 && target > 0) {
+      const double left = std::log(target / rr_now) / *rate;
+      if (left < kChunk) n = std::max(1, (int)std::ceil(left));
+    }
+    n = std::min(n, limit - *k);
     for (int j = 0; j < n; ++j) {
       hipError_t e = launch_iteration(v.g, v.prec, v.cgls, nullptr, args, 1, v.nbD, v.nbR, *k + j, st);
       if (e != hipSuccess) return e;
@@ -198,6 +207,8 @@ hipError_t run_until_stop(Fields* F, const SolveVecs& v, const IterArgs& args, i
       return hipSuccess;
     }
     *k += n;
+    if (stt->rr > 0 && rr_now > 0 && stt->rr < rr_now) *rate = std::log(stt->rr / rr_now) / n;
+    rr_now = stt->rr;
   }
   return hipSuccess;
 }
@@ -282,7 +293,8 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
     CHK(launch_state_reset(v.state, nullptr, 1, 1, st));
     IterArgs args;
     build_iteration(v, 0, thr, 0, 0.0, &args);
-    CHK(run_until_stop(F, v, args, &k, limit, &stt, st));
+    double rate = 0;
+    CHK(run_until_stop(F, v, args, &k, limit, &stt, st, rr0, thr, &rate));
     S.iters = stt.iters;
     S.rel_res = std::sqrt(stt.rr / bnorm2);
     if (fixed == 0 && !(stt.rr <= thr)) status = HMC_E_NOCONV;
@@ -290,9 +302,10 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
     IterArgs args;
     build_iteration(v, 0, thr, 1, delta * delta, &args);
     CHK(inner_restart(v, 0, true, st));  // the slot holds |r64|^2 = rr0
-    double rr64 = rr0;
+    double rr64 = rr0, rate = 0;
     while (true) {
-      CHK(run_until_stop(F, v, args, &k, limit, &stt, st));
+      // the inner iteration pauses once |r|^2 < delta^2 max|r|^2 (or <= thr)
+      CHK(run_until_stop(F, v, args, &k, limit, &stt, st, rr64, std::max(thr, delta * delta * rr64), &rate));
       CHK(reliable_update(v, st));
       CHK(read_slots(F, SL_SOLVER, 1, &rr64, st));
       S.reliable_updates++;
