@@ -98,6 +98,7 @@ def bind(path):
         "or_plaquette": (C.c_double, [_I, _P]),
         "or_gauge_action": (C.c_double, [_I, _P, C.c_double]),
         "or_gauge_force": (None, [_I, _P, C.c_double, _P]),
+        "or_gauge_force_sites": (None, [_I, _P, C.c_double, _P, C.c_long, _P]),
         "or_fermion_force": (None, [_I, _P, C.c_double, _P, _P, _P]),
         "or_mat_exp": (None, [_P, _P]),
         "or_reunit": (None, [_P]),
@@ -277,6 +278,15 @@ def gauge_action(L, U, beta):
 def gauge_force(L, U, beta):
     F = gauge_zeros(L)
     _load().or_gauge_force(_dims(L), _ptr(_c128(U)), float(beta), _ptr(F))
+    return F
+
+
+def gauge_force_sites(L, U, beta, sites):
+    """Gauge force at the listed lexicographic sites only -> (n, 4, 3, 3)."""
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    assert U.flags.c_contiguous and U.dtype == np.complex128
+    F = np.zeros((sites.size, 4, 3, 3), np.complex128)
+    _load().or_gauge_force_sites(_dims(L), _ptr(U), float(beta), _ptr(sites), sites.size, _ptr(F))
     return F
 
 

@@ -411,18 +411,29 @@ static void staple_sum(const int *L, const cplx *U, long i, int mu, cplx *A)
 
 /* Gauge force F_g = -(i beta / 12) TA(U_mu(x) A_mu(x)),
  * TA(W) = (W - W^dag) - Tr(W - W^dag)/3. */
+static void gauge_force_link(const int *L, const cplx *U, double beta, long i, int mu, cplx *F9)
+{
+    cplx A[9], W[9], Z[9];
+    staple_sum(L, U, i, mu, A);
+    mat_mul(&U[(i * 4 + mu) * 9], A, W);
+    traceless_antiherm(W, Z);
+    for (int k = 0; k < 9; ++k) F9[k] = -I * beta / 12.0 * Z[k];
+}
+
 void or_gauge_force(const int *L, const cplx *U, double beta, cplx *F)
 {
     long V = vol4(L);
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < V; ++i)
-        for (int mu = 0; mu < 4; ++mu) {
-            cplx A[9], W[9], Z[9];
-            staple_sum(L, U, i, mu, A);
-            mat_mul(&U[(i * 4 + mu) * 9], A, W);
-            traceless_antiherm(W, Z);
-            for (int k = 0; k < 9; ++k) F[(i * 4 + mu) * 9 + k] = -I * beta / 12.0 * Z[k];
-        }
+        for (int mu = 0; mu < 4; ++mu) gauge_force_link(L, U, beta, i, mu, &F[(i * 4 + mu) * 9]);
+}
+
+/* The same force at the listed lexicographic sites only: F[n][4][9]. */
+void or_gauge_force_sites(const int *L, const cplx *U, double beta, const long *sites, long n, cplx *F)
+{
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k)
+        for (int mu = 0; mu < 4; ++mu) gauge_force_link(L, U, beta, sites[k], mu, &F[(k * 4 + mu) * 9]);
 }
 
 /* Wilson fermion force for S_f = phi^dag (Mhat^dag Mhat)^-1 phi.

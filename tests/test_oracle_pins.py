@@ -493,3 +493,23 @@ def test_trajectory_bookkeeping(c1_setup):
     if not acc:
         assert np.array_equal(U1, U)
     assert abs(r["plaquette"] - O.plaquette(L, U1)) == 0
+
+
+def test_site_list_functions_match_full_lattice():
+    """The site-list forms used for sampled checks at large volume agree
+    bit for bit with the full-lattice functions pinned above."""
+    L = (4, 6, 4, 6)
+    V = synth.volume(L)
+    sites = np.array([0, 5, 17, 100, V - 1], dtype=np.int64)
+    U = synth.gauge_field(41, L, eps=0.6)
+    psi = synth.spinor(42, L)
+    full = O.dslash(L, U, psi, -1, 0)
+    assert np.array_equal(O.dslash_sites(L, U, psi, sites), full[sites])
+    fg = O.gauge_force(L, U, 5.6)
+    assert np.array_equal(O.gauge_force_sites(L, U, 5.6, sites), fg[sites])
+    Uw = np.zeros_like(U)
+    O.weak_field_sites(L, 3, 0.3, sites, Uw)
+    assert np.array_equal(Uw[sites], O.weak_field(L, 3, 0.3)[sites])
+    b = np.zeros_like(psi)
+    O.gauss_source_sites(7, 2, sites, b)
+    assert np.array_equal(b[sites], O.source(L, 0, 7, 2)[sites])
