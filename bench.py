@@ -10,6 +10,8 @@ Workloads (--workload):
   cg      24^3x48 kappa 0.157 Wilson solves of Gaussian sources to
           |b - M x| <= 1e-10 |b|: FP64 CGLS against mixed precision
           (FP32, FP16 and BF16 inner storage).
+  copy    a plain 2 GiB device-to-device copy (torch), the calibration
+          kernel for the HBM byte counters (known bytes read and written).
   serve   Poisson stream of Wilson solves over {8^4, 16^3x32, 24^3x48}
           through the continuous-batching service (mixed precision),
           throughput and p50/p99 latency against a one-at-a-time FP64 FIFO
@@ -224,6 +226,35 @@ def run_dslash(args, H, torch):
     return out
 
 
+# ------------------------------------------------------------------- copy
+
+
+def run_copy(args, H, torch):
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(st)
+    for _ in range(args.steps):
+        dst.copy_(src)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    gbps = 2 * nbytes / (ms * 1e-3) / 1e9
+    return {"metric": METRIC, "value": gbps, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "copy_2GiB", "bytes_read": nbytes, "bytes_written": nbytes,
+                       "parallelism": "1 GPU"},
+            "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbps / HBM_PEAK_GBS, "traffic": None, "kernel": "torch copy_",
+                         "avg_launch_ms": ms}}
+
+
 # --------------------------------------------------------------------- CG
 
 
@@ -379,7 +410,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="hmc", choices=["hmc", "dslash", "cg", "serve"])
+    ap.add_argument("--workload", default="hmc", choices=["hmc", "dslash", "cg", "serve", "copy"])
     ap.add_argument("--rho", type=float, default=0.9, help="serve: offered load relative to FP64 FIFO capacity")
     ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
     ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
@@ -390,7 +421,7 @@ def main():
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
-    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (4, 1), "serve": (64, 0)}[args.workload]
+    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (4, 1), "serve": (64, 0), "copy": (20, 2)}[args.workload]
     args.steps = args.steps if args.steps is not None else defaults[0]
     args.warmup = args.warmup if args.warmup is not None else defaults[1]
 
@@ -410,6 +441,8 @@ def main():
         out = run_dslash(args, H, torch)
     elif args.workload == "serve":
         out = run_serve(args, H, torch)
+    elif args.workload == "copy":
+        out = run_copy(args, H, torch)
     else:
         out = run_cg(args, H, torch)
     print(json.dumps(out))

@@ -137,6 +137,9 @@ typedef enum {
   HMC_FIELD_XE = 4   /* even half spinor: last solve of the fermion force */
 } hmc_field_id;
 hmc_status hmc_field_pointer(hmc_fields* f, hmc_field_id which, void** ptr);
+/* Writing U through the HMC_FIELD_GAUGE pointer: call hmc_sync_lowprec
+ * afterwards.  Fetching that pointer switches the hopping kernels to
+ * full-link loads until then (see hmc_links_two_row). */
 
 /* Canonical <-> device layout conversion (both buffers in device memory).
  * Spinors: `parity` 0 or 1 converts one half spinor (export writes zeros on
@@ -154,9 +157,20 @@ hmc_status hmc_export_spinor(hmc_fields* f, void* canon, const void* src, int32_
 /* Convert a half spinor between storage precisions (F64 <-> F32/F16/BF16). */
 hmc_status hmc_convert_spinor(hmc_fields* f, void* dst, hmc_prec dst_prec, const void* src, hmc_prec src_prec,
                               void* stream);
-/* Refresh the F32/F16/BF16 link copies from U (needs HMC_FIELDS_LOWPREC).
- * hmc_cg_solve calls it itself when U changed since the last refresh. */
+/* Re-derive everything the library keeps about U after U was written in
+ * place: checks whether every link's third row equals conj(row0 x row1)
+ * to 1e-14 (then the hopping kernels read two rows per link and rebuild
+ * the third; one reduction, synchronises the stream) and, with
+ * HMC_FIELDS_LOWPREC, refreshes the F32/F16/BF16 link copies (hmc_cg_solve
+ * refreshes those itself when the library changed U). */
 hmc_status hmc_sync_lowprec(hmc_fields* f, void* stream);
+/* *on = 1 if the hopping kernels read two rows per link (U is SU(3) to
+ * rounding: set by hmc_weak_field_start, hmc_exp_update_reunit and the
+ * integrator, which reunitarise, and by the check in hmc_import_gauge /
+ * hmc_sync_lowprec), else 0 (all nine entries are read).  Both forms give
+ * the same operator on SU(3) fields; the two-row form moves 2/3 of the
+ * link bytes. */
+hmc_status hmc_links_two_row(hmc_fields* f, int32_t* on);
 
 /* One half-lattice hop: out = D_{p <- 1-p} in (dagger: D^dag), p =
  * out_parity.  in/out are half spinors of storage `prec`; links come from U

@@ -33,6 +33,18 @@ template <typename T>
 __device__ __forceinline__ const HMC_GLOBAL T& gld(const void* base, unsigned idx) {
   return *(const HMC_GLOBAL T*)((const HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T));
 }
+// Same, with the non-temporal hint (data read once per sweep).
+#ifndef HMC_LINK_NT
+#define HMC_LINK_NT 0
+#endif
+template <typename T>
+__device__ __forceinline__ T gld_link(const void* base, unsigned idx) {
+#if HMC_LINK_NT
+  return __builtin_nontemporal_load((const HMC_GLOBAL T*)((const HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T)));
+#else
+  return gld<T>(base, idx);
+#endif
+}
 template <typename T>
 __device__ __forceinline__ HMC_GLOBAL T& gst(void* base, unsigned idx) {
   return *(HMC_GLOBAL T*)((HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T));
@@ -213,6 +225,16 @@ __device__ __forceinline__ void i_ta_compact(const mat3<R>& W, R c, R* out) {
 
 // Gram-Schmidt projection to SU(3) of rows: normalise row 0, orthogonalise
 // row 1 against it and normalise, row 2 = conj(row0 x row1).
+// Third row of an SU(3) matrix from the first two: conj(row0 x row1)
+// (unitarity with det = 1).  Shared by the reunitarisation and by the
+// two-row link loads, so a reunitarised link is rebuilt bit for bit.
+template <typename R>
+__device__ __forceinline__ void third_row(mat3<R>& u) {
+  u.m[6] = conj(u.m[1] * u.m[5] - u.m[2] * u.m[4]);
+  u.m[7] = conj(u.m[2] * u.m[3] - u.m[0] * u.m[5]);
+  u.m[8] = conj(u.m[0] * u.m[4] - u.m[1] * u.m[3]);
+}
+
 template <typename R>
 __device__ __forceinline__ void reunitarise(mat3<R>& u) {
   R n0 = norm2(u.m[0]) + norm2(u.m[1]) + norm2(u.m[2]);
@@ -228,9 +250,7 @@ __device__ __forceinline__ void reunitarise(mat3<R>& u) {
   n1 = R(1) / sqrt(n1);
 #pragma unroll
   for (int k = 0; k < 3; ++k) u.m[3 + k] = n1 * u.m[3 + k];
-  u.m[6] = conj(u.m[1] * u.m[5] - u.m[2] * u.m[4]);
-  u.m[7] = conj(u.m[2] * u.m[3] - u.m[0] * u.m[5]);
-  u.m[8] = conj(u.m[0] * u.m[4] - u.m[1] * u.m[3]);
+  third_row(u);
 }
 
 // exp(i Q) for traceless Hermitian Q.  With A = iQ traceless, the
@@ -540,12 +560,13 @@ struct SpBF16 {
 struct LkF64 {
   using R = double;
   static constexpr int kBytes = 144;
+  template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2d);
     mat3<R> u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      v2d t = gld<v2d>(p, k * stride + s);
+    for (int k = 0; k < K; ++k) {
+      v2d t = gld_link<v2d>(p, k * stride + s);
       u.m[k] = {t.x, t.y};
     }
     return u;
@@ -560,12 +581,13 @@ struct LkF64 {
 struct LkF32 {
   using R = float;
   static constexpr int kBytes = 72;
+  template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2f);
     mat3<R> u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      v2f t = gld<v2f>(p, k * stride + s);
+    for (int k = 0; k < K; ++k) {
+      v2f t = gld_link<v2f>(p, k * stride + s);
       u.m[k] = {t.x, t.y};
     }
     return u;
@@ -580,12 +602,13 @@ struct LkF32 {
 struct LkF16 {
   using R = float;
   static constexpr int kBytes = 36;
+  template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2h);
     mat3<R> u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      v2f t = __builtin_convertvector(gld<v2h>(p, k * stride + s), v2f);
+    for (int k = 0; k < K; ++k) {
+      v2f t = __builtin_convertvector(gld_link<v2h>(p, k * stride + s), v2f);
       u.m[k] = {t.x, t.y};
     }
     return u;
@@ -601,12 +624,13 @@ struct LkF16 {
 struct LkBF16 {
   using R = float;
   static constexpr int kBytes = 36;
+  template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(uint32_t);
     mat3<R> u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      uint32_t w = gld<uint32_t>(p, k * stride + s);
+    for (int k = 0; k < K; ++k) {
+      uint32_t w = gld_link<uint32_t>(p, k * stride + s);
       u.m[k] = {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
     }
     return u;
@@ -616,6 +640,20 @@ struct LkBF16 {
 #pragma unroll
     for (int k = 0; k < 9; ++k)
       gst<uint32_t>(p, k * stride + s) = f_to_bf16((float)u.m[k].re) | (f_to_bf16((float)u.m[k].im) << 16);
+  }
+};
+
+// Two-row form of any of the link formats above: reads components 0..5
+// (rows 0 and 1) and rebuilds row 2, for fields that are SU(3) to rounding.
+// Two thirds of the link bytes of a hop.
+template <class LK>
+struct LkRows2 {
+  using R = typename LK::R;
+  static constexpr int kBytes = LK::kBytes / 9 * 6;
+  __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
+    mat3<R> u = LK::template load<6>(base, stride, mu, par, s);
+    third_row(u);
+    return u;
   }
 };
 

@@ -15,6 +15,7 @@
 // and the XCD-aware block order keeps the +-y/+-z neighbours of a block on
 // the XCD that owns it.
 #include <cstdlib>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -232,8 +233,9 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   for (int k = 0; k < 4; ++k) g.L[k] = ga.L[k];
   g.Vh = ga.Vh;
   g.stride = ga.stride;
-  const bool split = dslash_split(ga.Vh);
-  dim3 grid(dslash_blocks(ga.Vh), nbatch), block(kBlock);
+  const hmc_prec prec = std::is_same_v<typename SP::R, double> ? HMC_F64 : HMC_F32;
+  const bool split = dslash_split(ga.Vh, prec);
+  dim3 grid(dslash_blocks(ga.Vh, prec), nbatch), block(kBlock);
 #define HMC_DS(D, E)                                                                                           \
   do {                                                                                                        \
     if (split) {                                                                                              \
@@ -259,31 +261,44 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   return hipGetLastError();
 }
 
-bool dslash_split(int Vh) {
+bool dslash_split(int Vh, hmc_prec prec) {
   static const int forced = [] {
     const char* e = getenv("HMC_DSLASH_SPLIT");
     return e ? atoi(e) : -1;
   }();
   if (forced >= 0) return forced != 0;
-  return Vh <= (1 << 17);  // up to 16^3x64: fewer than 2 wavefronts per SIMD otherwise
+  // measured on MI355X: the split form gains for FP32 arithmetic up to
+  // 16^3x32 and loses at 48^3x96; FP64 is even at 16^3x32
+  return prec != HMC_F64 && Vh <= (1 << 17);
+}
+
+bool link_rows2_enabled() {
+  static const bool v = [] {
+    const char* e = getenv("HMC_LINK_ROWS2");
+    return e ? atoi(e) != 0 : true;
+  }();
+  return v;
+}
+
+template <class SP, class LK>
+static hipError_t launch_links(int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table, int nbatch,
+                               const DslashArgs& one, hipStream_t st, int j) {
+  const bool rows2 = one.rows2 && link_rows2_enabled();
+  // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for y)
+  const double site_bytes =
+      8.0 * (rows2 ? LkRows2<LK>::kBytes : LK::kBytes) + 2 * SP::kBytes + (epi ? SP::kBytes : 0);
+  TimedScope ts(TK_DSLASH, st, site_bytes * g.Vh * nbatch);
+  if (rows2) return launch_typed<SP, LkRows2<LK>>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+  return launch_typed<SP, LK>(dagger, epi, g, out_par, table, nbatch, one, st, j);
 }
 
 hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,
                          int nbatch, const DslashArgs& one, hipStream_t st, int j) {
-  // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for y)
-  double site_bytes = 0;
   switch (prec) {
-    case HMC_F64: site_bytes = 8 * LkF64::kBytes + 2 * SpF64::kBytes + (epi ? SpF64::kBytes : 0); break;
-    case HMC_F32: site_bytes = 8 * LkF32::kBytes + 2 * SpF32::kBytes + (epi ? SpF32::kBytes : 0); break;
-    case HMC_F16: site_bytes = 8 * LkF16::kBytes + 2 * SpF16::kBytes + (epi ? SpF16::kBytes : 0); break;
-    default: site_bytes = 8 * LkBF16::kBytes + 2 * SpBF16::kBytes + (epi ? SpBF16::kBytes : 0); break;
-  }
-  TimedScope ts(TK_DSLASH, st, site_bytes * g.Vh * nbatch);
-  switch (prec) {
-    case HMC_F64: return launch_typed<SpF64, LkF64>(dagger, epi, g, out_par, table, nbatch, one, st, j);
-    case HMC_F32: return launch_typed<SpF32, LkF32>(dagger, epi, g, out_par, table, nbatch, one, st, j);
-    case HMC_F16: return launch_typed<SpF16, LkF16>(dagger, epi, g, out_par, table, nbatch, one, st, j);
-    case HMC_BF16: return launch_typed<SpBF16, LkBF16>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+    case HMC_F64: return launch_links<SpF64, LkF64>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+    case HMC_F32: return launch_links<SpF32, LkF32>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+    case HMC_F16: return launch_links<SpF16, LkF16>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+    case HMC_BF16: return launch_links<SpBF16, LkBF16>(dagger, epi, g, out_par, table, nbatch, one, st, j);
   }
   return hipErrorInvalidValue;
 }

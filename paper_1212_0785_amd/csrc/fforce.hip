@@ -40,7 +40,7 @@ __device__ __forceinline__ mat3<double> proj_outer(const cx<double>* ha, const c
   return m;
 }
 
-template <int MU>
+template <class LK, int MU>
 __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, const ForceVecs& v, double* P,
                                                    double c_ta, int par, int s) {
   Site x = cb_site(g, par, s);
@@ -60,7 +60,7 @@ __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, 
   spin_project<MU, +1>(a, ha);
   spin_project<MU, +1>(b, hb);
   mat3<double> M2 = proj_outer(ha, hb, sg);
-  mat3<double> u = LkF64::load(U, g.stride, MU, par, s);
+  mat3<double> u = LK::load(U, g.stride, MU, par, s);
   mat3<double> W = msub(mmul(u, M1), mmul_nd(M2, u));
   double f[8], c[8];
   i_ta_compact(W, c_ta, f);
@@ -70,16 +70,17 @@ __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, 
   store_compact(P, g.stride, MU, par, s, c);
 }
 
+template <class LK>
 __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, ForceVecs v, double* P,
                                                           double c_ta) {
   int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= 2 * g.Vh) return;
   int par = j >= g.Vh, s = j - par * g.Vh;
   switch (blockIdx.y) {
-    case 0: fermion_force_link<0>(g, U, v, P, c_ta, par, s); break;
-    case 1: fermion_force_link<1>(g, U, v, P, c_ta, par, s); break;
-    case 2: fermion_force_link<2>(g, U, v, P, c_ta, par, s); break;
-    default: fermion_force_link<3>(g, U, v, P, c_ta, par, s); break;
+    case 0: fermion_force_link<LK, 0>(g, U, v, P, c_ta, par, s); break;
+    case 1: fermion_force_link<LK, 1>(g, U, v, P, c_ta, par, s); break;
+    case 2: fermion_force_link<LK, 2>(g, U, v, P, c_ta, par, s); break;
+    default: fermion_force_link<LK, 3>(g, U, v, P, c_ta, par, s); break;
   }
 }
 
@@ -87,16 +88,21 @@ __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, 
 // i c_ta TA(W) with c_ta = -coef kappa^2 / 2 (coef passed already times
 // kappa^2 by the caller as `coef`).
 hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
-                                const void* Yo, double* P, double coef, hipStream_t st) {
+                                const void* Yo, double* P, double coef, hipStream_t st, bool rows2) {
+  rows2 = rows2 && link_rows2_enabled();
   // algorithmic: 4 links, X and Y (both read once), momenta read + written
-  TimedScope ts(TK_FERMION_FORCE, st, 2.0 * g.Vh * (4 * LkF64::kBytes + 2 * SpF64::kBytes + 2 * 4 * 64));
+  TimedScope ts(TK_FERMION_FORCE, st,
+                2.0 * g.Vh * (4 * (rows2 ? LkRows2<LkF64>::kBytes : LkF64::kBytes) + 2 * SpF64::kBytes + 2 * 4 * 64));
   ForceVecs v;
   v.X[0] = Xe;
   v.X[1] = Xo;
   v.Y[0] = Ye;
   v.Y[1] = Yo;
-  hipLaunchKernelGGL(k_fermion_force, dim3(ceil_div(2LL * g.Vh, kBlock), 4), dim3(kBlock), 0, st, to_lat(g), U, v, P,
-                     -0.5 * coef);
+  const dim3 grid(ceil_div(2LL * g.Vh, kBlock), 4);
+  if (rows2)
+    hipLaunchKernelGGL(k_fermion_force<LkRows2<LkF64>>, grid, dim3(kBlock), 0, st, to_lat(g), U, v, P, -0.5 * coef);
+  else
+    hipLaunchKernelGGL(k_fermion_force<LkF64>, grid, dim3(kBlock), 0, st, to_lat(g), U, v, P, -0.5 * coef);
   return hipGetLastError();
 }
 

@@ -65,6 +65,10 @@ struct Fields {
   void *lr, *lp, *lq, *ls, *lt, *lx;
   uint64_t u_version;
   uint64_t low_version[4];
+  // U is SU(3) to rounding in the sense the two-row link loads need: every
+  // stored third row equals conj(row0 x row1) (checked on import and sync,
+  // kept by the reunitarised updates).  su3_old: the same for U_old.
+  bool su3, su3_old;
   double* pinned;  // host, hipHostMalloc'ed, SL_COUNT + 64 doubles
 };
 
@@ -79,6 +83,8 @@ hipError_t dslash_f64(Fields* F, void* out, const void* in, int out_par, int dag
 // out = Mhat(dag) in on F64 half spinors (uses the odd temporary t).
 hipError_t mhat_f64(Fields* F, void* out, const void* in, int dag, double* partial, hipStream_t st);
 hipError_t ensure_lowprec(Fields* F, hmc_prec prec, hipStream_t st);
+// Re-derives F->su3 from the stored links (one reduction; syncs).
+hipError_t check_rows2(Fields* F, hipStream_t st);
 void* low_links(Fields* F, hmc_prec prec);
 // Read `n` device doubles from slots[first..] into the pinned buffer (syncs).
 hipError_t read_slots(Fields* F, int first, int n, double* out, hipStream_t st);

@@ -138,8 +138,8 @@ static size_t plan_fields(Fields* F, char* base, const LatArg& g, uint32_t flags
   };
   const int Vh = g.Vh;
   const size_t h64 = half_bytes(Vh, HMC_F64);
-  const int nbD = dslash_blocks(Vh), nbR = blas_blocks(Vh);
-  const int npart = 2 * std::max(nbD, nbR);
+  const int nbD = dslash_blocks(Vh, HMC_F64), nbR = blas_blocks(Vh);
+  const int npart = 2 * std::max(dslash_blocks_max(Vh), nbR);
   const int nb_multi = std::min(nbR, 1024);
   const size_t multi = (size_t)nb_multi * 2 * 1024 + 1024;
   Fields tmp;
@@ -208,6 +208,7 @@ hipError_t dslash_f64(Fields* F, void* out, const void* in, int out_par, int dag
   d.partial = partial;
   d.stop_at = stop_at;
   d.iter0 = iter;
+  d.rows2 = F->su3;
   return launch_dslash(HMC_F64, dag, epi, F->g, out_par, nullptr, 1, d, st);
 }
 
@@ -220,6 +221,20 @@ hipError_t ensure_lowprec(Fields* F, hmc_prec prec, hipStream_t st) {
   hipError_t e = launch_convert_gauge(F->g, F->U, F->Ulow[prec], prec, st);
   if (e == hipSuccess) F->low_version[prec] = F->u_version;
   return e;
+}
+
+// Largest |stored - rebuilt| third-row component for which the two-row
+// loads are taken to reproduce the link (links have entries of modulus <= 1).
+constexpr double kRows2Tol = 1e-14;
+
+hipError_t check_rows2(Fields* F, hipStream_t st) {
+  hipError_t e = launch_rows2_check(F->g, F->U, kRows2Tol, F->part[4], F->nbR, st);
+  if (e != hipSuccess) return e;
+  if ((e = launch_finalize(F->part[4], F->nbR, 1, F->slots + SL_RED, 1.0, 0, st))) return e;
+  double bad = -1;
+  if ((e = read_slots(F, SL_RED, 1, &bad, st))) return e;
+  F->su3 = bad == 0.0;
+  return hipSuccess;
 }
 
 // Mhat (dag) on F64 half spinors: out = in - kappa^2 D_eo D_oe in.
@@ -308,6 +323,7 @@ hmc_status hmc_alloc_fields(const hmc_geom* geom, const hmc_action* action, uint
   plan_fields(F, (char*)arena, g, flags);
   F->u_version = 1;
   for (int k = 0; k < 4; ++k) F->low_version[k] = 0;
+  F->su3 = F->su3_old = false;  // U holds whatever the arena held
   if (hipHostMalloc((void**)&F->pinned, (SL_COUNT + 64) * sizeof(double)) != hipSuccess) {
     delete F;
     set_error("hipHostMalloc of the scalar read-back buffer failed");
@@ -336,7 +352,10 @@ hmc_status hmc_field_pointer(hmc_fields* f, hmc_field_id which, void** ptr) {
   FIELDS(f);
   HMC_REQUIRE(ptr, "null output");
   switch (which) {
-    case HMC_FIELD_GAUGE: *ptr = F->U; break;
+    case HMC_FIELD_GAUGE:  // the caller may write U: full-link loads until hmc_sync_lowprec
+      *ptr = F->U;
+      F->su3 = false;
+      break;
     case HMC_FIELD_MOMENTA: *ptr = F->P; break;
     case HMC_FIELD_ETA: *ptr = F->eta; break;
     case HMC_FIELD_PHI: *ptr = F->phi; break;
@@ -346,11 +365,19 @@ hmc_status hmc_field_pointer(hmc_fields* f, hmc_field_id which, void** ptr) {
   return HMC_OK;
 }
 
+hmc_status hmc_links_two_row(hmc_fields* f, int32_t* on) {
+  FIELDS(f);
+  HMC_REQUIRE(on, "null output");
+  *on = (F->su3 && link_rows2_enabled()) ? 1 : 0;
+  return HMC_OK;
+}
+
 hmc_status hmc_import_gauge(hmc_fields* f, const void* canon, void* stream) {
   FIELDS(f);
   HMC_REQUIRE(canon, "null buffer");
   HMC_CHECK_HIP(launch_pack_gauge(F->g, canon, F->U, ST(stream)));
   F->u_version++;
+  HMC_CHECK_HIP(check_rows2(F, ST(stream)));
   return HMC_OK;
 }
 
@@ -403,8 +430,10 @@ hmc_status hmc_convert_spinor(hmc_fields* f, void* dst, hmc_prec dst_prec, const
 
 hmc_status hmc_sync_lowprec(hmc_fields* f, void* stream) {
   FIELDS(f);
-  HMC_REQUIRE(F->flags & HMC_FIELDS_LOWPREC, "fields were allocated without HMC_FIELDS_LOWPREC");
-  for (int p = HMC_F32; p <= HMC_BF16; ++p) HMC_CHECK_HIP(ensure_lowprec(F, (hmc_prec)p, ST(stream)));
+  F->u_version++;
+  HMC_CHECK_HIP(check_rows2(F, ST(stream)));
+  if (F->flags & HMC_FIELDS_LOWPREC)
+    for (int p = HMC_F32; p <= HMC_BF16; ++p) HMC_CHECK_HIP(ensure_lowprec(F, (hmc_prec)p, ST(stream)));
   return HMC_OK;
 }
 
@@ -419,6 +448,7 @@ hmc_status hmc_wilson_dslash(hmc_fields* f, void* out, const void* in, int32_t o
   HMC_CHECK_HIP(ensure_lowprec(F, prec, ST(stream)));
   DslashArgs d{};
   d.U = low_links(F, prec);
+  d.rows2 = F->su3;
   d.in = in;
   d.out = out;
   d.b = 1.0;
@@ -440,6 +470,7 @@ hmc_status hmc_mhat(hmc_fields* f, void* out, const void* in, int32_t dagger, hm
   HMC_CHECK_HIP(ensure_lowprec(F, prec, st));
   DslashArgs d{};
   d.U = low_links(F, prec);
+  d.rows2 = F->su3;
   d.in = in;
   d.out = F->lt;
   d.b = 1.0;
@@ -526,7 +557,7 @@ hmc_status hmc_plaquette(hmc_fields* f, double* out, void* stream) {
   HMC_REQUIRE(out, "null output");
   hipStream_t st = ST(stream);
   double sum;
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st, F->su3));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], F->nbR, 1, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &sum, st));
   *out = sum / (18.0 * F->V);
@@ -538,7 +569,7 @@ hmc_status hmc_gauge_action(hmc_fields* f, double* out, void* stream) {
   HMC_REQUIRE(out, "null output");
   hipStream_t st = ST(stream);
   double sum;
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st, F->su3));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], F->nbR, 1, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &sum, st));
   *out = F->beta * (6.0 * F->V - sum / 3.0);
@@ -557,7 +588,7 @@ hmc_status hmc_kinetic_energy(hmc_fields* f, double* out, void* stream) {
 
 hmc_status hmc_gauge_force(hmc_fields* f, double coef, void* stream) {
   FIELDS(f);
-  HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, coef * F->beta, ST(stream)));
+  HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, coef * F->beta, ST(stream), F->su3));
   return HMC_OK;
 }
 
@@ -568,7 +599,7 @@ static hipError_t fermion_force_impl(Fields* F, const void* Xe, double coef, hip
   if ((e = dslash_f64(F, F->Xo, Xe, 1, 0, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st))) return e;
   if ((e = dslash_f64(F, F->Ye, F->Xo, 0, 0, EPI_AXPY, Xe, 1.0, -k2, nullptr, nullptr, 0, st))) return e;
   if ((e = dslash_f64(F, F->Yo, F->Ye, 1, 1, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st))) return e;
-  return launch_fermion_force(F->g, F->U, Xe, F->Xo, F->Ye, F->Yo, F->P, coef * k2, st);
+  return launch_fermion_force(F->g, F->U, Xe, F->Xo, F->Ye, F->Yo, F->P, coef * k2, st, F->su3);
 }
 
 hmc_status hmc_fermion_force(hmc_fields* f, const void* X_e, double coef, void* stream) {
@@ -582,6 +613,7 @@ hmc_status hmc_exp_update_reunit(hmc_fields* f, double eps, void* stream) {
   FIELDS(f);
   HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, ST(stream)));
   F->u_version++;
+  F->su3 = true;  // third row rebuilt by the reunitarisation
   return HMC_OK;
 }
 
@@ -604,6 +636,7 @@ hmc_status hmc_weak_field_start(hmc_fields* f, uint64_t seed, double eps, void* 
   FIELDS(f);
   HMC_CHECK_HIP(launch_weak_field(F->g, seed, eps, F->U, ST(stream)));
   F->u_version++;
+  F->su3 = true;
   return HMC_OK;
 }
 
@@ -643,7 +676,7 @@ hmc_status hmc_cg_solve(hmc_fields* f, void* x, const void* b, const hmc_cg_para
 // One force evaluation: P -= coef (F_g + F_f) with the fermion force from a
 // fresh solve of phi_e into X_e.
 static hmc_status force_kick(Fields* F, double coef, const hmc_cg_params* cg, hmc_md_stats* ms, hipStream_t st) {
-  HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, coef * F->beta, st));
+  HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, coef * F->beta, st, F->su3));
   hmc_cg_params p = *cg;
   p.mode = HMC_CG_NORMAL_MHAT;
   hmc_cg_stats cs;
@@ -666,6 +699,7 @@ static hmc_status leapfrog_impl(Fields* F, double tau, int nsteps, const hmc_cg_
   for (int k = 1; k <= nsteps; ++k) {
     HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, st));
     F->u_version++;
+    F->su3 = true;
     s = force_kick(F, k < nsteps ? eps : 0.5 * eps, cg, ms, st);
     if (s) return s;
   }
@@ -693,12 +727,13 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
   auto t0 = std::chrono::steady_clock::now();
   const size_t ub = gauge_bytes(F->g.Vh, HMC_F64);
   HMC_CHECK_HIP(launch_copy(F->U_old, F->U, ub, st));
+  F->su3_old = F->su3;
   HMC_CHECK_HIP(launch_refresh_momenta(F->g, seed, traj, F->P, st));
   HMC_CHECK_HIP(refresh_pf(F, seed, traj, st));
   const int nb = F->nbR;
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_OLD, st));
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_OLD, st));
   HMC_CHECK_HIP(launch_norm2_partials(F->g, HMC_F64, F->eta, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_ETA2, st));
@@ -709,7 +744,7 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
 
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_NEW, st));
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_NEW, st));
   HMC_CHECK_HIP(launch_inner_partials(F->g, F->phi, F->Xe, F->part[1], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_PHIX, st));
@@ -721,9 +756,10 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
   if (!accepted) {
     HMC_CHECK_HIP(launch_copy(F->U, F->U_old, ub, st));
     F->u_version++;
+    F->su3 = F->su3_old;
   }
   double plaq_sum;
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &plaq_sum, st));
 

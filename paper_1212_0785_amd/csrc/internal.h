@@ -35,10 +35,15 @@ inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 
 // Dslash kernel shape: one site per work-item (256 sites per block) or the
 // direction-split form (64 sites per block, four wavefronts per group of
-// sites) for volumes too small to fill the GPU with one wavefront per 64
-// sites.  HMC_DSLASH_SPLIT=0/1 (read once) overrides the volume rule.
-bool dslash_split(int Vh);
-inline int dslash_blocks(int Vh) { return dslash_split(Vh) ? ceil_div(Vh, kThreads / 4) : site_blocks(Vh); }
+// sites), taken for the single-precision-arithmetic storages at volumes too
+// small to fill the GPU with one wavefront per 64 sites.
+// HMC_DSLASH_SPLIT=0/1 (read once) overrides the rule.
+bool dslash_split(int Vh, hmc_prec prec);
+inline int dslash_blocks(int Vh, hmc_prec prec) {
+  return dslash_split(Vh, prec) ? ceil_div(Vh, kThreads / 4) : site_blocks(Vh);
+}
+// Largest block count (and Dslash-epilogue partial count) of either shape.
+inline int dslash_blocks_max(int Vh) { return ceil_div(Vh, kThreads / 4); }
 
 // Iteration control of the Krylov solvers, resident in device memory.
 // Kernels of iteration k do nothing once k >= stop_at.  Only block 0 of the
@@ -68,7 +73,12 @@ struct DslashArgs {
   double* partial_pp[2];  // if set: partial_pp[(label + 1) & 1] instead
   const int* stop_at;   // solver control (may be null)
   int iter0;            // label offset compared with *stop_at
+  int rows2;            // host dispatch: links are SU(3), read two rows and rebuild the third
 };
+
+// Whether hopping kernels may read two link rows (HMC_LINK_ROWS2=0 turns the
+// two-row loads off; read once).
+bool link_rows2_enabled();
 
 enum Epilogue { EPI_PLAIN = 0, EPI_AXPY = 1, EPI_AXPY_NORM = 2 };
 
@@ -83,6 +93,8 @@ hipError_t launch_pack_spinor(const LatArg& g, const void* canon, void* half, in
 hipError_t launch_unpack_spinor(const LatArg& g, const void* half, void* canon, int par, hipStream_t st);
 hipError_t launch_pack_momenta(const LatArg& g, const void* canon, double* P, hipStream_t st);
 hipError_t launch_unpack_momenta(const LatArg& g, const double* P, void* canon, hipStream_t st);
+// Per-block counts of links whose third row is not conj(row0 x row1) to `tol`.
+hipError_t launch_rows2_check(const LatArg& g, const void* U, double tol, double* part, int nb, hipStream_t st);
 hipError_t launch_convert_gauge(const LatArg& g, const void* U64, void* Ulow, hmc_prec prec, hipStream_t st);
 hipError_t launch_convert_spinor(const LatArg& g, const void* in, hmc_prec pin, void* out, hmc_prec pout,
                                  int nbatch, const void* const* tab_in, void* const* tab_out, hipStream_t st);
@@ -137,12 +149,15 @@ hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbat
 hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st);  // x += xl; xl = 0
 
 // Gauge-field kernels.
-hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st);
+hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st,
+                                     bool rows2);
 hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* part, int nb, hipStream_t st);
-hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st);
+hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st,
+                              bool rows2);
 hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st);
 hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
-                                const void* Yo, double* P, double coef, hipStream_t st);
+                                const void* Yo, double* P, double coef, hipStream_t st,
+                                bool rows2);
 
 // Random fields (Philox4x64-10, counter = (block, lex site, stream, epoch),
 // key = (seed, 0)).

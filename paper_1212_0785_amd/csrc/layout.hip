@@ -96,6 +96,28 @@ __global__ void k_convert_gauge(Lat g, const void* U64, void* Ulow) {
   LK::store(Ulow, g.stride, mu, par, s, u);
 }
 
+// Counts the links whose stored third row differs from conj(row0 x row1)
+// by more than `tol` in any real component (per-block partial counts).
+__global__ void __launch_bounds__(kBlock) k_rows2_check(Lat g, const void* U, double tol, double* part) {
+  double v[1] = {0.0};
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < 2 * g.Vh; j += gridDim.x * kBlock) {
+    const int par = j >= g.Vh, s = j - par * g.Vh;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const mat3<double> u = LkF64::load(U, g.stride, mu, par, s);
+      mat3<double> r = u;
+      third_row(r);
+      bool bad = false;
+#pragma unroll
+      for (int k = 6; k < 9; ++k)
+        bad |= !(fabs(u.m[k].re - r.m[k].re) <= tol) || !(fabs(u.m[k].im - r.m[k].im) <= tol);
+      v[0] += bad ? 1.0 : 0.0;
+    }
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
 template <class SI, class SO>
 __global__ void k_convert_spinor(Lat g, const void* in, void* out, const void* const* tin, void* const* tout) {
   int s = blockIdx.x * kBlock + threadIdx.x;
@@ -138,6 +160,11 @@ hipError_t launch_pack_momenta(const LatArg& g, const void* canon, double* P, hi
 hipError_t launch_unpack_momenta(const LatArg& g, const double* P, void* canon, hipStream_t st) {
   hipLaunchKernelGGL(k_unpack_momenta, dim3(ceil_div(2LL * g.Vh, kBlock)), dim3(kBlock), 0, st, to_lat(g), P,
                      (double2*)canon);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows2_check(const LatArg& g, const void* U, double tol, double* part, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_rows2_check, dim3(nb), dim3(kBlock), 0, st, to_lat(g), U, tol, part);
   return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ size_t carve_request(char* base, const LatArg& g, int prec, SolveVecs* v, void**
   Carve c(base);
   const int Vh = g.Vh;
   const size_t h64 = half_bytes(Vh, HMC_F64);
-  const int nbD = dslash_blocks(Vh), nbR = blas_blocks(Vh);
+  const int nbD = dslash_blocks(Vh, (hmc_prec)prec), nbR = blas_blocks(Vh);
   SolveVecs t{};
   SolveVecs& s = v ? *v : t;
   *U64 = c.take((size_t)Vh * 8 * 144);
@@ -222,6 +222,7 @@ struct Service {
     v.cgls = 1;
     v.prec = (hmc_prec)prm.inner_prec;
     v.U64 = r->U64;
+    v.rows2 = 1;  // weak-field links are reunitarised: SU(3) rows
     v.x = r->x;
     if (v.prec == HMC_F64) v.xl = r->x;
     v.state = states + r->idx;
@@ -239,6 +240,7 @@ struct Service {
     // bhat_e = b_e + kappa D_eo b_o ; x_e = 0 ; r64 = bhat ; |r64|^2 into the solver slot
     DslashArgs d{};
     d.U = r->U64;
+    d.rows2 = 1;
     d.in = b + h64;
     d.out = v.rhs;
     d.y = b;
@@ -274,6 +276,7 @@ struct Service {
     hipError_t e;
     DslashArgs d{};
     d.U = r->U64;
+    d.rows2 = 1;
     d.in = x;
     d.out = x + h64;
     d.y = b + h64;

@@ -118,6 +118,7 @@ _SIGNATURES = {
     "hmc_export_spinor": (_I32, [_P, _P, _P, _I32, _P]),
     "hmc_convert_spinor": (_I32, [_P, _P, _I32, _P, _I32, _P]),
     "hmc_sync_lowprec": (_I32, [_P, _P]),
+    "hmc_links_two_row": (_I32, [_P, _P]),
     "hmc_wilson_dslash": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P]),
     "hmc_mhat": (_I32, [_P, _P, _P, _I32, _I32, _P]),
     "hmc_wilson_m": (_I32, [_P, _P, _P, _I32, _P]),
@@ -296,6 +297,12 @@ def hmc_convert_spinor(f, dst, dst_prec, src, src_prec, stream=None):
 
 def hmc_sync_lowprec(f, stream=None):
     check(lib().hmc_sync_lowprec(_h(f), _stream(stream)))
+
+
+def hmc_links_two_row(f) -> bool:
+    on = C.c_int32()
+    check(lib().hmc_links_two_row(_h(f), C.byref(on)))
+    return bool(on.value)
 
 
 def hmc_wilson_dslash(f, out, inp, out_parity, dagger=0, prec=F64, stream=None):

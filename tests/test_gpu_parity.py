@@ -480,3 +480,41 @@ def test_dslash_sampled_at_48c96(H):
     gv = half[:, torch.from_numpy(lex // 2).cuda(), :].cpu().numpy()
     got = (gv[..., 0] + 1j * gv[..., 1]).T.reshape(-1, 4, 3)
     assert rel(got, want) < 1e-14
+
+
+def test_gauge_force_sampled_at_48c96(H):
+    """Staple force at 48^3 x 96 (the kernel shape chosen for large volumes):
+    P_after - P_before = -F at ~130 sites of both parities (all four
+    directions), the oracle's force from its own weak-field draws of the
+    links those staples touch."""
+    L = (48, 48, 48, 96)
+    V = synth.volume(L)
+    Vh = V // 2
+    F = H.Fields(L, 5.6, 0.15)
+    H.hmc_weak_field_start(F, 2, 0.3)
+    H.hmc_refresh(F, 5, 0, H.REFRESH_MOM)
+    P = F.arena[F.pointer(H.FIELD_MOMENTA) - F.arena.data_ptr():].view(torch.float64)[: 4 * 2 * 8 * Vh]
+    P = P.view(4, 2, 8, Vh)
+    lex = np.random.default_rng(3).integers(0, V, 128)
+    lex = np.unique(np.concatenate([lex, [O.lex_index(L, 0, 0, 0, 0), O.lex_index(L, 47, 47, 47, 95)]]))
+    lex = lex.astype(np.int64)
+    c = _coords48(lex)
+    par = torch.from_numpy(c.sum(1) % 2).cuda()
+    cb = torch.from_numpy(lex // 2).cuda()
+    before = P[:, par, :, cb].clone()  # (n, 4, 8)
+    H.hmc_gauge_force(F, 1.0)
+    torch.cuda.synchronize()
+    dP = (P[:, par, :, cb] - before).cpu().numpy()
+    need = set()
+    offs = [np.array(o) for o in np.ndindex(3, 3, 3, 3) if sum(v != 1 for v in o) <= 2]
+    for x in c:
+        for o in offs:
+            y = (x + o - 1) % np.array(L)
+            need.add(O.lex_index(L, *[int(v) for v in y]))
+    need = np.array(sorted(need), dtype=np.int64)
+    U = np.zeros((V, 4, 3, 3), np.complex128)  # lazily zero pages: only the needed sites are touched
+    O.weak_field_sites(L, 2, 0.3, need, U)
+    Fo = O.gauge_force_sites(L, U, 5.6, lex)  # (n, 4, 3, 3), Hermitian traceless
+    want = -np.stack([Fo[..., 0, 0].real, Fo[..., 1, 1].real, Fo[..., 0, 1].real, Fo[..., 0, 1].imag,
+                      Fo[..., 0, 2].real, Fo[..., 0, 2].imag, Fo[..., 1, 2].real, Fo[..., 1, 2].imag], -1)
+    assert rel(dP, want) < 1e-12
