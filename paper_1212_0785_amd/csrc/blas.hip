@@ -190,6 +190,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(Lat g, const double2* b, dou
 //            sum(pp[nxt]) (CG) or sum(pr) (CGLS).
 // (CG: pp holds |r|^2, pq = <p, A p> = |Mhat p|^2.  CGLS: pp holds
 // |s|^2 = |Mhat^dag r|^2, pq = |q|^2 = |Mhat p|^2.)
+// Fused CG (CgArgs::fused): the update kernel is not launched; the
+// preceding Dslash computes alpha (block 0, into the solver state) and
+// r -= alpha q in its epilogue, and the p-update also does x += alpha p.
 template <class SP, class SX>
 __global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table, CgArgs one, int j) {
   const CgArgs a = table ? table[blockIdx.y] : one;
@@ -229,18 +232,20 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table
 // precision, when the inner residual fell by delta since the last FP64
 // update), sets stop_at = k + 1; blocks of this launch compare k only, so
 // none of them can observe a change that concerns it.
-template <class SP>
+template <class SP, class SX>
 __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* table, CgArgs one, int j) {
   const CgArgs a = table ? table[blockIdx.y] : one;
   SolverState* stt = a.state;
   const int k = a.iter0 + j;
   if (k >= stt->stop_at) return;
   using R = typename SP::R;
+  using XR = typename SX::R;
   const int cur = k & 1, nxt = cur ^ 1;
   const double nw = sum_partials(a.pp[nxt], a.n_pp);
   const double old = sum_partials(a.pp[cur], a.n_pp);
   const double rr = a.cgls ? sum_partials(a.pr, a.n_pr) : nw;
   const bool conv = rr <= a.thr;
+  const double alpha = a.fused ? stt->alpha : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     stt->iters += 1;
     stt->last = k;
@@ -257,12 +262,25 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
       stt->stop_at = k + 1;
     }
   }
-  if (conv && !a.mixed) return;
+  const bool p_done = conv && !a.mixed;  // converged: the search direction is not needed
+  if (p_done && !a.fused) return;
   const R beta = (R)(nw / old);
   const void* src = a.cgls ? a.s : a.r;
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
-    cx<R> p[12], q[12];
+    cx<R> p[12];
     SP::load(a.p, g.stride, s, p);
+    if (a.fused) {  // x += alpha p with the p of this iteration
+      cx<XR> x[12];
+      SX::load(a.x, g.stride, s, x);
+#pragma unroll
+      for (int m = 0; m < 12; ++m) {
+        x[m].re = fma((XR)alpha, (XR)p[m].re, x[m].re);
+        x[m].im = fma((XR)alpha, (XR)p[m].im, x[m].im);
+      }
+      SX::store(a.x, g.stride, s, x);
+    }
+    if (p_done) continue;
+    cx<R> q[12];
     SP::load(src, g.stride, s, q);
 #pragma unroll
     for (int m = 0; m < 12; ++m) {
@@ -397,10 +415,10 @@ hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, in
   TimedScope ts(TK_CG_BLAS, st, 0);
   dim3 grid(nb, nbatch), block(kBlock);
   switch (prec) {
-    case HMC_F64: hipLaunchKernelGGL(k_cg_pupdate<SpF64>, grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_F32: hipLaunchKernelGGL(k_cg_pupdate<SpF32>, grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_F16: hipLaunchKernelGGL(k_cg_pupdate<SpF16>, grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_BF16: hipLaunchKernelGGL(k_cg_pupdate<SpBF16>, grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F64: hipLaunchKernelGGL((k_cg_pupdate<SpF64, SpF64>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F32: hipLaunchKernelGGL((k_cg_pupdate<SpF32, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F16: hipLaunchKernelGGL((k_cg_pupdate<SpF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_BF16: hipLaunchKernelGGL((k_cg_pupdate<SpBF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
   }
   return hipGetLastError();
 }

@@ -86,6 +86,15 @@ __device__ __forceinline__ void hop_dir(const Lat& g, const Site& st, int out_pa
   }
 }
 
+// Block 0 computes the solver step length from the partial sums of the
+// previous kernels (see DslashArgs::alpha_out); the other blocks skip it.
+__device__ __forceinline__ void alpha_prologue(const DslashArgs& e, int label) {
+  if (!e.alpha_out || blockIdx.x != 0) return;
+  const double num = sum_partials(e.alpha_pp[label & 1], e.alpha_n_pp);
+  const double den = sum_partials(e.alpha_den, e.alpha_n_den);
+  if (threadIdx.x == 0) *(HMC_GLOBAL double*)e.alpha_out = num / den;
+}
+
 // BATCH: blockIdx.y selects an entry of `table` (same-volume requests share
 // one launch); otherwise the single entry `one` is read from the kernel
 // arguments.
@@ -102,6 +111,7 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
   const DslashArgs& e = *ep;
   const int label = e.iter0 + j;
   if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
+  alpha_prologue(e, label);
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int s = b * kBlock + threadIdx.x;
   double nrm[1] = {0.0};
@@ -126,12 +136,19 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
         for (int k = 0; k < 12; ++k) acc[k] = bb * acc[k];
       }
     }
-    if (EPI == EPI_AXPY_NORM)
+    if (EPI == EPI_CG) {  // acc = q = A p;  r <- r - alpha q
+      const R al = (R)(*(const HMC_GLOBAL double*)e.alpha_in);
+      cx<R> r[12];
+      SP::load(e.r, g.stride, s, r);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = {fma(-al, acc[k].re, r[k].re), fma(-al, acc[k].im, r[k].im)};
+    }
+    if (EPI == EPI_AXPY_NORM || EPI == EPI_CG)
 #pragma unroll
       for (int k = 0; k < 12; ++k) nrm[0] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
     SP::store(e.out, g.stride, s, acc);
   }
-  if (EPI == EPI_AXPY_NORM) {
+  if (EPI == EPI_AXPY_NORM || EPI == EPI_CG) {
     block_sum<1>(nrm);
     double* dst = e.partial_pp[0] ? e.partial_pp[(label + 1) & 1] : e.partial;
     if (threadIdx.x == 0) ((HMC_GLOBAL double*)dst)[b] = nrm[0];
@@ -158,6 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, con
   const DslashArgs& e = *ep;
   const int label = e.iter0 + j;
   if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
+  alpha_prologue(e, label);
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int mu = threadIdx.x >> 6;  // wave index = direction (uniform per wave)
   const int ls = threadIdx.x & (kSites - 1);
@@ -201,7 +219,15 @@ __global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, con
         }
       }
     }
-    if (EPI == EPI_AXPY_NORM)
+    if (EPI == EPI_CG) {
+      const R al = (R)(*(const HMC_GLOBAL double*)e.alpha_in);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<R> rv = SP::load_one(e.r, g.stride, s, 3 * mu + c);
+        o[c] = {fma(-al, o[c].re, rv.re), fma(-al, o[c].im, rv.im)};
+      }
+    }
+    if (EPI == EPI_AXPY_NORM || EPI == EPI_CG)
 #pragma unroll
       for (int c = 0; c < 3; ++c) nrm[0] += (double)o[c].re * o[c].re + (double)o[c].im * o[c].im;
   }
@@ -219,7 +245,7 @@ __global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, con
   } else {
     if (active) SP::store_part(e.out, g.stride, s, mu, o);
   }
-  if (EPI == EPI_AXPY_NORM) {
+  if (EPI == EPI_AXPY_NORM || EPI == EPI_CG) {
     block_sum<1>(nrm);
     double* dst = e.partial_pp[0] ? e.partial_pp[(label + 1) & 1] : e.partial;
     if (threadIdx.x == 0) ((HMC_GLOBAL double*)dst)[b] = nrm[0];
@@ -248,6 +274,14 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
     else                                                                                                      \
       hipLaunchKernelGGL((k_dslash<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one, j);        \
   } while (0)
+  if (epi == EPI_CG) {  // last hop of a CG iteration: dagger, one solve
+    if (table || !dagger) return hipErrorInvalidValue;
+    if (split)
+      hipLaunchKernelGGL((k_dslash_split<SP, LK, true, EPI_CG, false>), grid, block, 0, st, g, out_par, table, one, j);
+    else
+      hipLaunchKernelGGL((k_dslash<SP, LK, true, EPI_CG, false>), grid, block, 0, st, g, out_par, table, one, j);
+    return hipGetLastError();
+  }
   if (dagger) {
     if (epi == EPI_PLAIN) HMC_DS(true, EPI_PLAIN);
     else if (epi == EPI_AXPY) HMC_DS(true, EPI_AXPY);
@@ -284,9 +318,10 @@ template <class SP, class LK>
 static hipError_t launch_links(int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table, int nbatch,
                                const DslashArgs& one, hipStream_t st, int j) {
   const bool rows2 = one.rows2 && link_rows2_enabled();
-  // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for y)
-  const double site_bytes =
-      8.0 * (rows2 ? LkRows2<LK>::kBytes : LK::kBytes) + 2 * SP::kBytes + (epi ? SP::kBytes : 0);
+  // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for
+  // y, +1 more for the residual read by the CG epilogue)
+  const double site_bytes = 8.0 * (rows2 ? LkRows2<LK>::kBytes : LK::kBytes) + 2 * SP::kBytes +
+                            (epi ? SP::kBytes : 0) + (epi == EPI_CG ? SP::kBytes : 0);
   TimedScope ts(TK_DSLASH, st, site_bytes * g.Vh * nbatch);
   if (rows2) return launch_typed<SP, LkRows2<LK>>(dagger, epi, g, out_par, table, nbatch, one, st, j);
   return launch_typed<SP, LK>(dagger, epi, g, out_par, table, nbatch, one, st, j);

@@ -56,6 +56,7 @@ struct SolverState {
   int last;      // label of the last completed iteration
   double rr;     // last residual norm^2 seen by the p-update
   double maxrr;  // mixed precision: max inner |r|^2 since the last update
+  double alpha;  // CG step length of the current iteration (fused form)
 };
 
 // Iteration labels: a solver iteration carries the label iter0 + j, where
@@ -74,13 +75,22 @@ struct DslashArgs {
   const int* stop_at;   // solver control (may be null)
   int iter0;            // label offset compared with *stop_at
   int rows2;            // host dispatch: links are SU(3), read two rows and rebuild the third
+  // Step-length prologue (block 0 only, when alpha_out is set):
+  //   *alpha_out = sum(alpha_pp[label & 1][0..n_pp)) / sum(alpha_den[0..n_den))
+  const double* alpha_pp[2];
+  const double* alpha_den;
+  int alpha_n_pp, alpha_n_den;
+  double* alpha_out;
+  // EPI_CG: r <- r - (*alpha_in) (a y + b D in) with out == r, |r|^2 per block
+  const void* r;
+  const double* alpha_in;
 };
 
 // Whether hopping kernels may read two link rows (HMC_LINK_ROWS2=0 turns the
 // two-row loads off; read once).
 bool link_rows2_enabled();
 
-enum Epilogue { EPI_PLAIN = 0, EPI_AXPY = 1, EPI_AXPY_NORM = 2 };
+enum Epilogue { EPI_PLAIN = 0, EPI_AXPY = 1, EPI_AXPY_NORM = 2, EPI_CG = 3 };
 
 // Launchers (defined in the .hip files).  All return hipGetLastError().
 hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,
@@ -136,6 +146,7 @@ struct CgArgs {
   double thr;      // convergence threshold on |r|^2
   double delta2;   // mixed precision: reliable-update trigger (delta^2)
   int mixed;       // 1: never declare convergence, pause instead
+  int fused;       // CG with the residual update in the Dslash epilogue: the p-update also does x += alpha p
 };
 hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x, void* r, void* p, double* part,
                           int nb, hipStream_t st);

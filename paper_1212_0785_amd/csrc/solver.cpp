@@ -45,11 +45,18 @@ void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, doubl
   b.b = 1.0;
   for (int i = 0; i < 4; ++i) o->d[i] = b;
   if (!v.cgls) {
-    // t = D_oe p;  s = p - k^2 D_eo t (|s|^2 = <p, A p>);  t = D^dag_oe s;  q = s - k^2 D^dag_eo t
+    // t = D_oe p;  s = p - k^2 D_eo t (|s|^2 = <p, A p>);
+    // t = D^dag_oe s (block 0: alpha = |r|^2 / |s|^2);
+    // r -= alpha (s - k^2 D^dag_eo t) (|r|^2);  then x += alpha p, p = r + beta p
     o->d[0].in = v.p, o->d[0].out = v.t;
     o->d[1].in = v.t, o->d[1].out = v.s, o->d[1].y = v.p, o->d[1].b = -k2, o->d[1].partial = v.pq;
     o->d[2].in = v.s, o->d[2].out = v.t;
-    o->d[3].in = v.t, o->d[3].out = v.q, o->d[3].y = v.s, o->d[3].b = -k2;
+    o->d[2].alpha_pp[0] = v.pp[0], o->d[2].alpha_pp[1] = v.pp[1], o->d[2].alpha_den = v.pq;
+    o->d[2].alpha_n_pp = v.nbD, o->d[2].alpha_n_den = v.nbD;
+    o->d[2].alpha_out = &v.state->alpha;
+    o->d[3].in = v.t, o->d[3].out = v.r, o->d[3].y = v.s, o->d[3].b = -k2;
+    o->d[3].r = v.r, o->d[3].alpha_in = &v.state->alpha;
+    o->d[3].partial_pp[0] = v.pp[0], o->d[3].partial_pp[1] = v.pp[1];
   } else {
     // t = D_oe p;  q = p - k^2 D_eo t (|q|^2);  [update];  t = D^dag_oe r;  s = r - k^2 D^dag_eo t (|s|^2)
     o->d[0].in = v.p, o->d[0].out = v.t;
@@ -69,7 +76,7 @@ void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, doubl
   c.pp[1] = v.pp[1];
   c.pq = v.pq;
   c.pr = v.pr;
-  c.n_pp = v.cgls ? v.nbD : v.nbR;
+  c.n_pp = v.nbD;  // |r|^2 (CG) or |s|^2 (CGLS), both from a Dslash epilogue
   c.n_pq = v.nbD;
   c.n_pr = v.nbR;
   c.state = v.state;
@@ -78,6 +85,7 @@ void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, doubl
   c.thr = thr;
   c.delta2 = delta2;
   c.mixed = mixed;
+  c.fused = v.cgls ? 0 : 1;
   o->c[0] = c;
   o->c[1] = c;
 }
@@ -95,8 +103,7 @@ hipError_t launch_iteration(const LatArg& g, hmc_prec prec, int cgls, const Iter
     if ((e = D(0, 1, 0, EPI_PLAIN))) return e;
     if ((e = D(1, 0, 0, EPI_AXPY_NORM))) return e;
     if ((e = D(2, 1, 1, EPI_PLAIN))) return e;
-    if ((e = D(3, 0, 1, EPI_AXPY))) return e;
-    if ((e = UPD(0))) return e;
+    if ((e = D(3, 0, 1, EPI_CG))) return e;
     return PUP(1);
   }
   if ((e = D(0, 1, 0, EPI_PLAIN))) return e;
@@ -167,7 +174,7 @@ hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st) 
     if ((e = launch_dslash(v.prec, 1, EPI_AXPY_NORM, v.g, 0, nullptr, 1, d, st, 0))) return e;
     if (first && (e = launch_copy(v.p, v.s, lowbytes, st))) return e;
   } else {
-    if ((e = launch_norm2_partials(v.g, v.prec, v.r, part, v.nbR, st))) return e;
+    if ((e = launch_norm2_partials(v.g, v.prec, v.r, part, v.nbD, st))) return e;
     if (first && (e = launch_copy(v.p, v.r, lowbytes, st))) return e;
   }
   if (first && (e = launch_zero(v.xl, (size_t)v.g.Vh * 96, st))) return e;
@@ -277,8 +284,9 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
     // bhat_e = b_e + kappa D_eo b_o
     CHK(dslash_f64(F, F->bhat, bb + F->half64, 0, 0, EPI_AXPY, bb, 1.0, F->kappa, nullptr, nullptr, 0, st));
   }
-  CHK(launch_cg_init(F->g, HMC_F64, v.rhs, x, v.r64, prec == HMC_F64 ? v.p : v.q64, v.pp[0], F->nbR, st));
-  CHK(launch_finalize(v.pp[0], F->nbR, 1, v.slot, 1.0, 0, st));
+  // |r|^2 partials in pp[0] with the Dslash-epilogue count, as the iteration reads them
+  CHK(launch_cg_init(F->g, HMC_F64, v.rhs, x, v.r64, prec == HMC_F64 ? v.p : v.q64, v.pp[0], v.nbD, st));
+  CHK(launch_finalize(v.pp[0], v.nbD, 1, v.slot, 1.0, 0, st));
   CHK(read_slots(F, SL_SOLVER, 1, &rr0, st));
   if (!cgls) bnorm2 = rr0;
   const double thr = fixed > 0 ? -1.0 : prm->tol * prm->tol * bnorm2;
