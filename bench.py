@@ -75,10 +75,11 @@ def timed_kernel_roofline(H, name="dslash", timing=None):
 # ------------------------------------------------------------------- HMC
 
 
-def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sample=30):
-    """Time each oracle piece of one trajectory once (the CG over a fixed
-    n_cg_sample iterations) and project seconds per trajectory with the
-    measured GPU iteration count per solve (same algorithm, same count)."""
+def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sample=400, n_rep=3):
+    """Time the oracle's pieces of one trajectory (forces and link update
+    n_rep times each, the CG over a fixed n_cg_sample iterations; about 15 s
+    on 16 host cores) and project seconds per trajectory with the measured
+    GPU iteration count per solve (same algorithm, same count)."""
     import numpy as np  # noqa: F401
 
     import oracle as O
@@ -91,29 +92,32 @@ def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sam
     O.kinetic(L, P), O.gauge_action(L, U, beta)
     t_refresh = time.perf_counter() - ta
     ta = time.perf_counter()
-    F = O.gauge_force(L, U, beta)
-    t_gf = time.perf_counter() - ta
+    for _ in range(n_rep):
+        O.gauge_force(L, U, beta)
+    t_gf = (time.perf_counter() - ta) / n_rep
     ta = time.perf_counter()
     Xe, _ = O.cg_mhat(L, U, kappa, phi, fixed_iters=n_cg_sample)
     t_cg = (time.perf_counter() - ta) / n_cg_sample
     ta = time.perf_counter()
-    odd = O.parity_mask(L)
-    X = Xe.copy()
-    X[odd] = O.dslash(L, U, Xe, 1)[odd]
-    Y = O.mhat(L, U, kappa, Xe)
-    Y[odd] = O.dslash(L, U, Y, 1, dagger=True)[odd]
-    O.fermion_force(L, U, kappa * kappa, X, Y)
-    t_ff = time.perf_counter() - ta
+    for _ in range(n_rep):
+        odd = O.parity_mask(L)
+        X = Xe.copy()
+        X[odd] = O.dslash(L, U, Xe, 1)[odd]
+        Y = O.mhat(L, U, kappa, Xe)
+        Y[odd] = O.dslash(L, U, Y, 1, dagger=True)[odd]
+        O.fermion_force(L, U, kappa * kappa, X, Y)
+    t_ff = (time.perf_counter() - ta) / n_rep
     ta = time.perf_counter()
-    O.update_links(L, U, P, 1.0 / nsteps)
-    t_up = time.perf_counter() - ta
+    for _ in range(n_rep):
+        O.update_links(L, U, P, 1.0 / nsteps)
+    t_up = (time.perf_counter() - ta) / n_rep
     sample = time.perf_counter() - t0
     n_force = nsteps + 1
     proj = 2 * t_refresh + n_force * (t_gf + t_ff + cg_iters_per_solve * t_cg) + nsteps * t_up
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": proj, "unit": "s/traj", "cores": cores, "kind": "oracle",
-            "sample": (f"FP64 oracle on 16^3x32, trajectory 0 pieces timed once each: refresh + actions, "
-                       f"gauge force, fermion force, link update, and {n_cg_sample} CG iterations; "
+            "sample": (f"FP64 oracle on 16^3x32, trajectory 0 pieces: refresh + actions once, gauge force, "
+                       f"fermion force and link update {n_rep} times each, {n_cg_sample} CG iterations; "
                        f"projected to {n_force} force evaluations x {cg_iters_per_solve:.0f} CG iterations "
                        f"(the GPU's mean per solve) + {nsteps} link updates; sample wall {sample:.1f} s"),
             "per_cg_iter_s": t_cg, "force_eval_s": t_gf + t_ff}
@@ -159,13 +163,18 @@ def run_hmc(args, H, torch):
     if rf:
         out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": rf["achieved"] / HBM_PEAK_GBS, "traffic": load_traffic("hmc_16c32"),
-                           "kernel": "k_dslash F64 (half-lattice hop, plain and axpy/norm epilogues)",
+                           "kernel": ("k_dslash F64, two-row links (half-lattice hop; plain, axpy/norm and "
+                                      "CG-update epilogues: 1152/1344/1536 B per site)"),
                            "avg_launch_ms": rf["avg_ms"], "bytes_per_launch": rf["bytes_per_launch"],
                            "launches_timed": rf["launches_timed"]}
     return out, iters / solves, L, seed, beta, kappa, nsteps
 
 
 # ----------------------------------------------------------------- Dslash
+
+
+def synth_vh(L):
+    return L[0] * L[1] * L[2] * L[3] // 2
 
 
 def run_dslash(args, H, torch):
@@ -221,7 +230,8 @@ def run_dslash(args, H, torch):
         "kernels": res,
         "roofline": {"bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": best["frac"], "traffic": load_traffic("dslash_48c96"),
-                     "kernel": "k_dslash F64 plain, 1536 B/site", "avg_launch_ms": best["avg_ms"]},
+                     "kernel": f"k_dslash F64 plain, {best['bytes_per_launch'] / (synth_vh(L)):.0f} B/site",
+                     "avg_launch_ms": best["avg_ms"]},
     }
     return out
 
@@ -414,7 +424,9 @@ def main():
     ap.add_argument("--rho", type=float, default=0.9, help="serve: offered load relative to FP64 FIFO capacity")
     ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
     ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
-    ap.add_argument("--sample-every", type=int, default=8, help="time every n-th kernel launch with HIP events")
+    ap.add_argument("--sample-every", type=int, default=7,
+                    help="time every n-th launch of each kernel kind with HIP events (7: coprime to the
+                         four Dslash launches of a CG iteration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

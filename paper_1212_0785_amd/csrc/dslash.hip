@@ -14,6 +14,8 @@
 // contiguous 1 KiB (FP64) span; neighbour spinors are re-read through L2,
 // and the XCD-aware block order keeps the +-y/+-z neighbours of a block on
 // the XCD that owns it.
+#include <hip/hip_ext.h>
+
 #include <cstdlib>
 #include <type_traits>
 
@@ -254,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, con
 
 template <class SP, class LK>
 static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_par, const DslashArgs* table,
-                               int nbatch, const DslashArgs& one, hipStream_t st, int j) {
+                               int nbatch, const DslashArgs& one, hipStream_t st, int j, KernelEvents ev) {
   Lat g;
   for (int k = 0; k < 4; ++k) g.L[k] = ga.L[k];
   g.Vh = ga.Vh;
@@ -262,24 +264,26 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   const hmc_prec prec = std::is_same_v<typename SP::R, double> ? HMC_F64 : HMC_F32;
   const bool split = dslash_split(ga.Vh, prec);
   dim3 grid(dslash_blocks(ga.Vh, prec), nbatch), block(kBlock);
-#define HMC_DS(D, E)                                                                                           \
-  do {                                                                                                        \
-    if (split) {                                                                                              \
-      if (table)                                                                                              \
-        hipLaunchKernelGGL((k_dslash_split<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one, j);  \
-      else                                                                                                    \
-        hipLaunchKernelGGL((k_dslash_split<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one, j); \
-    } else if (table)                                                                                         \
-      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, true>), grid, block, 0, st, g, out_par, table, one, j);         \
-    else                                                                                                      \
-      hipLaunchKernelGGL((k_dslash<SP, LK, D, E, false>), grid, block, 0, st, g, out_par, table, one, j);        \
+#define HMC_LAUNCH(KERNEL) \
+  hipExtLaunchKernelGGL(KERNEL, grid, block, 0, st, ev.start, ev.stop, 0, g, out_par, table, one, j)
+#define HMC_DS(D, E)                                                   \
+  do {                                                                \
+    if (split) {                                                      \
+      if (table)                                                      \
+        HMC_LAUNCH((k_dslash_split<SP, LK, D, E, true>));             \
+      else                                                            \
+        HMC_LAUNCH((k_dslash_split<SP, LK, D, E, false>));            \
+    } else if (table)                                                 \
+      HMC_LAUNCH((k_dslash<SP, LK, D, E, true>));                     \
+    else                                                              \
+      HMC_LAUNCH((k_dslash<SP, LK, D, E, false>));                    \
   } while (0)
   if (epi == EPI_CG) {  // last hop of a CG iteration: dagger, one solve
     if (table || !dagger) return hipErrorInvalidValue;
     if (split)
-      hipLaunchKernelGGL((k_dslash_split<SP, LK, true, EPI_CG, false>), grid, block, 0, st, g, out_par, table, one, j);
+      HMC_LAUNCH((k_dslash_split<SP, LK, true, EPI_CG, false>));
     else
-      hipLaunchKernelGGL((k_dslash<SP, LK, true, EPI_CG, false>), grid, block, 0, st, g, out_par, table, one, j);
+      HMC_LAUNCH((k_dslash<SP, LK, true, EPI_CG, false>));
     return hipGetLastError();
   }
   if (dagger) {
@@ -292,6 +296,7 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
     else HMC_DS(false, EPI_AXPY_NORM);
   }
 #undef HMC_DS
+#undef HMC_LAUNCH
   return hipGetLastError();
 }
 
@@ -322,9 +327,9 @@ static hipError_t launch_links(int dagger, int epi, const LatArg& g, int out_par
   // y, +1 more for the residual read by the CG epilogue)
   const double site_bytes = 8.0 * (rows2 ? LkRows2<LK>::kBytes : LK::kBytes) + 2 * SP::kBytes +
                             (epi ? SP::kBytes : 0) + (epi == EPI_CG ? SP::kBytes : 0);
-  TimedScope ts(TK_DSLASH, st, site_bytes * g.Vh * nbatch);
-  if (rows2) return launch_typed<SP, LkRows2<LK>>(dagger, epi, g, out_par, table, nbatch, one, st, j);
-  return launch_typed<SP, LK>(dagger, epi, g, out_par, table, nbatch, one, st, j);
+  const KernelEvents ev = timing_kernel_events(TK_DSLASH, site_bytes * g.Vh * nbatch);
+  if (rows2) return launch_typed<SP, LkRows2<LK>>(dagger, epi, g, out_par, table, nbatch, one, st, j, ev);
+  return launch_typed<SP, LK>(dagger, epi, g, out_par, table, nbatch, one, st, j, ev);
 }
 
 hipError_t launch_dslash(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,

@@ -82,6 +82,25 @@ bool timing_begin(int kernel, hipStream_t st, double bytes) {
   return true;
 }
 
+KernelEvents timing_kernel_events(int kernel, double bytes) {
+  KernelEvents ev;
+  Timing& T = timing();
+  if (T.sample_every <= 0) return ev;
+  std::lock_guard<std::mutex> lk(T.mu);
+  if (T.counter[kernel]++ % T.sample_every) return ev;
+  int pair = (int)T.recs.size();
+  if (pair >= kMaxPairs) return ev;
+  while ((int)T.events.size() < 2 * (pair + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return ev;
+    T.events.push_back(e);
+  }
+  T.recs.push_back({kernel, pair, bytes});
+  ev.start = T.events[2 * pair];
+  ev.stop = T.events[2 * pair + 1];
+  return ev;
+}
+
 void timing_end(int kernel, hipStream_t st) {
   (void)kernel;
   Timing& T = timing();

@@ -226,6 +226,17 @@ const char* timed_kernel_name(int k);
 bool timing_begin(int kernel, hipStream_t st, double bytes);
 void timing_end(int kernel, hipStream_t st);
 
+// Event pair for a sampled launch of `kernel` (both null when this launch is
+// not sampled).  Passed to hipExtLaunchKernelGGL, the events take the
+// kernel's own start and end stamps, so their elapsed time is the kernel's
+// duration as a kernel trace reports it.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+KernelEvents timing_kernel_events(int kernel, double bytes);
+
+// Brackets a launch with events recorded on the stream (includes the
+// dispatch of the kernel).
 struct TimedScope {
   int k;
   hipStream_t st;
