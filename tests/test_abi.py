@@ -81,3 +81,15 @@ def test_arena_too_small_is_oom(H):
 def test_null_arguments_rejected(H):
     assert H.lib().hmc_free_fields(None) == H.HMC_E_ARG
     assert H.lib().hmc_plaquette(None, None, None) == H.HMC_E_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py has no multi-GPU path: --gpus N > 1 exits 2 with a message
+    (checked before anything touches a GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
