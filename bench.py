@@ -424,9 +424,9 @@ def main():
     ap.add_argument("--rho", type=float, default=0.9, help="serve: offered load relative to FP64 FIFO capacity")
     ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
     ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
-    ap.add_argument("--sample-every", type=int, default=7,
-                    help=("time every n-th launch of each kernel kind with HIP events (7: coprime to the "
-                          "four Dslash launches of a CG iteration)"))
+    ap.add_argument("--sample-every", type=int, default=31,
+                    help=("time every n-th launch of each kernel kind with HIP events (31: coprime to the "
+                          "four Dslash launches of a CG iteration; each sampled launch costs the GPU a few us)"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

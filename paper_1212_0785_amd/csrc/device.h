@@ -712,10 +712,10 @@ __device__ __forceinline__ void box_muller(uint64_t w0, uint64_t w1, double* g0,
 
 // Deterministic sum over the block: wave64 butterfly (fixed xor order),
 // then wave partials combined by thread 0 in wave order.  Result valid in
-// thread 0 only.  `N` values reduced at once.
-template <int N>
+// thread 0 only.  `N` values reduced at once; W wavefronts per block.
+template <int N, int W = kBlock / 64>
 __device__ __forceinline__ void block_sum(double* v) {
-  __shared__ double red[N][kBlock / 64];
+  __shared__ double red[N][W];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
@@ -730,18 +730,20 @@ __device__ __forceinline__ void block_sum(double* v) {
     for (int k = 0; k < N; ++k) {
       double s = red[k][0];
 #pragma unroll
-      for (int w = 1; w < kBlock / 64; ++w) s += red[k][w];
+      for (int w = 1; w < W; ++w) s += red[k][w];
       v[k] = s;
     }
 }
 
-// Every block sums the same n partials in the same order and gets the same
-// bit pattern; the result is broadcast to all threads of the block.
+// Every block (of W wavefronts) sums the same n partials in the same order
+// and gets the same bit pattern; the result is broadcast to all threads of
+// the block.
+template <int W = kBlock / 64>
 __device__ __forceinline__ double sum_partials(const double* part, int n) {
   __shared__ double bc;
   double v[1] = {0.0};
-  for (int k = threadIdx.x; k < n; k += kBlock) v[0] += part[k];
-  block_sum<1>(v);
+  for (int k = threadIdx.x; k < n; k += 64 * W) v[0] += part[k];
+  block_sum<1, W>(v);
   if (threadIdx.x == 0) bc = v[0];
   __syncthreads();
   double r = bc;

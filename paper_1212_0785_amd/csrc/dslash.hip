@@ -90,10 +90,11 @@ __device__ __forceinline__ void hop_dir(const Lat& g, const Site& st, int out_pa
 
 // Block 0 computes the solver step length from the partial sums of the
 // previous kernels (see DslashArgs::alpha_out); the other blocks skip it.
+template <int W = kBlock / 64>
 __device__ __forceinline__ void alpha_prologue(const DslashArgs& e, int label) {
   if (!e.alpha_out || blockIdx.x != 0) return;
-  const double num = sum_partials(e.alpha_pp[label & 1], e.alpha_n_pp);
-  const double den = sum_partials(e.alpha_den, e.alpha_n_den);
+  const double num = sum_partials<W>(e.alpha_pp[label & 1], e.alpha_n_pp);
+  const double den = sum_partials<W>(e.alpha_den, e.alpha_n_den);
   if (threadIdx.x == 0) *(HMC_GLOBAL double*)e.alpha_out = num / den;
 }
 
@@ -157,18 +158,21 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
   }
 }
 
-// Direction-split variant: a block covers 64 sites; wave w computes the two
-// hops along direction w for those sites and parks its partial sum in LDS;
-// after a barrier each work-item combines the four partials of 3 of the 12
-// components of one site (coalesced stores).  Four times the wavefronts of
-// the one-site-per-work-item kernel at the same registers per work-item,
-// and a quarter of the serial hop chain per wavefront.
-template <class SP, class LK, bool DAG, int EPI, bool BATCH>
-__global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, const DslashArgs* __restrict__ table,
-                                                         DslashArgs one, int j) {
+// Direction-split variant: a block covers 64 sites with NW wavefronts
+// (NW = 2 or 4); wave w computes the hops along directions
+// w*4/NW .. (w+1)*4/NW - 1 for those sites and parks its partial sum in
+// LDS; after a barrier each work-item combines the NW partials of 12/NW of
+// the 12 components of one site (coalesced stores).  NW times the
+// wavefronts of the one-site-per-work-item kernel at the same registers per
+// work-item, and 1/NW of its serial hop chain per wavefront.
+template <class SP, class LK, bool DAG, int EPI, bool BATCH, int NW>
+__global__ void __launch_bounds__(NW * 64) k_dslash_split(Lat g, int out_par, const DslashArgs* __restrict__ table,
+                                                          DslashArgs one, int j) {
   using R = typename SP::R;
-  constexpr int kSites = kBlock / 4;
-  __shared__ cx<R> part[4][12][kSites];
+  constexpr int kSites = 64;
+  constexpr int kDirs = 4 / NW;    // directions per wavefront
+  constexpr int kParts = 4 / NW;   // groups of 3 components per work-item in the combine
+  __shared__ cx<R> part[NW][12][kSites];
   const DslashArgs* ep;
   if constexpr (BATCH)
     ep = table + blockIdx.y;
@@ -177,9 +181,9 @@ __global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, con
   const DslashArgs& e = *ep;
   const int label = e.iter0 + j;
   if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
-  alpha_prologue(e, label);
+  alpha_prologue<NW>(e, label);
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int mu = threadIdx.x >> 6;  // wave index = direction (uniform per wave)
+  const int w = threadIdx.x >> 6;  // wave index (uniform per wave)
   const int ls = threadIdx.x & (kSites - 1);
   const int s = b * kSites + ls;
   {
@@ -188,33 +192,47 @@ __global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, con
     for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
     if (s < g.Vh) {
       const Site st = cb_site(g, out_par, s);
-      switch (mu) {
-        case 0: hop_dir<SP, LK, 0, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
-        case 1: hop_dir<SP, LK, 1, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
-        case 2: hop_dir<SP, LK, 2, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
-        default: hop_dir<SP, LK, 3, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+      if constexpr (NW == 4) {
+        switch (w) {
+          case 0: hop_dir<SP, LK, 0, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+          case 1: hop_dir<SP, LK, 1, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+          case 2: hop_dir<SP, LK, 2, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+          default: hop_dir<SP, LK, 3, DAG>(g, st, out_par, s, e.U, e.in, acc); break;
+        }
+      } else {
+        if (w == 0) {
+          hop_dir<SP, LK, 0, DAG>(g, st, out_par, s, e.U, e.in, acc);
+          hop_dir<SP, LK, 1, DAG>(g, st, out_par, s, e.U, e.in, acc);
+        } else {
+          hop_dir<SP, LK, 2, DAG>(g, st, out_par, s, e.U, e.in, acc);
+          hop_dir<SP, LK, 3, DAG>(g, st, out_par, s, e.U, e.in, acc);
+        }
       }
     }
 #pragma unroll
-    for (int k = 0; k < 12; ++k) part[mu][k][ls] = acc[k];
+    for (int k = 0; k < 12; ++k) part[w][k][ls] = acc[k];
   }
+  (void)kDirs;
   __syncthreads();
-  // work-item (ls, mu) now owns components 3*mu .. 3*mu+2 of site s
+  // work-item (ls, w) now owns components 3*kParts*w .. 3*kParts*(w+1)-1 of site s
   double nrm[1] = {0.0};
-  cx<R> o[3];
+  cx<R> o[3 * kParts];
   const bool active = s < g.Vh;
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int k = 3 * mu + c;
-      o[c] = part[0][k][ls] + part[1][k][ls] + part[2][k][ls] + part[3][k][ls];
+    for (int c = 0; c < 3 * kParts; ++c) {
+      const int k = 3 * kParts * w + c;
+      cx<R> t = part[0][k][ls];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) t = t + part[q][k][ls];
+      o[c] = t;
     }
     if (EPI != EPI_PLAIN) {
       const R a = (R)e.a, bb = (R)e.b;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 3 * kParts; ++c) {
         if (e.y) {
-          const cx<R> y = SP::load_one(e.y, g.stride, s, 3 * mu + c);
+          const cx<R> y = SP::load_one(e.y, g.stride, s, 3 * kParts * w + c);
           o[c] = {fma(bb, o[c].re, a * y.re), fma(bb, o[c].im, a * y.im)};
         } else {
           o[c] = bb * o[c];
@@ -224,31 +242,37 @@ __global__ void __launch_bounds__(kBlock) k_dslash_split(Lat g, int out_par, con
     if (EPI == EPI_CG) {
       const R al = (R)(*(const HMC_GLOBAL double*)e.alpha_in);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const cx<R> rv = SP::load_one(e.r, g.stride, s, 3 * mu + c);
+      for (int c = 0; c < 3 * kParts; ++c) {
+        const cx<R> rv = SP::load_one(e.r, g.stride, s, 3 * kParts * w + c);
         o[c] = {fma(-al, o[c].re, rv.re), fma(-al, o[c].im, rv.im)};
       }
     }
     if (EPI == EPI_AXPY_NORM || EPI == EPI_CG)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) nrm[0] += (double)o[c].re * o[c].re + (double)o[c].im * o[c].im;
+      for (int c = 0; c < 3 * kParts; ++c) nrm[0] += (double)o[c].re * o[c].re + (double)o[c].im * o[c].im;
   }
   if constexpr (SP::kScaled) {
     // the per-site scale needs the largest |re|, |im| over all 12 components
-    __shared__ float smax[4][kSites];
+    __shared__ float smax[NW][kSites];
     float m = 0.f;
     if (active)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf((float)o[c].re), fabsf((float)o[c].im)));
-    smax[mu][ls] = m;
+      for (int c = 0; c < 3 * kParts; ++c) m = fmaxf(m, fmaxf(fabsf((float)o[c].re), fabsf((float)o[c].im)));
+    smax[w][ls] = m;
     __syncthreads();
-    m = fmaxf(fmaxf(smax[0][ls], smax[1][ls]), fmaxf(smax[2][ls], smax[3][ls]));
-    if (active) SP::store_part_scaled(e.out, g.stride, s, mu, o, m);
+    m = smax[0][ls];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) m = fmaxf(m, smax[q][ls]);
+    if (active)
+#pragma unroll
+      for (int q = 0; q < kParts; ++q) SP::store_part_scaled(e.out, g.stride, s, kParts * w + q, o + 3 * q, m);
   } else {
-    if (active) SP::store_part(e.out, g.stride, s, mu, o);
+    if (active)
+#pragma unroll
+      for (int q = 0; q < kParts; ++q) SP::store_part(e.out, g.stride, s, kParts * w + q, o + 3 * q);
   }
   if (EPI == EPI_AXPY_NORM || EPI == EPI_CG) {
-    block_sum<1>(nrm);
+    block_sum<1, NW>(nrm);
     double* dst = e.partial_pp[0] ? e.partial_pp[(label + 1) & 1] : e.partial;
     if (threadIdx.x == 0) ((HMC_GLOBAL double*)dst)[b] = nrm[0];
   }
@@ -262,28 +286,30 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   g.Vh = ga.Vh;
   g.stride = ga.stride;
   const hmc_prec prec = std::is_same_v<typename SP::R, double> ? HMC_F64 : HMC_F32;
-  const bool split = dslash_split(ga.Vh, prec);
-  dim3 grid(dslash_blocks(ga.Vh, prec), nbatch), block(kBlock);
+  const int ways = dslash_split_ways(ga.Vh, prec);
+  const dim3 grid(dslash_blocks(ga.Vh, prec), nbatch);
+  const dim3 block(ways ? 64 * ways : kBlock);
 #define HMC_LAUNCH(KERNEL) \
   hipExtLaunchKernelGGL(KERNEL, grid, block, 0, st, ev.start, ev.stop, 0, g, out_par, table, one, j)
-#define HMC_DS(D, E)                                                   \
-  do {                                                                \
-    if (split) {                                                      \
-      if (table)                                                      \
-        HMC_LAUNCH((k_dslash_split<SP, LK, D, E, true>));             \
-      else                                                            \
-        HMC_LAUNCH((k_dslash_split<SP, LK, D, E, false>));            \
-    } else if (table)                                                 \
-      HMC_LAUNCH((k_dslash<SP, LK, D, E, true>));                     \
-    else                                                              \
-      HMC_LAUNCH((k_dslash<SP, LK, D, E, false>));                    \
+#define HMC_DS_B(D, E, B)                                  \
+  do {                                                     \
+    if (ways == 4)                                         \
+      HMC_LAUNCH((k_dslash_split<SP, LK, D, E, B, 4>));    \
+    else if (ways == 2)                                    \
+      HMC_LAUNCH((k_dslash_split<SP, LK, D, E, B, 2>));    \
+    else                                                   \
+      HMC_LAUNCH((k_dslash<SP, LK, D, E, B>));             \
+  } while (0)
+#define HMC_DS(D, E)            \
+  do {                          \
+    if (table)                  \
+      HMC_DS_B(D, E, true);     \
+    else                        \
+      HMC_DS_B(D, E, false);    \
   } while (0)
   if (epi == EPI_CG) {  // last hop of a CG iteration: dagger, one solve
     if (table || !dagger) return hipErrorInvalidValue;
-    if (split)
-      HMC_LAUNCH((k_dslash_split<SP, LK, true, EPI_CG, false>));
-    else
-      HMC_LAUNCH((k_dslash<SP, LK, true, EPI_CG, false>));
+    HMC_DS_B(true, EPI_CG, false);
     return hipGetLastError();
   }
   if (dagger) {
@@ -296,19 +322,22 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
     else HMC_DS(false, EPI_AXPY_NORM);
   }
 #undef HMC_DS
+#undef HMC_DS_B
 #undef HMC_LAUNCH
   return hipGetLastError();
 }
 
-bool dslash_split(int Vh, hmc_prec prec) {
+int dslash_split_ways(int Vh, hmc_prec prec) {
   static const int forced = [] {
     const char* e = getenv("HMC_DSLASH_SPLIT");
-    return e ? atoi(e) : -1;
+    if (!e) return -1;
+    const int v = atoi(e);
+    return v == 1 ? 4 : (v == 2 || v == 4) ? v : 0;
   }();
-  if (forced >= 0) return forced != 0;
-  // measured on MI355X: the split form gains for FP32 arithmetic up to
+  if (forced >= 0) return forced;
+  // measured on MI355X: the 4-way split gains for FP32 arithmetic up to
   // 16^3x32 and loses at 48^3x96; FP64 is even at 16^3x32
-  return prec != HMC_F64 && Vh <= (1 << 17);
+  return (prec != HMC_F64 && Vh <= (1 << 17)) ? 4 : 0;
 }
 
 bool link_rows2_enabled() {

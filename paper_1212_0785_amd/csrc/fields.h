@@ -70,6 +70,7 @@ struct Fields {
   // kept by the reunitarised updates).  su3_old: the same for U_old.
   bool su3, su3_old;
   double* pinned;  // host, hipHostMalloc'ed, SL_COUNT + 64 doubles
+  hipEvent_t state_ev[2];  // solver-state read-backs in flight (pinned + SL_COUNT + 8 * i)
 };
 
 inline Fields* as_fields(hmc_fields* f) { return reinterpret_cast<Fields*>(f); }

@@ -343,7 +343,17 @@ hmc_status hmc_alloc_fields(const hmc_geom* geom, const hmc_action* action, uint
   F->u_version = 1;
   for (int k = 0; k < 4; ++k) F->low_version[k] = 0;
   F->su3 = F->su3_old = false;  // U holds whatever the arena held
+  F->state_ev[0] = F->state_ev[1] = nullptr;
+  if (hipEventCreateWithFlags(&F->state_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&F->state_ev[1], hipEventDisableTiming) != hipSuccess) {
+    for (hipEvent_t e : F->state_ev)
+      if (e) hipEventDestroy(e);
+    delete F;
+    set_error("hipEventCreate failed");
+    return HMC_E_HIP;
+  }
   if (hipHostMalloc((void**)&F->pinned, (SL_COUNT + 64) * sizeof(double)) != hipSuccess) {
+    for (hipEvent_t e : F->state_ev) hipEventDestroy(e);
     delete F;
     set_error("hipHostMalloc of the scalar read-back buffer failed");
     return HMC_E_HIP;
@@ -355,6 +365,8 @@ hmc_status hmc_alloc_fields(const hmc_geom* geom, const hmc_action* action, uint
 hmc_status hmc_free_fields(hmc_fields* f) {
   FIELDS(f);
   if (F->pinned) hipHostFree(F->pinned);
+  for (hipEvent_t e : F->state_ev)
+    if (e) hipEventDestroy(e);
   delete F;
   return HMC_OK;
 }

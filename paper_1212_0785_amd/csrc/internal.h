@@ -34,13 +34,14 @@ inline int blas_blocks(int Vh) {
 inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 
 // Dslash kernel shape: one site per work-item (256 sites per block) or the
-// direction-split form (64 sites per block, four wavefronts per group of
+// direction-split form (64 sites per block, 2 or 4 wavefronts per group of
 // sites), taken for the single-precision-arithmetic storages at volumes too
-// small to fill the GPU with one wavefront per 64 sites.
-// HMC_DSLASH_SPLIT=0/1 (read once) overrides the rule.
-bool dslash_split(int Vh, hmc_prec prec);
+// small to fill the GPU with one wavefront per 64 sites.  Returns the
+// wavefronts per site group (0: one site per work-item);
+// HMC_DSLASH_SPLIT=0/2/4 (read once; 1 means 4) overrides the rule.
+int dslash_split_ways(int Vh, hmc_prec prec);
 inline int dslash_blocks(int Vh, hmc_prec prec) {
-  return dslash_split(Vh, prec) ? ceil_div(Vh, kThreads / 4) : site_blocks(Vh);
+  return dslash_split_ways(Vh, prec) ? ceil_div(Vh, kThreads / 4) : site_blocks(Vh);
 }
 // Largest block count (and Dslash-epilogue partial count) of either shape.
 inline int dslash_blocks_max(int Vh) { return ceil_div(Vh, kThreads / 4); }

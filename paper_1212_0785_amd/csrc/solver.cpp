@@ -191,36 +191,84 @@ hipError_t read_state(Fields* F, SolverState* out, hipStream_t st) {
   return hipSuccess;
 }
 
+// A chunk of enqueued iterations whose solver state is being copied back
+// into pinned slot `slot` (completion marked by F->state_ev[slot]).
+struct Chunk {
+  int k, n, slot;
+};
+
+hipError_t enqueue_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, const Chunk& c, hipStream_t st) {
+  for (int j = 0; j < c.n; ++j) {
+    hipError_t e = launch_iteration(v.g, v.prec, v.cgls, nullptr, args, 1, v.nbD, v.nbR, c.k + j, st);
+    if (e != hipSuccess) return e;
+  }
+  static_assert(sizeof(SolverState) <= 8 * sizeof(double), "state slot");
+  hipError_t e = hipMemcpyAsync(F->pinned + SL_COUNT + 8 * c.slot, F->state, sizeof(SolverState),
+                                hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(F->state_ev[c.slot], st);
+}
+
+hipError_t wait_chunk(Fields* F, const Chunk& c, SolverState* out) {
+  hipError_t e = hipEventSynchronize(F->state_ev[c.slot]);
+  if (e != hipSuccess) return e;
+  std::memcpy(out, F->pinned + SL_COUNT + 8 * c.slot, sizeof(SolverState));
+  return hipSuccess;
+}
+
 // Runs iterations with labels *k.. until the device stops or `limit` is
-// reached; leaves the next label in *k.  After the first chunk the chunk
-// length follows the observed convergence rate toward `target` (|r|^2 at
-// which the device will stop), so few iterations are enqueued past the stop.
-// *rate carries log(|r|^2) per iteration between calls (0 = unknown).
+// reached; leaves the next label in *k.  The chunk length follows the
+// observed convergence rate toward `target` (|r|^2 at which the device will
+// stop), so few iterations are enqueued past the stop; while the host waits
+// for one chunk's state, the next chunk is already queued whenever the
+// prediction says the stop lies beyond the first, so the GPU does not idle
+// during the read-back.  *rate carries log(|r|^2) per iteration between
+// calls (0 = unknown).  Iterations enqueued past the stop exit at once.
 hipError_t run_until_stop(Fields* F, const SolveVecs& v, const IterArgs& args, int* k, int limit, SolverState* stt,
                           hipStream_t st, double rr_start, double target, double* rate) {
+  const bool fixed = !(target > 0);
+  // iterations still needed from residual rr (kChunk when unknown)
+  auto predict = [&](double rr) -> double {
+    if (fixed) return limit;
+    if (*rate < 0 && rr > 0) return std::log(target / rr) / *rate;
+    return kChunk;
+  };
   double rr_now = rr_start;
-  while (*k < limit) {
-    int n = kChunk;
-    if (*rate < 0 && rr_now > 0 && target > 0) {
-      const double left = std::log(target / rr_now) / *rate;
-      if (left < kChunk) n = std::max(1, (int)std::ceil(left));
+  int next = *k;
+  if (next >= limit) return hipSuccess;
+  Chunk cur{next, std::min({kChunk, limit - next, std::max(1, (int)std::ceil(predict(rr_now)))}), 0};
+  hipError_t e = enqueue_chunk(F, v, args, cur, st);
+  if (e != hipSuccess) return e;
+  next += cur.n;
+  while (true) {
+    // queue the following chunk before waiting when the stop is predicted past this one
+    Chunk nxt{next, 0, cur.slot ^ 1};
+    const double after = predict(rr_now) - cur.n;
+    if (next < limit && (fixed ? after >= 1.0 : after >= 2.0)) {
+      // CG often speeds up near the end: queue 80% of the predicted rest
+      nxt.n = std::min({kChunk, limit - next, fixed ? (int)after : std::max(1, (int)(0.8 * after))});
+      if ((e = enqueue_chunk(F, v, args, nxt, st))) return e;
+      next += nxt.n;
     }
-    n = std::min(n, limit - *k);
-    for (int j = 0; j < n; ++j) {
-      hipError_t e = launch_iteration(v.g, v.prec, v.cgls, nullptr, args, 1, v.nbD, v.nbR, *k + j, st);
-      if (e != hipSuccess) return e;
-    }
-    hipError_t e = read_state(F, stt, st);
-    if (e != hipSuccess) return e;
+    if ((e = wait_chunk(F, cur, stt))) return e;
     if (stt->stop_at != INT_MAX) {
       *k = stt->last + 1;
+      return hipSuccess;  // a queued chunk after the stop exits at once
+    }
+    if (stt->rr > 0 && rr_now > 0 && stt->rr < rr_now) *rate = std::log(stt->rr / rr_now) / cur.n;
+    rr_now = stt->rr;
+    if (nxt.n > 0) {
+      cur = nxt;
+      continue;
+    }
+    if (next >= limit) {
+      *k = next;
       return hipSuccess;
     }
-    *k += n;
-    if (stt->rr > 0 && rr_now > 0 && stt->rr < rr_now) *rate = std::log(stt->rr / rr_now) / n;
-    rr_now = stt->rr;
+    cur = Chunk{next, std::min({kChunk, limit - next, std::max(1, (int)std::ceil(predict(rr_now)))}), cur.slot ^ 1};
+    if ((e = enqueue_chunk(F, v, args, cur, st))) return e;
+    next += cur.n;
   }
-  return hipSuccess;
 }
 
 }  // namespace
