@@ -422,6 +422,29 @@ def test_trajectory_parity_c1(H):
         assert rel(get_gauge(H, F), U) < 1e-12
 
 
+def test_trajectory_parity_c2_short(H):
+    """The benchmark's 16^3x32 HMC (beta 5.6, kappa 0.156, weak-field start
+    eps 0.3, seed 12120785, step 0.05) over a shortened trajectory (tau 0.1,
+    two leapfrog steps: three force evaluations and solves at full size):
+    energies, plaquette, links and the accept decision against the oracle."""
+    L = (16, 16, 16, 32)
+    seed, beta, k = 12120785, 5.6, 0.156
+    F = H.Fields(L, beta, k)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    U = O.weak_field(L, seed, 0.3)
+    assert rel(get_gauge(H, F), U) < 1e-14
+    r = H.hmc_trajectory(F, seed, 0, 0.1, 2, H.cg_params(tol=1e-10))
+    U, o = O.hmc_trajectory(L, U, beta, k, seed, 0, 0.1, 2, tol=1e-10)
+    assert r["status"] == 0 and o["status"] == 0
+    assert r["u"] == o["u"]
+    assert r["accepted"] == o["accepted"]
+    for key in ("H_old", "H_new", "KE_old", "KE_new", "S_g_old", "S_g_new", "S_f_old", "S_f_new"):
+        assert abs(r[key] - o[key]) < 1e-12 * abs(o[key]), key
+    assert abs(r["dH"] - o["dH"]) < 1e-12 * abs(o["H_old"])
+    assert abs(r["plaquette"] - o["plaquette"]) < 1e-12
+    assert rel(get_gauge(H, F), U) < 1e-12
+
+
 def test_trajectory_accepts_at_small_step(H):
     # a finer integration gives |dH| small enough to accept; both sides agree
     L = (4, 4, 4, 4)
