@@ -276,6 +276,7 @@ def run_cg(args, H, torch):
     nsrc = args.steps
     rows = {}
     ref = {}
+    first = {}  # solution of source 0 per precision (for the oracle comparison)
     b = F.spinor(full=True)
     x = F.spinor(full=True)
     for prec, name in ((H.F64, "f64"), (H.F32, "f32"), (H.F16, "f16"), (H.BF16, "bf16")):
@@ -288,6 +289,8 @@ def run_cg(args, H, torch):
             torch.cuda.synchronize()
             st = H.hmc_cg_solve(F, x, b, prm)
             torch.cuda.synchronize()
+            if k == 0:
+                first[name] = x.clone()
             if prec == H.F64:
                 ref[k] = x.clone()
                 err = 0.0
@@ -314,8 +317,35 @@ def run_cg(args, H, torch):
                         "max_rel_diff_vs_f64": max(r["rel_diff_vs_f64"] for r in v["solves"])}
                     for k, v in rows.items()},
         "fastest_mixed": best,
+        "_fields": F,
     }
-    return out
+    return out, first
+
+
+def oracle_solve_sample(L, kappa, first, H, F, torch):
+    """The FP64 oracle's CGLS Wilson solve of source 0 (the CPU baseline,
+    one solve, ~10-20 s on 16 host cores) and the difference of every GPU
+    precision's solution of the same source from it."""
+    import numpy as np
+
+    import oracle as O
+    U = O.weak_field(L, 1, 0.5)
+    b = O.source(L, 0, 1, 0)
+    t0 = time.perf_counter()
+    xo, st = O.wilson_solve(L, U, kappa, b, tol=1e-10, maxiter=50000)
+    dt = time.perf_counter() - t0
+    err = {}
+    for name, xg in first.items():
+        c = H.canon_spinor_zeros(L)
+        H.hmc_export_spinor(F, c, xg, -1)
+        torch.cuda.synchronize()
+        xgn = c.cpu().numpy()
+        err[name] = float(np.linalg.norm(xgn - xo) / np.linalg.norm(xo))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": dt, "unit": "s/solve", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle CGLS Wilson solve of source 0 (24^3x48, kappa {kappa}) to 1e-10: "
+                       f"{st['iters']} iterations, true residual {st['true_rel_res']:.2e}"),
+            "rel_err_vs_oracle": err}
 
 
 # ------------------------------------------------------------------ serve
@@ -433,7 +463,7 @@ def main():
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
-    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (4, 1), "serve": (64, 0), "copy": (20, 2)}[args.workload]
+    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (16, 1), "serve": (64, 0), "copy": (20, 2)}[args.workload]
     args.steps = args.steps if args.steps is not None else defaults[0]
     args.warmup = args.warmup if args.warmup is not None else defaults[1]
 
@@ -456,7 +486,12 @@ def main():
     elif args.workload == "copy":
         out = run_copy(args, H, torch)
     else:
-        out = run_cg(args, H, torch)
+        out, first = run_cg(args, H, torch)
+        if not args.no_cpu_baseline:
+            ob = oracle_solve_sample((24, 24, 24, 48), 0.157, first, H, out.pop("_fields"), torch)
+            out["cpu_baseline"] = {k: ob[k] for k in ("value", "unit", "cores", "kind", "sample")}
+            out["rel_err_vs_oracle"] = ob["rel_err_vs_oracle"]
+        out.pop("_fields", None)
     print(json.dumps(out))
 
 

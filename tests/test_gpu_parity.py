@@ -384,6 +384,32 @@ def test_wilson_solve_parity(H, prec):
         assert st["reliable_updates"] >= 1
 
 
+def test_wilson_solves_at_24c48_against_oracle(H):
+    """The precision study's configuration (24^3x48, kappa 0.157, weak-field
+    eps 0.5 seed 1, Gaussian source seed 1 epoch 0), generated on each side
+    from the seeds: FP64 and the three mixed-precision solves against the
+    oracle's FP64 CGLS solution."""
+    L = (24, 24, 24, 48)
+    k = 0.157
+    F = H.Fields(L, 5.6, k, flags=H.FIELDS_LOWPREC)
+    H.hmc_weak_field_start(F, 1, 0.5)
+    bb = F.spinor(full=True)
+    H.hmc_make_source(F, bb, 0, 1, 0)
+    U = O.weak_field(L, 1, 0.5)
+    b = O.source(L, 0, 1, 0)
+    assert rel(get_spinor(H, F, bb, -1), b) < 1e-15
+    want, ost = O.wilson_solve(L, U, k, b, tol=1e-10, maxiter=50000)
+    assert ost["status"] == 0 and ost["true_rel_res"] <= 1e-10
+    for prec in (0, 1, 2, 3):
+        x = F.spinor(full=True)
+        st = H.hmc_cg_solve(F, x, bb, H.cg_params(tol=1e-10, mode=H.CG_WILSON_SOLVE, prec=prec, maxiter=50000))
+        assert st["status"] == 0 and st["true_rel_res"] <= 1e-10, prec
+        got = get_spinor(H, F, x, -1)
+        # both solutions satisfy |b - M x| <= 1e-10 |b|; FP64 runs the same
+        # iteration as the oracle and agrees far closer than the bound
+        assert rel(got, want) < (1e-10 if prec == 0 else 1e-8), (prec, rel(got, want))
+
+
 # ------------------------------------------------------------------ HMC
 
 
