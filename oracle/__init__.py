@@ -48,6 +48,20 @@ class Action(C.Structure):
     _fields_ = [("beta", C.c_double), ("kappa", C.c_double), ("tol", C.c_double), ("maxiter", C.c_int)]
 
 
+class MtsAction(C.Structure):
+    _fields_ = [("beta", C.c_double), ("kappa", C.c_double), ("kappa_h", C.c_double), ("tol", C.c_double),
+                ("maxiter", C.c_int), ("n_ratio", C.c_int), ("n_heavy", C.c_int), ("n_gauge", C.c_int)]
+
+
+class MtsStats(C.Structure):
+    _fields_ = [("S1_old", C.c_double), ("S2_old", C.c_double), ("S1_new", C.c_double), ("S2_new", C.c_double),
+                ("solves_ratio", C.c_int), ("solves_heavy", C.c_int), ("gauge_forces", C.c_int),
+                ("link_updates", C.c_int)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class MdStats(C.Structure):
     _fields_ = [("solves", C.c_int), ("iters_total", C.c_int), ("iters_max", C.c_int),
                 ("nonconverged", C.c_int)]
@@ -98,6 +112,12 @@ def bind(path):
         "or_plaquette": (C.c_double, [_I, _P]),
         "or_gauge_action": (C.c_double, [_I, _P, C.c_double]),
         "or_gauge_force": (None, [_I, _P, C.c_double, _P]),
+        "or_eta2": (None, [_I, C.c_uint64, C.c_uint64, C.c_int, _P]),
+        "or_mts_force": (C.c_int, [_I, _P, _P, C.c_int, _P, _P, _P]),
+        "or_mts_schedule": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, _P, _P, C.c_int]),
+        "or_mts_integrate": (C.c_int, [_I, _P, _P, _P, _P, _P, C.c_double, _P, _P, _P, _P]),
+        "or_hmc_trajectory_mts": (C.c_int, [_I, _P, _P, C.c_uint64, C.c_uint64, C.c_double, _P, _P]),
+        "or_ratio_action": (C.c_double, [_I, _P, _P, _P]),
         "or_gauge_force_sites": (None, [_I, _P, C.c_double, _P, C.c_long, _P]),
         "or_fermion_force": (None, [_I, _P, C.c_double, _P, _P, _P]),
         "or_mat_exp": (None, [_P, _P]),
@@ -416,3 +436,62 @@ def hmc_trajectory(L, U, beta, kappa, seed, traj, tau, nsteps, tol=1e-10, maxite
     d = r.as_dict()
     d["status"] = status
     return U, d
+
+
+# ------------------------------------------------ mass preconditioning
+
+
+def mts_action(beta, kappa, kappa_h, n_ratio, n_heavy, n_gauge, tol=1e-10, maxiter=10000):
+    return MtsAction(beta, kappa, kappa_h, tol, maxiter, n_ratio, n_heavy, n_gauge)
+
+
+def eta2(L, seed, traj, parity=0):
+    e = spinor_zeros(L)
+    _load().or_eta2(_dims(L), seed, traj, parity, _ptr(e))
+    return e
+
+
+def mts_force(L, U, a: MtsAction, level, phi=None):
+    """Force of one monomial (0 ratio, 1 heavy, 2 gauge) -> (F, X, status)."""
+    F = gauge_zeros(L)
+    X = spinor_zeros(L)
+    ph = _c128(phi) if phi is not None else spinor_zeros(L)
+    s = _load().or_mts_force(_dims(L), _ptr(_c128(U)), C.byref(a), int(level), _ptr(ph), _ptr(X), _ptr(F))
+    return F, X, s
+
+
+def mts_schedule(n_ratio, n_heavy, n_gauge, tau):
+    """Coalesced nested-leapfrog schedule -> (coef[s, 3], eps[s])."""
+    m = n_ratio * n_heavy * n_gauge + 1
+    coef = np.zeros((m, 3))
+    eps = np.zeros(m)
+    ns = _load().or_mts_schedule(n_ratio, n_heavy, n_gauge, float(tau), _ptr(coef), _ptr(eps), m)
+    assert ns == m
+    return coef, eps
+
+
+def mts_integrate(L, U, P, phi1, phi2, a: MtsAction, tau):
+    """Returns (U, P, X1, X2, chi, stats, status); inputs untouched."""
+    U = _c128(U).copy(); P = _c128(P).copy()
+    X1, X2, chi = spinor_zeros(L), spinor_zeros(L), spinor_zeros(L)
+    ms = MtsStats()
+    s = _load().or_mts_integrate(_dims(L), _ptr(U), _ptr(P), _ptr(_c128(phi1)), _ptr(_c128(phi2)), C.byref(a),
+                                 float(tau), _ptr(X1), _ptr(X2), _ptr(chi), C.byref(ms))
+    return U, P, X1, X2, chi, ms.as_dict(), s
+
+
+def hmc_trajectory_mts(L, U, a: MtsAction, seed, traj, tau):
+    """One mass-preconditioned trajectory -> (U_after, result dict incl. the per-monomial actions)."""
+    U = _c128(U).copy()
+    r = TrajResult()
+    ms = MtsStats()
+    status = _load().or_hmc_trajectory_mts(_dims(L), _ptr(U), C.byref(a), seed, traj, float(tau), C.byref(r),
+                                           C.byref(ms))
+    d = r.as_dict()
+    d.update(ms.as_dict())
+    d["status"] = status
+    return U, d
+
+
+def ratio_action(L, U, a: MtsAction, phi2):
+    return _load().or_ratio_action(_dims(L), _ptr(_c128(U)), C.byref(a), _ptr(_c128(phi2)))

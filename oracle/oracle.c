@@ -585,7 +585,7 @@ void or_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64
 double or_u53(uint64_t w) { return ((double)(w >> 11) + 0.5) * 0x1p-53; }
 
 /* Random-stream assignment (counter word c2). */
-enum { ST_WEAKFIELD = 0, ST_MOMENTA = 1, ST_ETA = 2, ST_ACCEPT = 3, ST_SOURCE = 4 };
+enum { ST_WEAKFIELD = 0, ST_MOMENTA = 1, ST_ETA = 2, ST_ACCEPT = 3, ST_SOURCE = 4, ST_ETA2 = 5 };
 
 /* `nblocks` Philox blocks for site i: counter (block, i, stream, epoch),
  * key (seed, 0); words written in block order. */
@@ -672,9 +672,23 @@ void or_weak_field(const int *L, uint64_t seed, double eps, cplx *U)
     }
 }
 
+static void eta_stream(const int *L, uint64_t seed, uint64_t traj, int parity, int stream, cplx *eta);
+
 /* Pseudofermion noise eta on the sites of `parity`: complex Gaussian with
  * E|eta_k|^2 = 1, components (spin, colour, re/im) in that order. */
 void or_eta(const int *L, uint64_t seed, uint64_t traj, int parity, cplx *eta)
+{
+    eta_stream(L, seed, traj, parity, ST_ETA, eta);
+}
+
+/* The same noise from another Philox stream (the second pseudofermion of
+ * the mass-preconditioned action uses stream 5). */
+void or_eta2(const int *L, uint64_t seed, uint64_t traj, int parity, cplx *eta)
+{
+    eta_stream(L, seed, traj, parity, ST_ETA2, eta);
+}
+
+static void eta_stream(const int *L, uint64_t seed, uint64_t traj, int parity, int stream, cplx *eta)
 {
     long V = vol4(L);
     const double s = sqrt(0.5); /* 1/sqrt2, correctly rounded */
@@ -683,7 +697,7 @@ void or_eta(const int *L, uint64_t seed, uint64_t traj, int parity, cplx *eta)
         int c[4];
         coords_of(L, i, c);
         double g[24];
-        or_site_gaussians(seed, i, ST_ETA, traj, 24, g);
+        or_site_gaussians(seed, i, stream, traj, 24, g);
         for (int k = 0; k < 12; ++k)
             eta[i * 12 + k] = (parity_of(c) == parity) ? s * (g[2 * k] + I * g[2 * k + 1]) : 0;
     }
@@ -991,4 +1005,276 @@ int or_hmc_trajectory(const int *L, cplx *U, const or_action *a, uint64_t seed, 
     res->nonconverged = ms.nonconverged;
     free(U_old); free(P); free(eta); free(phi); free(Xe);
     return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Mass-preconditioned (Hasenbusch) action on several time scales.     */
+/* ------------------------------------------------------------------ */
+/* The paper's production run (Sec. 7) splits the two-flavour determinant
+ * with a heavier hopping parameter kappa_h < kappa,
+ *   det(A) = det(A_h) * det(A) / det(A_h),   A = Mhat^dag Mhat,
+ * with one pseudofermion per factor:
+ *   S_1 = phi_1^dag A_h^-1 phi_1,            phi_1 = Mhat_h^dag eta_1,
+ *   S_2 = chi^dag A^-1 chi, chi = Mhat_h^dag phi_2,
+ *                                            phi_2 = Mhat_h A_h^-1 Mhat^dag eta_2,
+ * so that S_1 = |eta_1|^2 and S_2 = |eta_2|^2 at the start (eta_1 from
+ * stream 2, eta_2 from stream 5).  The ratio force follows from
+ *   dS_2 = 2 Re(phi_2^dag dMhat_h X_2) - 2 Re((Mhat X_2)^dag dMhat X_2),
+ * X_2 = A^-1 chi: the fermion-force bilinear with (X_2, Mhat X_2, kappa)
+ * minus the same bilinear with (X_2, phi_2, kappa_h).  The monomials run on
+ * nested leapfrog time scales (Sexton-Weingarten): ratio (outer), heavy,
+ * gauge (inner), n_r, n_h, n_g steps per enclosing step. */
+
+typedef struct {
+    double beta, kappa, kappa_h;
+    double tol;
+    int maxiter;
+    int n_ratio, n_heavy, n_gauge;
+} or_mts_action;
+
+typedef struct {
+    double S1_old, S2_old, S1_new, S2_new;
+    int solves_ratio, solves_heavy, gauge_forces, link_updates;
+} or_mts_stats;
+
+/* Full-lattice X = (X_e, D_oe X_e) and Y = (Y_e, (D^dag)_oe Y_e). */
+static void bilinear_vectors(const int *L, const cplx *U, const cplx *Xe, const cplx *Ye, cplx *X, cplx *Y)
+{
+    long V = vol4(L), n = V * 12;
+    cplx *t = malloc(sizeof(cplx) * n);
+    or_dslash(L, U, Xe, t, 1, 0);
+    for (long i = 0; i < V; ++i) {
+        int even = or_site_parity(L, i) == 0;
+        for (int k = 0; k < 12; ++k) {
+            X[i * 12 + k] = even ? Xe[i * 12 + k] : t[i * 12 + k];
+            Y[i * 12 + k] = even ? Ye[i * 12 + k] : 0;
+        }
+    }
+    or_dslash(L, U, Y, t, 1, 1);
+    for (long i = 0; i < V; ++i)
+        if (or_site_parity(L, i) == 1)
+            for (int k = 0; k < 12; ++k) Y[i * 12 + k] = t[i * 12 + k];
+    free(t);
+}
+
+/* Force of the heavy monomial S_1 at U; X_1 = A_h^-1 phi_1 left in X1. */
+static int heavy_force(const int *L, const cplx *U, const or_mts_action *a, const cplx *phi1, cplx *X1, cplx *F,
+                       or_mts_stats *ms)
+{
+    long n = vol4(L) * 12;
+    or_cg_stats st;
+    int status = or_cg_mhat(L, U, a->kappa_h, phi1, X1, a->tol, a->maxiter, 0, &st);
+    ms->solves_heavy++;
+    cplx *ye = malloc(sizeof(cplx) * n), *X = malloc(sizeof(cplx) * n), *Y = malloc(sizeof(cplx) * n);
+    or_mhat(L, U, a->kappa_h, X1, ye, 0);
+    bilinear_vectors(L, U, X1, ye, X, Y);
+    or_fermion_force(L, U, a->kappa_h * a->kappa_h, X, Y, F);
+    free(ye); free(X); free(Y);
+    return status;
+}
+
+/* Force of the ratio monomial S_2 at U; X_2 = A^-1 chi left in X2 and chi
+ * = Mhat_h^dag phi_2 in chi. */
+static int ratio_force(const int *L, const cplx *U, const or_mts_action *a, const cplx *phi2, cplx *X2, cplx *chi,
+                       cplx *F, or_mts_stats *ms)
+{
+    long V = vol4(L), n = V * 12;
+    or_mhat(L, U, a->kappa_h, phi2, chi, 1);
+    or_cg_stats st;
+    int status = or_cg_mhat(L, U, a->kappa, chi, X2, a->tol, a->maxiter, 0, &st);
+    ms->solves_ratio++;
+    cplx *ye = malloc(sizeof(cplx) * n), *X = malloc(sizeof(cplx) * n), *Y = malloc(sizeof(cplx) * n);
+    cplx *F2 = malloc(sizeof(cplx) * V * 36);
+    or_mhat(L, U, a->kappa, X2, ye, 0);
+    bilinear_vectors(L, U, X2, ye, X, Y);
+    or_fermion_force(L, U, a->kappa * a->kappa, X, Y, F);
+    bilinear_vectors(L, U, X2, phi2, X, Y);
+    or_fermion_force(L, U, a->kappa_h * a->kappa_h, X, Y, F2);
+    for (long k = 0; k < V * 36; ++k) F[k] -= F2[k];
+    free(ye); free(X); free(Y); free(F2);
+    return status;
+}
+
+/* Monomial force (level 0 ratio, 1 heavy, 2 gauge), exposed for the force
+ * checks; returns the solver status. */
+int or_mts_force(const int *L, const cplx *U, const or_mts_action *a, int level, const cplx *phi, cplx *X,
+                 cplx *F)
+{
+    or_mts_stats ms;
+    memset(&ms, 0, sizeof ms);
+    long n = vol4(L) * 12;
+    if (level == 2) {
+        or_gauge_force(L, U, a->beta, F);
+        return 0;
+    }
+    if (level == 1) return heavy_force(L, U, a, phi, X, F, &ms);
+    cplx *chi = malloc(sizeof(cplx) * n);
+    int s = ratio_force(L, U, a, phi, X, chi, F, &ms);
+    free(chi);
+    return s;
+}
+
+/* The nested leapfrog as a flat list of operations: kicks (level, coef)
+ * and link updates (eps).  integrate(l, t): with e = t / n_l, a kick of
+ * e/2, then n_l times [the next level over e (links by e at the innermost
+ * level), a kick of e (e/2 after the last)].  Kicks between two link
+ * updates act on the same links and are summed per level. */
+typedef struct {
+    int kind;  /* 0..2 kick of that level, 3 link update */
+    double c;
+} mts_op;
+
+static void mts_emit(mts_op *ops, int *nops, int kind, double c)
+{
+    ops[*nops].kind = kind;
+    ops[*nops].c = c;
+    ++*nops;
+}
+
+static void mts_gen(const int *steps, int level, double t, mts_op *ops, int *nops)
+{
+    int n = steps[level];
+    double e = t / n;
+    mts_emit(ops, nops, level, 0.5 * e);
+    for (int k = 1; k <= n; ++k) {
+        if (level == 2)
+            mts_emit(ops, nops, 3, e);
+        else
+            mts_gen(steps, level + 1, e, ops, nops);
+        mts_emit(ops, nops, level, k < n ? e : 0.5 * e);
+    }
+}
+
+/* Coalesced schedule: for each stretch between link updates one summed
+ * coefficient per level (0 = not evaluated), then the update.  Returns the
+ * number of stretches; coef[s*3 + l], eps[s] (eps of the update that ends
+ * stretch s; 0 for the last). */
+int or_mts_schedule(int n_ratio, int n_heavy, int n_gauge, double tau, double *coef, double *eps, int max_stretch)
+{
+    int steps[3] = {n_ratio, n_heavy, n_gauge};
+    long cap = 4L * (2L * n_ratio + 2) * (2L * n_heavy + 2) * (2L * n_gauge + 2);
+    mts_op *ops = malloc(sizeof(mts_op) * cap);
+    int nops = 0;
+    mts_gen(steps, 0, tau, ops, &nops);
+    int s = 0;
+    double pend[3] = {0, 0, 0};
+    for (int k = 0; k < nops; ++k) {
+        if (ops[k].kind < 3) {
+            pend[ops[k].kind] += ops[k].c;
+            continue;
+        }
+        if (s >= max_stretch) { free(ops); return -1; }
+        for (int l = 0; l < 3; ++l) coef[s * 3 + l] = pend[l], pend[l] = 0;
+        eps[s] = ops[k].c;
+        ++s;
+    }
+    if (s >= max_stretch) { free(ops); return -1; }
+    for (int l = 0; l < 3; ++l) coef[s * 3 + l] = pend[l];
+    eps[s] = 0;
+    free(ops);
+    return s + 1;
+}
+
+/* Integrate over tau with the coalesced schedule; at each stretch the
+ * forces are applied in the order ratio, heavy, gauge.  X1/X2/chi receive
+ * the last solves. */
+int or_mts_integrate(const int *L, cplx *U, cplx *P, const cplx *phi1, const cplx *phi2, const or_mts_action *a,
+                     double tau, cplx *X1, cplx *X2, cplx *chi, or_mts_stats *ms)
+{
+    long V = vol4(L);
+    int maxs = a->n_ratio * a->n_heavy * a->n_gauge + 1;
+    double *coef = malloc(sizeof(double) * 3 * maxs), *eps = malloc(sizeof(double) * maxs);
+    int ns = or_mts_schedule(a->n_ratio, a->n_heavy, a->n_gauge, tau, coef, eps, maxs);
+    cplx *F = malloc(sizeof(cplx) * V * 36);
+    int status = ns < 0 ? -1 : 0;
+    for (int s = 0; s < ns; ++s) {
+        if (coef[s * 3 + 0] != 0) {
+            status |= ratio_force(L, U, a, phi2, X2, chi, F, ms);
+            or_momentum_update(L, P, F, coef[s * 3 + 0]);
+        }
+        if (coef[s * 3 + 1] != 0) {
+            status |= heavy_force(L, U, a, phi1, X1, F, ms);
+            or_momentum_update(L, P, F, coef[s * 3 + 1]);
+        }
+        if (coef[s * 3 + 2] != 0) {
+            or_gauge_force(L, U, a->beta, F);
+            ms->gauge_forces++;
+            or_momentum_update(L, P, F, coef[s * 3 + 2]);
+        }
+        if (eps[s] != 0) {
+            or_update_links(L, U, P, eps[s]);
+            ms->link_updates++;
+        }
+    }
+    free(coef); free(eps); free(F);
+    return status;
+}
+
+/* One mass-preconditioned HMC trajectory (momenta stream 1, eta_1 stream
+ * 2, eta_2 stream 5, Metropolis stream 3, all at epoch traj). */
+int or_hmc_trajectory_mts(const int *L, cplx *U, const or_mts_action *a, uint64_t seed, uint64_t traj, double tau,
+                          or_traj_result *res, or_mts_stats *ms)
+{
+    long V = vol4(L), n = V * 12;
+    cplx *U_old = malloc(sizeof(cplx) * V * 36), *P = malloc(sizeof(cplx) * V * 36);
+    cplx *eta1 = malloc(sizeof(cplx) * n), *eta2 = malloc(sizeof(cplx) * n);
+    cplx *phi1 = malloc(sizeof(cplx) * n), *phi2 = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
+    cplx *X1 = malloc(sizeof(cplx) * n), *X2 = malloc(sizeof(cplx) * n), *chi = malloc(sizeof(cplx) * n);
+    memset(ms, 0, sizeof *ms);
+    memcpy(U_old, U, sizeof(cplx) * V * 36);
+    or_refresh_momenta(L, seed, traj, P);
+    or_eta(L, seed, traj, 0, eta1);
+    or_eta2(L, seed, traj, 0, eta2);
+    or_mhat(L, U, a->kappa_h, eta1, phi1, 1);
+    /* phi_2 = Mhat_h A_h^-1 Mhat^dag eta_2 */
+    or_mhat(L, U, a->kappa, eta2, t, 1);
+    or_cg_stats st;
+    int status = or_cg_mhat(L, U, a->kappa_h, t, X1, a->tol, a->maxiter, 0, &st);
+    ms->solves_heavy++;
+    or_mhat(L, U, a->kappa_h, X1, phi2, 0);
+
+    res->KE_old = or_kinetic(L, P);
+    res->S_g_old = or_gauge_action(L, U, a->beta);
+    ms->S1_old = or_norm2(n, eta1);
+    ms->S2_old = or_norm2(n, eta2);
+    res->S_f_old = ms->S1_old + ms->S2_old;
+    res->H_old = res->KE_old + res->S_g_old + res->S_f_old;
+
+    status |= or_mts_integrate(L, U, P, phi1, phi2, a, tau, X1, X2, chi, ms);
+
+    double ri[2];
+    or_inner(n, phi1, X1, ri);
+    ms->S1_new = ri[0];
+    or_inner(n, chi, X2, ri);
+    ms->S2_new = ri[0];
+    res->KE_new = or_kinetic(L, P);
+    res->S_g_new = or_gauge_action(L, U, a->beta);
+    res->S_f_new = ms->S1_new + ms->S2_new;
+    res->H_new = res->KE_new + res->S_g_new + res->S_f_new;
+    res->dH = res->H_new - res->H_old;
+    res->u = or_accept_uniform(seed, traj);
+    res->accepted = (status == 0) && (res->dH <= 0 || res->u < exp(-res->dH));
+    if (res->dH != res->dH) res->accepted = 0;
+    if (!res->accepted) memcpy(U, U_old, sizeof(cplx) * V * 36);
+    res->plaquette = or_plaquette(L, U);
+    res->cg_iters_total = 0;
+    res->cg_iters_max = 0;
+    res->nonconverged = status != 0;
+    free(U_old); free(P); free(eta1); free(eta2); free(phi1); free(phi2); free(t);
+    free(X1); free(X2); free(chi);
+    return status;
+}
+
+/* S_2 at U for a given phi_2 (converged solve), for the force checks. */
+double or_ratio_action(const int *L, const cplx *U, const or_mts_action *a, const cplx *phi2)
+{
+    long n = vol4(L) * 12;
+    cplx *chi = malloc(sizeof(cplx) * n), *X = malloc(sizeof(cplx) * n);
+    or_mhat(L, U, a->kappa_h, phi2, chi, 1);
+    or_cg_stats st;
+    or_cg_mhat(L, U, a->kappa, chi, X, a->tol, a->maxiter, 0, &st);
+    double ri[2];
+    or_inner(n, chi, X, ri);
+    free(chi); free(X);
+    return ri[0];
 }

@@ -11,6 +11,8 @@ import os
 import pytest
 
 import oracle as O
+from tests import synth
+from tests import test_oracle_mts as M
 from tests import test_oracle_pins as P
 
 SRC = open(os.path.join(os.path.dirname(O.__file__), "oracle.c")).read()
@@ -23,6 +25,16 @@ def c1():
     eta = O.eta(L, 12120785, 0, 0)
     phi = O.mhat(L, U, 0.15, eta, dagger=True)
     return L, U, Pm, eta, phi
+
+
+def small():
+    L = [4, 2, 2, 4]
+    return L, O.weak_field(L, 7, 0.4), synth.hermitian_traceless(8, L), synth.spinor(9, L, O.parity_mask(L), 0)
+
+
+def schedules():
+    for n in [(1, 1, 1), (2, 3, 2)]:
+        M.test_schedule_structure(n)
 
 
 def free_field():
@@ -87,6 +99,18 @@ MUTANTS = {
     "Metropolis with exp(+dH)": (
         "res->u < exp(-res->dH)", "res->u < exp(res->dH)",
         [lambda: P.test_trajectory_bookkeeping(c1())]),
+    "ratio force: second bilinear added": (
+        "for (long k = 0; k < V * 36; ++k) F[k] -= F2[k];", "for (long k = 0; k < V * 36; ++k) F[k] += F2[k];",
+        [lambda: M.test_ratio_force_finite_difference(small())]),
+    "ratio force: kappa in place of kappa_h": (
+        "or_fermion_force(L, U, a->kappa_h * a->kappa_h, X, Y, F2);", "or_fermion_force(L, U, a->kappa * a->kappa, X, Y, F2);",
+        [lambda: M.test_ratio_force_finite_difference(small())]),
+    "nested leapfrog: last kick a full step": (
+        "mts_emit(ops, nops, level, k < n ? e : 0.5 * e);", "mts_emit(ops, nops, level, e);",
+        [schedules]),
+    "ratio heatbath without the heavy solve": (
+        "or_mhat(L, U, a->kappa_h, X1, phi2, 0);", "or_mhat(L, U, a->kappa_h, t, phi2, 0);",
+        [M.test_reduces_to_plain_hmc_at_equal_kappa]),
     "link update right-multiplies": (
         "mat_mul(E, &U[l * 9], &U[l * 9]);", "mat_mul(&U[l * 9], E, &U[l * 9]);",
         [P.test_update_links_is_left_multiplication_by_exp]),
