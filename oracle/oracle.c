@@ -966,6 +966,14 @@ typedef struct {
     int cg_iters_total, cg_iters_max, nonconverged;
 } or_traj_result;
 
+/* Accept iff every solve converged and u < exp(-dH) (always for dH <= 0);
+ * a non-finite dH rejects. */
+static int metropolis_accept(int status, double dH, double u)
+{
+    if (dH != dH) return 0;
+    return (status == 0) && (dH <= 0 || u < exp(-dH));
+}
+
 /* One HMC trajectory at index `traj` (momenta from stream 1, pseudofermion
  * noise from stream 2 on even sites, Metropolis uniform from stream 3, all
  * at epoch traj).  S_f(old) = eta^dag eta exactly, since phi = Mhat^dag eta. */
@@ -996,8 +1004,7 @@ int or_hmc_trajectory(const int *L, cplx *U, const or_action *a, uint64_t seed, 
     res->H_new = res->KE_new + res->S_g_new + res->S_f_new;
     res->dH = res->H_new - res->H_old;
     res->u = or_accept_uniform(seed, traj);
-    res->accepted = (status == 0) && (res->dH <= 0 || res->u < exp(-res->dH));
-    if (res->dH != res->dH) res->accepted = 0;
+    res->accepted = metropolis_accept(status, res->dH, res->u);
     if (!res->accepted) memcpy(U, U_old, sizeof(cplx) * V * 36);
     res->plaquette = or_plaquette(L, U);
     res->cg_iters_total = ms.iters_total;
@@ -1253,8 +1260,7 @@ int or_hmc_trajectory_mts(const int *L, cplx *U, const or_mts_action *a, uint64_
     res->H_new = res->KE_new + res->S_g_new + res->S_f_new;
     res->dH = res->H_new - res->H_old;
     res->u = or_accept_uniform(seed, traj);
-    res->accepted = (status == 0) && (res->dH <= 0 || res->u < exp(-res->dH));
-    if (res->dH != res->dH) res->accepted = 0;
+    res->accepted = metropolis_accept(status, res->dH, res->u);
     if (!res->accepted) memcpy(U, U_old, sizeof(cplx) * V * 36);
     res->plaquette = or_plaquette(L, U);
     res->cg_iters_total = 0;

@@ -97,7 +97,7 @@ MUTANTS = {
         "status |= force_kick(L, U, P, phi, a, 0.5 * eps, Xe, ms);", "status |= force_kick(L, U, P, phi, a, eps, Xe, ms);",
         [lambda: P.test_leapfrog_reversibility(c1())]),
     "Metropolis with exp(+dH)": (
-        "res->u < exp(-res->dH)", "res->u < exp(res->dH)",
+        "(dH <= 0 || u < exp(-dH))", "(dH <= 0 || u < exp(dH))",
         [lambda: P.test_trajectory_bookkeeping(c1())]),
     "ratio force: second bilinear added": (
         "for (long k = 0; k < V * 36; ++k) F[k] -= F2[k];", "for (long k = 0; k < V * 36; ++k) F[k] += F2[k];",
