@@ -331,6 +331,50 @@ typedef struct {
 hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_traj_params* params,
                           hmc_traj_result* result, void* stream);
 
+/* ---- Mass-preconditioned (Hasenbusch) two-flavour HMC on nested time
+ * scales (the production setup of Sec. 7).  det(A) is split with a heavier
+ * hopping parameter kappa_h (0 < kappa_h <= kappa), A = Mhat^dag Mhat:
+ *   S_1 = phi_1^dag A_h^-1 phi_1,             phi_1 = Mhat_h^dag eta_1,
+ *   S_2 = chi^dag A^-1 chi, chi = Mhat_h^dag phi_2,
+ *                                             phi_2 = Mhat_h A_h^-1 Mhat^dag eta_2,
+ * eta_1 from Philox stream 2, eta_2 from stream 5 (epoch traj, even
+ * sites).  Forces: S_1 is the Wilson force at kappa_h; S_2 is the Wilson
+ * bilinear of (X_2, Mhat X_2) at kappa minus that of (X_2, phi_2) at
+ * kappa_h, X_2 = A^-1 chi.  Integrator: nested PQP leapfrog, ratio
+ * monomial on the outer scale (n_ratio steps over tau), the heavy monomial
+ * n_heavy steps per outer step, the gauge force n_gauge steps per heavy
+ * step; kicks that fall between the same two link updates are applied
+ * together, ratio then heavy then gauge.  Force evaluations per
+ * trajectory: n_ratio + 1 ratio solves, n_ratio n_heavy + 1 heavy solves,
+ * n_ratio n_heavy n_gauge + 1 gauge forces. */
+typedef struct {
+  double tau;
+  double kappa_h;
+  int32_t n_ratio, n_heavy, n_gauge;
+  int32_t pad;
+  hmc_cg_params cg; /* both monomials (mode ignored: CG on A) */
+} hmc_mts_params;
+typedef struct {
+  double S1_old, S2_old, S1_new, S2_new;
+  int32_t solves_ratio, solves_heavy, gauge_forces, link_updates;
+  int32_t iters_ratio, iters_heavy, nonconverged, pad;
+} hmc_mts_stats;
+/* P -= coef F for the Wilson-force bilinear of X = (X_e, D_oe X_e) and
+ * Y = (Y_e, (D^dag)_oe Y_e) at hopping parameter kappa_c (the plain
+ * monomial is Y_e = Mhat X_e at kappa_c = kappa).  X_e, Y_e: even F64 half
+ * spinors. */
+hmc_status hmc_fermion_force_bilinear(hmc_fields* f, const void* X_e, const void* Y_e, double kappa_c, double coef,
+                                      void* stream);
+/* Integrate U and P over p->tau with the nested schedule; phi_1 is the
+ * fields' HMC_FIELD_PHI, phi_2 the given even half spinor.  tau may be
+ * negative.  Synchronises; fills *stats (actions left 0). */
+hmc_status hmc_md_mts(hmc_fields* f, const void* phi2, const hmc_mts_params* p, hmc_mts_stats* stats,
+                      void* stream);
+/* One mass-preconditioned trajectory; H = sum Tr P^2 + S_g + S_1 + S_2,
+ * accept/reject and return codes as hmc_trajectory. */
+hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_mts_params* p,
+                              hmc_traj_result* result, hmc_mts_stats* stats, void* stream);
+
 /* Solve service: continuous batching of Wilson solves M x = b (the
  * fermion-matrix inversions of Sec. 1 as a request stream).  Each request
  * brings its own lattice volume, kappa, weak-field gauge field (drawn on the

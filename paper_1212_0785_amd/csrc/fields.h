@@ -50,6 +50,8 @@ struct Fields {
   void* Xo;
   void* Ye;
   void* Yo;
+  // mass-preconditioned action: second pseudofermion, its noise, chi and X_2
+  void *eta2, *phi2, *chi, *X2;
   // FP64 solver vectors (even half spinors, t odd)
   void *r, *p, *q, *s, *t, *bhat, *tmp;
   // partial-sum buffers, each of npart doubles

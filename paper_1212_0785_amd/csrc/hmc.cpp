@@ -178,6 +178,10 @@ static size_t plan_fields(Fields* F, char* base, const LatArg& g, uint32_t flags
   f->Xo = take(h64);
   f->Ye = take(h64);
   f->Yo = take(h64);
+  f->eta2 = take(h64);
+  f->phi2 = take(h64);
+  f->chi = take(h64);
+  f->X2 = take(h64);
   f->r = take(h64);
   f->p = take(h64);
   f->q = take(h64);
@@ -872,3 +876,256 @@ hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------ mass preconditioning
+
+namespace hmc {
+namespace {
+
+// out = Mhat(kappa_c) in (dag: Mhat^dag) on F64 half spinors (uses F->t).
+hipError_t mhat_k(Fields* F, void* out, const void* in, int dag, double kappa_c, hipStream_t st) {
+  hipError_t e = dslash_f64(F, F->t, in, 1, dag, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st);
+  if (e != hipSuccess) return e;
+  return dslash_f64(F, out, F->t, 0, dag, EPI_AXPY, in, 1.0, -kappa_c * kappa_c, nullptr, nullptr, 0, st);
+}
+
+// P -= coef F for the bilinear of X = (X_e, D_oe X_e), Y = (Y_e, D^dag_oe Y_e)
+// at kappa_c (F->Xo / F->Yo are the odd halves; Y_e is read in place).
+hipError_t force_bilinear(Fields* F, const void* Xe, const void* Ye, double kappa_c, double coef, hipStream_t st) {
+  hipError_t e;
+  if ((e = dslash_f64(F, F->Xo, Xe, 1, 0, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st))) return e;
+  if ((e = dslash_f64(F, F->Yo, Ye, 1, 1, EPI_PLAIN, nullptr, 0, 1, nullptr, nullptr, 0, st))) return e;
+  return launch_fermion_force(F->g, F->U, Xe, F->Xo, Ye, F->Yo, F->P, coef * kappa_c * kappa_c, st, F->su3);
+}
+
+// x = (Mhat^dag Mhat)^-1 b at kappa_c.
+hmc_status solve_at(Fields* F, double kappa_c, void* x, const void* b, const hmc_cg_params* cg, int* iters,
+                    int* nonconv, hipStream_t st) {
+  hmc_cg_params p = *cg;
+  p.mode = HMC_CG_NORMAL_MHAT;
+  hmc_cg_stats cs{};
+  const double k0 = F->kappa;
+  F->kappa = kappa_c;
+  hmc_status s = cg_solve_impl(F, x, b, &p, &cs, st);
+  F->kappa = k0;
+  if (s != HMC_OK && s != HMC_E_NOCONV) return s;
+  *iters += cs.iters;
+  if (s == HMC_E_NOCONV) ++*nonconv;
+  return HMC_OK;
+}
+
+// Nested leapfrog, flattened: per stretch between two link updates the
+// summed kick of each level (ratio, heavy, gauge) and the update's eps.
+struct Stretch {
+  double coef[3];
+  double eps;
+};
+
+void mts_emit_level(const int* steps, int level, double t, std::vector<Stretch>* out, double* pend) {
+  const int n = steps[level];
+  const double e = t / n;
+  pend[level] += 0.5 * e;
+  for (int k = 1; k <= n; ++k) {
+    if (level == 2) {
+      Stretch s;
+      for (int l = 0; l < 3; ++l) s.coef[l] = pend[l], pend[l] = 0;
+      s.eps = e;
+      out->push_back(s);
+    } else {
+      mts_emit_level(steps, level + 1, e, out, pend);
+    }
+    pend[level] += k < n ? e : 0.5 * e;
+  }
+}
+
+std::vector<Stretch> mts_schedule(int n_ratio, int n_heavy, int n_gauge, double tau) {
+  const int steps[3] = {n_ratio, n_heavy, n_gauge};
+  std::vector<Stretch> out;
+  double pend[3] = {0, 0, 0};
+  mts_emit_level(steps, 0, tau, &out, pend);
+  Stretch last;
+  for (int l = 0; l < 3; ++l) last.coef[l] = pend[l];
+  last.eps = 0;
+  out.push_back(last);
+  return out;
+}
+
+hmc_status mts_integrate(Fields* F, const hmc_mts_params* p, hmc_mts_stats* ms, hipStream_t st) {
+  const double k = F->kappa, kh = p->kappa_h;
+  int nc = 0;
+  for (const Stretch& s : mts_schedule(p->n_ratio, p->n_heavy, p->n_gauge, p->tau)) {
+    if (s.coef[0] != 0) {  // ratio: chi = Mhat_h^dag phi_2, X_2 = A^-1 chi
+      HMC_CHECK_HIP(mhat_k(F, F->chi, F->phi2, 1, kh, st));
+      hmc_status r = solve_at(F, k, F->X2, F->chi, &p->cg, &ms->iters_ratio, &nc, st);
+      if (r) return r;
+      ms->solves_ratio++;
+      HMC_CHECK_HIP(mhat_k(F, F->Ye, F->X2, 0, k, st));
+      HMC_CHECK_HIP(force_bilinear(F, F->X2, F->Ye, k, s.coef[0], st));
+      HMC_CHECK_HIP(force_bilinear(F, F->X2, F->phi2, kh, -s.coef[0], st));
+    }
+    if (s.coef[1] != 0) {  // heavy: X_1 = A_h^-1 phi_1
+      hmc_status r = solve_at(F, kh, F->Xe, F->phi, &p->cg, &ms->iters_heavy, &nc, st);
+      if (r) return r;
+      ms->solves_heavy++;
+      HMC_CHECK_HIP(mhat_k(F, F->Ye, F->Xe, 0, kh, st));
+      HMC_CHECK_HIP(force_bilinear(F, F->Xe, F->Ye, kh, s.coef[1], st));
+    }
+    if (s.coef[2] != 0) {
+      HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, s.coef[2] * F->beta, st, F->su3));
+      ms->gauge_forces++;
+    }
+    if (s.eps != 0) {
+      HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, s.eps, st));
+      F->u_version++;
+      F->su3 = true;
+      ms->link_updates++;
+    }
+  }
+  ms->nonconverged = nc;
+  return HMC_OK;
+}
+
+hmc_status check_mts(const Fields* F, const hmc_mts_params* p) {
+  HMC_REQUIRE(p, "null parameters");
+  HMC_REQUIRE(p->n_ratio >= 1 && p->n_heavy >= 1 && p->n_gauge >= 1, "step counts must be >= 1");
+  HMC_REQUIRE((long long)p->n_ratio * p->n_heavy * p->n_gauge <= 1000000, "too many link updates");
+  HMC_REQUIRE(p->kappa_h > 0 && p->kappa_h <= F->kappa, "need 0 < kappa_h <= kappa");
+  HMC_REQUIRE(p->cg.prec == HMC_F64 || (F->flags & HMC_FIELDS_LOWPREC), "mixed precision needs HMC_FIELDS_LOWPREC");
+  return HMC_OK;
+}
+
+}  // namespace
+}  // namespace hmc
+
+using namespace hmc;
+
+hmc_status hmc_fermion_force_bilinear(hmc_fields* f, const void* X_e, const void* Y_e, double kappa_c, double coef,
+                                      void* stream) {
+  FIELDS(f);
+  HMC_REQUIRE(X_e && Y_e, "null buffer");
+  HMC_CHECK_HIP(force_bilinear(F, X_e, Y_e, kappa_c, coef, ST(stream)));
+  return HMC_OK;
+}
+
+hmc_status hmc_md_mts(hmc_fields* f, const void* phi2, const hmc_mts_params* p, hmc_mts_stats* stats,
+                      void* stream) {
+  FIELDS(f);
+  hmc_status s = check_mts(F, p);
+  if (s) return s;
+  HMC_REQUIRE(phi2 && stats, "null argument");
+  hipStream_t st = ST(stream);
+  HMC_CHECK_HIP(launch_copy(F->phi2, phi2, F->half64, st));
+  *stats = hmc_mts_stats{};
+  s = mts_integrate(F, p, stats, st);
+  if (s) return s;
+  HMC_CHECK_HIP(hipStreamSynchronize(st));
+  if (stats->nonconverged) {
+    set_error("%d solves did not converge", stats->nonconverged);
+    return HMC_E_NOCONV;
+  }
+  return HMC_OK;
+}
+
+hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_mts_params* p,
+                              hmc_traj_result* res, hmc_mts_stats* stats, void* stream) {
+  FIELDS(f);
+  hmc_status s = check_mts(F, p);
+  if (s) return s;
+  HMC_REQUIRE(res && stats, "null argument");
+  hipStream_t st = ST(stream);
+  auto t0 = std::chrono::steady_clock::now();
+  const double k = F->kappa, kh = p->kappa_h;
+  *stats = hmc_mts_stats{};
+  const size_t ub = gauge_bytes(F->g.Vh, HMC_F64);
+  HMC_CHECK_HIP(launch_copy(F->U_old, F->U, ub, st));
+  F->su3_old = F->su3;
+  HMC_CHECK_HIP(launch_refresh_momenta(F->g, seed, traj, F->P, st));
+  // phi_1 = Mhat_h^dag eta_1;  phi_2 = Mhat_h A_h^-1 Mhat^dag eta_2
+  HMC_CHECK_HIP(launch_eta(F->g, seed, traj, 0, F->eta, st, 0));
+  HMC_CHECK_HIP(launch_eta(F->g, seed, traj, 0, F->eta2, st, 1));
+  HMC_CHECK_HIP(mhat_k(F, F->phi, F->eta, 1, kh, st));
+  HMC_CHECK_HIP(mhat_k(F, F->chi, F->eta2, 1, k, st));
+  int nc = 0;
+  s = solve_at(F, kh, F->Xe, F->chi, &p->cg, &stats->iters_heavy, &nc, st);
+  if (s) return s;
+  stats->solves_heavy++;
+  HMC_CHECK_HIP(mhat_k(F, F->phi2, F->Xe, 0, kh, st));
+
+  const int nb = F->nbR;
+  HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_OLD, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_OLD, st));
+  // S_1 + S_2 = |eta_1|^2 + |eta_2|^2 into SL_ETA2 (parts in SL_RED + 0, + 1)
+  HMC_CHECK_HIP(launch_norm2_partials(F->g, HMC_F64, F->eta, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED + 0, st));
+  HMC_CHECK_HIP(launch_finalize(F->part[0], nb, 1, F->slots + SL_ETA2, 1.0, 0, st));
+  HMC_CHECK_HIP(launch_norm2_partials(F->g, HMC_F64, F->eta2, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED + 1, st));
+  HMC_CHECK_HIP(launch_finalize(F->part[0], nb, 1, F->slots + SL_ETA2, 1.0, 1, st));
+
+  int nc_md = 0;
+  s = mts_integrate(F, p, stats, st);
+  if (s) return s;
+  nc_md = stats->nonconverged;
+  stats->nonconverged += nc;
+
+  HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_NEW, st));
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_NEW, st));
+  // S_1 = <phi_1, X_1>, S_2 = <chi, X_2> at the final links (SL_RED + 2.., + 4..)
+  HMC_CHECK_HIP(launch_inner_partials(F->g, F->phi, F->Xe, F->part[1], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_RED + 2, st));
+  HMC_CHECK_HIP(launch_finalize(F->part[1], nb, 2, F->slots + SL_PHIX, 1.0, 0, st));
+  HMC_CHECK_HIP(launch_inner_partials(F->g, F->chi, F->X2, F->part[1], nb, st));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_RED + 4, st));
+  HMC_CHECK_HIP(launch_finalize(F->part[1], nb, 2, F->slots + SL_PHIX, 1.0, 1, st));
+  HMC_CHECK_HIP(launch_metropolis(seed, traj, F->beta, (double)F->V, F->slots, st));
+  double sl[13], parts[6];
+  HMC_CHECK_HIP(read_slots(F, 0, 13, sl, st));
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 6, parts, st));
+
+  const bool converged = stats->nonconverged == 0;
+  bool accepted = sl[SL_ACC] != 0.0 && converged;
+  if (!accepted) {
+    HMC_CHECK_HIP(launch_copy(F->U, F->U_old, ub, st));
+    F->u_version++;
+    F->su3 = F->su3_old;
+  }
+  double plaq_sum;
+  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
+  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED, st));
+  HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &plaq_sum, st));
+
+  stats->S1_old = parts[0];
+  stats->S2_old = parts[1];
+  stats->S1_new = parts[2];
+  stats->S2_new = parts[4];
+  res->KE_old = sl[SL_KE_OLD];
+  res->KE_new = sl[SL_KE_NEW];
+  res->S_f_old = sl[SL_ETA2];
+  res->S_g_old = sl[SL_SG_OLD];
+  res->S_g_new = sl[SL_SG_NEW];
+  res->H_old = sl[SL_H_OLD];
+  res->H_new = sl[SL_H_NEW];
+  res->dH = sl[SL_DH];
+  res->u = sl[SL_U];
+  res->S_f_new = sl[SL_PHIX];
+  res->accepted = accepted ? 1 : 0;
+  res->plaquette = plaq_sum / (18.0 * F->V);
+  res->cg_iters_total = stats->iters_ratio + stats->iters_heavy;
+  res->cg_iters_max = 0;
+  res->nonconverged = stats->nonconverged;
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  (void)nc_md;
+  if (!converged) {
+    set_error("%d solves did not converge; trajectory rejected", stats->nonconverged);
+    return HMC_E_NOCONV;
+  }
+  if (!(res->dH == res->dH) || std::isinf(res->dH)) {
+    set_error("non-finite energy change; trajectory rejected");
+    return HMC_E_NAN;
+  }
+  return HMC_OK;
+}

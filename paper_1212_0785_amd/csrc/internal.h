@@ -175,7 +175,10 @@ hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, 
 // key = (seed, 0)).
 hipError_t launch_refresh_momenta(const LatArg& g, uint64_t seed, uint64_t epoch, double* P, hipStream_t st);
 hipError_t launch_weak_field(const LatArg& g, uint64_t seed, double eps, void* U, hipStream_t st);
-hipError_t launch_eta(const LatArg& g, uint64_t seed, uint64_t epoch, int par, void* half, hipStream_t st);
+// Pseudofermion noise from Philox stream 2 (second = 0) or stream 5 (the
+// second pseudofermion of the mass-preconditioned action).
+hipError_t launch_eta(const LatArg& g, uint64_t seed, uint64_t epoch, int par, void* half, hipStream_t st,
+                      int second = 0);
 hipError_t launch_source(const LatArg& g, int kind, uint64_t seed, uint64_t epoch, void* even, void* odd,
                          hipStream_t st);
 hipError_t launch_site_words(uint64_t seed, uint64_t stream, uint64_t epoch, const long long* sites, int nsites,

@@ -17,7 +17,7 @@ static Lat to_lat(const LatArg& a) {
   return g;
 }
 
-enum { ST_WEAKFIELD = 0, ST_MOMENTA = 1, ST_ETA = 2, ST_ACCEPT = 3, ST_SOURCE = 4 };
+enum { ST_WEAKFIELD = 0, ST_MOMENTA = 1, ST_ETA = 2, ST_ACCEPT = 3, ST_SOURCE = 4, ST_ETA2 = 5 };
 
 // n (even, <= 32) Gaussians of one site, consecutive word pairs through
 // Box-Muller.
@@ -81,12 +81,13 @@ __global__ void __launch_bounds__(kBlock) k_weak_field(Lat g, uint64_t seed, dou
 }
 
 // eta on the sites of parity par: complex Gaussian with E|eta_k|^2 = 1.
-__global__ void __launch_bounds__(kBlock) k_eta(Lat g, uint64_t seed, uint64_t epoch, int par, double2* half) {
+__global__ void __launch_bounds__(kBlock) k_eta(Lat g, uint64_t seed, uint64_t epoch, int par, double2* half,
+                                                int rng_stream) {
   int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.Vh) return;
   Site x = cb_site(g, par, s);
   double gs[24];
-  site_gaussians<24>(seed, (uint64_t)x.lex, ST_ETA, epoch, gs);
+  site_gaussians<24>(seed, (uint64_t)x.lex, rng_stream, epoch, gs);
   const double r = 0.70710678118654752440;
 #pragma unroll
   for (int k = 0; k < 12; ++k) half[(size_t)k * g.stride + s] = make_double2(r * gs[2 * k], r * gs[2 * k + 1]);
@@ -189,10 +190,11 @@ hipError_t launch_weak_field(const LatArg& g, uint64_t seed, double eps, void* U
   hipLaunchKernelGGL(k_weak_field, dim3(ceil_div(2LL * g.Vh, kBlock)), dim3(kBlock), 0, st, to_lat(g), seed, eps, U);
   return hipGetLastError();
 }
-hipError_t launch_eta(const LatArg& g, uint64_t seed, uint64_t epoch, int par, void* half, hipStream_t st) {
+hipError_t launch_eta(const LatArg& g, uint64_t seed, uint64_t epoch, int par, void* half, hipStream_t st,
+                      int second) {
   TimedScope ts(TK_REFRESH, st, (double)g.Vh * SpF64::kBytes);
   hipLaunchKernelGGL(k_eta, dim3(site_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), seed, epoch, par,
-                     (double2*)half);
+                     (double2*)half, second ? (int)ST_ETA2 : (int)ST_ETA);
   return hipGetLastError();
 }
 hipError_t launch_source(const LatArg& g, int kind, uint64_t seed, uint64_t epoch, void* even, void* odd,

@@ -61,6 +61,17 @@ class TrajParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("nsteps", C.c_int32), ("pad", C.c_int32), ("cg", CgParams)]
 
 
+class MtsParams(C.Structure):
+    _fields_ = [("tau", C.c_double), ("kappa_h", C.c_double), ("n_ratio", C.c_int32), ("n_heavy", C.c_int32),
+                ("n_gauge", C.c_int32), ("pad", C.c_int32), ("cg", CgParams)]
+
+
+class MtsStats(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("S1_old", "S2_old", "S1_new", "S2_new")] + \
+        [(n, C.c_int32) for n in ("solves_ratio", "solves_heavy", "gauge_forces", "link_updates", "iters_ratio",
+                                  "iters_heavy", "nonconverged", "pad")]
+
+
 class TrajResult(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("H_old", "H_new", "dH", "S_g_old", "S_g_new", "S_f_old", "S_f_new",
                                           "KE_old", "KE_new", "plaquette", "u")] + \
@@ -139,6 +150,10 @@ _SIGNATURES = {
     "hmc_cg_solve": (_I32, [_P, _P, _P, C.POINTER(CgParams), C.POINTER(CgStats), _P]),
     "hmc_md_leapfrog": (_I32, [_P, _D, _I32, C.POINTER(CgParams), C.POINTER(MdStats), _P]),
     "hmc_trajectory": (_I32, [_P, _U64, _U64, C.POINTER(TrajParams), C.POINTER(TrajResult), _P]),
+    "hmc_fermion_force_bilinear": (_I32, [_P, _P, _P, C.c_double, C.c_double, _P]),
+    "hmc_md_mts": (_I32, [_P, _P, C.POINTER(MtsParams), C.POINTER(MtsStats), _P]),
+    "hmc_trajectory_mts": (_I32, [_P, _U64, _U64, C.POINTER(MtsParams), C.POINTER(TrajResult), C.POINTER(MtsStats),
+                                  _P]),
     "hmc_request_bytes": (_I32, [C.POINTER(SolveRequest), _I32, C.POINTER(C.c_size_t)]),
     "hmc_service_create": (_I32, [C.POINTER(ServiceParams), C.POINTER(_P)]),
     "hmc_service_submit": (_I32, [_P, C.POINTER(SolveRequest), C.POINTER(_U64)]),
@@ -355,6 +370,35 @@ def hmc_kinetic_energy(f, stream=None) -> float:
 
 def hmc_gauge_force(f, coef, stream=None):
     check(lib().hmc_gauge_force(_h(f), float(coef), _stream(stream)))
+
+
+def mts_params(tau, kappa_h, n_ratio, n_heavy, n_gauge, cg: CgParams):
+    return MtsParams(float(tau), float(kappa_h), int(n_ratio), int(n_heavy), int(n_gauge), 0, cg)
+
+
+def hmc_fermion_force_bilinear(f, X_e, Y_e, kappa_c, coef, stream=None):
+    check(lib().hmc_fermion_force_bilinear(_h(f), _ptr(X_e), _ptr(Y_e), float(kappa_c), float(coef),
+                                           _stream(stream)))
+
+
+def hmc_md_mts(f, phi2, p: MtsParams, stream=None, allow_noconv=False):
+    ms = MtsStats()
+    status = lib().hmc_md_mts(_h(f), _ptr(phi2), C.byref(p), C.byref(ms), _stream(stream))
+    check(status, allow=(HMC_E_NOCONV,) if allow_noconv else ())
+    d = struct_dict(ms)
+    d["status"] = status
+    return d
+
+
+def hmc_trajectory_mts(f, seed, traj, p: MtsParams, stream=None):
+    r = TrajResult()
+    ms = MtsStats()
+    status = lib().hmc_trajectory_mts(_h(f), seed, traj, C.byref(p), C.byref(r), C.byref(ms), _stream(stream))
+    check(status, allow=(HMC_E_NOCONV, HMC_E_NAN))
+    d = struct_dict(r)
+    d.update(struct_dict(ms))
+    d["status"] = status
+    return d
 
 
 def hmc_fermion_force(f, X_e, coef, stream=None):
