@@ -10,6 +10,10 @@ Workloads (--workload):
   cg      24^3x48 kappa 0.157 Wilson solves of Gaussian sources to
           |b - M x| <= 1e-10 |b|: FP64 CGLS against mixed precision
           (FP32, FP16 and BF16 inner storage).
+  mts     the same 16^3x32 chain with the mass-preconditioned (Hasenbusch)
+          action on nested time scales: kappa_h 0.10, 5 ratio steps x 2
+          heavy steps x 2 gauge steps (the innermost step equals the plain
+          run's 0.05), FP64 solves to 1e-10.
   copy    a plain 2 GiB device-to-device copy (torch), the calibration
           kernel for the HBM byte counters (known bytes read and written).
   serve   Poisson stream of Wilson solves over {8^4, 16^3x32, 24^3x48}
@@ -168,6 +172,36 @@ def run_hmc(args, H, torch):
                            "avg_launch_ms": rf["avg_ms"], "bytes_per_launch": rf["bytes_per_launch"],
                            "launches_timed": rf["launches_timed"]}
     return out, iters / solves, L, seed, beta, kappa, nsteps
+
+
+def run_mts(args, H, torch):
+    L = (16, 16, 16, 32)
+    seed, beta, kappa, kappa_h, tau = 12120785, 5.6, 0.156, args.kappa_h, 1.0
+    steps = tuple(int(v) for v in args.mts_steps.split(","))
+    F = H.Fields(L, beta, kappa)
+    p = H.mts_params(tau, kappa_h, *steps, H.cg_params(tol=1e-10, maxiter=10000))
+    H.hmc_weak_field_start(F, seed, 0.3)
+    for w in range(args.warmup):
+        H.hmc_trajectory_mts(F, seed, w, p)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [H.hmc_trajectory_mts(F, seed, k, p) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    keys = ("seconds", "dH", "accepted", "plaquette", "S1_old", "S2_old", "S1_new", "S2_new", "solves_ratio",
+            "solves_heavy", "iters_ratio", "iters_heavy", "gauge_forces", "link_updates")
+    return {
+        "metric": METRIC, "value": dt / args.steps, "unit": "s/traj", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "hmc_mts_16c32", "lattice": list(L), "beta": beta, "kappa": kappa,
+                   "kappa_h": kappa_h, "tau": tau, "steps_ratio_heavy_gauge": list(steps), "cg_tol": 1e-10,
+                   "start": "weak-field eps=0.3 seed 12120785", "trajectories": f"0..{args.steps - 1}",
+                   "parallelism": "1 GPU"},
+        "trajectories": [{"traj": k, **{x: r[x] for x in keys}} for k, r in enumerate(results)],
+        "acceptance": sum(r["accepted"] for r in results) / len(results),
+    }
 
 
 # ----------------------------------------------------------------- Dslash
@@ -450,7 +484,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="hmc", choices=["hmc", "dslash", "cg", "serve", "copy"])
+    ap.add_argument("--workload", default="hmc", choices=["hmc", "mts", "dslash", "cg", "serve", "copy"])
     ap.add_argument("--rho", type=float, default=0.9, help="serve: offered load relative to FP64 FIFO capacity")
     ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
     ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
@@ -458,12 +492,14 @@ def main():
                     help=("time every n-th launch of each kernel kind with HIP events (31: coprime to the "
                           "four Dslash launches of a CG iteration; each sampled launch costs the GPU a few us)"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kappa-h", type=float, default=0.10, help="mts: heavy hopping parameter")
+    ap.add_argument("--mts-steps", default="5,2,2", help="mts: ratio,heavy,gauge steps per enclosing step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
-    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (16, 1), "serve": (64, 0), "copy": (20, 2)}[args.workload]
+    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (16, 1), "serve": (64, 0), "copy": (20, 2), "mts": (5, 1)}[args.workload]
     args.steps = args.steps if args.steps is not None else defaults[0]
     args.warmup = args.warmup if args.warmup is not None else defaults[1]
 
@@ -485,6 +521,8 @@ def main():
         out = run_serve(args, H, torch)
     elif args.workload == "copy":
         out = run_copy(args, H, torch)
+    elif args.workload == "mts":
+        out = run_mts(args, H, torch)
     else:
         out, first = run_cg(args, H, torch)
         if not args.no_cpu_baseline:
