@@ -113,6 +113,10 @@ def bind(path):
         "or_gauge_action": (C.c_double, [_I, _P, C.c_double]),
         "or_gauge_force": (None, [_I, _P, C.c_double, _P]),
         "or_eta2": (None, [_I, C.c_uint64, C.c_uint64, C.c_int, _P]),
+        "or_cg_mhat_x0": (C.c_int, [_I, _P, C.c_double, _P, _P, C.c_double, C.c_int, _P]),
+        "or_chrono_guess": (C.c_int, [_I, _P, C.c_double, _P, _P, C.c_int, _P]),
+        "or_hmc_trajectory_chrono": (C.c_int, [_I, _P, _P, C.c_uint64, C.c_uint64, C.c_double, C.c_int, C.c_int,
+                                               _P]),
         "or_mts_force": (C.c_int, [_I, _P, _P, C.c_int, _P, _P, _P]),
         "or_mts_schedule": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, _P, _P, C.c_int]),
         "or_mts_integrate": (C.c_int, [_I, _P, _P, _P, _P, _P, C.c_double, _P, _P, _P, _P]),
@@ -495,3 +499,35 @@ def hmc_trajectory_mts(L, U, a: MtsAction, seed, traj, tau):
 
 def ratio_action(L, U, a: MtsAction, phi2):
     return _load().or_ratio_action(_dims(L), _ptr(_c128(U)), C.byref(a), _ptr(_c128(phi2)))
+
+
+# ------------------------------------------------ chronological guess
+
+
+def cg_mhat_x0(L, U, kappa, b, x0, tol=1e-10, maxiter=10000):
+    """CG on Mhat^dag Mhat started from x0 -> (x, stats)."""
+    x = _c128(x0).copy()
+    st = CgStats()
+    status = _load().or_cg_mhat_x0(_dims(L), _ptr(_c128(U)), float(kappa), _ptr(_c128(b)), _ptr(x), float(tol),
+                                   int(maxiter), C.byref(st))
+    return x, {"status": status, "iters": st.iters, "rel_res": st.rel_res, "true_rel_res": st.true_rel_res}
+
+
+def chrono_guess(L, U, kappa, b, history):
+    """Minimal-residual extrapolation over the solutions in `history` (oldest first)."""
+    m = len(history)
+    Y = np.ascontiguousarray(np.stack([_c128(h) for h in history]))
+    x0 = spinor_zeros(L)
+    s = _load().or_chrono_guess(_dims(L), _ptr(_c128(U)), float(kappa), _ptr(_c128(b)), _ptr(Y), m, _ptr(x0))
+    return x0, s
+
+
+def hmc_trajectory_chrono(L, U, beta, kappa, seed, traj, tau, nsteps, n_chrono, tol=1e-10, maxiter=10000):
+    U = _c128(U).copy()
+    a = Action(beta, kappa, tol, maxiter)
+    r = TrajResult()
+    status = _load().or_hmc_trajectory_chrono(_dims(L), _ptr(U), C.byref(a), seed, traj, float(tau), int(nsteps),
+                                              int(n_chrono), C.byref(r))
+    d = r.as_dict()
+    d["status"] = status
+    return U, d

@@ -790,14 +790,35 @@ static void normal_op(const int *L, const cplx *U, double kappa, const cplx *in,
  * Stops at the first k with ||r_k|| <= tol ||b|| (recursive residual), or
  * after exactly `fixed_iters` iterations when that is positive.
  * Returns 0 on convergence, -4 when maxiter is reached first. */
+static int cg_mhat_from(const int *L, const cplx *U, double kappa, const cplx *b, cplx *x, int start_zero,
+                        double tol, int maxiter, int fixed_iters, or_cg_stats *st);
+
 int or_cg_mhat(const int *L, const cplx *U, double kappa, const cplx *b, cplx *x, double tol, int maxiter,
                int fixed_iters, or_cg_stats *st)
+{
+    return cg_mhat_from(L, U, kappa, b, x, 1, tol, maxiter, fixed_iters, st);
+}
+
+/* The same iteration started from the x passed in (r0 = b - A x0). */
+int or_cg_mhat_x0(const int *L, const cplx *U, double kappa, const cplx *b, cplx *x, double tol, int maxiter,
+                  or_cg_stats *st)
+{
+    return cg_mhat_from(L, U, kappa, b, x, 0, tol, maxiter, 0, st);
+}
+
+static int cg_mhat_from(const int *L, const cplx *U, double kappa, const cplx *b, cplx *x, int start_zero,
+                        double tol, int maxiter, int fixed_iters, or_cg_stats *st)
 {
     long V = vol4(L), n = V * 12;
     cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
     cplx *q = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
-    for (long k = 0; k < n; ++k) { x[k] = 0; r[k] = b[k]; p[k] = b[k]; }
-    double bb = or_norm2(n, b), rr = bb;
+    if (start_zero) {
+        for (long k = 0; k < n; ++k) { x[k] = 0; r[k] = b[k]; p[k] = b[k]; }
+    } else {
+        normal_op(L, U, kappa, x, q, tmp);
+        for (long k = 0; k < n; ++k) { r[k] = b[k] - q[k]; p[k] = r[k]; }
+    }
+    double bb = or_norm2(n, b), rr = or_norm2(n, r);
     int k = 0, status = 0;
     int limit = fixed_iters > 0 ? fixed_iters : maxiter;
     while (1) {
@@ -1283,4 +1304,144 @@ double or_ratio_action(const int *L, const cplx *U, const or_mts_action *a, cons
     or_inner(n, chi, X, ri);
     free(chi); free(X);
     return ri[0];
+}
+
+/* ------------------------------------------------------------------ */
+/* Chronological initial guess (minimal-residual extrapolation).       */
+/* ------------------------------------------------------------------ */
+/* Brower, Ivanenko, Levi, Orginos, Nucl. Phys. B 484 (1997) 353: the
+ * initial guess for A x = b is the Galerkin projection onto the span of the
+ * last m solutions y_1..y_m, x0 = sum_k c_k y_k with
+ *   sum_k <y_j, A y_k> c_k = <y_j, b>   (j = 1..m),
+ * i.e. the x0 in the span with the smallest A-norm error.  G is Hermitian
+ * positive definite for independent y; solved here by Gaussian elimination
+ * with partial pivoting.  Returns 0, or -1 when G is singular (then x0 = 0). */
+int or_chrono_guess(const int *L, const cplx *U, double kappa, const cplx *b, const cplx *Y, int m, cplx *x0)
+{
+    long n = vol4(L) * 12;
+    cplx *AY = malloc(sizeof(cplx) * n * m), *tmp = malloc(sizeof(cplx) * n);
+    cplx G[64], f[8];
+    for (int k = 0; k < m; ++k) normal_op(L, U, kappa, &Y[k * n], &AY[k * n], tmp);
+    for (int j = 0; j < m; ++j) {
+        double ri[2];
+        for (int k = 0; k < m; ++k) {
+            or_inner(n, &Y[j * n], &AY[k * n], ri);
+            G[j * m + k] = ri[0] + I * ri[1];
+        }
+        or_inner(n, &Y[j * n], b, ri);
+        f[j] = ri[0] + I * ri[1];
+    }
+    int status = 0;
+    /* forward elimination with partial pivoting */
+    for (int c = 0; c < m && !status; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < m; ++r)
+            if (cabs(G[r * m + c]) > cabs(G[piv * m + c])) piv = r;
+        if (cabs(G[piv * m + c]) == 0) { status = -1; break; }
+        if (piv != c) {
+            for (int k = 0; k < m; ++k) { cplx t = G[c * m + k]; G[c * m + k] = G[piv * m + k]; G[piv * m + k] = t; }
+            cplx t = f[c]; f[c] = f[piv]; f[piv] = t;
+        }
+        for (int r = c + 1; r < m; ++r) {
+            cplx l = G[r * m + c] / G[c * m + c];
+            for (int k = c; k < m; ++k) G[r * m + k] -= l * G[c * m + k];
+            f[r] -= l * f[c];
+        }
+    }
+    cplx coef[8];
+    for (int c = m - 1; c >= 0 && !status; --c) {
+        cplx s = f[c];
+        for (int k = c + 1; k < m; ++k) s -= G[c * m + k] * coef[k];
+        coef[c] = s / G[c * m + c];
+    }
+    for (long i = 0; i < n; ++i) {
+        cplx s = 0;
+        if (!status)
+            for (int k = 0; k < m; ++k) s += coef[k] * Y[k * n + i];
+        x0[i] = s;
+    }
+    free(AY); free(tmp);
+    return status;
+}
+
+/* Plain HMC trajectory whose force solves start from the chronological
+ * guess over the last n_chrono solutions of the same trajectory (the
+ * history is cleared at the start; n_chrono <= 8). */
+static int force_kick_chrono(const int *L, const cplx *U, cplx *P, const cplx *phi, const or_action *a, double coef,
+                             cplx *Xe, cplx *hist, int *nh, int n_chrono, or_md_stats *ms)
+{
+    long V = vol4(L), n = V * 12;
+    cplx *F = malloc(sizeof(cplx) * V * 36);
+    or_gauge_force(L, U, a->beta, F);
+    or_momentum_update(L, P, F, coef);
+    or_cg_stats st;
+    int status;
+    if (*nh > 0) {
+        or_chrono_guess(L, U, a->kappa, phi, hist, *nh, Xe);
+        status = or_cg_mhat_x0(L, U, a->kappa, phi, Xe, a->tol, a->maxiter, &st);
+    } else {
+        status = or_cg_mhat(L, U, a->kappa, phi, Xe, a->tol, a->maxiter, 0, &st);
+    }
+    ms->solves++;
+    ms->iters_total += st.iters;
+    if (st.iters > ms->iters_max) ms->iters_max = st.iters;
+    if (status) ms->nonconverged++;
+    /* push the solution, oldest dropped */
+    if (*nh == n_chrono) {
+        memmove(hist, hist + n, sizeof(cplx) * n * (n_chrono - 1));
+        --*nh;
+    }
+    memcpy(hist + *nh * n, Xe, sizeof(cplx) * n);
+    ++*nh;
+    cplx *X = malloc(sizeof(cplx) * n), *Y = malloc(sizeof(cplx) * n);
+    force_vectors(L, U, a->kappa, Xe, X, Y);
+    or_fermion_force(L, U, a->kappa * a->kappa, X, Y, F);
+    or_momentum_update(L, P, F, coef);
+    free(X); free(Y); free(F);
+    return status;
+}
+
+int or_hmc_trajectory_chrono(const int *L, cplx *U, const or_action *a, uint64_t seed, uint64_t traj, double tau,
+                             int nsteps, int n_chrono, or_traj_result *res)
+{
+    long V = vol4(L), n = V * 12;
+    if (n_chrono < 1 || n_chrono > 8) return -1;
+    cplx *U_old = malloc(sizeof(cplx) * V * 36), *P = malloc(sizeof(cplx) * V * 36);
+    cplx *eta = malloc(sizeof(cplx) * n), *phi = malloc(sizeof(cplx) * n), *Xe = malloc(sizeof(cplx) * n);
+    cplx *hist = malloc(sizeof(cplx) * n * n_chrono);
+    int nh = 0;
+    memcpy(U_old, U, sizeof(cplx) * V * 36);
+    or_refresh_momenta(L, seed, traj, P);
+    or_eta(L, seed, traj, 0, eta);
+    or_mhat(L, U, a->kappa, eta, phi, 1);
+    res->KE_old = or_kinetic(L, P);
+    res->S_g_old = or_gauge_action(L, U, a->beta);
+    res->S_f_old = or_norm2(n, eta);
+    res->H_old = res->KE_old + res->S_g_old + res->S_f_old;
+
+    or_md_stats ms;
+    memset(&ms, 0, sizeof ms);
+    double eps = tau / nsteps;
+    int status = force_kick_chrono(L, U, P, phi, a, 0.5 * eps, Xe, hist, &nh, n_chrono, &ms);
+    for (int k = 1; k <= nsteps; ++k) {
+        or_update_links(L, U, P, eps);
+        status |= force_kick_chrono(L, U, P, phi, a, k < nsteps ? eps : 0.5 * eps, Xe, hist, &nh, n_chrono, &ms);
+    }
+
+    double ri[2];
+    or_inner(n, phi, Xe, ri);
+    res->KE_new = or_kinetic(L, P);
+    res->S_g_new = or_gauge_action(L, U, a->beta);
+    res->S_f_new = ri[0];
+    res->H_new = res->KE_new + res->S_g_new + res->S_f_new;
+    res->dH = res->H_new - res->H_old;
+    res->u = or_accept_uniform(seed, traj);
+    res->accepted = metropolis_accept(status, res->dH, res->u);
+    if (!res->accepted) memcpy(U, U_old, sizeof(cplx) * V * 36);
+    res->plaquette = or_plaquette(L, U);
+    res->cg_iters_total = ms.iters_total;
+    res->cg_iters_max = ms.iters_max;
+    res->nonconverged = ms.nonconverged;
+    free(U_old); free(P); free(eta); free(phi); free(Xe); free(hist);
+    return status;
 }

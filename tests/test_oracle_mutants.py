@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 from tests import synth
+from tests import test_oracle_chrono as CH
 from tests import test_oracle_mts as M
 from tests import test_oracle_pins as P
 
@@ -111,6 +112,13 @@ MUTANTS = {
     "ratio heatbath without the heavy solve": (
         "or_mhat(L, U, a->kappa_h, X1, phi2, 0);", "or_mhat(L, U, a->kappa_h, t, phi2, 0);",
         [M.test_reduces_to_plain_hmc_at_equal_kappa]),
+    "chronological guess: Gram matrix conjugated": (
+        "G[j * m + k] = ri[0] + I * ri[1];", "G[j * m + k] = ri[0] - I * ri[1];",
+        [CH.test_guess_satisfies_the_galerkin_condition]),
+    "CG from a guess: residual not recomputed": (
+        "for (long k = 0; k < n; ++k) { r[k] = b[k] - q[k]; p[k] = r[k]; }",
+        "for (long k = 0; k < n; ++k) { r[k] = b[k]; p[k] = r[k]; }",
+        [CH.test_cg_from_the_solution_takes_no_iteration]),
     "link update right-multiplies": (
         "mat_mul(E, &U[l * 9], &U[l * 9]);", "mat_mul(&U[l * 9], E, &U[l * 9]);",
         [P.test_update_links_is_left_multiplication_by_exp]),
