@@ -279,6 +279,9 @@ typedef struct {
   int32_t prec;   /* hmc_prec of the inner iteration */
   int32_t fixed_iters;
   double reliable_delta; /* <= 0 selects 0.1 */
+  int32_t initial_guess; /* CG on Mhat^dag Mhat only: != 0 starts from the x passed in
+                            (r0 = b - A x0); 0 starts from x0 = 0 */
+  int32_t pad;
 } hmc_cg_params;
 typedef struct {
   int32_t iters;            /* total (inner) iterations */
@@ -314,7 +317,11 @@ hmc_status hmc_md_leapfrog(hmc_fields* f, double tau, int32_t nsteps, const hmc_
 typedef struct {
   double tau;
   int32_t nsteps;
-  int32_t pad;
+  int32_t n_chrono; /* 0: every force solve starts from x0 = 0; 1..4: from the
+                       chronological guess, the Galerkin projection of the
+                       solve onto the span of the last n_chrono solutions of
+                       the same trajectory (Brower et al., Nucl. Phys. B 484
+                       (1997) 353) */
   hmc_cg_params cg;
 } hmc_traj_params;
 typedef struct {

@@ -361,6 +361,38 @@ hipError_t launch_axpby(const LatArg& g, double a, const void* x, double b, void
   return hipGetLastError();
 }
 
+// out = sum_k c_k y_k over n <= 4 F64 half spinors (complex coefficients).
+struct LinComb {
+  const double2* y[4];
+  double2 c[4];
+  int n;
+};
+
+__global__ void __launch_bounds__(kBlock) k_lincomb(Lat g, LinComb a, double2* out) {
+  const size_t total = (size_t)12 * g.stride;
+  for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < total; j += (size_t)gridDim.x * kBlock) {
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < a.n; ++k) {
+      const double2 v = a.y[k][j];
+      re += a.c[k].x * v.x - a.c[k].y * v.y;
+      im += a.c[k].x * v.y + a.c[k].y * v.x;
+    }
+    out[j] = make_double2(re, im);
+  }
+}
+
+hipError_t launch_lincomb(const LatArg& g, const void* const* y, const double* c, int n, void* out, hipStream_t st) {
+  if (n < 1 || n > 4) return hipErrorInvalidValue;
+  LinComb a{};
+  for (int k = 0; k < n; ++k) {
+    a.y[k] = (const double2*)y[k];
+    a.c[k] = make_double2(c[2 * k], c[2 * k + 1]);
+  }
+  a.n = n;
+  hipLaunchKernelGGL(k_lincomb, dim3(blas_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), a, (double2*)out);
+  return hipGetLastError();
+}
+
 hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* r, double* part, int nb,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_xmy_norm, dim3(nb), dim3(kBlock), 0, st, to_lat(g), (const double2*)b, (const double2*)q,

@@ -26,7 +26,8 @@ enum Slot {
   SL_SG_NEW = 12,
   SL_RED = 16,  // 16..31 general reductions
   SL_SOLVER = 32,  // 32..47 solver scalars
-  SL_COUNT = 64
+  SL_CHRONO = 64,  // 64..103 Gram matrix and right-hand side of the chronological guess
+  SL_COUNT = 128
 };
 
 constexpr int kNumPart = 8;
@@ -52,6 +53,10 @@ struct Fields {
   void* Yo;
   // mass-preconditioned action: second pseudofermion, its noise, chi and X_2
   void *eta2, *phi2, *chi, *X2;
+  // chronological guess: previous solutions of the trajectory, oldest first
+  static constexpr int kChronoMax = 4;
+  void* hist[kChronoMax];
+  int n_hist;
   // FP64 solver vectors (even half spinors, t odd)
   void *r, *p, *q, *s, *t, *bhat, *tmp;
   // partial-sum buffers, each of npart doubles

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -182,6 +183,8 @@ static size_t plan_fields(Fields* F, char* base, const LatArg& g, uint32_t flags
   f->phi2 = take(h64);
   f->chi = take(h64);
   f->X2 = take(h64);
+  for (int k = 0; k < Fields::kChronoMax; ++k) f->hist[k] = take(h64);
+  f->n_hist = 0;
   f->r = take(h64);
   f->p = take(h64);
   f->q = take(h64);
@@ -710,13 +713,95 @@ hmc_status hmc_cg_solve(hmc_fields* f, void* x, const void* b, const hmc_cg_para
 
 // One force evaluation: P -= coef (F_g + F_f) with the fermion force from a
 // fresh solve of phi_e into X_e.
-static hmc_status force_kick(Fields* F, double coef, const hmc_cg_params* cg, hmc_md_stats* ms, hipStream_t st) {
+// Chronological guess into x: the Galerkin projection of A x = phi onto the
+// span of the stored solutions F->hist[0..n_hist) (Brower, Ivanenko, Levi,
+// Orginos, Nucl. Phys. B 484 (1997) 353).  G_jk = <y_j, A y_k>, f_j =
+// <y_j, phi>, G c = f by Gaussian elimination with partial pivoting on the
+// host, x = sum_k c_k y_k.  *ok is false (x untouched) when G is singular.
+static hmc_status chrono_guess(Fields* F, const void* phi, void* x, bool* ok, hipStream_t st) {
+  const int m = F->n_hist, nb = F->nbR;
+  *ok = false;
+  if (m < 1) return HMC_OK;
+  for (int k = 0; k < m; ++k) {
+    HMC_CHECK_HIP(mhat_f64(F, F->s, F->hist[k], 0, nullptr, st));
+    HMC_CHECK_HIP(mhat_f64(F, F->q, F->s, 1, nullptr, st));
+    for (int j = 0; j < m; ++j) {
+      HMC_CHECK_HIP(launch_inner_partials(F->g, F->hist[j], F->q, F->part[1], nb, st));
+      HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_CHRONO + 2 * (j * m + k), st));
+    }
+  }
+  for (int j = 0; j < m; ++j) {
+    HMC_CHECK_HIP(launch_inner_partials(F->g, F->hist[j], phi, F->part[1], nb, st));
+    HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_CHRONO + 2 * (m * m + j), st));
+  }
+  double v[2 * (Fields::kChronoMax * Fields::kChronoMax + Fields::kChronoMax)];
+  HMC_CHECK_HIP(read_slots(F, SL_CHRONO, 2 * (m * m + m), v, st));
+  using C = std::complex<double>;
+  C G[Fields::kChronoMax][Fields::kChronoMax], f[Fields::kChronoMax], c[Fields::kChronoMax];
+  for (int j = 0; j < m; ++j) {
+    for (int k = 0; k < m; ++k) G[j][k] = C(v[2 * (j * m + k)], v[2 * (j * m + k) + 1]);
+    f[j] = C(v[2 * (m * m + j)], v[2 * (m * m + j) + 1]);
+  }
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::abs(G[r][col]) > std::abs(G[piv][col])) piv = r;
+    if (!(std::abs(G[piv][col]) > 0)) return HMC_OK;
+    if (piv != col) {
+      for (int k = 0; k < m; ++k) std::swap(G[col][k], G[piv][k]);
+      std::swap(f[col], f[piv]);
+    }
+    for (int r = col + 1; r < m; ++r) {
+      const C l = G[r][col] / G[col][col];
+      for (int k = col; k < m; ++k) G[r][k] -= l * G[col][k];
+      f[r] -= l * f[col];
+    }
+  }
+  for (int r = m - 1; r >= 0; --r) {
+    C s = f[r];
+    for (int k = r + 1; k < m; ++k) s -= G[r][k] * c[k];
+    c[r] = s / G[r][r];
+  }
+  double cc[2 * Fields::kChronoMax];
+  for (int k = 0; k < m; ++k) {
+    if (!std::isfinite(c[k].real()) || !std::isfinite(c[k].imag())) return HMC_OK;
+    cc[2 * k] = c[k].real();
+    cc[2 * k + 1] = c[k].imag();
+  }
+  HMC_CHECK_HIP(launch_lincomb(F->g, F->hist, cc, m, x, st));
+  *ok = true;
+  return HMC_OK;
+}
+
+// Appends the solution x to the history (the oldest drops out at n_chrono).
+static hmc_status chrono_push(Fields* F, const void* x, int n_chrono, hipStream_t st) {
+  if (F->n_hist == n_chrono) {
+    void* oldest = F->hist[0];
+    for (int k = 1; k < n_chrono; ++k) F->hist[k - 1] = F->hist[k];
+    F->hist[n_chrono - 1] = oldest;
+    --F->n_hist;
+  }
+  HMC_CHECK_HIP(launch_copy(F->hist[F->n_hist], x, F->half64, st));
+  ++F->n_hist;
+  return HMC_OK;
+}
+
+static hmc_status force_kick(Fields* F, double coef, const hmc_cg_params* cg, hmc_md_stats* ms, hipStream_t st,
+                             int n_chrono = 0) {
   HMC_CHECK_HIP(launch_gauge_force(F->g, F->U, F->P, coef * F->beta, st, F->su3));
   hmc_cg_params p = *cg;
   p.mode = HMC_CG_NORMAL_MHAT;
+  p.initial_guess = 0;
+  if (n_chrono > 0) {
+    bool ok = false;
+    hmc_status g = chrono_guess(F, F->phi, F->Xe, &ok, st);
+    if (g) return g;
+    p.initial_guess = ok ? 1 : 0;
+  }
   hmc_cg_stats cs;
   hmc_status s = cg_solve_impl(F, F->Xe, F->phi, &p, &cs, st);
   if (s != HMC_OK && s != HMC_E_NOCONV) return s;
+  if (n_chrono > 0 && (s = chrono_push(F, F->Xe, n_chrono, st))) return s;
   ms->solves++;
   ms->iters_total += cs.iters;
   ms->iters_max = std::max(ms->iters_max, cs.iters);
@@ -726,16 +811,17 @@ static hmc_status force_kick(Fields* F, double coef, const hmc_cg_params* cg, hm
 }
 
 static hmc_status leapfrog_impl(Fields* F, double tau, int nsteps, const hmc_cg_params* cg, hmc_md_stats* ms,
-                                hipStream_t st) {
+                                hipStream_t st, int n_chrono = 0) {
   const double eps = tau / nsteps;
   *ms = hmc_md_stats{0, 0, 0, 0};
-  hmc_status s = force_kick(F, 0.5 * eps, cg, ms, st);
+  F->n_hist = 0;
+  hmc_status s = force_kick(F, 0.5 * eps, cg, ms, st, n_chrono);
   if (s) return s;
   for (int k = 1; k <= nsteps; ++k) {
     HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, st));
     F->u_version++;
     F->su3 = true;
-    s = force_kick(F, k < nsteps ? eps : 0.5 * eps, cg, ms, st);
+    s = force_kick(F, k < nsteps ? eps : 0.5 * eps, cg, ms, st, n_chrono);
     if (s) return s;
   }
   return HMC_OK;
@@ -758,6 +844,8 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
   FIELDS(f);
   HMC_REQUIRE(params && res, "null argument");
   HMC_REQUIRE(params->nsteps >= 1, "nsteps must be >= 1");
+  HMC_REQUIRE(params->n_chrono >= 0 && params->n_chrono <= Fields::kChronoMax, "n_chrono must be in 0..%d",
+              Fields::kChronoMax);
   hipStream_t st = ST(stream);
   auto t0 = std::chrono::steady_clock::now();
   const size_t ub = gauge_bytes(F->g.Vh, HMC_F64);
@@ -774,7 +862,7 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_ETA2, st));
 
   hmc_md_stats ms;
-  hmc_status s = leapfrog_impl(F, params->tau, params->nsteps, &params->cg, &ms, st);
+  hmc_status s = leapfrog_impl(F, params->tau, params->nsteps, &params->cg, &ms, st, params->n_chrono);
   if (s) return s;
 
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
@@ -903,6 +991,7 @@ hmc_status solve_at(Fields* F, double kappa_c, void* x, const void* b, const hmc
                     int* nonconv, hipStream_t st) {
   hmc_cg_params p = *cg;
   p.mode = HMC_CG_NORMAL_MHAT;
+  p.initial_guess = 0;
   hmc_cg_stats cs{};
   const double k0 = F->kappa;
   F->kappa = kappa_c;

@@ -321,8 +321,10 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   v.nbR = F->nbR;
   hmc_cg_stats S{};
 
-  // ---- set-up in FP64: |b|^2, the even right-hand side, x = 0, r = rhs
+  // ---- set-up in FP64: |b|^2, the even right-hand side, x = x0 (0 unless
+  // initial_guess), r = rhs - A x0
   const char* bb = (const char*)b;
+  const bool guess = !cgls && prm->initial_guess;
   double bnorm2 = 0, rr0 = 0;
   if (cgls) {
     CHK(launch_norm2_partials(F->g, HMC_F64, bb, v.red, F->nbR, st));
@@ -332,11 +334,22 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
     // bhat_e = b_e + kappa D_eo b_o
     CHK(dslash_f64(F, F->bhat, bb + F->half64, 0, 0, EPI_AXPY, bb, 1.0, F->kappa, nullptr, nullptr, 0, st));
   }
-  // |r|^2 partials in pp[0] with the Dslash-epilogue count, as the iteration reads them
-  CHK(launch_cg_init(F->g, HMC_F64, v.rhs, x, v.r64, prec == HMC_F64 ? v.p : v.q64, v.pp[0], v.nbD, st));
+  if (guess) {
+    CHK(launch_norm2_partials(F->g, HMC_F64, bb, v.red, F->nbR, st));
+    CHK(launch_finalize(v.red, F->nbR, 1, v.slot, 1.0, 0, st));
+    CHK(read_slots(F, SL_SOLVER, 1, &bnorm2, st));
+    // r = b - Mhat^dag Mhat x0, |r|^2 partials in pp[0]; p = r (F64)
+    CHK(mhat64(v, v.s64, x, 0, nullptr, st));
+    CHK(mhat64(v, v.q64, v.s64, 1, nullptr, st));
+    CHK(launch_xmy_norm(F->g, v.rhs, v.q64, v.r64, v.pp[0], v.nbD, st));
+    if (prec == HMC_F64) CHK(launch_copy(v.p, v.r64, F->half64, st));
+  } else {
+    // |r|^2 partials in pp[0] with the Dslash-epilogue count, as the iteration reads them
+    CHK(launch_cg_init(F->g, HMC_F64, v.rhs, x, v.r64, prec == HMC_F64 ? v.p : v.q64, v.pp[0], v.nbD, st));
+  }
   CHK(launch_finalize(v.pp[0], v.nbD, 1, v.slot, 1.0, 0, st));
   CHK(read_slots(F, SL_SOLVER, 1, &rr0, st));
-  if (!cgls) bnorm2 = rr0;
+  if (!cgls && !guess) bnorm2 = rr0;
   const double thr = fixed > 0 ? -1.0 : prm->tol * prm->tol * bnorm2;
 
   int k = 0;

@@ -44,7 +44,8 @@ class Action(C.Structure):
 
 class CgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("mode", C.c_int32), ("prec", C.c_int32),
-                ("fixed_iters", C.c_int32), ("reliable_delta", C.c_double)]
+                ("fixed_iters", C.c_int32), ("reliable_delta", C.c_double), ("initial_guess", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class CgStats(C.Structure):
@@ -58,7 +59,7 @@ class MdStats(C.Structure):
 
 
 class TrajParams(C.Structure):
-    _fields_ = [("tau", C.c_double), ("nsteps", C.c_int32), ("pad", C.c_int32), ("cg", CgParams)]
+    _fields_ = [("tau", C.c_double), ("nsteps", C.c_int32), ("n_chrono", C.c_int32), ("cg", CgParams)]
 
 
 class MtsParams(C.Structure):
@@ -436,8 +437,9 @@ def hmc_random_gaussians(seed, rng_stream, epoch, sites, n, stream=None):
     return out
 
 
-def cg_params(tol=1e-10, maxiter=10000, mode=CG_NORMAL_MHAT, prec=F64, fixed_iters=0, reliable_delta=0.1):
-    return CgParams(tol, maxiter, mode, prec, fixed_iters, reliable_delta)
+def cg_params(tol=1e-10, maxiter=10000, mode=CG_NORMAL_MHAT, prec=F64, fixed_iters=0, reliable_delta=0.1,
+              initial_guess=0):
+    return CgParams(tol, maxiter, mode, prec, fixed_iters, reliable_delta, initial_guess, 0)
 
 
 def hmc_cg_solve(f, x, b, params: CgParams, stream=None, allow_noconv=False):
@@ -458,8 +460,8 @@ def hmc_md_leapfrog(f, tau, nsteps, params: CgParams, stream=None, allow_noconv=
     return d
 
 
-def hmc_trajectory(f, seed, traj, tau, nsteps, params: CgParams, stream=None):
-    tp = TrajParams(float(tau), int(nsteps), 0, params)
+def hmc_trajectory(f, seed, traj, tau, nsteps, params: CgParams, stream=None, n_chrono=0):
+    tp = TrajParams(float(tau), int(nsteps), int(n_chrono), params)
     r = TrajResult()
     status = lib().hmc_trajectory(_h(f), seed, traj, C.byref(tp), C.byref(r), _stream(stream))
     check(status, allow=(HMC_E_NOCONV, HMC_E_NAN))
