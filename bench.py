@@ -135,13 +135,14 @@ def run_hmc(args, H, torch):
     prm = H.cg_params(tol=1e-10, maxiter=10000)
     H.hmc_weak_field_start(F, seed, 0.3)
     for w in range(args.warmup):
-        H.hmc_trajectory(F, seed, w, tau, nsteps, prm)
+        H.hmc_trajectory(F, seed, w, tau, nsteps, prm, n_chrono=args.chrono)
     H.hmc_weak_field_start(F, seed, 0.3)  # timed chain starts at trajectory 0
     torch.cuda.synchronize()
     H.hmc_timing_reset()
     H.hmc_timing_enable(args.sample_every)
     t0 = time.perf_counter()
-    results = [H.hmc_trajectory(F, seed, k, tau, nsteps, prm, stream=stream) for k in range(args.steps)]
+    results = [H.hmc_trajectory(F, seed, k, tau, nsteps, prm, stream=stream, n_chrono=args.chrono)
+               for k in range(args.steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     H.hmc_timing_enable(0)
@@ -155,7 +156,9 @@ def run_hmc(args, H, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "hmc_16c32", "lattice": list(L), "beta": beta, "kappa": kappa, "tau": tau,
                    "nsteps": nsteps, "cg_tol": 1e-10, "start": "weak-field eps=0.3 seed 12120785",
-                   "trajectories": f"0..{args.steps - 1}", "parallelism": "1 GPU"},
+                   "trajectories": f"0..{args.steps - 1}", "initial_guess": (
+                       f"chronological, last {args.chrono} solutions" if args.chrono else "zero"),
+                   "parallelism": "1 GPU"},
         "trajectories": [{"traj": k, "seconds": r["seconds"], "dH": r["dH"], "accepted": r["accepted"],
                           "plaquette": r["plaquette"], "cg_iters": r["cg_iters_total"]}
                          for k, r in enumerate(results)],
@@ -493,6 +496,8 @@ def main():
                           "four Dslash launches of a CG iteration; each sampled launch costs the GPU a few us)"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kappa-h", type=float, default=0.10, help="mts: heavy hopping parameter")
+    ap.add_argument("--chrono", type=int, default=0,
+                    help="hmc: start each force solve from the chronological guess over the last N solutions")
     ap.add_argument("--mts-steps", default="5,2,2", help="mts: ratio,heavy,gauge steps per enclosing step")
     args = ap.parse_args()
     if args.gpus != 1:
