@@ -338,6 +338,29 @@ typedef struct {
 hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_traj_params* params,
                           hmc_traj_result* result, void* stream);
 
+/* ---- Launch auto-tuning (the auto-tuner of Sec. 4, for the launch shapes
+ * this library offers).  Kinds: HMC_TUNE_DSLASH (choice 1 = one site per
+ * work-item, 2 / 4 = direction split with that many wavefronts per 64-site
+ * group; one entry per storage precision) and HMC_TUNE_GAUGE_FORCE (0 = one
+ * link per work-item, 1 = plane split; prec HMC_F64).  Decision order:
+ * environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES) > table entry
+ * for the lattice extents > built-in rule.  HMC_TUNE_DB names a table file
+ * read on first use.  Table file: text lines "kind L0 L1 L2 L3 prec choice
+ * us"; unknown or malformed lines are ignored.  Shapes are fixed per solve
+ * (and per service request) when it starts; do not tune while solves or a
+ * service run on the same lattice extents. */
+typedef enum { HMC_TUNE_DSLASH = 0, HMC_TUNE_GAUGE_FORCE = 1 } hmc_tune_kind;
+/* Times every candidate shape on f's lattice (Dslash for F64 and, with
+ * HMC_FIELDS_LOWPREC, the low precisions; the staple force with coef 0,
+ * which leaves P unchanged) and stores the fastest in the table; with
+ * db_path != NULL the table is merged into that file.  Overwrites f's
+ * solver work vectors.  Synchronises. */
+hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream);
+hmc_status hmc_tune_load(const char* path, int32_t* n_entries);
+hmc_status hmc_tune_save(const char* path, int32_t* n_entries);
+/* Active decision for lattice L (*tuned = 1 when it comes from the table). */
+hmc_status hmc_tune_query(const int32_t* L, int32_t kind, int32_t prec, int32_t* choice, int32_t* tuned);
+
 /* ---- Mass-preconditioned (Hasenbusch) two-flavour HMC on nested time
  * scales (the production setup of Sec. 7).  det(A) is split with a heavier
  * hopping parameter kappa_h (0 < kappa_h <= kappa), A = Mhat^dag Mhat:

@@ -286,8 +286,9 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   g.Vh = ga.Vh;
   g.stride = ga.stride;
   const hmc_prec prec = std::is_same_v<typename SP::R, double> ? HMC_F64 : HMC_F32;
-  const int ways = dslash_split_ways(ga.Vh, prec);
-  const dim3 grid(dslash_blocks(ga.Vh, prec), nbatch);
+  const int shape = one.shape ? one.shape : dslash_shape(ga, prec);
+  const int ways = shape == 1 ? 0 : shape;
+  const dim3 grid(dslash_shape_blocks(ga.Vh, shape), nbatch);
   const dim3 block(ways ? 64 * ways : kBlock);
 #define HMC_LAUNCH(KERNEL) \
   hipExtLaunchKernelGGL(KERNEL, grid, block, 0, st, ev.start, ev.stop, 0, g, out_par, table, one, j)
@@ -327,18 +328,6 @@ static hipError_t launch_typed(int dagger, int epi, const LatArg& ga, int out_pa
   return hipGetLastError();
 }
 
-int dslash_split_ways(int Vh, hmc_prec prec) {
-  static const int forced = [] {
-    const char* e = getenv("HMC_DSLASH_SPLIT");
-    if (!e) return -1;
-    const int v = atoi(e);
-    return v == 1 ? 4 : (v == 2 || v == 4) ? v : 0;
-  }();
-  if (forced >= 0) return forced;
-  // measured on MI355X: the 4-way split gains for FP32 arithmetic up to
-  // 16^3x32 and loses at 48^3x96; FP64 is even at 16^3x32
-  return (prec != HMC_F64 && Vh <= (1 << 17)) ? 4 : 0;
-}
 
 bool link_rows2_enabled() {
   static const bool v = [] {

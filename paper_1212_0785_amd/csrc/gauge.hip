@@ -252,21 +252,9 @@ hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* par
   return hipGetLastError();
 }
 
-// Plane-split form for large volumes (measured on MI355X: 6% faster at
-// 48^3x96, 20% slower at 16^3x32); HMC_GFORCE_PLANES=0/1 (read once)
-// overrides.
-static bool gauge_force_planes(int Vh) {
-  static const int forced = [] {
-    const char* e = getenv("HMC_GFORCE_PLANES");
-    return e ? atoi(e) : -1;
-  }();
-  if (forced >= 0) return forced != 0;
-  return Vh > (1 << 20);
-}
-
 template <class LK>
-static void gauge_force_typed(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st) {
-  if (gauge_force_planes(g.Vh))
+static void gauge_force_typed(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st, int shape) {
+  if (shape == 1)
     hipLaunchKernelGGL(k_gauge_force_planes<LK>, dim3(ceil_div(2LL * g.Vh, kGfSites), 4), dim3(3 * kGfSites), 0, st,
                        to_lat(g), U, P, coef_beta);
   else
@@ -275,15 +263,16 @@ static void gauge_force_typed(const LatArg& g, const void* U, double* P, double 
 }
 
 hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st,
-                              bool rows2) {
+                              bool rows2, int shape) {
+  if (shape < 0) shape = gauge_force_shape(g);
   rows2 = rows2 && link_rows2_enabled();
   // algorithmic: 4 links read, momenta read + written, per site
   TimedScope ts(TK_GAUGE_FORCE, st,
                 2.0 * g.Vh * (4 * (rows2 ? LkRows2<LkF64>::kBytes : LkF64::kBytes) + 2 * 4 * 64));
   if (rows2)
-    gauge_force_typed<LkRows2<LkF64>>(g, U, P, coef_beta, st);
+    gauge_force_typed<LkRows2<LkF64>>(g, U, P, coef_beta, st, shape);
   else
-    gauge_force_typed<LkF64>(g, U, P, coef_beta, st);
+    gauge_force_typed<LkF64>(g, U, P, coef_beta, st, shape);
   return hipGetLastError();
 }
 

@@ -158,7 +158,7 @@ static size_t plan_fields(Fields* F, char* base, const LatArg& g, uint32_t flags
   };
   const int Vh = g.Vh;
   const size_t h64 = half_bytes(Vh, HMC_F64);
-  const int nbD = dslash_blocks(Vh, HMC_F64), nbR = blas_blocks(Vh);
+  const int nbD = dslash_blocks(g, HMC_F64), nbR = blas_blocks(Vh);
   const int npart = 2 * std::max(dslash_blocks_max(Vh), nbR);
   const int nb_multi = std::min(nbR, 1024);
   const size_t multi = (size_t)nb_multi * 2 * 1024 + 1024;
@@ -1216,5 +1216,121 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
     set_error("non-finite energy change; trajectory rejected");
     return HMC_E_NAN;
   }
+  return HMC_OK;
+}
+
+// ------------------------------------------------------- auto-tuning
+
+hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
+  FIELDS(f);
+  hipStream_t st = ST(stream);
+  hipEvent_t e0, e1;
+  HMC_CHECK_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return HMC_E_HIP;
+  }
+  auto time_us = [&](auto&& launch, int reps) -> double {
+    for (int w = 0; w < 2; ++w)
+      if (launch() != hipSuccess) return -1;
+    if (hipEventRecord(e0, st) != hipSuccess) return -1;
+    for (int r = 0; r < reps; ++r)
+      if (launch() != hipSuccess) return -1;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1;
+    return 1e3 * ms / reps;
+  };
+  hmc_status status = HMC_OK;
+  const int nprec = (F->flags & HMC_FIELDS_LOWPREC) ? 4 : 1;
+  for (int pi = 0; pi < nprec && status == HMC_OK; ++pi) {
+    const hmc_prec prec = (hmc_prec)pi;
+    if (ensure_lowprec(F, prec, st) != hipSuccess) {
+      status = HMC_E_HIP;
+      break;
+    }
+    void* in = prec == HMC_F64 ? F->p : F->lp;
+    void* out = prec == HMC_F64 ? F->s : F->ls;
+    if (launch_zero(in, prec == HMC_F64 ? F->half64 : F->halflow, st) != hipSuccess) {
+      status = HMC_E_HIP;
+      break;
+    }
+    int best = 0;
+    double best_us = 0;
+    for (int shape : {1, 2, 4}) {
+      DslashArgs d{};
+      d.U = low_links(F, prec);
+      d.in = in;
+      d.out = out;
+      d.b = 1.0;
+      d.rows2 = F->su3;
+      d.shape = shape;
+      const double us = time_us([&] { return launch_dslash(prec, 0, EPI_PLAIN, F->g, 0, nullptr, 1, d, st); }, 10);
+      if (us < 0) {
+        status = HMC_E_HIP;
+        break;
+      }
+      if (!best || us < best_us) best = shape, best_us = us;
+    }
+    if (status == HMC_OK) tune_store(F->g.L, TUNE_DSLASH, prec, best, best_us);
+  }
+  if (status == HMC_OK) {
+    int best = -1;
+    double best_us = 0;
+    for (int shape : {0, 1}) {
+      const double us = time_us(
+          [&] { return launch_gauge_force(F->g, F->U, F->P, 0.0, st, F->su3, shape); }, 5);
+      if (us < 0) {
+        status = HMC_E_HIP;
+        break;
+      }
+      if (best < 0 || us < best_us) best = shape, best_us = us;
+    }
+    if (status == HMC_OK) tune_store(F->g.L, TUNE_GFORCE, HMC_F64, best, best_us);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (status != HMC_OK) {
+    set_error("a timed launch failed during tuning");
+    return status;
+  }
+  if (db_path && tune_save(db_path) < 0) {
+    set_error("could not write the tuning table to %s", db_path);
+    return HMC_E_ARG;
+  }
+  return HMC_OK;
+}
+
+hmc_status hmc_tune_load(const char* path, int32_t* n_entries) {
+  HMC_REQUIRE(path, "null path");
+  const int n = tune_load(path);
+  HMC_REQUIRE(n >= 0, "cannot read %s", path);
+  if (n_entries) *n_entries = n;
+  return HMC_OK;
+}
+
+hmc_status hmc_tune_save(const char* path, int32_t* n_entries) {
+  HMC_REQUIRE(path, "null path");
+  const int n = tune_save(path);
+  HMC_REQUIRE(n >= 0, "cannot write %s", path);
+  if (n_entries) *n_entries = n;
+  return HMC_OK;
+}
+
+hmc_status hmc_tune_query(const int32_t* L, int32_t kind, int32_t prec, int32_t* choice, int32_t* tuned) {
+  HMC_REQUIRE(L && choice, "null argument");
+  HMC_REQUIRE(kind == HMC_TUNE_DSLASH || kind == HMC_TUNE_GAUGE_FORCE, "bad kind %d", kind);
+  HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision %d", prec);
+  hmc_geom geom;
+  for (int k = 0; k < 4; ++k) geom.L[k] = L[k];
+  LatArg g;
+  long long V;
+  hmc_status s = check_geom(&geom, &g, &V);
+  if (s) return s;
+  const int ints[4] = {L[0], L[1], L[2], L[3]};
+  const int t = tune_lookup(ints, kind, kind == HMC_TUNE_DSLASH ? prec : HMC_F64);
+  *choice = kind == HMC_TUNE_DSLASH ? dslash_shape(g, (hmc_prec)prec) : gauge_force_shape(g);
+  if (tuned) *tuned = t >= 0 ? 1 : 0;
   return HMC_OK;
 }

@@ -33,18 +33,23 @@ inline int blas_blocks(int Vh) {
 }
 inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 
-// Dslash kernel shape: one site per work-item (256 sites per block) or the
-// direction-split form (64 sites per block, 2 or 4 wavefronts per group of
-// sites), taken for the single-precision-arithmetic storages at volumes too
-// small to fill the GPU with one wavefront per 64 sites.  Returns the
-// wavefronts per site group (0: one site per work-item);
-// HMC_DSLASH_SPLIT=0/2/4 (read once; 1 means 4) overrides the rule.
-int dslash_split_ways(int Vh, hmc_prec prec);
-inline int dslash_blocks(int Vh, hmc_prec prec) {
-  return dslash_split_ways(Vh, prec) ? ceil_div(Vh, kThreads / 4) : site_blocks(Vh);
-}
-// Largest block count (and Dslash-epilogue partial count) of either shape.
+// Launch shapes (tune.cpp).  Dslash shape: 1 = one site per work-item (256
+// sites per block), 2 / 4 = direction split with that many wavefronts per
+// 64-site group.  Staple-force shape: 0 = one link per work-item, 1 = plane
+// split.  Decided by the environment override, else the tuning table, else
+// the built-in rule.
+enum TuneKind { TUNE_DSLASH = 0, TUNE_GFORCE = 1 };
+int dslash_shape(const LatArg& g, hmc_prec prec);
+int gauge_force_shape(const LatArg& g);
+inline int dslash_shape_blocks(int Vh, int shape) { return shape == 1 ? site_blocks(Vh) : ceil_div(Vh, kThreads / 4); }
+inline int dslash_blocks(const LatArg& g, hmc_prec prec) { return dslash_shape_blocks(g.Vh, dslash_shape(g, prec)); }
+// Largest block count (and Dslash-epilogue partial count) of any shape.
 inline int dslash_blocks_max(int Vh) { return ceil_div(Vh, kThreads / 4); }
+// Tuning table: -1 when absent; load/save return entries read/written or -1.
+int tune_lookup(const int* L, int kind, int prec);
+void tune_store(const int* L, int kind, int prec, int choice, double us);
+int tune_load(const char* path);
+int tune_save(const char* path);
 
 // Iteration control of the Krylov solvers, resident in device memory.
 // Kernels of iteration k do nothing once k >= stop_at.  Only block 0 of the
@@ -76,6 +81,7 @@ struct DslashArgs {
   const int* stop_at;   // solver control (may be null)
   int iter0;            // label offset compared with *stop_at
   int rows2;            // host dispatch: links are SU(3), read two rows and rebuild the third
+  int shape;            // host dispatch: 0 = dslash_shape(), else a fixed Dslash shape (1, 2, 4)
   // Step-length prologue (block 0 only, when alpha_out is set):
   //   *alpha_out = sum(alpha_pp[label & 1][0..n_pp)) / sum(alpha_den[0..n_den))
   const double* alpha_pp[2];
@@ -166,8 +172,9 @@ hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStre
 hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st,
                                      bool rows2);
 hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* part, int nb, hipStream_t st);
+// shape: -1 = gauge_force_shape(), 0 / 1 = fixed.
 hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st,
-                              bool rows2);
+                              bool rows2, int shape = -1);
 hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st);
 hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
                                 const void* Yo, double* P, double coef, hipStream_t st,

@@ -63,7 +63,8 @@ size_t carve_request(char* base, const LatArg& g, int prec, SolveVecs* v, void**
   Carve c(base);
   const int Vh = g.Vh;
   const size_t h64 = half_bytes(Vh, HMC_F64);
-  const int nbD = dslash_blocks(Vh, (hmc_prec)prec), nbR = blas_blocks(Vh);
+  const int shape = dslash_shape(g, (hmc_prec)prec);
+  const int nbD = dslash_shape_blocks(Vh, shape), nbR = blas_blocks(Vh);
   SolveVecs t{};
   SolveVecs& s = v ? *v : t;
   *U64 = c.take((size_t)Vh * 8 * 144);
@@ -83,13 +84,17 @@ size_t carve_request(char* base, const LatArg& g, int prec, SolveVecs* v, void**
     s.r = c.take(hl), s.p = c.take(hl), s.q = c.take(hl), s.s = c.take(hl), s.t = c.take(hl);
     s.xl = c.take(half_bytes(Vh, HMC_F32));
   }
-  s.pp[0] = (double*)c.take((size_t)nbD * 8);
-  s.pp[1] = (double*)c.take((size_t)nbD * 8);
-  s.pq = (double*)c.take((size_t)nbD * 8);
+  // sized for the largest shape, so the footprint does not depend on tuning
+  const size_t np = (size_t)dslash_blocks_max(Vh);
+  s.pp[0] = (double*)c.take(np * 8);
+  s.pp[1] = (double*)c.take(np * 8);
+  s.pq = (double*)c.take(np * 8);
   s.pr = (double*)c.take((size_t)nbR * 8);
   s.red = (double*)c.take((size_t)2 * nbR * 8);
   s.nbD = nbD;
   s.nbR = nbR;
+  s.shape = shape;
+  s.shape64 = dslash_shape(g, HMC_F64);
   return c.off;
 }
 

@@ -39,6 +39,7 @@ void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, doubl
   DslashArgs b{};
   b.U = v.Ulow;
   b.rows2 = v.rows2;
+  b.shape = v.shape;
   b.stop_at = &v.state->stop_at;
   b.iter0 = iter0;
   b.a = 1.0;
@@ -119,6 +120,7 @@ static hipError_t ds64(const SolveVecs& v, void* out, const void* in, int out_pa
   DslashArgs d{};
   d.U = v.U64;
   d.rows2 = v.rows2;
+  d.shape = v.shape64;
   d.in = in;
   d.out = out;
   d.y = y;
@@ -161,6 +163,7 @@ hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st) 
     DslashArgs d{};
     d.U = v.Ulow;
     d.rows2 = v.rows2;
+    d.shape = v.shape;
     d.in = v.r;
     d.out = v.t;
     d.a = 1.0;
@@ -317,7 +320,10 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   v.red = F->part[4];
   v.slot = F->slots + SL_SOLVER;
   v.state = F->state;
-  v.nbD = dslash_blocks(F->g.Vh, prec);
+  // shapes fixed for the whole solve (the partial counts follow from them)
+  v.shape = dslash_shape(F->g, prec);
+  v.shape64 = dslash_shape(F->g, HMC_F64);
+  v.nbD = dslash_shape_blocks(F->g.Vh, v.shape);
   v.nbR = F->nbR;
   hmc_cg_stats S{};
 

@@ -152,6 +152,11 @@ _SIGNATURES = {
     "hmc_md_leapfrog": (_I32, [_P, _D, _I32, C.POINTER(CgParams), C.POINTER(MdStats), _P]),
     "hmc_trajectory": (_I32, [_P, _U64, _U64, C.POINTER(TrajParams), C.POINTER(TrajResult), _P]),
     "hmc_fermion_force_bilinear": (_I32, [_P, _P, _P, C.c_double, C.c_double, _P]),
+    "hmc_autotune": (_I32, [_P, C.c_char_p, _P]),
+    "hmc_tune_load": (_I32, [C.c_char_p, C.POINTER(C.c_int32)]),
+    "hmc_tune_save": (_I32, [C.c_char_p, C.POINTER(C.c_int32)]),
+    "hmc_tune_query": (_I32, [C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32)]),
     "hmc_md_mts": (_I32, [_P, _P, C.POINTER(MtsParams), C.POINTER(MtsStats), _P]),
     "hmc_trajectory_mts": (_I32, [_P, _U64, _U64, C.POINTER(MtsParams), C.POINTER(TrajResult), C.POINTER(MtsStats),
                                   _P]),
@@ -371,6 +376,33 @@ def hmc_kinetic_energy(f, stream=None) -> float:
 
 def hmc_gauge_force(f, coef, stream=None):
     check(lib().hmc_gauge_force(_h(f), float(coef), _stream(stream)))
+
+
+TUNE_DSLASH, TUNE_GAUGE_FORCE = 0, 1
+
+
+def hmc_autotune(f, db_path=None, stream=None):
+    check(lib().hmc_autotune(_h(f), db_path.encode() if db_path else None, _stream(stream)))
+
+
+def hmc_tune_load(path) -> int:
+    n = C.c_int32()
+    check(lib().hmc_tune_load(path.encode(), C.byref(n)))
+    return n.value
+
+
+def hmc_tune_save(path) -> int:
+    n = C.c_int32()
+    check(lib().hmc_tune_save(path.encode(), C.byref(n)))
+    return n.value
+
+
+def hmc_tune_query(L, kind, prec=F64):
+    """-> (choice, tuned): the active launch shape for lattice L."""
+    arr = (C.c_int32 * 4)(*[int(v) for v in L])
+    ch, tu = C.c_int32(), C.c_int32()
+    check(lib().hmc_tune_query(arr, int(kind), int(prec), C.byref(ch), C.byref(tu)))
+    return ch.value, bool(tu.value)
 
 
 def mts_params(tau, kappa_h, n_ratio, n_heavy, n_gauge, cg: CgParams):

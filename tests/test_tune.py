@@ -1,0 +1,48 @@
+"""The launch-shape tuning table (host side of libhmc; no GPU needed)."""
+import os
+
+import pytest
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1212_0785_amd", "libhmc.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhmc.so not built")
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1212_0785_amd import hmc
+    hmc.lib()
+    return hmc
+
+
+def test_table_load_query_and_save(H, tmp_path):
+    if os.environ.get("HMC_DSLASH_SPLIT") or os.environ.get("HMC_GFORCE_PLANES"):
+        pytest.skip("environment overrides the table")
+    src = tmp_path / "tune.txt"
+    src.write_text("# comment line\n"
+                   "dslash 6 2 2 10 0 2 12.5\n"
+                   "dslash 6 2 2 10 1 4 7.0\n"
+                   "gauge_force 6 2 2 10 0 1 90.0\n"
+                   "dslash 6 2 2 10 0 3 1.0\n"       # invalid shape: ignored
+                   "nonsense 1 2 3\n"
+                   "dslash 6 2 2 10 9 1 1.0\n")      # invalid precision: ignored
+    assert H.hmc_tune_load(str(src)) == 3
+    assert H.hmc_tune_query((6, 2, 2, 10), H.TUNE_DSLASH, H.F64) == (2, True)
+    assert H.hmc_tune_query((6, 2, 2, 10), H.TUNE_DSLASH, H.F32) == (4, True)
+    assert H.hmc_tune_query((6, 2, 2, 10), H.TUNE_GAUGE_FORCE) == (1, True)
+    # untuned entries follow the built-in rule (small volume: F64 one site
+    # per work-item, FP32 arithmetic 4-way split, staple force unsplit)
+    assert H.hmc_tune_query((6, 2, 2, 10), H.TUNE_DSLASH, H.F16) == (4, False)
+    assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_DSLASH, H.F64) == (1, False)
+    assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_GAUGE_FORCE) == (0, False)
+    # save merges with what the file already holds
+    dst = tmp_path / "out.txt"
+    dst.write_text("dslash 2 2 2 2 0 4 3.0\n")
+    n = H.hmc_tune_save(str(dst))
+    lines = [ln.split() for ln in dst.read_text().splitlines() if ln and not ln.startswith("#")]
+    assert n == len(lines) >= 4
+    assert ["dslash", "2", "2", "2", "2", "0", "4", "3.000"] in lines
+    assert ["dslash", "6", "2", "2", "10", "1", "4", "7.000"] in lines
+    with pytest.raises(H.HmcError):
+        H.hmc_tune_query((5, 2, 2, 10), H.TUNE_DSLASH, H.F64)  # odd extent
+    with pytest.raises(H.HmcError):
+        H.hmc_tune_load(str(tmp_path / "missing.txt"))
