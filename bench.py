@@ -65,6 +65,19 @@ def load_traffic(workload: str):
     return e.get("bytes_per_launch")
 
 
+def launch_shapes(H, L, db):
+    """The Dslash and staple-force shapes in force for lattice L (Dslash: 1 =
+    one site per work-item, 2/4 = direction split; staple force: 1 = plane
+    split) and where each came from."""
+    out = {"table": db}
+    for p, name in ((H.F64, "dslash_f64"), (H.F32, "dslash_f32"), (H.F16, "dslash_f16"), (H.BF16, "dslash_bf16")):
+        c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH, p)
+        out[name] = [c, "table" if tuned else "rule"]
+    c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE)
+    out["gauge_force_planes"] = [c, "table" if tuned else "rule"]
+    return out
+
+
 def timed_kernel_roofline(H, name="dslash", timing=None):
     t = (timing if timing is not None else H.hmc_timing_read()).get(name)
     if not t or not t["launches"]:
@@ -499,6 +512,9 @@ def main():
     ap.add_argument("--chrono", type=int, default=0,
                     help="hmc: start each force solve from the chronological guess over the last N solutions")
     ap.add_argument("--mts-steps", default="5,2,2", help="mts: ratio,heavy,gauge steps per enclosing step")
+    ap.add_argument("--tune-db", default=None,
+                    help=("launch-shape table to load (hmc_tune_load) before the run, e.g. "
+                          "paper_1212_0785_amd/tune/mi355x.txt; default: the built-in shape rule"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -514,6 +530,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     H.lib()
     torch.cuda.set_device(0)
+    if args.tune_db:
+        H.hmc_tune_load(args.tune_db)
     if args.workload == "hmc":
         out, iters_per_solve, L, seed, beta, kappa, nsteps = run_hmc(args, H, torch)
         if not args.no_cpu_baseline:
@@ -535,6 +553,10 @@ def main():
             out["cpu_baseline"] = {k: ob[k] for k in ("value", "unit", "cores", "kind", "sample")}
             out["rel_err_vs_oracle"] = ob["rel_err_vs_oracle"]
         out.pop("_fields", None)
+    if "config" in out and "lattice" in out["config"]:
+        out["config"]["launch_shapes"] = launch_shapes(H, out["config"]["lattice"], args.tune_db)
+        if args.workload in ("hmc", "dslash") and "roofline" in out:
+            out["roofline"]["dslash_shape"] = out["config"]["launch_shapes"]["dslash_f64"][0]
     print(json.dumps(out))
 
 

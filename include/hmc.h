@@ -346,15 +346,18 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
  * environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES) > table entry
  * for the lattice extents > built-in rule.  HMC_TUNE_DB names a table file
  * read on first use.  Table file: text lines "kind L0 L1 L2 L3 prec choice
- * us"; unknown or malformed lines are ignored.  Shapes are fixed per solve
+ * us" ('#' lines and malformed lines are ignored).  Shapes are fixed per solve
  * (and per service request) when it starts; do not tune while solves or a
  * service run on the same lattice extents. */
 typedef enum { HMC_TUNE_DSLASH = 0, HMC_TUNE_GAUGE_FORCE = 1 } hmc_tune_kind;
-/* Times every candidate shape on f's lattice (Dslash for F64 and, with
- * HMC_FIELDS_LOWPREC, the low precisions; the staple force with coef 0,
- * which leaves P unchanged) and stores the fastest in the table; with
- * db_path != NULL the table is merged into that file.  Overwrites f's
- * solver work vectors.  Synchronises. */
+/* Times every candidate shape on f's lattice and stores the fastest in the
+ * table: the Dslash shape of each storage precision where it runs, inside
+ * a solve (CG on Mhat^dag Mhat from Gaussian noise to 1e-10 or 100
+ * iterations: FP64 CG, and with HMC_FIELDS_LOWPREC mixed-precision CG with
+ * that storage inside; "us" = microseconds per iteration), the staple force
+ * per launch with coef 0 (P unchanged).  With db_path != NULL the table is
+ * merged into that file.  Overwrites f's eta, X_e and solver work vectors.
+ * HMC_E_ARG when an environment override is set.  Synchronises. */
 hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream);
 hmc_status hmc_tune_load(const char* path, int32_t* n_entries);
 hmc_status hmc_tune_save(const char* path, int32_t* n_entries);

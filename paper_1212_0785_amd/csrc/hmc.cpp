@@ -1223,6 +1223,7 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
 
 hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
   FIELDS(f);
+  HMC_REQUIRE(!tune_env_forced(), "HMC_DSLASH_SPLIT or HMC_GFORCE_PLANES forces the launch shapes; unset it to tune");
   hipStream_t st = ST(stream);
   hipEvent_t e0, e1;
   HMC_CHECK_HIP(hipEventCreate(&e0));
@@ -1231,56 +1232,68 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
     set_error("hipEventCreate failed");
     return HMC_E_HIP;
   }
-  auto time_us = [&](auto&& launch, int reps) -> double {
-    for (int w = 0; w < 2; ++w)
-      if (launch() != hipSuccess) return -1;
+  auto elapsed_us = [&](auto&& work) -> double {  // GPU time of work() on st, gaps included
     if (hipEventRecord(e0, st) != hipSuccess) return -1;
-    for (int r = 0; r < reps; ++r)
-      if (launch() != hipSuccess) return -1;
+    if (!work()) return -1;
     if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1;
     float ms = 0;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1;
-    return 1e3 * ms / reps;
+    return hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? 1e3 * ms : -1;
   };
   hmc_status status = HMC_OK;
+  const std::string err0 = "a timed launch failed during tuning";
+  std::string err = err0;
+  // Dslash: each shape timed where it runs, inside a solve (CG on
+  // Mhat^dag Mhat from Gaussian noise, tolerance 1e-10 or kIters iterations;
+  // FP64 CG, else mixed precision with the storage inside), per iteration.
+  // The candidate is installed as the table entry, since a solve takes its
+  // shapes from the table when it starts; FP64 goes first because the
+  // mixed-precision solves run their FP64 steps in the FP64 shape.
+  constexpr int kIters = 100, kReps = 3;
+  if (launch_eta(F->g, 1, 0, 0, F->eta, st) != hipSuccess) status = HMC_E_HIP;
   const int nprec = (F->flags & HMC_FIELDS_LOWPREC) ? 4 : 1;
   for (int pi = 0; pi < nprec && status == HMC_OK; ++pi) {
     const hmc_prec prec = (hmc_prec)pi;
-    if (ensure_lowprec(F, prec, st) != hipSuccess) {
-      status = HMC_E_HIP;
-      break;
-    }
-    void* in = prec == HMC_F64 ? F->p : F->lp;
-    void* out = prec == HMC_F64 ? F->s : F->ls;
-    if (launch_zero(in, prec == HMC_F64 ? F->half64 : F->halflow, st) != hipSuccess) {
-      status = HMC_E_HIP;
-      break;
-    }
+    hmc_cg_params prm{};
+    prm.tol = 1e-10;
+    prm.maxiter = kIters;
+    prm.mode = HMC_CG_NORMAL_MHAT;
+    prm.prec = prec;
     int best = 0;
     double best_us = 0;
     for (int shape : {1, 2, 4}) {
-      DslashArgs d{};
-      d.U = low_links(F, prec);
-      d.in = in;
-      d.out = out;
-      d.b = 1.0;
-      d.rows2 = F->su3;
-      d.shape = shape;
-      const double us = time_us([&] { return launch_dslash(prec, 0, EPI_PLAIN, F->g, 0, nullptr, 1, d, st); }, 10);
-      if (us < 0) {
-        status = HMC_E_HIP;
-        break;
+      tune_store(F->g.L, TUNE_DSLASH, prec, shape, 0);
+      double us = -1;
+      for (int r = 0; r <= kReps && status == HMC_OK; ++r) {  // r = 0 warms up
+        hmc_cg_stats cs{};
+        hmc_status s = HMC_OK;
+        const double t = elapsed_us([&] {
+          s = cg_solve_impl(F, F->Xe, F->eta, &prm, &cs, st);
+          return s == HMC_OK || s == HMC_E_NOCONV;
+        });
+        if (t < 0 || cs.iters <= 0) {
+          status = s != HMC_OK && s != HMC_E_NOCONV ? s : HMC_E_HIP;
+          if (s != HMC_OK && s != HMC_E_NOCONV) err = hmc_last_error();
+          break;
+        }
+        if (r > 0 && (us < 0 || t / cs.iters < us)) us = t / cs.iters;
       }
+      if (status != HMC_OK) break;
       if (!best || us < best_us) best = shape, best_us = us;
     }
     if (status == HMC_OK) tune_store(F->g.L, TUNE_DSLASH, prec, best, best_us);
   }
+  // staple force: the launch alone (coef 0 leaves P unchanged)
   if (status == HMC_OK) {
     int best = -1;
     double best_us = 0;
     for (int shape : {0, 1}) {
-      const double us = time_us(
-          [&] { return launch_gauge_force(F->g, F->U, F->P, 0.0, st, F->su3, shape); }, 5);
+      auto launch = [&] { return launch_gauge_force(F->g, F->U, F->P, 0.0, st, F->su3, shape) == hipSuccess; };
+      double us = -1;
+      if (launch() && launch()) us = elapsed_us([&] {
+        for (int r = 0; r < 5; ++r)
+          if (!launch()) return false;
+        return true;
+      }) / 5;
       if (us < 0) {
         status = HMC_E_HIP;
         break;
@@ -1292,7 +1305,7 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (status != HMC_OK) {
-    set_error("a timed launch failed during tuning");
+    set_error("%s", err.c_str());
     return status;
   }
   if (db_path && tune_save(db_path) < 0) {

@@ -50,6 +50,8 @@ int tune_lookup(const int* L, int kind, int prec);
 void tune_store(const int* L, int kind, int prec, int choice, double us);
 int tune_load(const char* path);
 int tune_save(const char* path);
+// True when HMC_DSLASH_SPLIT or HMC_GFORCE_PLANES forces the shapes.
+bool tune_env_forced();
 
 // Iteration control of the Krylov solvers, resident in device memory.
 // Kernels of iteration k do nothing once k >= stop_at.  Only block 0 of the

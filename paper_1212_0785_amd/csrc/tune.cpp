@@ -116,7 +116,10 @@ int tune_save(const char* path) {
   const std::string tmp_path = std::string(path) + ".tmp";
   FILE* f = std::fopen(tmp_path.c_str(), "w");
   if (!f) return -1;
-  std::fprintf(f, "# kind L0 L1 L2 L3 prec choice us  (dslash: 1 site/work-item, 2|4 split; gauge_force: 0|1 planes)\n");
+  std::fprintf(f,
+               "# kind L0 L1 L2 L3 prec choice us\n"
+               "# dslash: choice 1 = one site per work-item, 2|4 = direction split; us per CG iteration in a solve\n"
+               "# gauge_force: choice 0 = one link per work-item, 1 = plane split; us per launch\n");
   for (const auto& kv : merged) {
     const Key& k = kv.first;
     std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", kind_name(std::get<4>(k)), std::get<0>(k), std::get<1>(k),
@@ -125,6 +128,8 @@ int tune_save(const char* path) {
   std::fclose(f);
   return std::rename(tmp_path.c_str(), path) == 0 ? (int)merged.size() : -1;
 }
+
+bool tune_env_forced() { return env_int("HMC_DSLASH_SPLIT") >= 0 || env_int("HMC_GFORCE_PLANES") >= 0; }
 
 int dslash_shape(const LatArg& g, hmc_prec prec) {
   static const int forced = [] {
