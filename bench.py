@@ -47,7 +47,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_traffic.json")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("dslash.hip", "device.h"):
+    for f in ("dslash_kernels.h", "device.h"):
         h.update(open(os.path.join(ROOT, "paper_1212_0785_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -158,18 +158,23 @@ hmc_status hmc_export_spinor(hmc_fields* f, void* canon, const void* src, int32_
 hmc_status hmc_convert_spinor(hmc_fields* f, void* dst, hmc_prec dst_prec, const void* src, hmc_prec src_prec,
                               void* stream);
 /* Re-derive everything the library keeps about U after U was written in
- * place: checks whether every link's third row equals conj(row0 x row1)
- * to 1e-14 (then the hopping kernels read two rows per link and rebuild
- * the third; one reduction, synchronises the stream) and, with
- * HMC_FIELDS_LOWPREC, refreshes the F32/F16/BF16 link copies (hmc_cg_solve
- * refreshes those itself when the library changed U). */
+ * place: checks whether every link is SU(3) to 1e-14 (rows 0 and 1
+ * orthonormal, row 2 = conj(row0 x row1); then the hopping and staple
+ * kernels read a compact form of each link and rebuild the rest; one
+ * reduction, synchronises the stream) and, with HMC_FIELDS_LOWPREC,
+ * refreshes the F32/F16/BF16 link copies (hmc_cg_solve refreshes those
+ * itself when the library changed U). */
 hmc_status hmc_sync_lowprec(hmc_fields* f, void* stream);
-/* *on = 1 if the hopping kernels read two rows per link (U is SU(3) to
- * rounding: set by hmc_weak_field_start, hmc_exp_update_reunit and the
- * integrator, which reunitarise, and by the check in hmc_import_gauge /
- * hmc_sync_lowprec), else 0 (all nine entries are read).  Both forms give
- * the same operator on SU(3) fields; the two-row form moves 2/3 of the
- * link bytes. */
+/* *on = 1 if the kernels read a compact form of each link, else 0 (all
+ * nine entries are read).  Compact forms need U to be SU(3) to rounding:
+ * set by hmc_weak_field_start, hmc_exp_update_reunit and the integrator,
+ * which reunitarise, and by the check in hmc_import_gauge /
+ * hmc_sync_lowprec.  The forms: rows 0 and 1, rebuilding row 2 as
+ * conj(row0 x row1) (2/3 of the link bytes), or row 0 and column 2,
+ * rebuilding u10, u11 from orthogonality and det = 1 and then row 2 (5/9 of
+ * the link bytes; links with |u02|^2 > 15/16 read u10, u11); which one per
+ * lattice and kernel family: hmc_tune_query.  Every form gives the same
+ * operator on SU(3) fields up to rounding. */
 hmc_status hmc_links_two_row(hmc_fields* f, int32_t* on);
 
 /* One half-lattice hop: out = D_{p <- 1-p} in (dagger: D^dag), p =
@@ -339,25 +344,38 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
                           hmc_traj_result* result, void* stream);
 
 /* ---- Launch auto-tuning (the auto-tuner of Sec. 4, for the launch shapes
- * this library offers).  Kinds: HMC_TUNE_DSLASH (choice 1 = one site per
- * work-item, 2 / 4 = direction split with that many wavefronts per 64-site
- * group; one entry per storage precision) and HMC_TUNE_GAUGE_FORCE (0 = one
- * link per work-item, 1 = plane split; prec HMC_F64).  Decision order:
- * environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES) > table entry
- * for the lattice extents > built-in rule.  HMC_TUNE_DB names a table file
- * read on first use.  Table file: text lines "kind L0 L1 L2 L3 prec choice
- * us" ('#' lines and malformed lines are ignored).  Shapes are fixed per solve
- * (and per service request) when it starts; do not tune while solves or a
- * service run on the same lattice extents. */
-typedef enum { HMC_TUNE_DSLASH = 0, HMC_TUNE_GAUGE_FORCE = 1 } hmc_tune_kind;
-/* Times every candidate shape on f's lattice and stores the fastest in the
- * table: the Dslash shape of each storage precision where it runs, inside
- * a solve (CG on Mhat^dag Mhat from Gaussian noise to 1e-10 or 100
- * iterations: FP64 CG, and with HMC_FIELDS_LOWPREC mixed-precision CG with
- * that storage inside; "us" = microseconds per iteration), the staple force
- * per launch with coef 0 (P unchanged).  With db_path != NULL the table is
- * merged into that file.  Overwrites f's eta, X_e and solver work vectors.
- * HMC_E_ARG when an environment override is set.  Synchronises. */
+ * and link forms this library offers).  Kinds: HMC_TUNE_DSLASH (choice 1 =
+ * one site per work-item, 2 / 4 = direction split with that many wavefronts
+ * per 64-site group; one entry per storage precision), HMC_TUNE_GAUGE_FORCE
+ * (0 = one link per work-item, 1 = plane split; prec HMC_F64),
+ * HMC_TUNE_DSLASH_LINKS (reals read per SU(3) link by the hopping kernels,
+ * 12 = rows 0 and 1, 10 = row 0 and column 2; per storage precision; the
+ * fermion force follows the FP64 entry) and HMC_TUNE_GAUGE_FORCE_LINKS (the
+ * same for the staple force and the plaquette; prec HMC_F64).  Decision
+ * order: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES,
+ * HMC_LINK_FORM = 18 / 12 / 10) > table entry for the lattice extents >
+ * built-in rule.  HMC_TUNE_DB names a table file read on first use.  Table
+ * file: text lines "kind L0 L1 L2 L3 prec choice us" with kind dslash,
+ * gauge_force, dslash_links or gauge_force_links ('#' lines and malformed
+ * lines are ignored).  Shapes are fixed per solve (and per service request)
+ * when it starts; do not tune while solves or a service run on the same
+ * lattice extents. */
+typedef enum {
+  HMC_TUNE_DSLASH = 0,
+  HMC_TUNE_GAUGE_FORCE = 1,
+  HMC_TUNE_DSLASH_LINKS = 2,
+  HMC_TUNE_GAUGE_FORCE_LINKS = 3
+} hmc_tune_kind;
+/* Times every candidate on f's lattice and stores the fastest in the
+ * table: for each storage precision the Dslash shape x link form pair
+ * where it runs, inside a solve (CG on Mhat^dag Mhat from Gaussian noise to
+ * 1e-10 or 100 iterations: FP64 CG, and with HMC_FIELDS_LOWPREC
+ * mixed-precision CG with that storage inside; "us" = microseconds per
+ * iteration); the staple force's shape x link form per launch with coef 0
+ * (P unchanged).  Link forms are tuned only when U is SU(3) (see
+ * hmc_links_two_row).  With db_path != NULL the table is merged into that
+ * file.  Overwrites f's eta, X_e and solver work vectors.  HMC_E_ARG when
+ * an environment override is set.  Synchronises. */
 hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream);
 hmc_status hmc_tune_load(const char* path, int32_t* n_entries);
 hmc_status hmc_tune_save(const char* path, int32_t* n_entries);

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhmc.so")
 
-SOURCES = ["dslash.hip", "layout.hip", "blas.hip", "gauge.hip", "fforce.hip", "rng.hip", "hmc.cpp", "solver.cpp", "service.cpp",
+SOURCES = ["dslash.hip", "dslash_f64.hip", "dslash_f32.hip", "dslash_f16.hip", "dslash_bf16.hip", "layout.hip", "blas.hip", "gauge.hip", "fforce.hip", "rng.hip", "hmc.cpp", "solver.cpp", "service.cpp",
            "tune.cpp"]
 
 ARCH = "gfx950"

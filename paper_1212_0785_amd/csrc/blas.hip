@@ -9,6 +9,7 @@
 // kernels re-sum the partials they need in every block (the same bits in
 // every block), which removes the separate finalisation launches from the
 // iteration.
+#include <algorithm>
 #include <climits>
 
 #include "device.h"
@@ -182,6 +183,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(Lat g, const double2* b, dou
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// The arguments of this block's solve: entry blockIdx.y of a batch table,
+// or the single entry passed by value.  Chosen at compile time, so the
+// by-value entry is read in place from the kernel arguments (a run-time
+// choice copies the struct to per-lane scratch memory).
+template <bool BATCH>
+__device__ __forceinline__ const CgArgs& cg_args(const CgArgs* table, const CgArgs& one) {
+  if constexpr (BATCH)
+    return table[blockIdx.y];
+  else
+    return one;
+}
+
 // One solver iteration with label k = iter0 + j; cur = k & 1, nxt = cur ^ 1.
 //   update:  alpha = sum(pp[cur]) / sum(pq);  x += alpha p;  r -= alpha q;
 //            per-block |r|^2 -> pp[nxt] (CG) or pr (CGLS)
@@ -193,9 +206,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(Lat g, const double2* b, dou
 // Fused CG (CgArgs::fused): the update kernel is not launched; the
 // preceding Dslash computes alpha (block 0, into the solver state) and
 // r -= alpha q in its epilogue, and the p-update also does x += alpha p.
-template <class SP, class SX>
+template <class SP, class SX, bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table, CgArgs one, int j) {
-  const CgArgs a = table ? table[blockIdx.y] : one;
+  const CgArgs& a = cg_args<BATCH>(table, one);
   const int k = a.iter0 + j;
   if (k >= a.state->stop_at) return;
   using R = typename SP::R;
@@ -232,18 +245,37 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table
 // precision, when the inner residual fell by delta since the last FP64
 // update), sets stop_at = k + 1; blocks of this launch compare k only, so
 // none of them can observe a change that concerns it.
-template <class SP, class SX>
+//
+// NP work-items share a site: work-item (part, s) updates the colour
+// vectors 12/NP * part .. of site s (NP = 4 only for storages without a
+// per-site scale).  Every input of an element is loaded before any output
+// is stored (x, p and r are distinct arrays), so a work-item makes one
+// round trip to memory.
+template <class SP, class SX, int NP, bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* table, CgArgs one, int j) {
-  const CgArgs a = table ? table[blockIdx.y] : one;
+  static_assert(NP == 1 || (NP == 4 && !SP::kScaled), "parts need an unscaled storage");
+  const CgArgs& a = cg_args<BATCH>(table, one);
   SolverState* stt = a.state;
   const int k = a.iter0 + j;
   if (k >= stt->stop_at) return;
   using R = typename SP::R;
   using XR = typename SX::R;
+  constexpr int NC = 12 / NP;  // components per work-item
   const int cur = k & 1, nxt = cur ^ 1;
-  const double nw = sum_partials(a.pp[nxt], a.n_pp);
-  const double old = sum_partials(a.pp[cur], a.n_pp);
-  const double rr = a.cgls ? sum_partials(a.pr, a.n_pr) : nw;
+  // the three sums of this step in one block reduction (same order, hence
+  // the same bits, in every block)
+  __shared__ double bc[3];
+  {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < a.n_pp; i += kBlock) v[0] += a.pp[nxt][i], v[1] += a.pp[cur][i];
+    if (a.cgls)
+      for (int i = threadIdx.x; i < a.n_pr; i += kBlock) v[2] += a.pr[i];
+    block_sum<3>(v);
+    if (threadIdx.x == 0) bc[0] = v[0], bc[1] = v[1], bc[2] = v[2];
+    __syncthreads();
+  }
+  const double nw = bc[0], old = bc[1];
+  const double rr = a.cgls ? bc[2] : nw;
   const bool conv = rr <= a.thr;
   const double alpha = a.fused ? stt->alpha : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -266,28 +298,53 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
   if (p_done && !a.fused) return;
   const R beta = (R)(nw / old);
   const void* src = a.cgls ? a.s : a.r;
-  for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
-    cx<R> p[12];
-    SP::load(a.p, g.stride, s, p);
-    if (a.fused) {  // x += alpha p with the p of this iteration
-      cx<XR> x[12];
-      SX::load(a.x, g.stride, s, x);
+  // XCD x (hardware blocks b with b % 8 == x; gridDim.x is a multiple of
+  // 8) updates the sites [x Vh / 8, (x + 1) Vh / 8), the range the Dslash's
+  // XCD-aware block order gives the same XCD, so p, r and x stay in the L2
+  // of the XCD that reads them next.
+  const int xcd = blockIdx.x & 7, nbx = gridDim.x >> 3;
+  const int lo = (int)((long long)g.Vh * xcd / 8), nsx = (int)((long long)g.Vh * (xcd + 1) / 8) - lo;
+  const int nwork = nsx * NP;
+  for (int i = (blockIdx.x >> 3) * kBlock + threadIdx.x; i < nwork; i += nbx * kBlock) {
+    const int part = NP == 1 ? 0 : i / nsx;
+    const int s = lo + i - part * nsx;
+    cx<R> p[NC], q[NC];
+    cx<XR> x[NC];
+    if constexpr (NP == 1) {
+      SP::load(a.p, g.stride, s, p);
+      if (a.fused) SX::load(a.x, g.stride, s, x);
+      if (!p_done) SP::load(src, g.stride, s, q);
+    } else {
 #pragma unroll
-      for (int m = 0; m < 12; ++m) {
+      for (int c = 0; c < NC; ++c) p[c] = SP::load_one(a.p, g.stride, s, NC * part + c);
+      if (a.fused)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = SX::load_one(a.x, g.stride, s, NC * part + c);
+      if (!p_done)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = SP::load_one(src, g.stride, s, NC * part + c);
+    }
+    if (a.fused) {  // x += alpha p with the p of this iteration
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
         x[m].re = fma((XR)alpha, (XR)p[m].re, x[m].re);
         x[m].im = fma((XR)alpha, (XR)p[m].im, x[m].im);
       }
-      SX::store(a.x, g.stride, s, x);
+      if constexpr (NP == 1)
+        SX::store(a.x, g.stride, s, x);
+      else
+        SX::store_part(a.x, g.stride, s, part, x);
     }
     if (p_done) continue;
-    cx<R> q[12];
-    SP::load(src, g.stride, s, q);
 #pragma unroll
-    for (int m = 0; m < 12; ++m) {
+    for (int m = 0; m < NC; ++m) {
       p[m].re = fma(beta, p[m].re, q[m].re);
       p[m].im = fma(beta, p[m].im, q[m].im);
     }
-    SP::store(a.p, g.stride, s, p);
+    if constexpr (NP == 1)
+      SP::store(a.p, g.stride, s, p);
+    else
+      SP::store_part(a.p, g.stride, s, part, p);
   }
 }
 
@@ -432,12 +489,18 @@ hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x
 hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
                             int nbatch, int j, hipStream_t st) {
   TimedScope ts(TK_CG_BLAS, st, 0);
-  dim3 grid(nb, nbatch), block(kBlock);
+  const dim3 grid(nb, nbatch), block(kBlock);
+  auto go = [&](auto kernel_single, auto kernel_batch) {
+    if (table)
+      hipLaunchKernelGGL(kernel_batch, grid, block, 0, st, to_lat(g), table, a, j);
+    else
+      hipLaunchKernelGGL(kernel_single, grid, block, 0, st, to_lat(g), table, a, j);
+  };
   switch (prec) {
-    case HMC_F64: hipLaunchKernelGGL((k_cg_update<SpF64, SpF64>), grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_F32: hipLaunchKernelGGL((k_cg_update<SpF32, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_F16: hipLaunchKernelGGL((k_cg_update<SpF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_BF16: hipLaunchKernelGGL((k_cg_update<SpBF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F64: go(k_cg_update<SpF64, SpF64, false>, k_cg_update<SpF64, SpF64, true>); break;
+    case HMC_F32: go(k_cg_update<SpF32, SpF32, false>, k_cg_update<SpF32, SpF32, true>); break;
+    case HMC_F16: go(k_cg_update<SpF16, SpF32, false>, k_cg_update<SpF16, SpF32, true>); break;
+    case HMC_BF16: go(k_cg_update<SpBF16, SpF32, false>, k_cg_update<SpBF16, SpF32, true>); break;
   }
   return hipGetLastError();
 }
@@ -445,12 +508,23 @@ hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int
 hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
                              int nbatch, int j, hipStream_t st) {
   TimedScope ts(TK_CG_BLAS, st, 0);
-  dim3 grid(nb, nbatch), block(kBlock);
+  (void)nb;  // the update writes no partial sums: its grid is its own
+  // multiples of 8 blocks (one share per XCD)
+  const int nb4 = std::min(8 * ceil_div(4LL * g.Vh, 8 * kBlock), 2048);
+  const int nb1 = std::min(8 * ceil_div(g.Vh, 8 * kBlock), 2048);
+  const dim3 block(kBlock);
+  auto go = [&](int nb_, auto kernel_single, auto kernel_batch) {
+    const dim3 grid(nb_, nbatch);
+    if (table)
+      hipLaunchKernelGGL(kernel_batch, grid, block, 0, st, to_lat(g), table, a, j);
+    else
+      hipLaunchKernelGGL(kernel_single, grid, block, 0, st, to_lat(g), table, a, j);
+  };
   switch (prec) {
-    case HMC_F64: hipLaunchKernelGGL((k_cg_pupdate<SpF64, SpF64>), grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_F32: hipLaunchKernelGGL((k_cg_pupdate<SpF32, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_F16: hipLaunchKernelGGL((k_cg_pupdate<SpF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
-    case HMC_BF16: hipLaunchKernelGGL((k_cg_pupdate<SpBF16, SpF32>), grid, block, 0, st, to_lat(g), table, a, j); break;
+    case HMC_F64: go(nb4, k_cg_pupdate<SpF64, SpF64, 4, false>, k_cg_pupdate<SpF64, SpF64, 4, true>); break;
+    case HMC_F32: go(nb4, k_cg_pupdate<SpF32, SpF32, 4, false>, k_cg_pupdate<SpF32, SpF32, 4, true>); break;
+    case HMC_F16: go(nb1, k_cg_pupdate<SpF16, SpF32, 1, false>, k_cg_pupdate<SpF16, SpF32, 1, true>); break;
+    case HMC_BF16: go(nb4, k_cg_pupdate<SpBF16, SpF32, 4, false>, k_cg_pupdate<SpBF16, SpF32, 4, true>); break;
   }
   return hipGetLastError();
 }

@@ -560,6 +560,13 @@ struct SpBF16 {
 struct LkF64 {
   using R = double;
   static constexpr int kBytes = 144;
+  // component K (row K / 3, column K % 3) alone
+  template <int K>
+  __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
+    const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2d);
+    v2d t = gld_link<v2d>(p, K * stride + s);
+    return {t.x, t.y};
+  }
   template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2d);
@@ -581,6 +588,13 @@ struct LkF64 {
 struct LkF32 {
   using R = float;
   static constexpr int kBytes = 72;
+  // component K (row K / 3, column K % 3) alone
+  template <int K>
+  __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
+    const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2f);
+    v2f t = gld_link<v2f>(p, K * stride + s);
+    return {t.x, t.y};
+  }
   template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2f);
@@ -602,6 +616,13 @@ struct LkF32 {
 struct LkF16 {
   using R = float;
   static constexpr int kBytes = 36;
+  // component K (row K / 3, column K % 3) alone
+  template <int K>
+  __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
+    const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2h);
+    v2f t = __builtin_convertvector(gld_link<v2h>(p, K * stride + s), v2f);
+    return {t.x, t.y};
+  }
   template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2h);
@@ -624,6 +645,13 @@ struct LkF16 {
 struct LkBF16 {
   using R = float;
   static constexpr int kBytes = 36;
+  // component K (row K / 3, column K % 3) alone
+  template <int K>
+  __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
+    const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(uint32_t);
+    uint32_t w = gld_link<uint32_t>(p, K * stride + s);
+    return {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
+  }
   template <int K = 9>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(uint32_t);
@@ -652,6 +680,42 @@ struct LkRows2 {
   static constexpr int kBytes = LK::kBytes / 9 * 6;
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     mat3<R> u = LK::template load<6>(base, stride, mu, par, s);
+    third_row(u);
+    return u;
+  }
+};
+
+// Row 0 and column 2 of any of the link formats above (components 0, 1, 2,
+// 5, 8: 5/9 of the link bytes), for fields that are SU(3) to rounding.
+// Row 1's first two entries solve the 2x2 system of orthogonality to row 0
+// and det U = 1 (through row 2 = conj(row0 x row1)), whose determinant is
+// D = |u00|^2 + |u01|^2 = 1 - |u02|^2; row 2 is then rebuilt as in the
+// two-row form.  The solve amplifies rounding by 1/D, so a link with
+// D < 1/16 reads u10 and u11 instead (exact; on smooth fields no work-item
+// takes that branch).
+template <class LK>
+struct LkRowCol {
+  using R = typename LK::R;
+  static constexpr int kBytes = LK::kBytes / 9 * 5;
+  __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
+    mat3<R> u;
+    u.m[0] = LK::template one<0>(base, stride, mu, par, s);
+    u.m[1] = LK::template one<1>(base, stride, mu, par, s);
+    u.m[2] = LK::template one<2>(base, stride, mu, par, s);
+    u.m[5] = LK::template one<5>(base, stride, mu, par, s);
+    u.m[8] = LK::template one<8>(base, stride, mu, par, s);
+    const R d = norm2(u.m[0]) + norm2(u.m[1]);
+    if (d < R(0.0625)) {
+      u.m[3] = LK::template one<3>(base, stride, mu, par, s);
+      u.m[4] = LK::template one<4>(base, stride, mu, par, s);
+    } else {
+      // u10 = -(u00 conj(u02) u12 + conj(u01) conj(u22)) / D
+      // u11 = (conj(u00) conj(u22) - u01 conj(u02) u12) / D
+      const R inv = R(1) / d;
+      const cx<R> w = conj(u.m[2]) * u.m[5];
+      u.m[3] = (-inv) * (u.m[0] * w + conj(u.m[1]) * conj(u.m[8]));
+      u.m[4] = inv * (conj(u.m[0]) * conj(u.m[8]) - u.m[1] * w);
+    }
     third_row(u);
     return u;
   }

@@ -88,21 +88,26 @@ __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, 
 // i c_ta TA(W) with c_ta = -coef kappa^2 / 2 (coef passed already times
 // kappa^2 by the caller as `coef`).
 hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
-                                const void* Yo, double* P, double coef, hipStream_t st, bool rows2) {
-  rows2 = rows2 && link_rows2_enabled();
+                                const void* Yo, double* P, double coef, hipStream_t st, bool su3) {
+  // the link form of the FP64 hop kernels (same per-link work pattern)
+  const int form = link_form_for(su3, dslash_link_form(g, HMC_F64));
+  const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
+                                                                                     : LkF64::kBytes;
   // algorithmic: 4 links, X and Y (both read once), momenta read + written
-  TimedScope ts(TK_FERMION_FORCE, st,
-                2.0 * g.Vh * (4 * (rows2 ? LkRows2<LkF64>::kBytes : LkF64::kBytes) + 2 * SpF64::kBytes + 2 * 4 * 64));
+  TimedScope ts(TK_FERMION_FORCE, st, 2.0 * g.Vh * (4 * lb + 2 * SpF64::kBytes + 2 * 4 * 64));
   ForceVecs v;
   v.X[0] = Xe;
   v.X[1] = Xo;
   v.Y[0] = Ye;
   v.Y[1] = Yo;
-  const dim3 grid(ceil_div(2LL * g.Vh, kBlock), 4);
-  if (rows2)
-    hipLaunchKernelGGL(k_fermion_force<LkRows2<LkF64>>, grid, dim3(kBlock), 0, st, to_lat(g), U, v, P, -0.5 * coef);
+  const dim3 grid(ceil_div(2LL * g.Vh, kBlock), 4), block(kBlock);
+  const double c = -0.5 * coef;
+  if (form == LINK_ROWCOL)
+    hipLaunchKernelGGL(k_fermion_force<LkRowCol<LkF64>>, grid, block, 0, st, to_lat(g), U, v, P, c);
+  else if (form == LINK_ROWS2)
+    hipLaunchKernelGGL(k_fermion_force<LkRows2<LkF64>>, grid, block, 0, st, to_lat(g), U, v, P, c);
   else
-    hipLaunchKernelGGL(k_fermion_force<LkF64>, grid, dim3(kBlock), 0, st, to_lat(g), U, v, P, -0.5 * coef);
+    hipLaunchKernelGGL(k_fermion_force<LkF64>, grid, block, 0, st, to_lat(g), U, v, P, c);
   return hipGetLastError();
 }
 

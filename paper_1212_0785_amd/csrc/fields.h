@@ -92,7 +92,7 @@ hipError_t dslash_f64(Fields* F, void* out, const void* in, int out_par, int dag
 hipError_t mhat_f64(Fields* F, void* out, const void* in, int dag, double* partial, hipStream_t st);
 hipError_t ensure_lowprec(Fields* F, hmc_prec prec, hipStream_t st);
 // Re-derives F->su3 from the stored links (one reduction; syncs).
-hipError_t check_rows2(Fields* F, hipStream_t st);
+hipError_t check_su3(Fields* F, hipStream_t st);
 void* low_links(Fields* F, hmc_prec prec);
 // Read `n` device doubles from slots[first..] into the pinned buffer (syncs).
 hipError_t read_slots(Fields* F, int first, int n, double* out, hipStream_t st);

@@ -51,14 +51,30 @@ __device__ __forceinline__ double plaq(const Lat& g, const void* U, const Site& 
   return s;
 }
 
+// x, returned through an empty asm that also "reads" the running sum sp.
+__device__ __forceinline__ Site plane_site(Site x, double& sp) {
+  asm volatile("" : "+v"(sp), "+v"(x.lex), "+v"(x.c[0]), "+v"(x.c[1]), "+v"(x.c[2]), "+v"(x.c[3]));
+  return x;
+}
+
 template <class LK>
 __global__ void __launch_bounds__(kBlock) k_plaquette_partials(Lat g, const void* U, double* part) {
   double v[1] = {0.0};
   for (int j = blockIdx.x * kBlock + threadIdx.x; j < 2 * g.Vh; j += gridDim.x * kBlock) {
     int par = j >= g.Vh, s = j - par * g.Vh;
     Site x = cb_site(g, par, s);
-    v[0] += plaq<LK, 0, 1>(g, U, x) + plaq<LK, 0, 2>(g, U, x) + plaq<LK, 0, 3>(g, U, x) +
-            plaq<LK, 1, 2>(g, U, x) + plaq<LK, 1, 3>(g, U, x) + plaq<LK, 2, 3>(g, U, x);
+    // one plane at a time: the site of each plane passes through an empty
+    // asm that also takes the running sum, so the loads of a plane cannot
+    // be issued before the previous plane is done (all 24 links in flight
+    // at once exceed the register file)
+    double sp = 0.0;
+    sp += plaq<LK, 0, 1>(g, U, plane_site(x, sp));
+    sp += plaq<LK, 0, 2>(g, U, plane_site(x, sp));
+    sp += plaq<LK, 0, 3>(g, U, plane_site(x, sp));
+    sp += plaq<LK, 1, 2>(g, U, plane_site(x, sp));
+    sp += plaq<LK, 1, 3>(g, U, plane_site(x, sp));
+    sp += plaq<LK, 2, 3>(g, U, plane_site(x, sp));
+    v[0] += sp;
   }
   block_sum<1>(v);
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -236,13 +252,18 @@ __global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const dou
 }
 
 hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st,
-                                     bool rows2) {
-  rows2 = rows2 && link_rows2_enabled();
-  TimedScope ts(TK_PLAQUETTE, st, 2.0 * g.Vh * 4 * (rows2 ? LkRows2<LkF64>::kBytes : LkF64::kBytes));
-  if (rows2)
-    hipLaunchKernelGGL(k_plaquette_partials<LkRows2<LkF64>>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), U, part);
+                                     bool su3) {
+  const int form = link_form_for(su3, staple_link_form(g));
+  const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
+                                                                                     : LkF64::kBytes;
+  TimedScope ts(TK_PLAQUETTE, st, 2.0 * g.Vh * 4 * lb);
+  const dim3 grid(nb), block(kBlock);
+  if (form == LINK_ROWCOL)
+    hipLaunchKernelGGL(k_plaquette_partials<LkRowCol<LkF64>>, grid, block, 0, st, to_lat(g), U, part);
+  else if (form == LINK_ROWS2)
+    hipLaunchKernelGGL(k_plaquette_partials<LkRows2<LkF64>>, grid, block, 0, st, to_lat(g), U, part);
   else
-    hipLaunchKernelGGL(k_plaquette_partials<LkF64>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), U, part);
+    hipLaunchKernelGGL(k_plaquette_partials<LkF64>, grid, block, 0, st, to_lat(g), U, part);
   return hipGetLastError();
 }
 
@@ -263,13 +284,16 @@ static void gauge_force_typed(const LatArg& g, const void* U, double* P, double 
 }
 
 hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st,
-                              bool rows2, int shape) {
+                              bool su3, int shape, int form) {
   if (shape < 0) shape = gauge_force_shape(g);
-  rows2 = rows2 && link_rows2_enabled();
+  form = link_form_for(su3, form ? form : staple_link_form(g));
+  const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
+                                                                                     : LkF64::kBytes;
   // algorithmic: 4 links read, momenta read + written, per site
-  TimedScope ts(TK_GAUGE_FORCE, st,
-                2.0 * g.Vh * (4 * (rows2 ? LkRows2<LkF64>::kBytes : LkF64::kBytes) + 2 * 4 * 64));
-  if (rows2)
+  TimedScope ts(TK_GAUGE_FORCE, st, 2.0 * g.Vh * (4 * lb + 2 * 4 * 64));
+  if (form == LINK_ROWCOL)
+    gauge_force_typed<LkRowCol<LkF64>>(g, U, P, coef_beta, st, shape);
+  else if (form == LINK_ROWS2)
     gauge_force_typed<LkRows2<LkF64>>(g, U, P, coef_beta, st, shape);
   else
     gauge_force_typed<LkF64>(g, U, P, coef_beta, st, shape);

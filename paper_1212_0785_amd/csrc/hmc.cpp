@@ -234,7 +234,7 @@ hipError_t dslash_f64(Fields* F, void* out, const void* in, int out_par, int dag
   d.partial = partial;
   d.stop_at = stop_at;
   d.iter0 = iter;
-  d.rows2 = F->su3;
+  d.su3 = F->su3;
   return launch_dslash(HMC_F64, dag, epi, F->g, out_par, nullptr, 1, d, st);
 }
 
@@ -251,10 +251,10 @@ hipError_t ensure_lowprec(Fields* F, hmc_prec prec, hipStream_t st) {
 
 // Largest |stored - rebuilt| third-row component for which the two-row
 // loads are taken to reproduce the link (links have entries of modulus <= 1).
-constexpr double kRows2Tol = 1e-14;
+constexpr double kSu3Tol = 1e-14;
 
-hipError_t check_rows2(Fields* F, hipStream_t st) {
-  hipError_t e = launch_rows2_check(F->g, F->U, kRows2Tol, F->part[4], F->nbR, st);
+hipError_t check_su3(Fields* F, hipStream_t st) {
+  hipError_t e = launch_su3_check(F->g, F->U, kSu3Tol, F->part[4], F->nbR, st);
   if (e != hipSuccess) return e;
   if ((e = launch_finalize(F->part[4], F->nbR, 1, F->slots + SL_RED, 1.0, 0, st))) return e;
   double bad = -1;
@@ -406,7 +406,7 @@ hmc_status hmc_field_pointer(hmc_fields* f, hmc_field_id which, void** ptr) {
 hmc_status hmc_links_two_row(hmc_fields* f, int32_t* on) {
   FIELDS(f);
   HMC_REQUIRE(on, "null output");
-  *on = (F->su3 && link_rows2_enabled()) ? 1 : 0;
+  *on = (F->su3 && dslash_link_form(F->g, HMC_F64) != LINK_FULL) ? 1 : 0;
   return HMC_OK;
 }
 
@@ -415,7 +415,7 @@ hmc_status hmc_import_gauge(hmc_fields* f, const void* canon, void* stream) {
   HMC_REQUIRE(canon, "null buffer");
   HMC_CHECK_HIP(launch_pack_gauge(F->g, canon, F->U, ST(stream)));
   F->u_version++;
-  HMC_CHECK_HIP(check_rows2(F, ST(stream)));
+  HMC_CHECK_HIP(check_su3(F, ST(stream)));
   return HMC_OK;
 }
 
@@ -469,7 +469,7 @@ hmc_status hmc_convert_spinor(hmc_fields* f, void* dst, hmc_prec dst_prec, const
 hmc_status hmc_sync_lowprec(hmc_fields* f, void* stream) {
   FIELDS(f);
   F->u_version++;
-  HMC_CHECK_HIP(check_rows2(F, ST(stream)));
+  HMC_CHECK_HIP(check_su3(F, ST(stream)));
   if (F->flags & HMC_FIELDS_LOWPREC)
     for (int p = HMC_F32; p <= HMC_BF16; ++p) HMC_CHECK_HIP(ensure_lowprec(F, (hmc_prec)p, ST(stream)));
   return HMC_OK;
@@ -486,7 +486,7 @@ hmc_status hmc_wilson_dslash(hmc_fields* f, void* out, const void* in, int32_t o
   HMC_CHECK_HIP(ensure_lowprec(F, prec, ST(stream)));
   DslashArgs d{};
   d.U = low_links(F, prec);
-  d.rows2 = F->su3;
+  d.su3 = F->su3;
   d.in = in;
   d.out = out;
   d.b = 1.0;
@@ -508,7 +508,7 @@ hmc_status hmc_mhat(hmc_fields* f, void* out, const void* in, int32_t dagger, hm
   HMC_CHECK_HIP(ensure_lowprec(F, prec, st));
   DslashArgs d{};
   d.U = low_links(F, prec);
-  d.rows2 = F->su3;
+  d.su3 = F->su3;
   d.in = in;
   d.out = F->lt;
   d.b = 1.0;
@@ -1242,13 +1242,16 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
   hmc_status status = HMC_OK;
   const std::string err0 = "a timed launch failed during tuning";
   std::string err = err0;
-  // Dslash: each shape timed where it runs, inside a solve (CG on
-  // Mhat^dag Mhat from Gaussian noise, tolerance 1e-10 or kIters iterations;
-  // FP64 CG, else mixed precision with the storage inside), per iteration.
-  // The candidate is installed as the table entry, since a solve takes its
-  // shapes from the table when it starts; FP64 goes first because the
-  // mixed-precision solves run their FP64 steps in the FP64 shape.
+  // Dslash: each (shape, link form) timed where it runs, inside a solve (CG
+  // on Mhat^dag Mhat from Gaussian noise, tolerance 1e-10 or kIters
+  // iterations; FP64 CG, else mixed precision with the storage inside), per
+  // iteration.  The candidate is installed as the table entries, since a
+  // solve takes its shapes from the table when it starts; FP64 goes first
+  // because the mixed-precision solves run their FP64 steps with the FP64
+  // choice.  Link forms are tuned on SU(3) fields only (others read every
+  // entry).
   constexpr int kIters = 100, kReps = 3;
+  const std::vector<int> forms = F->su3 ? std::vector<int>{LINK_ROWS2, LINK_ROWCOL} : std::vector<int>{0};
   if (launch_eta(F->g, 1, 0, 0, F->eta, st) != hipSuccess) status = HMC_E_HIP;
   const int nprec = (F->flags & HMC_FIELDS_LOWPREC) ? 4 : 1;
   for (int pi = 0; pi < nprec && status == HMC_OK; ++pi) {
@@ -1258,49 +1261,65 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
     prm.maxiter = kIters;
     prm.mode = HMC_CG_NORMAL_MHAT;
     prm.prec = prec;
-    int best = 0;
+    int best = 0, best_form = 0;
     double best_us = 0;
-    for (int shape : {1, 2, 4}) {
-      tune_store(F->g.L, TUNE_DSLASH, prec, shape, 0);
-      double us = -1;
-      for (int r = 0; r <= kReps && status == HMC_OK; ++r) {  // r = 0 warms up
-        hmc_cg_stats cs{};
-        hmc_status s = HMC_OK;
-        const double t = elapsed_us([&] {
-          s = cg_solve_impl(F, F->Xe, F->eta, &prm, &cs, st);
-          return s == HMC_OK || s == HMC_E_NOCONV;
-        });
-        if (t < 0 || cs.iters <= 0) {
-          status = s != HMC_OK && s != HMC_E_NOCONV ? s : HMC_E_HIP;
-          if (s != HMC_OK && s != HMC_E_NOCONV) err = hmc_last_error();
-          break;
+    for (int form : forms) {
+      for (int shape : {1, 2, 4}) {
+        tune_store(F->g.L, TUNE_DSLASH, prec, shape, 0);
+        if (form) tune_store(F->g.L, TUNE_DSLASH_LINKS, prec, form, 0);
+        double us = -1;
+        for (int r = 0; r <= kReps && status == HMC_OK; ++r) {  // r = 0 warms up
+          hmc_cg_stats cs{};
+          hmc_status s = HMC_OK;
+          const double t = elapsed_us([&] {
+            s = cg_solve_impl(F, F->Xe, F->eta, &prm, &cs, st);
+            return s == HMC_OK || s == HMC_E_NOCONV;
+          });
+          if (t < 0 || cs.iters <= 0) {
+            status = s != HMC_OK && s != HMC_E_NOCONV ? s : HMC_E_HIP;
+            if (s != HMC_OK && s != HMC_E_NOCONV) err = hmc_last_error();
+            break;
+          }
+          if (r > 0 && (us < 0 || t / cs.iters < us)) us = t / cs.iters;
         }
-        if (r > 0 && (us < 0 || t / cs.iters < us)) us = t / cs.iters;
+        if (status != HMC_OK) break;
+        if (!best || us < best_us) best = shape, best_form = form, best_us = us;
       }
       if (status != HMC_OK) break;
-      if (!best || us < best_us) best = shape, best_us = us;
     }
-    if (status == HMC_OK) tune_store(F->g.L, TUNE_DSLASH, prec, best, best_us);
+    if (status == HMC_OK) {
+      tune_store(F->g.L, TUNE_DSLASH, prec, best, best_us);
+      if (best_form) tune_store(F->g.L, TUNE_DSLASH_LINKS, prec, best_form, best_us);
+    }
   }
-  // staple force: the launch alone (coef 0 leaves P unchanged)
+  // staple force: the launch alone (coef 0 leaves P unchanged), each shape
+  // and link form
   if (status == HMC_OK) {
-    int best = -1;
+    int best = -1, best_form = 0;
     double best_us = 0;
-    for (int shape : {0, 1}) {
-      auto launch = [&] { return launch_gauge_force(F->g, F->U, F->P, 0.0, st, F->su3, shape) == hipSuccess; };
-      double us = -1;
-      if (launch() && launch()) us = elapsed_us([&] {
-        for (int r = 0; r < 5; ++r)
-          if (!launch()) return false;
-        return true;
-      }) / 5;
-      if (us < 0) {
-        status = HMC_E_HIP;
-        break;
+    for (int form : forms) {
+      for (int shape : {0, 1}) {
+        auto launch = [&] {
+          return launch_gauge_force(F->g, F->U, F->P, 0.0, st, F->su3, shape, form) == hipSuccess;
+        };
+        double us = -1;
+        if (launch() && launch()) us = elapsed_us([&] {
+          for (int r = 0; r < 5; ++r)
+            if (!launch()) return false;
+          return true;
+        }) / 5;
+        if (us < 0) {
+          status = HMC_E_HIP;
+          break;
+        }
+        if (best < 0 || us < best_us) best = shape, best_form = form, best_us = us;
       }
-      if (best < 0 || us < best_us) best = shape, best_us = us;
+      if (status != HMC_OK) break;
     }
-    if (status == HMC_OK) tune_store(F->g.L, TUNE_GFORCE, HMC_F64, best, best_us);
+    if (status == HMC_OK) {
+      tune_store(F->g.L, TUNE_GFORCE, HMC_F64, best, best_us);
+      if (best_form) tune_store(F->g.L, TUNE_GFORCE_LINKS, HMC_F64, best_form, best_us);
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -1333,7 +1352,7 @@ hmc_status hmc_tune_save(const char* path, int32_t* n_entries) {
 
 hmc_status hmc_tune_query(const int32_t* L, int32_t kind, int32_t prec, int32_t* choice, int32_t* tuned) {
   HMC_REQUIRE(L && choice, "null argument");
-  HMC_REQUIRE(kind == HMC_TUNE_DSLASH || kind == HMC_TUNE_GAUGE_FORCE, "bad kind %d", kind);
+  HMC_REQUIRE(kind >= HMC_TUNE_DSLASH && kind <= HMC_TUNE_GAUGE_FORCE_LINKS, "bad kind %d", kind);
   HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision %d", prec);
   hmc_geom geom;
   for (int k = 0; k < 4; ++k) geom.L[k] = L[k];
@@ -1342,8 +1361,14 @@ hmc_status hmc_tune_query(const int32_t* L, int32_t kind, int32_t prec, int32_t*
   hmc_status s = check_geom(&geom, &g, &V);
   if (s) return s;
   const int ints[4] = {L[0], L[1], L[2], L[3]};
-  const int t = tune_lookup(ints, kind, kind == HMC_TUNE_DSLASH ? prec : HMC_F64);
-  *choice = kind == HMC_TUNE_DSLASH ? dslash_shape(g, (hmc_prec)prec) : gauge_force_shape(g);
+  const bool per_prec = kind == HMC_TUNE_DSLASH || kind == HMC_TUNE_DSLASH_LINKS;
+  const int t = tune_lookup(ints, kind, per_prec ? prec : HMC_F64);
+  switch (kind) {
+    case HMC_TUNE_DSLASH: *choice = dslash_shape(g, (hmc_prec)prec); break;
+    case HMC_TUNE_GAUGE_FORCE: *choice = gauge_force_shape(g); break;
+    case HMC_TUNE_DSLASH_LINKS: *choice = dslash_link_form(g, (hmc_prec)prec); break;
+    default: *choice = staple_link_form(g); break;
+  }
   if (tuned) *tuned = t >= 0 ? 1 : 0;
   return HMC_OK;
 }

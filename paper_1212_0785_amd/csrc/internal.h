@@ -33,14 +33,24 @@ inline int blas_blocks(int Vh) {
 }
 inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 
-// Launch shapes (tune.cpp).  Dslash shape: 1 = one site per work-item (256
-// sites per block), 2 / 4 = direction split with that many wavefronts per
-// 64-site group.  Staple-force shape: 0 = one link per work-item, 1 = plane
-// split.  Decided by the environment override, else the tuning table, else
+// Launch shapes and link forms (tune.cpp).  Dslash shape: 1 = one site per
+// work-item (256 sites per block), 2 / 4 = direction split with that many
+// wavefronts per 64-site group.  Staple-force shape: 0 = one link per
+// work-item, 1 = plane split.  Link form: the reals read per link (LinkForm).
+// Each is decided by the environment override, else the tuning table, else
 // the built-in rule.
-enum TuneKind { TUNE_DSLASH = 0, TUNE_GFORCE = 1 };
+enum TuneKind { TUNE_DSLASH = 0, TUNE_GFORCE = 1, TUNE_DSLASH_LINKS = 2, TUNE_GFORCE_LINKS = 3 };
+// All nine entries; rows 0 and 1 (LkRows2); row 0 and column 2 (LkRowCol).
+// The compact forms need SU(3) links.
+enum LinkForm { LINK_FULL = 18, LINK_ROWS2 = 12, LINK_ROWCOL = 10 };
 int dslash_shape(const LatArg& g, hmc_prec prec);
 int gauge_force_shape(const LatArg& g);
+// Compact form of the hop kernels (Dslash at storage prec; the fermion
+// force follows FP64) and of the staple kernels (gauge force, plaquette).
+int dslash_link_form(const LatArg& g, hmc_prec prec);
+int staple_link_form(const LatArg& g);
+// The form a kernel reads: the compact one on SU(3) links, else all entries.
+inline int link_form_for(bool su3, int compact) { return su3 ? compact : (int)LINK_FULL; }
 inline int dslash_shape_blocks(int Vh, int shape) { return shape == 1 ? site_blocks(Vh) : ceil_div(Vh, kThreads / 4); }
 inline int dslash_blocks(const LatArg& g, hmc_prec prec) { return dslash_shape_blocks(g.Vh, dslash_shape(g, prec)); }
 // Largest block count (and Dslash-epilogue partial count) of any shape.
@@ -50,7 +60,8 @@ int tune_lookup(const int* L, int kind, int prec);
 void tune_store(const int* L, int kind, int prec, int choice, double us);
 int tune_load(const char* path);
 int tune_save(const char* path);
-// True when HMC_DSLASH_SPLIT or HMC_GFORCE_PLANES forces the shapes.
+// True when HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES or HMC_LINK_FORM forces a
+// decision.
 bool tune_env_forced();
 
 // Iteration control of the Krylov solvers, resident in device memory.
@@ -82,7 +93,7 @@ struct DslashArgs {
   double* partial_pp[2];  // if set: partial_pp[(label + 1) & 1] instead
   const int* stop_at;   // solver control (may be null)
   int iter0;            // label offset compared with *stop_at
-  int rows2;            // host dispatch: links are SU(3), read two rows and rebuild the third
+  int su3;              // host dispatch: links are SU(3) (compact link forms allowed)
   int shape;            // host dispatch: 0 = dslash_shape(), else a fixed Dslash shape (1, 2, 4)
   // Step-length prologue (block 0 only, when alpha_out is set):
   //   *alpha_out = sum(alpha_pp[label & 1][0..n_pp)) / sum(alpha_den[0..n_den))
@@ -95,9 +106,6 @@ struct DslashArgs {
   const double* alpha_in;
 };
 
-// Whether hopping kernels may read two link rows (HMC_LINK_ROWS2=0 turns the
-// two-row loads off; read once).
-bool link_rows2_enabled();
 
 enum Epilogue { EPI_PLAIN = 0, EPI_AXPY = 1, EPI_AXPY_NORM = 2, EPI_CG = 3 };
 
@@ -113,7 +121,7 @@ hipError_t launch_unpack_spinor(const LatArg& g, const void* half, void* canon, 
 hipError_t launch_pack_momenta(const LatArg& g, const void* canon, double* P, hipStream_t st);
 hipError_t launch_unpack_momenta(const LatArg& g, const double* P, void* canon, hipStream_t st);
 // Per-block counts of links whose third row is not conj(row0 x row1) to `tol`.
-hipError_t launch_rows2_check(const LatArg& g, const void* U, double tol, double* part, int nb, hipStream_t st);
+hipError_t launch_su3_check(const LatArg& g, const void* U, double tol, double* part, int nb, hipStream_t st);
 hipError_t launch_convert_gauge(const LatArg& g, const void* U64, void* Ulow, hmc_prec prec, hipStream_t st);
 hipError_t launch_convert_spinor(const LatArg& g, const void* in, hmc_prec pin, void* out, hmc_prec pout,
                                  int nbatch, const void* const* tab_in, void* const* tab_out, hipStream_t st);
@@ -171,16 +179,18 @@ hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbat
 hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st);  // x += xl; xl = 0
 
 // Gauge-field kernels.
+// su3: U is SU(3) to rounding (compact link forms allowed).
 hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st,
-                                     bool rows2);
+                                     bool su3);
 hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* part, int nb, hipStream_t st);
-// shape: -1 = gauge_force_shape(), 0 / 1 = fixed.
+// shape: -1 = gauge_force_shape(), 0 / 1 = fixed; form: 0 =
+// staple_link_form(), else a fixed compact form (used on SU(3) links only).
 hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st,
-                              bool rows2, int shape = -1);
+                              bool su3, int shape = -1, int form = 0);
 hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st);
 hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
                                 const void* Yo, double* P, double coef, hipStream_t st,
-                                bool rows2);
+                                bool su3);
 
 // Random fields (Philox4x64-10, counter = (block, lex site, stream, epoch),
 // key = (seed, 0)).

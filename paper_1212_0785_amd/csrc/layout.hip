@@ -96,9 +96,12 @@ __global__ void k_convert_gauge(Lat g, const void* U64, void* Ulow) {
   LK::store(Ulow, g.stride, mu, par, s, u);
 }
 
-// Counts the links whose stored third row differs from conj(row0 x row1)
-// by more than `tol` in any real component (per-block partial counts).
-__global__ void __launch_bounds__(kBlock) k_rows2_check(Lat g, const void* U, double tol, double* part) {
+// Counts the links that are not SU(3) to within `tol`: rows 0 and 1 not
+// orthonormal (|row|^2 - 1, <row0, row1>), or the stored third row not
+// conj(row0 x row1) (which then makes det U = 1), in any real component
+// (per-block partial counts).  The compact link forms rebuild entries from
+// exactly these relations.
+__global__ void __launch_bounds__(kBlock) k_su3_check(Lat g, const void* U, double tol, double* part) {
   double v[1] = {0.0};
   for (int j = blockIdx.x * kBlock + threadIdx.x; j < 2 * g.Vh; j += gridDim.x * kBlock) {
     const int par = j >= g.Vh, s = j - par * g.Vh;
@@ -111,6 +114,12 @@ __global__ void __launch_bounds__(kBlock) k_rows2_check(Lat g, const void* U, do
 #pragma unroll
       for (int k = 6; k < 9; ++k)
         bad |= !(fabs(u.m[k].re - r.m[k].re) <= tol) || !(fabs(u.m[k].im - r.m[k].im) <= tol);
+      const double n0 = norm2(u.m[0]) + norm2(u.m[1]) + norm2(u.m[2]);
+      const double n1 = norm2(u.m[3]) + norm2(u.m[4]) + norm2(u.m[5]);
+      cx<double> o = cmadd_conj(cx<double>{0, 0}, u.m[0], u.m[3]);
+      o = cmadd_conj(o, u.m[1], u.m[4]);
+      o = cmadd_conj(o, u.m[2], u.m[5]);
+      bad |= !(fabs(n0 - 1.0) <= tol) || !(fabs(n1 - 1.0) <= tol) || !(fabs(o.re) <= tol) || !(fabs(o.im) <= tol);
       v[0] += bad ? 1.0 : 0.0;
     }
   }
@@ -163,8 +172,8 @@ hipError_t launch_unpack_momenta(const LatArg& g, const double* P, void* canon, 
   return hipGetLastError();
 }
 
-hipError_t launch_rows2_check(const LatArg& g, const void* U, double tol, double* part, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_rows2_check, dim3(nb), dim3(kBlock), 0, st, to_lat(g), U, tol, part);
+hipError_t launch_su3_check(const LatArg& g, const void* U, double tol, double* part, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_su3_check, dim3(nb), dim3(kBlock), 0, st, to_lat(g), U, tol, part);
   return hipGetLastError();
 }
 

@@ -227,7 +227,7 @@ struct Service {
     v.cgls = 1;
     v.prec = (hmc_prec)prm.inner_prec;
     v.U64 = r->U64;
-    v.rows2 = 1;  // weak-field links are reunitarised: SU(3) rows
+    v.su3 = 1;  // weak-field links are reunitarised: SU(3) rows
     v.x = r->x;
     if (v.prec == HMC_F64) v.xl = r->x;
     v.state = states + r->idx;
@@ -245,7 +245,7 @@ struct Service {
     // bhat_e = b_e + kappa D_eo b_o ; x_e = 0 ; r64 = bhat ; |r64|^2 into the solver slot
     DslashArgs d{};
     d.U = r->U64;
-    d.rows2 = 1;
+    d.su3 = 1;
     d.in = b + h64;
     d.out = v.rhs;
     d.y = b;
@@ -281,7 +281,7 @@ struct Service {
     hipError_t e;
     DslashArgs d{};
     d.U = r->U64;
-    d.rows2 = 1;
+    d.su3 = 1;
     d.in = x;
     d.out = x + h64;
     d.y = b + h64;

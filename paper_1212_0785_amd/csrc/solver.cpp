@@ -38,7 +38,7 @@ void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, doubl
   const double k2 = v.kappa * v.kappa;
   DslashArgs b{};
   b.U = v.Ulow;
-  b.rows2 = v.rows2;
+  b.su3 = v.su3;
   b.shape = v.shape;
   b.stop_at = &v.state->stop_at;
   b.iter0 = iter0;
@@ -119,7 +119,7 @@ static hipError_t ds64(const SolveVecs& v, void* out, const void* in, int out_pa
                        double a, double b, double* partial, hipStream_t st) {
   DslashArgs d{};
   d.U = v.U64;
-  d.rows2 = v.rows2;
+  d.su3 = v.su3;
   d.shape = v.shape64;
   d.in = in;
   d.out = out;
@@ -162,7 +162,7 @@ hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st) 
   if (v.cgls) {
     DslashArgs d{};
     d.U = v.Ulow;
-    d.rows2 = v.rows2;
+    d.su3 = v.su3;
     d.shape = v.shape;
     d.in = v.r;
     d.out = v.t;
@@ -301,7 +301,7 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   v.prec = prec;
   v.U64 = F->U;
   v.Ulow = low_links(F, prec);
-  v.rows2 = F->su3;
+  v.su3 = F->su3;
   v.x = x;
   v.r64 = F->r;
   v.rhs = cgls ? F->bhat : const_cast<void*>(b);

@@ -17,7 +17,7 @@ struct SolveVecs {
   hmc_prec prec;     // storage of the inner iteration
   const void* U64;   // FP64 links
   const void* Ulow;  // links in `prec` (== U64 for F64)
-  int rows2;         // links are SU(3): two-row link loads
+  int su3;           // links are SU(3): compact link forms allowed
   int shape, shape64;  // Dslash shapes of the solve (inner storage, FP64), fixed at its start
   void* x;           // FP64 solution, even half
   void* r64;         // FP64 residual (mixed) / residual (F64)

@@ -1,11 +1,14 @@
-// Launch-shape decisions and their persisted tuning table (the auto-tuner
-// of Sec. 4, for the shapes this library offers): per lattice and storage,
-// the Dslash shape (one site per work-item, 2- or 4-way direction split)
-// and the staple-force shape (one link per work-item or plane split).
+// Launch-shape and link-form decisions and their persisted tuning table
+// (the auto-tuner of Sec. 4, for the choices this library offers): per
+// lattice and storage, the Dslash shape (one site per work-item, 2- or
+// 4-way direction split), the staple-force shape (one link per work-item or
+// plane split), and the compact link form of the hop and staple kernels
+// (two rows, or row 0 and column 2).
 //
-// Precedence: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES) >
-// tuned entry > built-in rule measured on MI355X.  HMC_TUNE_DB names a table
-// file loaded on first use; hmc_autotune fills and saves entries.
+// Precedence: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES,
+// HMC_LINK_FORM) > tuned entry > built-in rule measured on MI355X.
+// HMC_TUNE_DB names a table file loaded on first use; hmc_autotune fills and
+// saves entries.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -43,9 +46,23 @@ Table& table() {
 
 Key make_key(const int* L, int kind, int prec) { return Key(L[0], L[1], L[2], L[3], kind, prec); }
 
-const char* kind_name(int kind) { return kind == TUNE_DSLASH ? "dslash" : "gauge_force"; }
+const char* const kKindNames[] = {"dslash", "gauge_force", "dslash_links", "gauge_force_links"};
 
-bool valid_choice(int kind, int c) { return kind == TUNE_DSLASH ? (c == 1 || c == 2 || c == 4) : (c == 0 || c == 1); }
+const char* kind_name(int kind) { return kKindNames[kind]; }
+
+int kind_of(const char* name) {
+  for (int k = 0; k < 4; ++k)
+    if (std::strcmp(name, kKindNames[k]) == 0) return k;
+  return -1;
+}
+
+bool valid_choice(int kind, int c) {
+  switch (kind) {
+    case TUNE_DSLASH: return c == 1 || c == 2 || c == 4;
+    case TUNE_GFORCE: return c == 0 || c == 1;
+    default: return c == LINK_ROWS2 || c == LINK_ROWCOL;
+  }
+}
 
 // Parses "kind L0 L1 L2 L3 prec choice us" lines; others are skipped.
 int load_locked(Table& t, const char* path) {
@@ -59,7 +76,7 @@ int load_locked(Table& t, const char* path) {
     double us;
     if (std::sscanf(line, "%31s %d %d %d %d %d %d %lf", kind, &L[0], &L[1], &L[2], &L[3], &prec, &choice, &us) != 8)
       continue;
-    int k = std::strcmp(kind, "dslash") == 0 ? TUNE_DSLASH : std::strcmp(kind, "gauge_force") == 0 ? TUNE_GFORCE : -1;
+    const int k = kind_of(kind);
     if (k < 0 || !valid_choice(k, choice) || prec < 0 || prec > 3) continue;
     t.map[make_key(L, k, prec)] = Entry{choice, us};
     ++n;
@@ -119,7 +136,8 @@ int tune_save(const char* path) {
   std::fprintf(f,
                "# kind L0 L1 L2 L3 prec choice us\n"
                "# dslash: choice 1 = one site per work-item, 2|4 = direction split; us per CG iteration in a solve\n"
-               "# gauge_force: choice 0 = one link per work-item, 1 = plane split; us per launch\n");
+               "# gauge_force: choice 0 = one link per work-item, 1 = plane split; us per launch\n"
+               "# dslash_links, gauge_force_links: reals read per SU(3) link, 12 = two rows, 10 = row 0 and column 2\n");
   for (const auto& kv : merged) {
     const Key& k = kv.first;
     std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", kind_name(std::get<4>(k)), std::get<0>(k), std::get<1>(k),
@@ -129,7 +147,37 @@ int tune_save(const char* path) {
   return std::rename(tmp_path.c_str(), path) == 0 ? (int)merged.size() : -1;
 }
 
-bool tune_env_forced() { return env_int("HMC_DSLASH_SPLIT") >= 0 || env_int("HMC_GFORCE_PLANES") >= 0; }
+bool tune_env_forced() {
+  return env_int("HMC_DSLASH_SPLIT") >= 0 || env_int("HMC_GFORCE_PLANES") >= 0 || env_int("HMC_LINK_FORM") >= 0;
+}
+
+namespace {
+// HMC_LINK_FORM: 18 = all entries even on SU(3) links, 12, 10; else unset.
+int forced_link_form() {
+  static const int forced = [] {
+    const int v = env_int("HMC_LINK_FORM");
+    return (v == LINK_FULL || v == LINK_ROWS2 || v == LINK_ROWCOL) ? v : -1;
+  }();
+  return forced;
+}
+}  // namespace
+
+int dslash_link_form(const LatArg& g, hmc_prec prec) {
+  if (forced_link_form() > 0) return forced_link_form();
+  const int t = tune_lookup(g.L, TUNE_DSLASH_LINKS, prec);
+  if (t > 0) return t;
+  // measured on MI355X: the 10-real form's reconstruction lengthens each
+  // hop, which costs at 16^3x32 (latency-bound) and pays at 48^3x96
+  return g.Vh >= (1 << 20) ? LINK_ROWCOL : LINK_ROWS2;
+}
+
+int staple_link_form(const LatArg& g) {
+  if (forced_link_form() > 0) return forced_link_form();
+  const int t = tune_lookup(g.L, TUNE_GFORCE_LINKS, HMC_F64);
+  if (t > 0) return t;
+  // measured on MI355X: faster at 16^3x32 and 48^3x96
+  return LINK_ROWCOL;
+}
 
 int dslash_shape(const LatArg& g, hmc_prec prec) {
   static const int forced = [] {

@@ -378,7 +378,8 @@ def hmc_gauge_force(f, coef, stream=None):
     check(lib().hmc_gauge_force(_h(f), float(coef), _stream(stream)))
 
 
-TUNE_DSLASH, TUNE_GAUGE_FORCE = 0, 1
+TUNE_DSLASH, TUNE_GAUGE_FORCE, TUNE_DSLASH_LINKS, TUNE_GAUGE_FORCE_LINKS = 0, 1, 2, 3
+LINK_FULL, LINK_ROWS2, LINK_ROWCOL = 18, 12, 10
 
 
 def hmc_autotune(f, db_path=None, stream=None):

@@ -1,9 +1,11 @@
-"""GPU: the two link-load forms of the hopping kernels.
+"""GPU: the link-load forms of the hopping and staple kernels.
 
-On SU(3) fields the kernels read rows 0 and 1 of each link and rebuild row 2
-as conj(row0 x row1); on any other field they read all nine entries.  Both
-must reproduce the oracle's Wilson operator, and the library must pick the
-two-row form only when every stored third row equals the rebuilt one.
+On SU(3) fields the kernels read a compact form of each link: rows 0 and 1
+(row 2 rebuilt as conj(row0 x row1)), or row 0 and column 2 (u10, u11 from
+orthogonality and det = 1, exact reads where |u02| is close to 1); on any
+other field they read all nine entries.  Every form must reproduce the
+oracle, and the library must use a compact form only when every link is
+SU(3) to rounding.
 """
 import numpy as np
 import pytest
@@ -56,6 +58,12 @@ def test_two_row_flag_follows_the_field(H):
     U[17, 2, 2, 1] += 1e-12
     put_gauge(H, F, U)
     assert not H.hmc_links_two_row(F)
+    # third row = conj(row0 x row1) but rows 0, 1 not orthonormal
+    U = synth.gauge_field(7, L)
+    U[5, 1, 0, :] *= 1.0 + 1e-12
+    U[5, 1, 2, :] = np.conj(np.cross(U[5, 1, 0, :], U[5, 1, 1, :]))
+    put_gauge(H, F, U)
+    assert not H.hmc_links_two_row(F)
 
 
 @pytest.mark.parametrize("L", SMALL)
@@ -104,3 +112,76 @@ def test_two_row_and_full_forms_agree(H, L):
     want = O.dslash(L, U, psi, 0, 1)
     assert rel(outs[0], want) < 1e-14 and rel(outs[1], want) < 1e-14
     assert rel(outs[0], outs[1]) < 1e-14
+
+
+# Extents used by no other test: the table entries that select the form
+# for them leave every other test's lattice alone.
+FORM_L = [(6, 4, 4, 8), (8, 6, 4, 6)]
+
+
+def set_forms(H, path, L, hop, staple):
+    ext = " ".join(map(str, L))
+    lines = [f"dslash_links {ext} {p} {hop} 0" for p in range(4)] + [f"gauge_force_links {ext} 0 {staple} 0"]
+    path.write_text("\n".join(lines) + "\n")
+    H.hmc_tune_load(str(path))
+    for p in range(4):
+        assert H.hmc_tune_query(L, H.TUNE_DSLASH_LINKS, p) == (hop, True)
+    assert H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE_LINKS) == (staple, True)
+
+
+def permuted_field(seed, L):
+    """SU(3) links C V, V near the identity, C the cyclic permutation
+    (det 1): |u02| is close to 1 on every link, and about half of them have
+    |u02|^2 > 15/16, where the row-0 / column-2 form reads u10, u11 instead
+    of solving for them; most wavefronts take both branches."""
+    C = np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]], dtype=complex)
+    return C @ synth.gauge_field(seed, L, eps=0.2)
+
+
+FIELDS = {"haar": lambda L: synth.gauge_field(41, L),
+          "weak": lambda L: O.weak_field(L, 42, 0.3),
+          "permuted": lambda L: permuted_field(43, L)}
+
+
+@pytest.mark.parametrize("field", sorted(FIELDS))
+@pytest.mark.parametrize("L", FORM_L)
+def test_compact_forms_match_oracle(H, tmp_path, L, field):
+    from tests.test_gpu_parity import get_momenta, put_momenta
+    k, beta = 0.15, 5.6
+    U = FIELDS[field](L)
+    if field == "permuted":
+        assert 0.2 < np.mean(np.abs(U[..., 0, 2]) ** 2 > 15 / 16) < 0.8
+    psi = synth.spinor(44, L)
+    odd = O.parity_mask(L)
+    Xe, Ye = synth.spinor(45, L, odd, 0), synth.spinor(46, L, odd, 0)
+    P = synth.hermitian_traceless(47, L)
+    want_ds = {(par, dag): O.dslash(L, U, psi, par, dag) for par in (0, 1) for dag in (0, 1)}
+    X, Y = Xe.copy(), Ye.copy()
+    X[odd] = O.dslash(L, U, Xe, 1)[odd]
+    Y[odd] = O.dslash(L, U, Ye, 1, dagger=True)[odd]
+    want_ff = P - 0.37 * O.fermion_force(L, U, 0.13 ** 2, X, Y)
+    want_gf = P - 0.3 * O.gauge_force(L, U, beta)
+    want_plaq = O.plaquette(L, U)
+    for hop, staple in ((12, 10), (10, 12), (10, 10)):
+        set_forms(H, tmp_path / f"f{hop}_{staple}.txt", L, hop, staple)
+        F = H.Fields(L, beta, k, flags=H.FIELDS_LOWPREC)
+        put_gauge(H, F, U)
+        assert H.hmc_links_two_row(F)
+        for (par, dag), want in want_ds.items():
+            b = put_spinor(H, F, psi, 1 - par)
+            out = F.spinor()
+            H.hmc_wilson_dslash(F, out, b, par, dag)
+            assert rel(get_spinor(H, F, out, par), want) < 1e-14, (hop, par, dag)
+        for prec, tol in ((1, 1e-6), (2, 3e-3), (3, 2e-2)):
+            bl = put_spinor(H, F, psi, 1, prec=prec)
+            ol = F.spinor(prec=prec)
+            H.hmc_wilson_dslash(F, ol, bl, 0, 0, prec)
+            assert rel(get_spinor(H, F, ol, 0, prec=prec), want_ds[(0, 0)]) < tol, (hop, prec)
+        put_momenta(H, F, P)
+        H.hmc_fermion_force_bilinear(F, put_spinor(H, F, Xe, 0), put_spinor(H, F, Ye, 0), 0.13, 0.37)
+        assert rel(get_momenta(H, F), want_ff) < 1e-13, hop
+        put_momenta(H, F, P)
+        H.hmc_gauge_force(F, 0.3)
+        assert rel(get_momenta(H, F), want_gf) < 1e-13, staple
+        assert abs(H.hmc_plaquette(F) - want_plaq) < 1e-13, staple
+        del F

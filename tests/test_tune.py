@@ -46,3 +46,26 @@ def test_table_load_query_and_save(H, tmp_path):
         H.hmc_tune_query((5, 2, 2, 10), H.TUNE_DSLASH, H.F64)  # odd extent
     with pytest.raises(H.HmcError):
         H.hmc_tune_load(str(tmp_path / "missing.txt"))
+
+
+def test_link_form_entries(H, tmp_path):
+    if os.environ.get("HMC_LINK_FORM"):
+        pytest.skip("environment overrides the table")
+    src = tmp_path / "links.txt"
+    src.write_text("dslash_links 6 4 2 10 0 10 80.0\n"
+                   "dslash_links 6 4 2 10 1 12 40.0\n"
+                   "gauge_force_links 6 4 2 10 0 12 90.0\n"
+                   "dslash_links 6 4 2 10 2 18 1.0\n"    # the full form is not a tunable choice
+                   "gauge_force_links 6 4 2 10 0 11 1.0\n")
+    assert H.hmc_tune_load(str(src)) == 3
+    assert H.hmc_tune_query((6, 4, 2, 10), H.TUNE_DSLASH_LINKS, H.F64) == (H.LINK_ROWCOL, True)
+    assert H.hmc_tune_query((6, 4, 2, 10), H.TUNE_DSLASH_LINKS, H.F32) == (H.LINK_ROWS2, True)
+    assert H.hmc_tune_query((6, 4, 2, 10), H.TUNE_GAUGE_FORCE_LINKS) == (H.LINK_ROWS2, True)
+    # built-in rule: two rows for the hop kernels below 2^20 half-lattice
+    # sites, row 0 + column 2 above it and for the staple kernels
+    assert H.hmc_tune_query((6, 4, 2, 10), H.TUNE_DSLASH_LINKS, H.F16) == (H.LINK_ROWS2, False)
+    assert H.hmc_tune_query((48, 48, 48, 96), H.TUNE_DSLASH_LINKS, H.F64)[0] in (H.LINK_ROWCOL, H.LINK_ROWS2)
+    assert H.hmc_tune_query((64, 64, 64, 64), H.TUNE_DSLASH_LINKS, H.F64) == (H.LINK_ROWCOL, False)
+    assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_GAUGE_FORCE_LINKS) == (H.LINK_ROWCOL, False)
+    with pytest.raises(H.HmcError):
+        H.hmc_tune_query((6, 4, 2, 10), 4, H.F64)  # no such kind
