@@ -66,15 +66,21 @@ def load_traffic(workload: str):
 
 
 def launch_shapes(H, L, db):
-    """The Dslash and staple-force shapes in force for lattice L (Dslash: 1 =
-    one site per work-item, 2/4 = direction split; staple force: 1 = plane
-    split) and where each came from."""
+    """The launch decisions in force for lattice L and where each came from:
+    Dslash shape (1 = one site per work-item, 2/4 = direction split) and
+    link form (reals read per SU(3) link: 12 = two rows, 10 = row 0 and
+    column 2) per storage, staple-force shape (1 = plane split) and link
+    form."""
     out = {"table": db}
-    for p, name in ((H.F64, "dslash_f64"), (H.F32, "dslash_f32"), (H.F16, "dslash_f16"), (H.BF16, "dslash_bf16")):
+    for p, name in ((H.F64, "f64"), (H.F32, "f32"), (H.F16, "f16"), (H.BF16, "bf16")):
         c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH, p)
-        out[name] = [c, "table" if tuned else "rule"]
+        out[f"dslash_{name}"] = [c, "table" if tuned else "rule"]
+        c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_LINKS, p)
+        out[f"dslash_links_{name}"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE)
     out["gauge_force_planes"] = [c, "table" if tuned else "rule"]
+    c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE_LINKS)
+    out["gauge_force_links"] = [c, "table" if tuned else "rule"]
     return out
 
 
@@ -183,8 +189,8 @@ def run_hmc(args, H, torch):
     if rf:
         out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": rf["achieved"] / HBM_PEAK_GBS, "traffic": load_traffic("hmc_16c32"),
-                           "kernel": ("k_dslash F64, two-row links (half-lattice hop; plain, axpy/norm and "
-                                      "CG-update epilogues: 1152/1344/1536 B per site)"),
+                           "kernel": ("k_dslash F64 (half-lattice hop; plain, axpy/norm and CG-update "
+                                      "epilogues; link form in config.launch_shapes.dslash_links_f64)"),
                            "avg_launch_ms": rf["avg_ms"], "bytes_per_launch": rf["bytes_per_launch"],
                            "launches_timed": rf["launches_timed"]}
     return out, iters / solves, L, seed, beta, kappa, nsteps
@@ -557,6 +563,7 @@ def main():
         out["config"]["launch_shapes"] = launch_shapes(H, out["config"]["lattice"], args.tune_db)
         if args.workload in ("hmc", "dslash") and "roofline" in out:
             out["roofline"]["dslash_shape"] = out["config"]["launch_shapes"]["dslash_f64"][0]
+            out["roofline"]["link_reals"] = out["config"]["launch_shapes"]["dslash_links_f64"][0]
     print(json.dumps(out))
 
 
