@@ -69,14 +69,16 @@ def launch_shapes(H, L, db):
     """The launch decisions in force for lattice L and where each came from:
     Dslash shape (1 = one site per work-item, 2/4 = direction split) and
     link form (reals read per SU(3) link: 12 = two rows, 10 = row 0 and
-    column 2) per storage, staple-force shape (1 = plane split) and link
-    form."""
-    out = {"table": db}
+    column 2) and streaming (non-temporal link loads and output stores) per
+    storage, staple-force shape (1 = plane split) and link form."""
+    out = {"table": db or (os.environ.get("HMC_TUNE_DB") or H.TUNE_TABLE)}
     for p, name in ((H.F64, "f64"), (H.F32, "f32"), (H.F16, "f16"), (H.BF16, "bf16")):
         c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH, p)
         out[f"dslash_{name}"] = [c, "table" if tuned else "rule"]
         c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_LINKS, p)
         out[f"dslash_links_{name}"] = [c, "table" if tuned else "rule"]
+        c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_STREAM, p)
+        out[f"dslash_stream_{name}"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE)
     out["gauge_force_planes"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE_LINKS)
@@ -519,8 +521,9 @@ def main():
                     help="hmc: start each force solve from the chronological guess over the last N solutions")
     ap.add_argument("--mts-steps", default="5,2,2", help="mts: ratio,heavy,gauge steps per enclosing step")
     ap.add_argument("--tune-db", default=None,
-                    help=("launch-shape table to load (hmc_tune_load) before the run, e.g. "
-                          "paper_1212_0785_amd/tune/mi355x.txt; default: the built-in shape rule"))
+                    help=("extra launch-shape table to load (hmc_tune_load) before the run; the binding "
+                          "already loads paper_1212_0785_amd/tune/mi355x.txt unless HMC_TUNE_DB is set "
+                          "(HMC_TUNE_DB=none: built-in rules only)"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -564,6 +567,7 @@ def main():
         if args.workload in ("hmc", "dslash") and "roofline" in out:
             out["roofline"]["dslash_shape"] = out["config"]["launch_shapes"]["dslash_f64"][0]
             out["roofline"]["link_reals"] = out["config"]["launch_shapes"]["dslash_links_f64"][0]
+            out["roofline"]["stream"] = out["config"]["launch_shapes"]["dslash_stream_f64"][0]
     print(json.dumps(out))
 
 

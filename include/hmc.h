@@ -351,23 +351,27 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
  * HMC_TUNE_DSLASH_LINKS (reals read per SU(3) link by the hopping kernels,
  * 12 = rows 0 and 1, 10 = row 0 and column 2; per storage precision; the
  * fermion force follows the FP64 entry) and HMC_TUNE_GAUGE_FORCE_LINKS (the
- * same for the staple force and the plaquette; prec HMC_F64).  Decision
- * order: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES,
- * HMC_LINK_FORM = 18 / 12 / 10) > table entry for the lattice extents >
- * built-in rule.  HMC_TUNE_DB names a table file read on first use.  Table
+ * same for the staple force and the plaquette; prec HMC_F64) and
+ * HMC_TUNE_DSLASH_STREAM (1 = the Dslash at that storage reads its compact
+ * links and writes its output with non-temporal hints; per storage
+ * precision).  Decision order: environment override (HMC_DSLASH_SPLIT,
+ * HMC_GFORCE_PLANES, HMC_LINK_FORM = 18 / 12 / 10, HMC_LINK_STREAM = 0 / 1)
+ * > table entry for the lattice extents > built-in rule.  HMC_TUNE_DB names a table file read on first use.  Table
  * file: text lines "kind L0 L1 L2 L3 prec choice us" with kind dslash,
- * gauge_force, dslash_links or gauge_force_links ('#' lines and malformed
- * lines are ignored).  Shapes are fixed per solve (and per service request)
+ * gauge_force, dslash_links, gauge_force_links or dslash_stream ('#' lines
+ * and malformed lines are ignored).  Shapes are fixed per solve (and per service request)
  * when it starts; do not tune while solves or a service run on the same
  * lattice extents. */
 typedef enum {
   HMC_TUNE_DSLASH = 0,
   HMC_TUNE_GAUGE_FORCE = 1,
   HMC_TUNE_DSLASH_LINKS = 2,
-  HMC_TUNE_GAUGE_FORCE_LINKS = 3
+  HMC_TUNE_GAUGE_FORCE_LINKS = 3,
+  HMC_TUNE_DSLASH_STREAM = 4
 } hmc_tune_kind;
 /* Times every candidate on f's lattice and stores the fastest in the
- * table: for each storage precision the Dslash shape x link form pair
+ * table: for each storage precision the Dslash shape x link form pairs
+ * (then streaming on and off for the best pair)
  * where it runs, inside a solve (CG on Mhat^dag Mhat from Gaussian noise to
  * 1e-10 or 100 iterations: FP64 CG, and with HMC_FIELDS_LOWPREC
  * mixed-precision CG with that storage inside; "us" = microseconds per

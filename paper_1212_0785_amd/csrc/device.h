@@ -33,21 +33,27 @@ template <typename T>
 __device__ __forceinline__ const HMC_GLOBAL T& gld(const void* base, unsigned idx) {
   return *(const HMC_GLOBAL T*)((const HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T));
 }
-// Same, with the non-temporal hint (data read once per sweep).
-#ifndef HMC_LINK_NT
-#define HMC_LINK_NT 0
-#endif
-template <typename T>
+// Same, with the non-temporal hint when NT (data used once per sweep, which
+// then leaves the caches to data that is reused).
+template <typename T, bool NT = false>
 __device__ __forceinline__ T gld_link(const void* base, unsigned idx) {
-#if HMC_LINK_NT
-  return __builtin_nontemporal_load((const HMC_GLOBAL T*)((const HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T)));
-#else
-  return gld<T>(base, idx);
-#endif
+  if constexpr (NT)
+    return __builtin_nontemporal_load((const HMC_GLOBAL T*)((const HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T)));
+  else
+    return gld<T>(base, idx);
 }
 template <typename T>
 __device__ __forceinline__ HMC_GLOBAL T& gst(void* base, unsigned idx) {
   return *(HMC_GLOBAL T*)((HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T));
+}
+// A store, with the non-temporal hint when NT.
+template <bool NT, typename T>
+__device__ __forceinline__ void gput(void* base, unsigned idx, T v) {
+  HMC_GLOBAL T* p = (HMC_GLOBAL T*)((HMC_GLOBAL char*)base + idx * (unsigned)sizeof(T));
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // ------------------------------------------------------------ complex
@@ -451,9 +457,10 @@ struct SpF64 {
       v[k] = {t.x, t.y};
     }
   }
+  template <bool NT = false>
   __device__ static void store(void* base, int stride, int s, const cx<R>* v) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) gst<v2d>(base, k * stride + s) = v2d{v[k].re, v[k].im};
+    for (int k = 0; k < 12; ++k) gput<NT>(base, k * stride + s, v2d{v[k].re, v[k].im});
   }
   // component k of site s
   __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
@@ -461,9 +468,10 @@ struct SpF64 {
     return {t.x, t.y};
   }
   // components 3*part .. 3*part+2 of site s
+  template <bool NT = false>
   __device__ static void store_part(void* base, int stride, int s, int part, const cx<R>* v) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gst<v2d>(base, (3 * part + c) * stride + s) = v2d{v[c].re, v[c].im};
+    for (int c = 0; c < 3; ++c) gput<NT>(base, (3 * part + c) * stride + s, v2d{v[c].re, v[c].im});
   }
 };
 
@@ -478,17 +486,19 @@ struct SpF32 {
       v[k] = {t.x, t.y};
     }
   }
+  template <bool NT = false>
   __device__ static void store(void* base, int stride, int s, const cx<R>* v) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) gst<v2f>(base, k * stride + s) = v2f{v[k].re, v[k].im};
+    for (int k = 0; k < 12; ++k) gput<NT>(base, k * stride + s, v2f{v[k].re, v[k].im});
   }
   __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
     v2f t = gld<v2f>(base, k * stride + s);
     return {t.x, t.y};
   }
+  template <bool NT = false>
   __device__ static void store_part(void* base, int stride, int s, int part, const cx<R>* v) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gst<v2f>(base, (3 * part + c) * stride + s) = v2f{v[c].re, v[c].im};
+    for (int c = 0; c < 3; ++c) gput<NT>(base, (3 * part + c) * stride + s, v2f{v[c].re, v[c].im});
   }
 };
 
@@ -504,15 +514,16 @@ struct SpF16 {
       v[k] = {t.x * f, t.y * f};
     }
   }
+  template <bool NT = false>
   __device__ static void store(void* base, int stride, int s, const cx<R>* v) {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
     float inv = m > 0.f ? 1.f / m : 0.f;
-    gst<float>(base, 12 * stride + s) = m;
+    gput<NT>(base, 12 * stride + s, m);
 #pragma unroll
     for (int k = 0; k < 12; ++k)
-      gst<v2h>(base, k * stride + s) = __builtin_convertvector((v2f{v[k].re * inv, v[k].im * inv}), v2h);
+      gput<NT>(base, k * stride + s, __builtin_convertvector((v2f{v[k].re * inv, v[k].im * inv}), v2h));
   }
   __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
     const float f = gld<float>(base, 12 * stride + s);
@@ -521,12 +532,13 @@ struct SpF16 {
   }
   // components 3*part .. 3*part+2 of site s, with the site's max |re|,|im|
   // m computed by the caller over all 12 components (part 0 writes it)
+  template <bool NT = false>
   __device__ static void store_part_scaled(void* base, int stride, int s, int part, const cx<R>* v, float m) {
     const float inv = m > 0.f ? 1.f / m : 0.f;
-    if (part == 0) gst<float>(base, 12 * stride + s) = m;
+    if (part == 0) gput<NT>(base, 12 * stride + s, m);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      gst<v2h>(base, (3 * part + c) * stride + s) = __builtin_convertvector((v2f{v[c].re * inv, v[c].im * inv}), v2h);
+      gput<NT>(base, (3 * part + c) * stride + s, __builtin_convertvector((v2f{v[c].re * inv, v[c].im * inv}), v2h));
   }
 };
 
@@ -541,39 +553,42 @@ struct SpBF16 {
       v[k] = {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
     }
   }
+  template <bool NT = false>
   __device__ static void store(void* base, int stride, int s, const cx<R>* v) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) gst<uint32_t>(base, k * stride + s) = f_to_bf16(v[k].re) | (f_to_bf16(v[k].im) << 16);
+    for (int k = 0; k < 12; ++k) gput<NT>(base, k * stride + s, f_to_bf16(v[k].re) | (f_to_bf16(v[k].im) << 16));
   }
   __device__ static cx<R> load_one(const void* base, int stride, int s, int k) {
     uint32_t w = gld<uint32_t>(base, k * stride + s);
     return {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
   }
+  template <bool NT = false>
   __device__ static void store_part(void* base, int stride, int s, int part, const cx<R>* v) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      gst<uint32_t>(base, (3 * part + c) * stride + s) = f_to_bf16(v[c].re) | (f_to_bf16(v[c].im) << 16);
+      gput<NT>(base, (3 * part + c) * stride + s, f_to_bf16(v[c].re) | (f_to_bf16(v[c].im) << 16));
   }
 };
 
 // Links: element (mu, parity, k, s) at ((mu*2 + parity)*9 + k)*stride + s.
 struct LkF64 {
+  static constexpr bool kStream = false;
   using R = double;
   static constexpr int kBytes = 144;
   // component K (row K / 3, column K % 3) alone
-  template <int K>
+  template <int K, bool NT = false>
   __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2d);
-    v2d t = gld_link<v2d>(p, K * stride + s);
+    v2d t = gld_link<v2d, NT>(p, K * stride + s);
     return {t.x, t.y};
   }
-  template <int K = 9>
+  template <int K = 9, bool NT = false>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2d);
     mat3<R> u;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      v2d t = gld_link<v2d>(p, k * stride + s);
+      v2d t = gld_link<v2d, NT>(p, k * stride + s);
       u.m[k] = {t.x, t.y};
     }
     return u;
@@ -586,22 +601,23 @@ struct LkF64 {
 };
 
 struct LkF32 {
+  static constexpr bool kStream = false;
   using R = float;
   static constexpr int kBytes = 72;
   // component K (row K / 3, column K % 3) alone
-  template <int K>
+  template <int K, bool NT = false>
   __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2f);
-    v2f t = gld_link<v2f>(p, K * stride + s);
+    v2f t = gld_link<v2f, NT>(p, K * stride + s);
     return {t.x, t.y};
   }
-  template <int K = 9>
+  template <int K = 9, bool NT = false>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2f);
     mat3<R> u;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      v2f t = gld_link<v2f>(p, k * stride + s);
+      v2f t = gld_link<v2f, NT>(p, k * stride + s);
       u.m[k] = {t.x, t.y};
     }
     return u;
@@ -614,22 +630,23 @@ struct LkF32 {
 };
 
 struct LkF16 {
+  static constexpr bool kStream = false;
   using R = float;
   static constexpr int kBytes = 36;
   // component K (row K / 3, column K % 3) alone
-  template <int K>
+  template <int K, bool NT = false>
   __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2h);
-    v2f t = __builtin_convertvector(gld_link<v2h>(p, K * stride + s), v2f);
+    v2f t = __builtin_convertvector(gld_link<v2h, NT>(p, K * stride + s), v2f);
     return {t.x, t.y};
   }
-  template <int K = 9>
+  template <int K = 9, bool NT = false>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2h);
     mat3<R> u;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      v2f t = __builtin_convertvector(gld_link<v2h>(p, k * stride + s), v2f);
+      v2f t = __builtin_convertvector(gld_link<v2h, NT>(p, k * stride + s), v2f);
       u.m[k] = {t.x, t.y};
     }
     return u;
@@ -643,22 +660,23 @@ struct LkF16 {
 };
 
 struct LkBF16 {
+  static constexpr bool kStream = false;
   using R = float;
   static constexpr int kBytes = 36;
   // component K (row K / 3, column K % 3) alone
-  template <int K>
+  template <int K, bool NT = false>
   __device__ static cx<R> one(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(uint32_t);
-    uint32_t w = gld_link<uint32_t>(p, K * stride + s);
+    uint32_t w = gld_link<uint32_t, NT>(p, K * stride + s);
     return {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
   }
-  template <int K = 9>
+  template <int K = 9, bool NT = false>
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     const void* p = (const char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(uint32_t);
     mat3<R> u;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      uint32_t w = gld_link<uint32_t>(p, k * stride + s);
+      uint32_t w = gld_link<uint32_t, NT>(p, k * stride + s);
       u.m[k] = {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
     }
     return u;
@@ -674,12 +692,13 @@ struct LkBF16 {
 // Two-row form of any of the link formats above: reads components 0..5
 // (rows 0 and 1) and rebuilds row 2, for fields that are SU(3) to rounding.
 // Two thirds of the link bytes of a hop.
-template <class LK>
+template <class LK, bool NT = false>
 struct LkRows2 {
   using R = typename LK::R;
   static constexpr int kBytes = LK::kBytes / 9 * 6;
+  static constexpr bool kStream = NT;  // non-temporal link loads (and output stores)
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
-    mat3<R> u = LK::template load<6>(base, stride, mu, par, s);
+    mat3<R> u = LK::template load<6, NT>(base, stride, mu, par, s);
     third_row(u);
     return u;
   }
@@ -693,21 +712,22 @@ struct LkRows2 {
 // two-row form.  The solve amplifies rounding by 1/D, so a link with
 // D < 1/16 reads u10 and u11 instead (exact; on smooth fields no work-item
 // takes that branch).
-template <class LK>
+template <class LK, bool NT = false>
 struct LkRowCol {
   using R = typename LK::R;
   static constexpr int kBytes = LK::kBytes / 9 * 5;
+  static constexpr bool kStream = NT;  // non-temporal link loads (and output stores)
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
     mat3<R> u;
-    u.m[0] = LK::template one<0>(base, stride, mu, par, s);
-    u.m[1] = LK::template one<1>(base, stride, mu, par, s);
-    u.m[2] = LK::template one<2>(base, stride, mu, par, s);
-    u.m[5] = LK::template one<5>(base, stride, mu, par, s);
-    u.m[8] = LK::template one<8>(base, stride, mu, par, s);
+    u.m[0] = LK::template one<0, NT>(base, stride, mu, par, s);
+    u.m[1] = LK::template one<1, NT>(base, stride, mu, par, s);
+    u.m[2] = LK::template one<2, NT>(base, stride, mu, par, s);
+    u.m[5] = LK::template one<5, NT>(base, stride, mu, par, s);
+    u.m[8] = LK::template one<8, NT>(base, stride, mu, par, s);
     const R d = norm2(u.m[0]) + norm2(u.m[1]);
     if (d < R(0.0625)) {
-      u.m[3] = LK::template one<3>(base, stride, mu, par, s);
-      u.m[4] = LK::template one<4>(base, stride, mu, par, s);
+      u.m[3] = LK::template one<3, NT>(base, stride, mu, par, s);
+      u.m[4] = LK::template one<4, NT>(base, stride, mu, par, s);
     } else {
       // u10 = -(u00 conj(u02) u12 + conj(u01) conj(u22)) / D
       // u11 = (conj(u00) conj(u22) - u01 conj(u02) u12) / D

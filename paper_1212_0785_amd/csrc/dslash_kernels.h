@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
     if (EPI == EPI_AXPY_NORM || EPI == EPI_CG)
 #pragma unroll
       for (int k = 0; k < 12; ++k) nrm[0] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
-    SP::store(e.out, g.stride, s, acc);
+    SP::template store<LK::kStream>(e.out, g.stride, s, acc);
   }
   if (EPI == EPI_AXPY_NORM || EPI == EPI_CG) {
     block_sum<1>(nrm);
@@ -268,11 +268,12 @@ __global__ void __launch_bounds__(NW * 64) k_dslash_split(Lat g, int out_par, co
     for (int q = 1; q < NW; ++q) m = fmaxf(m, smax[q][ls]);
     if (active)
 #pragma unroll
-      for (int q = 0; q < kParts; ++q) SP::store_part_scaled(e.out, g.stride, s, kParts * w + q, o + 3 * q, m);
+      for (int q = 0; q < kParts; ++q)
+        SP::template store_part_scaled<LK::kStream>(e.out, g.stride, s, kParts * w + q, o + 3 * q, m);
   } else {
     if (active)
 #pragma unroll
-      for (int q = 0; q < kParts; ++q) SP::store_part(e.out, g.stride, s, kParts * w + q, o + 3 * q);
+      for (int q = 0; q < kParts; ++q) SP::template store_part<LK::kStream>(e.out, g.stride, s, kParts * w + q, o + 3 * q);
   }
   if (EPI == EPI_AXPY_NORM || EPI == EPI_CG) {
     block_sum<1, NW>(nrm);
@@ -331,12 +332,13 @@ static hipError_t launch_typed(hmc_prec prec, int dagger, int epi, const LatArg&
   return hipGetLastError();
 }
 
-// Link form (SU(3) fields: the tuned compact form, else all entries), then
-// shape and epilogue.
+// Link form (SU(3) fields: the tuned compact form and streaming choice,
+// else all entries), then shape and epilogue.
 template <class SP, class LK>
 hipError_t launch_links(hmc_prec prec, int dagger, int epi, const LatArg& g, int out_par, const DslashArgs* table,
                         int nbatch, const DslashArgs& one, hipStream_t st, int j) {
   const int form = link_form_for(one.su3, dslash_link_form(g, prec));
+  const bool stream = form != LINK_FULL && dslash_link_stream(g, prec);
   const int link_bytes = form == LINK_ROWCOL ? LkRowCol<LK>::kBytes : form == LINK_ROWS2 ? LkRows2<LK>::kBytes
                                                                                           : LK::kBytes;
   // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for
@@ -344,10 +346,16 @@ hipError_t launch_links(hmc_prec prec, int dagger, int epi, const LatArg& g, int
   const double site_bytes =
       8.0 * link_bytes + 2 * SP::kBytes + (epi ? SP::kBytes : 0) + (epi == EPI_CG ? SP::kBytes : 0);
   const KernelEvents ev = timing_kernel_events(TK_DSLASH, site_bytes * g.Vh * nbatch);
-  if (form == LINK_ROWCOL)
+  if (form == LINK_ROWCOL) {
+    if (stream)
+      return launch_typed<SP, LkRowCol<LK, true>>(prec, dagger, epi, g, out_par, table, nbatch, one, st, j, ev);
     return launch_typed<SP, LkRowCol<LK>>(prec, dagger, epi, g, out_par, table, nbatch, one, st, j, ev);
-  if (form == LINK_ROWS2)
+  }
+  if (form == LINK_ROWS2) {
+    if (stream)
+      return launch_typed<SP, LkRows2<LK, true>>(prec, dagger, epi, g, out_par, table, nbatch, one, st, j, ev);
     return launch_typed<SP, LkRows2<LK>>(prec, dagger, epi, g, out_par, table, nbatch, one, st, j, ev);
+  }
   return launch_typed<SP, LK>(prec, dagger, epi, g, out_par, table, nbatch, one, st, j, ev);
 }
 

@@ -39,7 +39,7 @@ inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 // work-item, 1 = plane split.  Link form: the reals read per link (LinkForm).
 // Each is decided by the environment override, else the tuning table, else
 // the built-in rule.
-enum TuneKind { TUNE_DSLASH = 0, TUNE_GFORCE = 1, TUNE_DSLASH_LINKS = 2, TUNE_GFORCE_LINKS = 3 };
+enum TuneKind { TUNE_DSLASH = 0, TUNE_GFORCE = 1, TUNE_DSLASH_LINKS = 2, TUNE_GFORCE_LINKS = 3, TUNE_DSLASH_STREAM = 4 };
 // All nine entries; rows 0 and 1 (LkRows2); row 0 and column 2 (LkRowCol).
 // The compact forms need SU(3) links.
 enum LinkForm { LINK_FULL = 18, LINK_ROWS2 = 12, LINK_ROWCOL = 10 };
@@ -49,6 +49,11 @@ int gauge_force_shape(const LatArg& g);
 // force follows FP64) and of the staple kernels (gauge force, plaquette).
 int dslash_link_form(const LatArg& g, hmc_prec prec);
 int staple_link_form(const LatArg& g);
+// Whether the Dslash at storage prec streams: non-temporal loads of its
+// (compact) links and stores of its output, which keep that once-used data
+// from displacing the neighbour spinors in L2 (pays at large volumes) but
+// also from the last-level cache (costs where the fields fit in it).
+bool dslash_link_stream(const LatArg& g, hmc_prec prec);
 // The form a kernel reads: the compact one on SU(3) links, else all entries.
 inline int link_form_for(bool su3, int compact) { return su3 ? compact : (int)LINK_FULL; }
 inline int dslash_shape_blocks(int Vh, int shape) { return shape == 1 ? site_blocks(Vh) : ceil_div(Vh, kThreads / 4); }
@@ -60,8 +65,8 @@ int tune_lookup(const int* L, int kind, int prec);
 void tune_store(const int* L, int kind, int prec, int choice, double us);
 int tune_load(const char* path);
 int tune_save(const char* path);
-// True when HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES or HMC_LINK_FORM forces a
-// decision.
+// True when HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES, HMC_LINK_FORM or
+// HMC_LINK_STREAM forces a decision.
 bool tune_env_forced();
 
 // Iteration control of the Krylov solvers, resident in device memory.

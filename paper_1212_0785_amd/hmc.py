@@ -173,8 +173,14 @@ _SIGNATURES = {
 }
 
 
+# The launch-shape table measured on MI355X, loaded by lib() unless
+# HMC_TUNE_DB is set (the library then reads that file; "none" loads none).
+TUNE_TABLE = os.path.join(_HERE, "tune", "mi355x.txt")
+
+
 def lib():
-    """Load libhmc.so (raises if it has not been built)."""
+    """Load libhmc.so (raises if it has not been built) and, unless
+    HMC_TUNE_DB is set, the MI355X tuning table TUNE_TABLE."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -186,6 +192,9 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        if os.environ.get("HMC_TUNE_DB") is None and os.path.exists(TUNE_TABLE):
+            n = C.c_int32()
+            check(L.hmc_tune_load(TUNE_TABLE.encode(), C.byref(n)))
     return _lib
 
 
@@ -378,7 +387,7 @@ def hmc_gauge_force(f, coef, stream=None):
     check(lib().hmc_gauge_force(_h(f), float(coef), _stream(stream)))
 
 
-TUNE_DSLASH, TUNE_GAUGE_FORCE, TUNE_DSLASH_LINKS, TUNE_GAUGE_FORCE_LINKS = 0, 1, 2, 3
+TUNE_DSLASH, TUNE_GAUGE_FORCE, TUNE_DSLASH_LINKS, TUNE_GAUGE_FORCE_LINKS, TUNE_DSLASH_STREAM = 0, 1, 2, 3, 4
 LINK_FULL, LINK_ROWS2, LINK_ROWCOL = 18, 12, 10
 
 

@@ -2,7 +2,8 @@
 
 On SU(3) fields the kernels read a compact form of each link: rows 0 and 1
 (row 2 rebuilt as conj(row0 x row1)), or row 0 and column 2 (u10, u11 from
-orthogonality and det = 1, exact reads where |u02| is close to 1); on any
+orthogonality and det = 1, exact reads where |u02| is close to 1), with or
+without non-temporal hints on those loads and the output stores; on any
 other field they read all nine entries.  Every form must reproduce the
 oracle, and the library must use a compact form only when every link is
 SU(3) to rounding.
@@ -119,13 +120,15 @@ def test_two_row_and_full_forms_agree(H, L):
 FORM_L = [(6, 4, 4, 8), (8, 6, 4, 6)]
 
 
-def set_forms(H, path, L, hop, staple):
+def set_forms(H, path, L, hop, staple, stream):
     ext = " ".join(map(str, L))
-    lines = [f"dslash_links {ext} {p} {hop} 0" for p in range(4)] + [f"gauge_force_links {ext} 0 {staple} 0"]
+    lines = ([f"dslash_links {ext} {p} {hop} 0" for p in range(4)] +
+             [f"dslash_stream {ext} {p} {stream} 0" for p in range(4)] + [f"gauge_force_links {ext} 0 {staple} 0"])
     path.write_text("\n".join(lines) + "\n")
     H.hmc_tune_load(str(path))
     for p in range(4):
         assert H.hmc_tune_query(L, H.TUNE_DSLASH_LINKS, p) == (hop, True)
+        assert H.hmc_tune_query(L, H.TUNE_DSLASH_STREAM, p) == (stream, True)
     assert H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE_LINKS) == (staple, True)
 
 
@@ -162,8 +165,9 @@ def test_compact_forms_match_oracle(H, tmp_path, L, field):
     want_ff = P - 0.37 * O.fermion_force(L, U, 0.13 ** 2, X, Y)
     want_gf = P - 0.3 * O.gauge_force(L, U, beta)
     want_plaq = O.plaquette(L, U)
-    for hop, staple in ((12, 10), (10, 12), (10, 10)):
-        set_forms(H, tmp_path / f"f{hop}_{staple}.txt", L, hop, staple)
+    # (hop form, staple form, streamed hop kernels)
+    for hop, staple, stream in ((12, 10, 0), (10, 12, 1), (12, 12, 1), (10, 10, 0)):
+        set_forms(H, tmp_path / f"f{hop}_{staple}_{stream}.txt", L, hop, staple, stream)
         F = H.Fields(L, beta, k, flags=H.FIELDS_LOWPREC)
         put_gauge(H, F, U)
         assert H.hmc_links_two_row(F)
@@ -171,12 +175,12 @@ def test_compact_forms_match_oracle(H, tmp_path, L, field):
             b = put_spinor(H, F, psi, 1 - par)
             out = F.spinor()
             H.hmc_wilson_dslash(F, out, b, par, dag)
-            assert rel(get_spinor(H, F, out, par), want) < 1e-14, (hop, par, dag)
+            assert rel(get_spinor(H, F, out, par), want) < 1e-14, (hop, stream, par, dag)
         for prec, tol in ((1, 1e-6), (2, 3e-3), (3, 2e-2)):
             bl = put_spinor(H, F, psi, 1, prec=prec)
             ol = F.spinor(prec=prec)
             H.hmc_wilson_dslash(F, ol, bl, 0, 0, prec)
-            assert rel(get_spinor(H, F, ol, 0, prec=prec), want_ds[(0, 0)]) < tol, (hop, prec)
+            assert rel(get_spinor(H, F, ol, 0, prec=prec), want_ds[(0, 0)]) < tol, (hop, stream, prec)
         put_momenta(H, F, P)
         H.hmc_fermion_force_bilinear(F, put_spinor(H, F, Xe, 0), put_spinor(H, F, Ye, 0), 0.13, 0.37)
         assert rel(get_momenta(H, F), want_ff) < 1e-13, hop

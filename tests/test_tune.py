@@ -68,4 +68,19 @@ def test_link_form_entries(H, tmp_path):
     assert H.hmc_tune_query((64, 64, 64, 64), H.TUNE_DSLASH_LINKS, H.F64) == (H.LINK_ROWCOL, False)
     assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_GAUGE_FORCE_LINKS) == (H.LINK_ROWCOL, False)
     with pytest.raises(H.HmcError):
-        H.hmc_tune_query((6, 4, 2, 10), 4, H.F64)  # no such kind
+        H.hmc_tune_query((6, 4, 2, 10), 5, H.F64)  # no such kind
+
+
+def test_stream_entries(H, tmp_path):
+    if os.environ.get("HMC_LINK_STREAM"):
+        pytest.skip("environment overrides the table")
+    src = tmp_path / "stream.txt"
+    src.write_text("dslash_stream 6 4 4 10 0 1 80.0\n"
+                   "dslash_stream 6 4 4 10 1 0 40.0\n"
+                   "dslash_stream 6 4 4 10 2 2 1.0\n")   # not 0/1: ignored
+    assert H.hmc_tune_load(str(src)) == 2
+    assert H.hmc_tune_query((6, 4, 4, 10), H.TUNE_DSLASH_STREAM, H.F64) == (1, True)
+    assert H.hmc_tune_query((6, 4, 4, 10), H.TUNE_DSLASH_STREAM, H.F32) == (0, True)
+    # rule: streaming from 2^20 half-lattice sites
+    assert H.hmc_tune_query((6, 4, 4, 10), H.TUNE_DSLASH_STREAM, H.F16) == (0, False)
+    assert H.hmc_tune_query((64, 64, 64, 64), H.TUNE_DSLASH_STREAM, H.BF16) == (1, False)
