@@ -41,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 METRIC = "HMC s/traj @16^3x32; Dslash HBM GB/s; mixed vs FP64 CG; solve p50/p99"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_traffic.json")
 
@@ -263,10 +264,16 @@ def run_dslash(args, H, torch):
         rf = timed_kernel_roofline(H, "dslash")
         res[name] = {"avg_ms": rf["avg_ms"], "GBps": rf["achieved"], "frac": rf["achieved"] / HBM_PEAK_GBS,
                      "wall_ms": 1e3 * wall, "bytes_per_launch": rf["bytes_per_launch"]}
-    # other field kernels (FP64)
-    for name, fn, kern in (
-            ("gauge_force", lambda: H.hmc_gauge_force(F, 1e-3), "gauge_force"),
-            ("exp_update", lambda: H.hmc_exp_update_reunit(F, 1e-3), "exp_update")):
+    # other field kernels (FP64); flops per site (all four links) are the
+    # approximate counts of the kernels' arithmetic, for the FP64 fraction
+    # of the kernels near the ridge
+    V = 2 * synth_vh(L)
+    for name, fn, kern, flops_site in (
+            ("gauge_force", lambda: H.hmc_gauge_force(F, 1e-3), "gauge_force", 11500),
+            ("exp_update", lambda: H.hmc_exp_update_reunit(F, 1e-3), "exp_update", 2800),
+            ("plaquette", lambda: H.hmc_plaquette(F), "plaquette", 3600),
+            ("norm2", lambda: H.hmc_norm2(F, inp[H.F64], 1), "reduce", None),
+            ("inner", lambda: H.hmc_inner(F, inp[H.F64], outb[H.F64], 1), "reduce", None)):
         H.hmc_refresh(F, 5, 0, H.REFRESH_MOM)
         fn()
         torch.cuda.synchronize()
@@ -278,6 +285,9 @@ def run_dslash(args, H, torch):
         H.hmc_timing_enable(0)
         rf = timed_kernel_roofline(H, kern)
         res[name] = {"avg_ms": rf["avg_ms"], "GBps": rf["achieved"], "frac": rf["achieved"] / HBM_PEAK_GBS}
+        if flops_site:
+            tf = flops_site * V / (rf["avg_ms"] * 1e-3) / 1e12
+            res[name].update({"TFLOPs_approx": tf, "fp64_frac_approx": tf / FP64_PEAK_TFLOPS})
     best = res["f64"]
     out = {
         "metric": METRIC, "value": best["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -292,6 +302,43 @@ def run_dslash(args, H, torch):
                      "avg_launch_ms": best["avg_ms"]},
     }
     return out
+
+
+# ------------------------------------------------------------------- triad
+
+
+def run_triad(args, H, torch):
+    """STREAM triad a = b + s c over three 2 GiB FP64 arrays with the
+    library's kernel, with and without non-temporal hints: the attainable
+    streaming rate for 16-byte lanes."""
+    n = (2 << 30) // 8
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 0.5, dtype=torch.float64, device="cuda")
+    a = torch.empty_like(b)
+    st = torch.cuda.current_stream()
+    res = {}
+    for nt in (False, True):
+        for _ in range(args.warmup):
+            H.hmc_stream_triad(a, b, c, 3.0, nt, stream=st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(args.steps):
+            H.hmc_stream_triad(a, b, c, 3.0, nt, stream=st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res["nontemporal" if nt else "plain"] = {"avg_ms": ms, "GBps": 3 * 8 * n / (ms * 1e-3) / 1e9}
+    assert float(a[12345]) == 2.5 and float(a[-1]) == 2.5
+    best = max(res.values(), key=lambda r: r["GBps"])
+    return {"metric": METRIC, "value": best["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": best["avg_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "stream_triad_3x2GiB", "bytes_per_launch": 3 * 8 * n, "parallelism": "1 GPU"},
+            "kernels": res,
+            "roofline": {"bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": best["GBps"] / HBM_PEAK_GBS, "traffic": None, "kernel": "k_triad",
+                         "avg_launch_ms": best["avg_ms"]}}
 
 
 # ------------------------------------------------------------------- copy
@@ -508,7 +555,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="hmc", choices=["hmc", "mts", "dslash", "cg", "serve", "copy"])
+    ap.add_argument("--workload", default="hmc", choices=["hmc", "mts", "dslash", "cg", "serve", "copy", "triad"])
     ap.add_argument("--rho", type=float, default=0.9, help="serve: offered load relative to FP64 FIFO capacity")
     ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
     ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
@@ -529,7 +576,8 @@ def main():
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
-    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (16, 1), "serve": (64, 0), "copy": (20, 2), "mts": (5, 1)}[args.workload]
+    defaults = {"hmc": (5, 1), "dslash": (50, 5), "cg": (16, 1), "serve": (64, 0), "copy": (20, 2), "mts": (5, 1),
+                "triad": (20, 2)}[args.workload]
     args.steps = args.steps if args.steps is not None else defaults[0]
     args.warmup = args.warmup if args.warmup is not None else defaults[1]
 
@@ -553,6 +601,8 @@ def main():
         out = run_serve(args, H, torch)
     elif args.workload == "copy":
         out = run_copy(args, H, torch)
+    elif args.workload == "triad":
+        out = run_triad(args, H, torch)
     elif args.workload == "mts":
         out = run_mts(args, H, torch)
     else:

@@ -343,6 +343,14 @@ typedef struct {
 hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_traj_params* params,
                           hmc_traj_result* result, void* stream);
 
+/* STREAM triad a = b + s c over n doubles (n even; device buffers, 16-byte
+ * aligned, a distinct from b and c), with non-temporal loads and stores
+ * when nontemporal != 0: the attainable streaming rate for the access
+ * pattern of the field kernels (16-byte lanes), against which their
+ * bandwidth is read.  Asynchronous on the stream. */
+hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uint64_t n, int32_t nontemporal,
+                            void* stream);
+
 /* ---- Launch auto-tuning (the auto-tuner of Sec. 4, for the launch shapes
  * and link forms this library offers).  Kinds: HMC_TUNE_DSLASH (choice 1 =
  * one site per work-item, 2 / 4 = direction split with that many wavefronts

@@ -123,6 +123,32 @@ __global__ void k_axpby(Lat g, double a, const double2* x, double b, double2* y)
   }
 }
 
+// STREAM triad a = b + s c over n2 double2 elements, four per work-item
+// (all loads before the stores), optionally with non-temporal hints: the
+// attainable streaming rate of this chip for the access pattern of the
+// field kernels (16-byte lanes, contiguous waves).
+template <bool NT>
+__global__ void __launch_bounds__(kBlock) k_triad(void* a, const void* b, const void* c, double sc, size_t n2) {
+  constexpr int U = 4;
+  const size_t step = (size_t)gridDim.x * kBlock;
+  for (size_t j0 = (size_t)blockIdx.x * kBlock + threadIdx.x; j0 < n2; j0 += step * U) {
+    v2d x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t j = j0 + u * step;
+      if (j < n2) {
+        x[u] = gld_link<v2d, NT>((const char*)b + j * 16, 0);
+        y[u] = gld_link<v2d, NT>((const char*)c + j * 16, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t j = j0 + u * step;
+      if (j < n2) gput<NT>((char*)a + j * 16, 0, v2d{fma(sc, y[u].x, x[u].x), fma(sc, y[u].y, x[u].y)});
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_xmy_norm(Lat g, const double2* b, const double2* q, double2* r,
                                                     double* part) {
   double v[1] = {0.0};
@@ -376,9 +402,20 @@ __global__ void k_add_low_to_f64(Lat g, double2* x64, float2* x32) {
 
 // ------------------------------------------------------------ launchers
 
+hipError_t launch_triad(void* a, const void* b, const void* c, double sc, size_t n2, bool nt, hipStream_t st) {
+  TimedScope ts(TK_OTHER, st, 48.0 * n2);
+  const int nb = (int)std::min<size_t>((n2 + 4 * kBlock - 1) / (4 * kBlock), 65536);
+  if (nt)
+    hipLaunchKernelGGL(k_triad<true>, dim3(nb), dim3(kBlock), 0, st, a, b, c, sc, n2);
+  else
+    hipLaunchKernelGGL(k_triad<false>, dim3(nb), dim3(kBlock), 0, st, a, b, c, sc, n2);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm2_partials(const LatArg& g, hmc_prec prec, const void* x, double* part, int nb,
                                  hipStream_t st) {
-  TimedScope ts(TK_REDUCE, st, 0);
+  const double kb[4] = {SpF64::kBytes, SpF32::kBytes, SpF16::kBytes, SpBF16::kBytes};
+  TimedScope ts(TK_REDUCE, st, kb[prec] * g.Vh);
   switch (prec) {
     case HMC_F64: hipLaunchKernelGGL(k_norm2_partials<SpF64>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
     case HMC_F32: hipLaunchKernelGGL(k_norm2_partials<SpF32>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
@@ -390,7 +427,7 @@ hipError_t launch_norm2_partials(const LatArg& g, hmc_prec prec, const void* x, 
 
 hipError_t launch_inner_partials(const LatArg& g, const void* a, const void* b, double* part, int nb,
                                  hipStream_t st) {
-  TimedScope ts(TK_REDUCE, st, 0);
+  TimedScope ts(TK_REDUCE, st, 2.0 * SpF64::kBytes * g.Vh);
   hipLaunchKernelGGL(k_inner_partials, dim3(nb), dim3(kBlock), 0, st, to_lat(g), (const double2*)a,
                      (const double2*)b, part);
   return hipGetLastError();

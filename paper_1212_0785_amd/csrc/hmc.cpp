@@ -1349,6 +1349,16 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
   return HMC_OK;
 }
 
+hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uint64_t n, int32_t nontemporal,
+                            void* stream) {
+  HMC_REQUIRE(a && b && c, "null buffer");
+  HMC_REQUIRE(n % 2 == 0, "n = %llu must be even", (unsigned long long)n);
+  HMC_REQUIRE(((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) % 16 == 0, "buffers must be 16-byte aligned");
+  if (n == 0) return HMC_OK;
+  HMC_CHECK_HIP(launch_triad(a, b, c, s, n / 2, nontemporal != 0, ST(stream)));
+  return HMC_OK;
+}
+
 hmc_status hmc_tune_load(const char* path, int32_t* n_entries) {
   HMC_REQUIRE(path, "null path");
   const int n = tune_load(path);

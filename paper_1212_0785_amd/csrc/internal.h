@@ -181,6 +181,8 @@ hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, in
 // state[k].stop_at = INT_MAX, reason = 0; iters kept unless reset_iters;
 // maxrr from maxrr[k] (may be null -> 0).
 hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, hipStream_t st);
+// STREAM triad a = b + sc * c over n2 double2 elements (nt: non-temporal).
+hipError_t launch_triad(void* a, const void* b, const void* c, double sc, size_t n2, bool nt, hipStream_t st);
 hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st);  // x += xl; xl = 0
 
 // Gauge-field kernels.

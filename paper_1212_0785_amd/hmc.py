@@ -131,6 +131,7 @@ _SIGNATURES = {
     "hmc_convert_spinor": (_I32, [_P, _P, _I32, _P, _I32, _P]),
     "hmc_sync_lowprec": (_I32, [_P, _P]),
     "hmc_links_two_row": (_I32, [_P, _P]),
+    "hmc_stream_triad": (_I32, [_P, _P, _P, C.c_double, C.c_uint64, C.c_int32, _P]),
     "hmc_wilson_dslash": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P]),
     "hmc_mhat": (_I32, [_P, _P, _P, _I32, _I32, _P]),
     "hmc_wilson_m": (_I32, [_P, _P, _P, _I32, _P]),
@@ -327,6 +328,14 @@ def hmc_convert_spinor(f, dst, dst_prec, src, src_prec, stream=None):
 
 def hmc_sync_lowprec(f, stream=None):
     check(lib().hmc_sync_lowprec(_h(f), _stream(stream)))
+
+
+def hmc_stream_triad(a, b, c, s, nontemporal=False, stream=None):
+    """a = b + s c over float64 device tensors of one size."""
+    n = a.numel()
+    assert b.numel() == n and c.numel() == n
+    check(lib().hmc_stream_triad(_ptr(a), _ptr(b), _ptr(c), float(s), int(n), int(bool(nontemporal)),
+                                 _stream(stream)))
 
 
 def hmc_links_two_row(f) -> bool:

@@ -83,6 +83,16 @@ def test_null_arguments_rejected(H):
     assert H.lib().hmc_plaquette(None, None, None) == H.HMC_E_ARG
 
 
+def test_triad_argument_errors(H):
+    lib = H.lib()
+    # checked before any device work: odd length, misaligned or null buffers
+    assert lib.hmc_stream_triad(4096, 8192, 12288, 1.0, 3, 0, None) == H.HMC_E_ARG
+    assert lib.hmc_stream_triad(4096, 8200, 12288, 1.0, 4, 0, None) == H.HMC_E_ARG
+    assert lib.hmc_stream_triad(None, 8192, 12288, 1.0, 4, 0, None) == H.HMC_E_ARG
+    assert "even" in H.last_error() or "null" in H.last_error()
+    assert lib.hmc_stream_triad(4096, 8192, 12288, 1.0, 0, 1, None) == H.HMC_OK  # empty: no launch
+
+
 def test_bench_refuses_more_than_one_gpu():
     """bench.py has no multi-GPU path: --gpus N > 1 exits 2 with a message
     (checked before anything touches a GPU)."""
