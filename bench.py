@@ -87,6 +87,29 @@ def launch_shapes(H, L, db):
     return out
 
 
+def triad_ceiling(H, torch, mib=512, reps=10):
+    """Live STREAM-triad rate (GB/s, best of plain and non-temporal) over
+    three arrays of `mib` MiB: the attainable streaming rate the roofline
+    fraction is also read against."""
+    n = mib * (1 << 20) // 8
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.ones(n, dtype=torch.float64, device="cuda")
+    a = torch.empty_like(b)
+    st = torch.cuda.current_stream()
+    best = 0.0
+    for nt in (False, True):
+        H.hmc_stream_triad(a, b, c, 2.0, nt, stream=st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            H.hmc_stream_triad(a, b, c, 2.0, nt, stream=st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        best = max(best, 3 * 8 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b, c
+    return best
+
+
 def timed_kernel_roofline(H, name="dslash", timing=None):
     t = (timing if timing is not None else H.hmc_timing_read()).get(name)
     if not t or not t["launches"]:
@@ -615,6 +638,8 @@ def main():
     if "config" in out and "lattice" in out["config"]:
         out["config"]["launch_shapes"] = launch_shapes(H, out["config"]["lattice"], args.tune_db)
         if args.workload in ("hmc", "dslash") and "roofline" in out:
+            tri = triad_ceiling(H, torch)
+            out["roofline"]["attainable"] = {"triad_GBps": tri, "frac": out["roofline"]["achieved"] / tri}
             out["roofline"]["dslash_shape"] = out["config"]["launch_shapes"]["dslash_f64"][0]
             out["roofline"]["link_reals"] = out["config"]["launch_shapes"]["dslash_links_f64"][0]
             out["roofline"]["stream"] = out["config"]["launch_shapes"]["dslash_stream_f64"][0]
