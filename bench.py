@@ -80,6 +80,8 @@ def launch_shapes(H, L, db):
         out[f"dslash_links_{name}"] = [c, "table" if tuned else "rule"]
         c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_STREAM, p)
         out[f"dslash_stream_{name}"] = [c, "table" if tuned else "rule"]
+        c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_ORDER, p)
+        out[f"dslash_order_{name}"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE)
     out["gauge_force_planes"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE_LINKS)
@@ -643,6 +645,7 @@ def main():
             out["roofline"]["dslash_shape"] = out["config"]["launch_shapes"]["dslash_f64"][0]
             out["roofline"]["link_reals"] = out["config"]["launch_shapes"]["dslash_links_f64"][0]
             out["roofline"]["stream"] = out["config"]["launch_shapes"]["dslash_stream_f64"][0]
+            out["roofline"]["tiled_order"] = out["config"]["launch_shapes"]["dslash_order_f64"][0]
     print(json.dumps(out))
 
 

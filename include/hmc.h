@@ -362,12 +362,17 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
  * same for the staple force and the plaquette; prec HMC_F64) and
  * HMC_TUNE_DSLASH_STREAM (1 = the Dslash at that storage reads its compact
  * links and writes its output with non-temporal hints; per storage
- * precision).  Decision order: environment override (HMC_DSLASH_SPLIT,
- * HMC_GFORCE_PLANES, HMC_LINK_FORM = 18 / 12 / 10, HMC_LINK_STREAM = 0 / 1)
- * > table entry for the lattice extents > built-in rule.  HMC_TUNE_DB names a table file read on first use.  Table
+ * precision) and HMC_TUNE_DSLASH_ORDER (1 = the one-site-per-work-item
+ * Dslash walks each XCD's t-slices z-plane by z-plane, t-slice by t-slice,
+ * so neighbour spinors are reused in that XCD's L2; lattices with
+ * L0 L1 / 2 a multiple of 64, L3 a multiple of 8 and Vh a multiple of
+ * 2048; per storage precision).  Decision order: environment override
+ * (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES, HMC_LINK_FORM = 18 / 12 / 10,
+ * HMC_LINK_STREAM = 0 / 1, HMC_DSLASH_ORDER = 0 / 1) > table entry for the
+ * lattice extents > built-in rule.  HMC_TUNE_DB names a table file read on first use.  Table
  * file: text lines "kind L0 L1 L2 L3 prec choice us" with kind dslash,
- * gauge_force, dslash_links, gauge_force_links or dslash_stream ('#' lines
- * and malformed lines are ignored).  Shapes are fixed per solve (and per service request)
+ * gauge_force, dslash_links, gauge_force_links, dslash_stream or
+ * dslash_order ('#' lines and malformed lines are ignored).  Shapes are fixed per solve (and per service request)
  * when it starts; do not tune while solves or a service run on the same
  * lattice extents. */
 typedef enum {
@@ -375,11 +380,12 @@ typedef enum {
   HMC_TUNE_GAUGE_FORCE = 1,
   HMC_TUNE_DSLASH_LINKS = 2,
   HMC_TUNE_GAUGE_FORCE_LINKS = 3,
-  HMC_TUNE_DSLASH_STREAM = 4
+  HMC_TUNE_DSLASH_STREAM = 4,
+  HMC_TUNE_DSLASH_ORDER = 5
 } hmc_tune_kind;
 /* Times every candidate on f's lattice and stores the fastest in the
  * table: for each storage precision the Dslash shape x link form pairs
- * (then streaming on and off for the best pair)
+ * (then streaming and the tiled order on and off for the best pair)
  * where it runs, inside a solve (CG on Mhat^dag Mhat from Gaussian noise to
  * 1e-10 or 100 iterations: FP64 CG, and with HMC_FIELDS_LOWPREC
  * mixed-precision CG with that storage inside; "us" = microseconds per

@@ -17,13 +17,6 @@
 
 namespace hmc {
 
-static Lat to_lat(const LatArg& a) {
-  Lat g;
-  for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
-  g.Vh = a.Vh;
-  g.stride = a.stride;
-  return g;
-}
 
 // ------------------------------------------------------------- sums
 

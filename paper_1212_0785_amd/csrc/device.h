@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.h"
+
 namespace hmc {
 
 // Global-memory pointer qualifier: field pointers read from argument structs
@@ -362,7 +364,20 @@ struct Lat {
   int L[4];
   int Vh;      // sites per parity
   int stride;  // elements between successive components of a field (= Vh)
+  // Tiled site order of the one-site-per-work-item Dslash (tiled = 0: the
+  // linear order with XCD-contiguous ranges): checkerboard sites per z-plane
+  // and per t-slice, 64-site chunks per z-plane, t-slices per XCD.
+  int tiled, plane, slice, tile_r, tile_t;
 };
+
+inline Lat to_lat(const LatArg& a) {
+  Lat g;
+  for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
+  g.Vh = a.Vh;
+  g.stride = a.stride;
+  g.tiled = g.plane = g.slice = g.tile_r = g.tile_t = 0;
+  return g;
+}
 
 struct Site {
   int c[4];
@@ -421,6 +436,30 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   int q = nb / X, r = nb % X;
   int xcd = b % X, k = b / X;
   return xcd * q + min(xcd, r) + k;
+}
+
+// Output site of this work-item in a one-site-per-work-item launch of
+// 256-site blocks; *part gets the block's partial-sum slot.  Linear order:
+// block b covers sites 256 b .. 256 b + 255, XCD-contiguous (xcd_remap).
+// Tiled order: XCD x (blocks with blockIdx.x % 8 == x) owns the t-slices
+// [x tile_t, (x + 1) tile_t) and walks its wavefronts z-plane by z-plane,
+// within a plane t-slice by t-slice, within a (z, t) row of the x-y plane
+// 64 sites at a time; the +-t neighbours of a site are then one row of
+// chunks away and the +-z neighbours tile_t rows away, both still in the
+// XCD's L2, where the linear order has the t neighbours a whole t-slice
+// (tens of MB of traffic) away.
+__device__ __forceinline__ int dslash_site(const Lat& g, int* part) {
+  if (g.tiled) {
+    const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+    const int w = k * 4 + (threadIdx.x >> 6);  // wavefront of this XCD, in walk order
+    const int r = w % g.tile_r, q = w / g.tile_r;
+    const int t = xcd * g.tile_t + q % g.tile_t, z = q / g.tile_t;
+    *part = blockIdx.x;
+    return t * g.slice + z * g.plane + r * 64 + (threadIdx.x & 63);
+  }
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  *part = b;
+  return b * kBlock + threadIdx.x;
 }
 
 // ------------------------------------------------------ storage formats

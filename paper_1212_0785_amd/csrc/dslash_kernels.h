@@ -118,8 +118,8 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
   const int label = e.iter0 + j;
   if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
   alpha_prologue(e, label);
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = b * kBlock + threadIdx.x;
+  int b;
+  const int s = dslash_site(g, &b);
   double nrm[1] = {0.0};
   if (s < g.Vh) {
     const Site st = cb_site(g, out_par, s);
@@ -286,16 +286,26 @@ template <class SP, class LK>
 static hipError_t launch_typed(hmc_prec prec, int dagger, int epi, const LatArg& ga, int out_par,
                                const DslashArgs* table, int nbatch, const DslashArgs& one, hipStream_t st, int j,
                                KernelEvents ev) {
-  Lat g;
-  for (int k = 0; k < 4; ++k) g.L[k] = ga.L[k];
-  g.Vh = ga.Vh;
-  g.stride = ga.stride;
+  Lat g = to_lat(ga);
   const int shape = one.shape ? one.shape : dslash_shape(ga, prec);
+  if (shape == 1 && dslash_tiled_order(ga, prec)) {
+    g.tiled = 1;
+    g.plane = ga.L[0] * ga.L[1] / 2;
+    g.slice = g.plane * ga.L[2];
+    g.tile_r = g.plane / 64;
+    g.tile_t = ga.L[3] / 8;
+  }
   const int ways = shape == 1 ? 0 : shape;
   const dim3 grid(dslash_shape_blocks(ga.Vh, shape), nbatch);
   const dim3 block(ways ? 64 * ways : kBlock);
+  // The tiled order reserves LDS it does not use: 54,000 bytes per block
+  // leave room for two blocks per CU (2 wavefronts per SIMD), so an XCD's
+  // wavefronts in flight span a few (z, t) rows instead of dozens and the
+  // neighbours they share are still in its L2 (measured at 48^3x96: 1.36 ms
+  // without the cap, 1.25 ms with it, 1.30 ms for the linear order).
+  const size_t lds_cap = g.tiled ? 54000 : 0;
 #define HMC_LAUNCH(KERNEL) \
-  hipExtLaunchKernelGGL(KERNEL, grid, block, 0, st, ev.start, ev.stop, 0, g, out_par, table, one, j)
+  hipExtLaunchKernelGGL(KERNEL, grid, block, lds_cap, st, ev.start, ev.stop, 0, g, out_par, table, one, j)
 #define HMC_DS_B(D, E, B)                                  \
   do {                                                     \
     if (ways == 4)                                         \

@@ -39,7 +39,14 @@ inline int site_blocks(int Vh) { return ceil_div(Vh, kThreads); }
 // work-item, 1 = plane split.  Link form: the reals read per link (LinkForm).
 // Each is decided by the environment override, else the tuning table, else
 // the built-in rule.
-enum TuneKind { TUNE_DSLASH = 0, TUNE_GFORCE = 1, TUNE_DSLASH_LINKS = 2, TUNE_GFORCE_LINKS = 3, TUNE_DSLASH_STREAM = 4 };
+enum TuneKind {
+  TUNE_DSLASH = 0,
+  TUNE_GFORCE = 1,
+  TUNE_DSLASH_LINKS = 2,
+  TUNE_GFORCE_LINKS = 3,
+  TUNE_DSLASH_STREAM = 4,
+  TUNE_DSLASH_ORDER = 5
+};
 // All nine entries; rows 0 and 1 (LkRows2); row 0 and column 2 (LkRowCol).
 // The compact forms need SU(3) links.
 enum LinkForm { LINK_FULL = 18, LINK_ROWS2 = 12, LINK_ROWCOL = 10 };
@@ -54,6 +61,15 @@ int staple_link_form(const LatArg& g);
 // from displacing the neighbour spinors in L2 (pays at large volumes) but
 // also from the last-level cache (costs where the fields fit in it).
 bool dslash_link_stream(const LatArg& g, hmc_prec prec);
+// Whether the one-site-per-work-item Dslash walks its sites in the tiled
+// order (dslash_site in device.h), and whether the lattice admits it: whole
+// 256-site blocks, a multiple of 8 of them, 64-site chunks per z-plane and
+// a multiple of 8 t-slices.
+bool dslash_tiled_order(const LatArg& g, hmc_prec prec);
+inline bool tiled_order_valid(const LatArg& g) {
+  const int plane = g.L[0] * g.L[1] / 2;
+  return g.Vh % kThreads == 0 && (g.Vh / kThreads) % 8 == 0 && plane % 64 == 0 && g.L[3] % 8 == 0;
+}
 // The form a kernel reads: the compact one on SU(3) links, else all entries.
 inline int link_form_for(bool su3, int compact) { return su3 ? compact : (int)LINK_FULL; }
 inline int dslash_shape_blocks(int Vh, int shape) { return shape == 1 ? site_blocks(Vh) : ceil_div(Vh, kThreads / 4); }
@@ -65,8 +81,8 @@ int tune_lookup(const int* L, int kind, int prec);
 void tune_store(const int* L, int kind, int prec, int choice, double us);
 int tune_load(const char* path);
 int tune_save(const char* path);
-// True when HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES, HMC_LINK_FORM or
-// HMC_LINK_STREAM forces a decision.
+// True when HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES, HMC_LINK_FORM,
+// HMC_LINK_STREAM or HMC_DSLASH_ORDER forces a decision.
 bool tune_env_forced();
 
 // Iteration control of the Krylov solvers, resident in device memory.

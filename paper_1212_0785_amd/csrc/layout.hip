@@ -10,13 +10,6 @@
 
 namespace hmc {
 
-static Lat to_lat(const LatArg& a) {
-  Lat g;
-  for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
-  g.Vh = a.Vh;
-  g.stride = a.stride;
-  return g;
-}
 
 __global__ void k_pack_gauge(Lat g, const double2* canon, double2* U) {
   int i = blockIdx.x * kBlock + threadIdx.x;

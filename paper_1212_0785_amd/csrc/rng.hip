@@ -9,13 +9,6 @@
 
 namespace hmc {
 
-static Lat to_lat(const LatArg& a) {
-  Lat g;
-  for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
-  g.Vh = a.Vh;
-  g.stride = a.stride;
-  return g;
-}
 
 enum { ST_WEAKFIELD = 0, ST_MOMENTA = 1, ST_ETA = 2, ST_ACCEPT = 3, ST_SOURCE = 4, ST_ETA2 = 5 };
 

@@ -46,8 +46,9 @@ Table& table() {
 
 Key make_key(const int* L, int kind, int prec) { return Key(L[0], L[1], L[2], L[3], kind, prec); }
 
-const char* const kKindNames[] = {"dslash", "gauge_force", "dslash_links", "gauge_force_links", "dslash_stream"};
-constexpr int kNumKinds = 5;
+const char* const kKindNames[] = {"dslash", "gauge_force", "dslash_links", "gauge_force_links", "dslash_stream",
+                                  "dslash_order"};
+constexpr int kNumKinds = 6;
 
 const char* kind_name(int kind) { return kKindNames[kind]; }
 
@@ -61,7 +62,8 @@ bool valid_choice(int kind, int c) {
   switch (kind) {
     case TUNE_DSLASH: return c == 1 || c == 2 || c == 4;
     case TUNE_GFORCE:
-    case TUNE_DSLASH_STREAM: return c == 0 || c == 1;
+    case TUNE_DSLASH_STREAM:
+    case TUNE_DSLASH_ORDER: return c == 0 || c == 1;
     default: return c == LINK_ROWS2 || c == LINK_ROWCOL;
   }
 }
@@ -140,7 +142,8 @@ int tune_save(const char* path) {
                "# dslash: choice 1 = one site per work-item, 2|4 = direction split; us per CG iteration in a solve\n"
                "# gauge_force: choice 0 = one link per work-item, 1 = plane split; us per launch\n"
                "# dslash_links, gauge_force_links: reals read per SU(3) link, 12 = two rows, 10 = row 0 and column 2\n"
-               "# dslash_stream: 1 = non-temporal link loads and output stores\n");
+               "# dslash_stream: 1 = non-temporal link loads and output stores\n"
+               "# dslash_order: 1 = tiled site order (one site per work-item shape)\n");
   for (const auto& kv : merged) {
     const Key& k = kv.first;
     std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", kind_name(std::get<4>(k)), std::get<0>(k), std::get<1>(k),
@@ -152,7 +155,7 @@ int tune_save(const char* path) {
 
 bool tune_env_forced() {
   return env_int("HMC_DSLASH_SPLIT") >= 0 || env_int("HMC_GFORCE_PLANES") >= 0 || env_int("HMC_LINK_FORM") >= 0 ||
-         env_int("HMC_LINK_STREAM") >= 0;
+         env_int("HMC_LINK_STREAM") >= 0 || env_int("HMC_DSLASH_ORDER") >= 0;
 }
 
 namespace {
@@ -183,6 +186,15 @@ bool dslash_link_stream(const LatArg& g, hmc_prec prec) {
   // measured on MI355X: 17% faster FP64 Dslash at 48^3x96, 30% slower at
   // 16^3x32, whose fields stay in the last-level cache between launches
   return g.Vh >= (1 << 20);
+}
+
+bool dslash_tiled_order(const LatArg& g, hmc_prec prec) {
+  if (!tiled_order_valid(g)) return false;
+  static const int forced = env_int("HMC_DSLASH_ORDER");
+  if (forced >= 0) return forced != 0;
+  const int t = tune_lookup(g.L, TUNE_DSLASH_ORDER, prec);
+  if (t >= 0) return t != 0;
+  return false;
 }
 
 int staple_link_form(const LatArg& g) {

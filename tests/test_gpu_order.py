@@ -1,0 +1,80 @@
+"""GPU: the tiled site order of the one-site-per-work-item Dslash.
+
+Only the work-item that computes a site changes, not its arithmetic, so
+every output equals the linear order's bit for bit; the partial sums of
+the norm epilogues cover other site sets, so solves agree with the oracle
+to their tolerance instead."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import synth
+from tests.test_gpu_parity import get_spinor, put_gauge, put_spinor, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# extents that admit the tiled order and that no other test uses (their
+# table entries leave the other tests' lattices alone)
+ORDER_L = [(16, 8, 4, 8), (16, 16, 4, 16)]
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1212_0785_amd import hmc
+    hmc.lib()
+    return hmc
+
+
+def set_order(H, path, L, order):
+    ext = " ".join(map(str, L))
+    lines = [f"dslash {ext} {p} 1 0" for p in range(4)] + [f"dslash_order {ext} {p} {order} 0" for p in range(4)]
+    path.write_text("\n".join(lines) + "\n")
+    H.hmc_tune_load(str(path))
+    for p in range(4):
+        assert H.hmc_tune_query(L, H.TUNE_DSLASH, p) == (1, True)
+        assert H.hmc_tune_query(L, H.TUNE_DSLASH_ORDER, p) == (order, True)
+
+
+@pytest.mark.parametrize("L", ORDER_L)
+def test_tiled_order_bit_identical_and_oracle(H, tmp_path, L):
+    U = synth.gauge_field(61, L, eps=0.5)
+    psi = synth.spinor(62, L)
+    outs = {}
+    for order in (0, 1):
+        set_order(H, tmp_path / f"o{order}.txt", L, order)
+        F = H.Fields(L, 5.6, 0.15, flags=H.FIELDS_LOWPREC)
+        put_gauge(H, F, U)
+        for prec in range(4):
+            for par in (0, 1):
+                for dag in (0, 1):
+                    b = put_spinor(H, F, psi, 1 - par, prec=prec)
+                    out = F.spinor(prec=prec)
+                    H.hmc_wilson_dslash(F, out, b, par, dag, prec)
+                    outs[(order, prec, par, dag)] = out.clone()
+                    if prec == 0 and order == 1:
+                        want = O.dslash(L, U, psi, par, dag)
+                        assert rel(get_spinor(H, F, out, par), want) < 1e-14
+        del F
+    for key in [k for k in outs if k[0] == 0]:
+        assert torch.equal(outs[key], outs[(1,) + key[1:]]), key
+
+
+@pytest.mark.parametrize("L", ORDER_L)
+def test_tiled_order_solves(H, tmp_path, L):
+    k = 0.15
+    set_order(H, tmp_path / "o1.txt", L, 1)
+    F = H.Fields(L, 5.6, k, flags=H.FIELDS_LOWPREC)
+    U = synth.gauge_field(63, L, eps=0.5)
+    put_gauge(H, F, U)
+    odd = O.parity_mask(L)
+    b = synth.spinor(64, L, odd, 0)
+    want, _ = O.cg_mhat(L, U, k, b, tol=1e-12)
+    bb = put_spinor(H, F, b, 0)
+    for prec in (0, 1, 2):
+        x = F.spinor()
+        st = H.hmc_cg_solve(F, x, bb, H.cg_params(tol=1e-10, prec=prec, maxiter=20000))
+        assert st["status"] == 0 and st["true_rel_res"] <= 1e-10, prec
+        assert rel(get_spinor(H, F, x, 0), want) < 1e-8, prec

@@ -68,7 +68,7 @@ def test_link_form_entries(H, tmp_path):
     assert H.hmc_tune_query((64, 64, 64, 64), H.TUNE_DSLASH_LINKS, H.F64) == (H.LINK_ROWCOL, False)
     assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_GAUGE_FORCE_LINKS) == (H.LINK_ROWCOL, False)
     with pytest.raises(H.HmcError):
-        H.hmc_tune_query((6, 4, 2, 10), 5, H.F64)  # no such kind
+        H.hmc_tune_query((6, 4, 2, 10), 6, H.F64)  # no such kind
 
 
 def test_stream_entries(H, tmp_path):
@@ -84,3 +84,15 @@ def test_stream_entries(H, tmp_path):
     # rule: streaming from 2^20 half-lattice sites
     assert H.hmc_tune_query((6, 4, 4, 10), H.TUNE_DSLASH_STREAM, H.F16) == (0, False)
     assert H.hmc_tune_query((64, 64, 64, 64), H.TUNE_DSLASH_STREAM, H.BF16) == (1, False)
+
+
+def test_order_entries_need_an_admissible_lattice(H, tmp_path):
+    if os.environ.get("HMC_DSLASH_ORDER"):
+        pytest.skip("environment overrides the table")
+    src = tmp_path / "order.txt"
+    src.write_text("dslash_order 16 8 4 8 0 1 1.0\n"     # admissible
+                   "dslash_order 6 4 4 10 0 1 1.0\n")    # 6*4/2 = 12 sites per z-plane: not a multiple of 64
+    assert H.hmc_tune_load(str(src)) == 2
+    assert H.hmc_tune_query((16, 8, 4, 8), H.TUNE_DSLASH_ORDER, H.F64) == (1, True)
+    assert H.hmc_tune_query((6, 4, 4, 10), H.TUNE_DSLASH_ORDER, H.F64) == (0, True)
+    assert H.hmc_tune_query((16, 8, 4, 8), H.TUNE_DSLASH_ORDER, H.F32) == (0, False)
