@@ -89,6 +89,20 @@ def launch_shapes(H, L, db):
     return out
 
 
+def event_floor(H, torch, n=200):
+    """Average duration an empty one-wavefront kernel shows through the
+    kernel-stamped event pair that times the sampled launches: the part of
+    a timed launch that is the events' own."""
+    H.hmc_timing_reset()
+    H.hmc_timing_enable(1)
+    H.hmc_timing_probe(n, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    t = H.hmc_timing_read().get("other")
+    H.hmc_timing_enable(0)
+    H.hmc_timing_reset()
+    return t["total_ms"] / t["launches"] if t and t["launches"] else None
+
+
 def triad_ceiling(H, torch, mib=512, reps=10):
     """Live STREAM-triad rate (GB/s, best of plain and non-temporal) over
     three arrays of `mib` MiB: the attainable streaming rate the roofline
@@ -640,6 +654,7 @@ def main():
     if "config" in out and "lattice" in out["config"]:
         out["config"]["launch_shapes"] = launch_shapes(H, out["config"]["lattice"], args.tune_db)
         if args.workload in ("hmc", "dslash") and "roofline" in out:
+            out["roofline"]["event_floor_ms"] = event_floor(H, torch)
             tri = triad_ceiling(H, torch)
             out["roofline"]["attainable"] = {"triad_GBps": tri, "frac": out["roofline"]["achieved"] / tri}
             out["roofline"]["dslash_shape"] = out["config"]["launch_shapes"]["dslash_f64"][0]

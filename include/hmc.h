@@ -529,6 +529,10 @@ typedef struct {
 hmc_status hmc_timing_enable(int32_t sample_every);
 hmc_status hmc_timing_reset(void);
 hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* n_entries);
+/* Launches n empty one-wavefront kernels through the same kernel-stamped
+ * event mechanism (family "other"): their timed duration is the floor that
+ * the event pair adds to every timed launch. */
+hmc_status hmc_timing_probe(int32_t n, void* stream);
 
 #ifdef __cplusplus
 }

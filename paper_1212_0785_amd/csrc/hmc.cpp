@@ -934,6 +934,12 @@ hmc_status hmc_timing_reset(void) {
   return HMC_OK;
 }
 
+hmc_status hmc_timing_probe(int32_t n, void* stream) {
+  HMC_REQUIRE(n >= 0, "n = %d < 0", n);
+  for (int i = 0; i < n; ++i) HMC_CHECK_HIP(launch_empty_timed(ST(stream)));
+  return HMC_OK;
+}
+
 hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* n_entries) {
   HMC_REQUIRE(n_entries, "null output");
   Timing& T = timing();

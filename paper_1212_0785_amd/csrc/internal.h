@@ -282,6 +282,9 @@ struct KernelEvents {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 KernelEvents timing_kernel_events(int kernel, double bytes);
+// An empty one-wavefront kernel launched with the event pair of the "other"
+// family (sampled like any launch).
+hipError_t launch_empty_timed(hipStream_t st);
 
 // Brackets a launch with events recorded on the stream (includes the
 // dispatch of the kernel).

@@ -170,6 +170,7 @@ _SIGNATURES = {
     "hmc_service_destroy": (_I32, [_P]),
     "hmc_timing_enable": (_I32, [_I32]),
     "hmc_timing_reset": (_I32, []),
+    "hmc_timing_probe": (_I32, [_I32, _P]),
     "hmc_timing_read": (_I32, [C.POINTER(TimingEntry), _I32, C.POINTER(_I32)]),
 }
 
@@ -524,6 +525,10 @@ def hmc_trajectory(f, seed, traj, tau, nsteps, params: CgParams, stream=None, n_
 
 def hmc_timing_enable(sample_every: int):
     check(lib().hmc_timing_enable(int(sample_every)))
+
+
+def hmc_timing_probe(n: int, stream=None):
+    check(lib().hmc_timing_probe(int(n), _stream(stream)))
 
 
 def hmc_timing_reset():
