@@ -599,8 +599,9 @@ def main():
     ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
     ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
     ap.add_argument("--sample-every", type=int, default=31,
-                    help=("time every n-th launch of each kernel kind with HIP events (31: coprime to the "
-                          "four Dslash launches of a CG iteration; each sampled launch costs the GPU a few us)"))
+                    help=("time every n-th launch of each kernel kind with HIP events (the four Dslash "
+                          "launches of a CG iteration count as one, bracketed by one event pair; each sampled "
+                          "launch costs the GPU a few us)"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kappa-h", type=float, default=0.10, help="mts: heavy hopping parameter")
     ap.add_argument("--chrono", type=int, default=0,

@@ -40,6 +40,7 @@ struct TimingRec {
   int kernel;
   int pair;
   double bytes;
+  int launches;  // launches the pair brackets (a group shares one pair)
 };
 struct Timing {
   std::mutex mu;
@@ -51,6 +52,8 @@ struct Timing {
   double ms[TK_COUNT] = {};
   double bytes[TK_COUNT] = {};
   int open_pair = -1;
+  // open group: family, launches still to come, its record (-1: unsampled)
+  int group_kernel = -1, group_left = 0, group_rec = -1;
 };
 Timing& timing() {
   static Timing t;
@@ -78,9 +81,21 @@ bool timing_begin(int kernel, hipStream_t st, double bytes) {
     T.events.push_back(e);
   }
   if (hipEventRecord(T.events[2 * pair], st) != hipSuccess) return false;
-  T.recs.push_back({kernel, pair, bytes});
+  T.recs.push_back({kernel, pair, bytes, 1});
   T.open_pair = pair;
   return true;
+}
+
+// A free event pair for a new record, or -1 (pool exhausted / HIP error).
+static int new_pair(Timing& T) {
+  const int pair = (int)T.recs.size();
+  if (pair >= kMaxPairs) return -1;
+  while ((int)T.events.size() < 2 * (pair + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    T.events.push_back(e);
+  }
+  return pair;
 }
 
 KernelEvents timing_kernel_events(int kernel, double bytes) {
@@ -88,18 +103,55 @@ KernelEvents timing_kernel_events(int kernel, double bytes) {
   Timing& T = timing();
   if (T.sample_every <= 0) return ev;
   std::lock_guard<std::mutex> lk(T.mu);
-  if (T.counter[kernel]++ % T.sample_every) return ev;
-  int pair = (int)T.recs.size();
-  if (pair >= kMaxPairs) return ev;
-  while ((int)T.events.size() < 2 * (pair + 1)) {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return ev;
-    T.events.push_back(e);
+  if (T.group_left > 0 && T.group_kernel == kernel) {  // inside a group
+    const bool first = T.group_rec == -2, last = T.group_left == 1;
+    --T.group_left;
+    if (first) {  // the group's sampling decision, on its first launch
+      T.group_rec = -1;
+      if (T.counter[kernel]++ % T.sample_every == 0) {
+        const int pair = new_pair(T);
+        if (pair >= 0) {
+          T.recs.push_back({kernel, pair, 0.0, 0});
+          T.group_rec = (int)T.recs.size() - 1;
+          ev.start = T.events[2 * pair];
+        }
+      }
+    }
+    if (T.group_rec >= 0) {
+      TimingRec& r = T.recs[T.group_rec];
+      r.bytes += bytes;
+      r.launches += 1;
+      if (last) ev.stop = T.events[2 * r.pair + 1];
+    }
+    if (last) T.group_kernel = -1;
+    return ev;
   }
-  T.recs.push_back({kernel, pair, bytes});
+  if (T.counter[kernel]++ % T.sample_every) return ev;
+  const int pair = new_pair(T);
+  if (pair < 0) return ev;
+  T.recs.push_back({kernel, pair, bytes, 1});
   ev.start = T.events[2 * pair];
   ev.stop = T.events[2 * pair + 1];
   return ev;
+}
+
+void timing_group_end() {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  // an unfinished group (a launch failed) has no stop event: drop its record
+  if (T.group_left > 0 && T.group_rec >= 0 && T.group_rec == (int)T.recs.size() - 1) T.recs.pop_back();
+  T.group_kernel = -1;
+  T.group_left = 0;
+  T.group_rec = -1;
+}
+
+void timing_group_begin(int kernel, int n) {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  if (T.sample_every <= 0 || n <= 0) return;
+  T.group_kernel = kernel;
+  T.group_left = n;
+  T.group_rec = -2;  // decided on the first launch
 }
 
 void timing_end(int kernel, hipStream_t st) {
@@ -949,7 +1001,7 @@ hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* 
     HMC_CHECK_HIP(hipEventSynchronize(b));
     float ms = 0;
     HMC_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
-    T.launches[r.kernel]++;
+    T.launches[r.kernel] += r.launches;
     T.ms[r.kernel] += ms;
     T.bytes[r.kernel] += r.bytes;
   }

@@ -282,6 +282,13 @@ struct KernelEvents {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 KernelEvents timing_kernel_events(int kernel, double bytes);
+// The next n launches of `kernel` (consecutive on one stream, nothing of
+// another family between them) form one sample: one event pair from the
+// start of the first to the end of the last, so the pair's own cost is
+// paid once for the group; their bytes and launch count add up.
+void timing_group_begin(int kernel, int n);
+// Closes the group (drops its sample if fewer than n launches happened).
+void timing_group_end();
 // An empty one-wavefront kernel launched with the event pair of the "other"
 // family (sampled like any launch).
 hipError_t launch_empty_timed(hipStream_t st);

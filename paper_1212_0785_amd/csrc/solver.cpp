@@ -101,10 +101,12 @@ hipError_t launch_iteration(const LatArg& g, hmc_prec prec, int cgls, const Iter
   auto UPD = [&](int i) { return launch_cg_update(g, prec, one.c[i], nbR, tab ? tab->c[i] : nullptr, nbatch, j, st); };
   auto PUP = [&](int i) { return launch_cg_pupdate(g, prec, one.c[i], nbR, tab ? tab->c[i] : nullptr, nbatch, j, st); };
   if (!cgls) {
-    if ((e = D(0, 1, 0, EPI_PLAIN))) return e;
-    if ((e = D(1, 0, 0, EPI_AXPY_NORM))) return e;
-    if ((e = D(2, 1, 1, EPI_PLAIN))) return e;
-    if ((e = D(3, 0, 1, EPI_CG))) return e;
+    // the four hops are consecutive: one timing sample brackets them all
+    timing_group_begin(TK_DSLASH, 4);
+    if (!(e = D(0, 1, 0, EPI_PLAIN)) && !(e = D(1, 0, 0, EPI_AXPY_NORM)) && !(e = D(2, 1, 1, EPI_PLAIN)))
+      e = D(3, 0, 1, EPI_CG);
+    timing_group_end();
+    if (e) return e;
     return PUP(1);
   }
   if ((e = D(0, 1, 0, EPI_PLAIN))) return e;
