@@ -471,6 +471,26 @@ def test_trajectory_parity_c2_short(H):
     assert rel(get_gauge(H, F), U) < 1e-12
 
 
+def test_leapfrog_reversible_at_c2(H):
+    """At the benchmark's 16^3x32 shape and launch configuration, with no
+    oracle: leapfrog over tau = 0.2 and back over -0.2 returns to the start
+    (links and momenta), the full-size check that the integrator and every
+    force kernel are time-reversible."""
+    L = (16, 16, 16, 32)
+    seed = 12120785
+    F = H.Fields(L, 5.6, 0.156)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    H.hmc_refresh(F, seed, 0)
+    U0, P0 = get_gauge(H, F), get_momenta(H, F)
+    prm = H.cg_params(tol=1e-12)
+    st = H.hmc_md_leapfrog(F, 0.2, 4, prm)
+    U1 = get_gauge(H, F)
+    assert st["solves"] == 5 and rel(U1, U0) > 1e-3
+    H.hmc_md_leapfrog(F, -0.2, 4, prm)
+    assert rel(get_gauge(H, F), U0) < 1e-11
+    assert rel(get_momenta(H, F), P0) < 1e-10
+
+
 def test_trajectory_accepts_at_small_step(H):
     # a finer integration gives |dH| small enough to accept; both sides agree
     L = (4, 4, 4, 4)
