@@ -191,9 +191,10 @@ def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sam
 def run_hmc(args, H, torch):
     L = (16, 16, 16, 32)
     seed, beta, kappa, tau, nsteps = 12120785, 5.6, 0.156, 1.0, 20
-    F = H.Fields(L, beta, kappa)
+    cg_prec = H.PREC_NAMES[args.cg_prec]
+    F = H.Fields(L, beta, kappa, flags=H.FIELDS_LOWPREC if cg_prec != H.F64 else 0)
     stream = torch.cuda.current_stream()
-    prm = H.cg_params(tol=1e-10, maxiter=10000)
+    prm = H.cg_params(tol=1e-10, maxiter=10000, prec=cg_prec)
     H.hmc_weak_field_start(F, seed, 0.3)
     for w in range(args.warmup):
         H.hmc_trajectory(F, seed, w, tau, nsteps, prm, n_chrono=args.chrono)
@@ -214,11 +215,14 @@ def run_hmc(args, H, torch):
     out = {
         "metric": METRIC, "value": dt / args.steps, "unit": "s/traj", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if cg_prec == H.F64 else f"f64 ({args.cg_prec} inner solver storage)", "data": "synthetic",
         "config": {"workload": "hmc_16c32", "lattice": list(L), "beta": beta, "kappa": kappa, "tau": tau,
                    "nsteps": nsteps, "cg_tol": 1e-10, "start": "weak-field eps=0.3 seed 12120785",
                    "trajectories": f"0..{args.steps - 1}", "initial_guess": (
                        f"chronological, last {args.chrono} solutions" if args.chrono else "zero"),
+                   "force_solves": ("FP64 CG" if cg_prec == H.F64 else
+                                    f"mixed-precision CG, {args.cg_prec} inner storage, FP64 reliable updates"),
                    "parallelism": "1 GPU"},
         "trajectories": [{"traj": k, "seconds": r["seconds"], "dH": r["dH"], "accepted": r["accepted"],
                           "plaquette": r["plaquette"], "cg_iters": r["cg_iters_total"]}
@@ -607,6 +611,8 @@ def main():
     ap.add_argument("--chrono", type=int, default=0,
                     help="hmc: start each force solve from the chronological guess over the last N solutions")
     ap.add_argument("--mts-steps", default="5,2,2", help="mts: ratio,heavy,gauge steps per enclosing step")
+    ap.add_argument("--cg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"],
+                    help="hmc: storage of the force solves' inner iteration (default f64: the plain FP64 HMC)")
     ap.add_argument("--tune-db", default=None,
                     help=("extra launch-shape table to load (hmc_tune_load) before the run; the binding "
                           "already loads paper_1212_0785_amd/tune/mi355x.txt unless HMC_TUNE_DB is set "
