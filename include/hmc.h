@@ -352,29 +352,32 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
                             void* stream);
 
 /* ---- Launch auto-tuning (the auto-tuner of Sec. 4, for the launch shapes
- * and link forms this library offers).  Kinds: HMC_TUNE_DSLASH (choice 1 =
- * one site per work-item, 2 / 4 = direction split with that many wavefronts
- * per 64-site group; one entry per storage precision), HMC_TUNE_GAUGE_FORCE
- * (0 = one link per work-item, 1 = plane split; prec HMC_F64),
- * HMC_TUNE_DSLASH_LINKS (reals read per SU(3) link by the hopping kernels,
- * 12 = rows 0 and 1, 10 = row 0 and column 2; per storage precision; the
- * fermion force follows the FP64 entry) and HMC_TUNE_GAUGE_FORCE_LINKS (the
- * same for the staple force and the plaquette; prec HMC_F64) and
- * HMC_TUNE_DSLASH_STREAM (1 = the Dslash at that storage reads its compact
- * links and writes its output with non-temporal hints; per storage
- * precision) and HMC_TUNE_DSLASH_ORDER (1 = the one-site-per-work-item
- * Dslash walks each XCD's t-slices z-plane by z-plane, t-slice by t-slice,
- * so neighbour spinors are reused in that XCD's L2; lattices with
- * L0 L1 / 2 a multiple of 64, L3 a multiple of 8 and Vh a multiple of
- * 2048; per storage precision).  Decision order: environment override
- * (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES, HMC_LINK_FORM = 18 / 12 / 10,
- * HMC_LINK_STREAM = 0 / 1, HMC_DSLASH_ORDER = 0 / 1) > table entry for the
- * lattice extents > built-in rule.  HMC_TUNE_DB names a table file read on first use.  Table
- * file: text lines "kind L0 L1 L2 L3 prec choice us" with kind dslash,
- * gauge_force, dslash_links, gauge_force_links, dslash_stream or
- * dslash_order ('#' lines and malformed lines are ignored).  Shapes are fixed per solve (and per service request)
- * when it starts; do not tune while solves or a service run on the same
- * lattice extents. */
+ * and link forms this library offers).  Kinds:
+ *   HMC_TUNE_DSLASH (per storage precision): 1 = one site per work-item,
+ *     2 / 4 = direction split with that many wavefronts per 64-site group;
+ *   HMC_TUNE_GAUGE_FORCE (prec HMC_F64): 0 = one link per work-item,
+ *     1 = plane split;
+ *   HMC_TUNE_DSLASH_LINKS (per storage precision): reals read per SU(3)
+ *     link by the hopping kernels, 12 = rows 0 and 1, 10 = row 0 and
+ *     column 2 (the fermion force follows the FP64 entry);
+ *   HMC_TUNE_GAUGE_FORCE_LINKS (prec HMC_F64): the same for the staple
+ *     force and the plaquette;
+ *   HMC_TUNE_DSLASH_STREAM (per storage precision): 1 = the Dslash reads its
+ *     compact links and writes its output with non-temporal hints;
+ *   HMC_TUNE_DSLASH_ORDER (per storage precision): 1 = the one-site-per-
+ *     work-item Dslash walks each XCD's t-slices z-plane by z-plane, t-slice
+ *     by t-slice, so neighbour spinors are reused in that XCD's L2 (lattices
+ *     with L0 L1 / 2 a multiple of 64, L3 a multiple of 8 and Vh a multiple
+ *     of 2048).
+ * Decision order: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES,
+ * HMC_LINK_FORM = 18 / 12 / 10, HMC_LINK_STREAM = 0 / 1, HMC_DSLASH_ORDER =
+ * 0 / 1) > table entry for the lattice extents > built-in rule.
+ * HMC_TUNE_DB names a table file read on first use.  Table file: text lines
+ * "kind L0 L1 L2 L3 prec choice us" with kind dslash, gauge_force,
+ * dslash_links, gauge_force_links, dslash_stream or dslash_order ('#'
+ * lines and malformed lines are ignored).  Shapes are fixed per solve (and
+ * per service request) when it starts; do not tune while solves or a
+ * service run on the same lattice extents. */
 typedef enum {
   HMC_TUNE_DSLASH = 0,
   HMC_TUNE_GAUGE_FORCE = 1,
