@@ -72,7 +72,10 @@ def launch_shapes(H, L, db):
     link form (reals read per SU(3) link: 12 = two rows, 10 = row 0 and
     column 2) and streaming (non-temporal link loads and output stores) per
     storage, staple-force shape (1 = plane split) and link form."""
-    out = {"table": db or (os.environ.get("HMC_TUNE_DB") or H.TUNE_TABLE)}
+    table = db or (os.environ.get("HMC_TUNE_DB") or H.TUNE_TABLE)
+    if os.path.isabs(table) and table.startswith(ROOT + os.sep):
+        table = os.path.relpath(table, ROOT)
+    out = {"table": table}
     for p, name in ((H.F64, "f64"), (H.F32, "f32"), (H.F16, "f16"), (H.BF16, "bf16")):
         c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH, p)
         out[f"dslash_{name}"] = [c, "table" if tuned else "rule"]
