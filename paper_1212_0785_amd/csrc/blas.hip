@@ -110,14 +110,6 @@ __global__ void k_sum_multi_final(const double* part, int nrows, int nsub, doubl
 
 // ------------------------------------------------------- element-wise
 
-__global__ void k_axpby(Lat g, double a, const double2* x, double b, double2* y) {
-  const size_t n = (size_t)12 * g.stride;
-  for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)gridDim.x * kBlock) {
-    double2 u = x[j], v = y[j];
-    y[j] = make_double2(fma(a, u.x, b * v.x), fma(a, u.y, b * v.y));
-  }
-}
-
 // STREAM triad a = b + s c over n2 double2 elements, four per work-item
 // (all loads before the stores), optionally with non-temporal hints: the
 // attainable streaming rate of this chip for the access pattern of the
@@ -158,17 +150,6 @@ __global__ void __launch_bounds__(kBlock) k_xmy_norm(Lat g, const double2* b, co
   }
   block_sum<1>(v);
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-}
-
-__global__ void k_gamma5(Lat g, const double2* in, double2* out) {
-  int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= g.Vh) return;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    double2 a = in[(size_t)k * g.stride + s];
-    double sg = k < 6 ? 1.0 : -1.0;  // gamma5 = diag(1, 1, -1, -1)
-    out[(size_t)k * g.stride + s] = make_double2(sg * a.x, sg * a.y);
-  }
 }
 
 __global__ void k_zero(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
@@ -454,12 +435,6 @@ hipError_t launch_sum_multi(const LatArg& g, const void* x, int nhalves, const i
   return hipGetLastError();
 }
 
-hipError_t launch_axpby(const LatArg& g, double a, const void* x, double b, void* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpby, dim3(blas_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), a, (const double2*)x, b,
-                     (double2*)y);
-  return hipGetLastError();
-}
-
 // out = sum_k c_k y_k over n <= 4 F64 half spinors (complex coefficients).
 struct LinComb {
   const double2* y[4];
@@ -496,12 +471,6 @@ hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* 
                            hipStream_t st) {
   hipLaunchKernelGGL(k_xmy_norm, dim3(nb), dim3(kBlock), 0, st, to_lat(g), (const double2*)b, (const double2*)q,
                      (double2*)r, part);
-  return hipGetLastError();
-}
-
-hipError_t launch_gamma5(const LatArg& g, const void* in, void* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_gamma5, dim3(site_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), (const double2*)in,
-                     (double2*)out);
   return hipGetLastError();
 }
 

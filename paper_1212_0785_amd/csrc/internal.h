@@ -159,12 +159,10 @@ hipError_t launch_sum_multi(const LatArg& g, const void* x, int nhalves, const i
                             int nb, double* out, hipStream_t st);
 
 // Element-wise FP64 helpers.
-hipError_t launch_axpby(const LatArg& g, double a, const void* x, double b, void* y, hipStream_t st);  // y=a x+b y
 // out = sum_k (c[2k] + i c[2k+1]) y[k], n in 1..4 F64 half spinors.
 hipError_t launch_lincomb(const LatArg& g, const void* const* y, const double* c, int n, void* out, hipStream_t st);
 hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* r, double* part, int nb,
                            hipStream_t st);  // r = b - q, partials of |r|^2
-hipError_t launch_gamma5(const LatArg& g, const void* in, void* out, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 
