@@ -231,9 +231,13 @@ def run_hmc(args, H, torch):
                           "plaquette": r["plaquette"], "cg_iters": r["cg_iters_total"]}
                          for k, r in enumerate(results)],
         "cg_iters_per_solve": iters / solves,
-        "kernels_sampled": {k: {"launches_timed": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
+        "kernels_sampled": {k: {"launches_timed": v["launches"], "launches_all": v["calls"],
+                                "avg_ms": v["total_ms"] / v["launches"],
                                 "GBps": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9 if v["bytes"] else None}
-                            for k, v in timing.items()},
+                            for k, v in timing.items() if v["launches"]},
+        # per kernel family: sampled average x all launches, per trajectory
+        "time_split_ms_per_traj": {k: v["total_ms"] / v["launches"] * v["calls"] / args.steps
+                                   for k, v in timing.items() if v["launches"]},
     }
     if rf:
         out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

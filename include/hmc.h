@@ -521,13 +521,15 @@ hmc_status hmc_service_destroy(hmc_service* svc);
  * events (up to a fixed pool; later launches go untimed); 0 disables.
  * hmc_timing_read synchronises the recorded events and returns, per family,
  * the number of timed launches, their summed milliseconds and summed
- * algorithmic bytes.  Process-wide, not thread-safe against concurrent
+ * algorithmic bytes, and the number of all launches (timed or not), so that
+ * average x calls estimates the family's total time.  Process-wide, not thread-safe against concurrent
  * launches. */
 typedef struct {
   char name[32];
   int64_t launches;
   double total_ms;
   double bytes;
+  int64_t calls; /* all launches of the family while timing was enabled */
 } hmc_timing_entry;
 hmc_status hmc_timing_enable(int32_t sample_every);
 hmc_status hmc_timing_reset(void);

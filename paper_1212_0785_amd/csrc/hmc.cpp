@@ -49,6 +49,7 @@ struct Timing {
   std::vector<TimingRec> recs;
   long long counter[TK_COUNT] = {};
   long long launches[TK_COUNT] = {};
+  long long calls[TK_COUNT] = {};  // every launch while enabled
   double ms[TK_COUNT] = {};
   double bytes[TK_COUNT] = {};
   int open_pair = -1;
@@ -72,6 +73,7 @@ bool timing_begin(int kernel, hipStream_t st, double bytes) {
   Timing& T = timing();
   if (T.sample_every <= 0) return false;
   std::lock_guard<std::mutex> lk(T.mu);
+  ++T.calls[kernel];
   if (T.counter[kernel]++ % T.sample_every) return false;
   int pair = (int)T.recs.size();
   if (pair >= kMaxPairs) return false;
@@ -103,6 +105,7 @@ KernelEvents timing_kernel_events(int kernel, double bytes) {
   Timing& T = timing();
   if (T.sample_every <= 0) return ev;
   std::lock_guard<std::mutex> lk(T.mu);
+  ++T.calls[kernel];
   if (T.group_left > 0 && T.group_kernel == kernel) {  // inside a group
     const bool first = T.group_rec == -2, last = T.group_left == 1;
     --T.group_left;
@@ -980,6 +983,7 @@ hmc_status hmc_timing_reset(void) {
   for (int k = 0; k < TK_COUNT; ++k) {
     T.counter[k] = 0;
     T.launches[k] = 0;
+    T.calls[k] = 0;
     T.ms[k] = 0;
     T.bytes[k] = 0;
   }
@@ -1008,12 +1012,13 @@ hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* 
   T.recs.clear();
   int n = 0;
   for (int k = 0; k < TK_COUNT; ++k) {
-    if (!T.launches[k]) continue;
+    if (!T.launches[k] && !T.calls[k]) continue;
     if (out && n < max_entries) {
       std::snprintf(out[n].name, sizeof out[n].name, "%s", timed_kernel_name(k));
       out[n].launches = T.launches[k];
       out[n].total_ms = T.ms[k];
       out[n].bytes = T.bytes[k];
+      out[n].calls = T.calls[k];
     }
     ++n;
   }

@@ -99,7 +99,8 @@ class SolveResult(C.Structure):
 
 
 class TimingEntry(C.Structure):
-    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double)]
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
+                ("calls", C.c_int64)]
 
 
 def struct_dict(s) -> dict:
@@ -540,7 +541,7 @@ def hmc_timing_read() -> dict:
     buf = (TimingEntry * 16)()
     check(lib().hmc_timing_read(buf, 16, C.byref(n)))
     return {buf[k].name.decode(): {"launches": buf[k].launches, "total_ms": buf[k].total_ms,
-                                   "bytes": buf[k].bytes} for k in range(min(n.value, 16))}
+                                   "bytes": buf[k].bytes, "calls": buf[k].calls} for k in range(min(n.value, 16))}
 
 
 # ------------------------------------------------------- solve service

@@ -41,6 +41,7 @@ def test_cg_iterations_timed_in_groups(H):
     ds = t["dslash"]
     # 12 iterations of four hops, plus the set-up and final-residual hops
     assert ds["launches"] >= 4 * 12
+    assert ds["calls"] == ds["launches"]  # every launch sampled
     per_site = ds["bytes"] / ds["launches"] / Vh
     assert 8 * 96 + 2 * 192 <= per_site <= 8 * 96 + 4 * 192
     assert ds["total_ms"] > 0
@@ -49,6 +50,15 @@ def test_cg_iterations_timed_in_groups(H):
     H.hmc_cg_solve(F, x, b, prm)
     torch.cuda.synchronize()
     assert "dslash" not in H.hmc_timing_read()
+    # every 5th sample: all launches still counted, a fifth of the groups timed
+    H.hmc_timing_reset()
+    H.hmc_timing_enable(5)
+    H.hmc_cg_solve(F, x, b, prm)
+    torch.cuda.synchronize()
+    ds5 = H.hmc_timing_read()["dslash"]
+    H.hmc_timing_enable(0)
+    H.hmc_timing_reset()
+    assert ds5["calls"] == ds["calls"] and 0 < ds5["launches"] < ds["launches"]
 
 
 def test_probe(H):
