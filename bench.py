@@ -70,8 +70,10 @@ def launch_shapes(H, L, db):
     """The launch decisions in force for lattice L and where each came from:
     Dslash shape (1 = one site per work-item, 2/4 = direction split) and
     link form (reals read per SU(3) link: 12 = two rows, 10 = row 0 and
-    column 2) and streaming (non-temporal link loads and output stores) per
-    storage, staple-force shape (1 = plane split) and link form."""
+    column 2), streaming (non-temporal link loads and output stores), site
+    order (0 linear, 1 tiled by z-planes, n tiled by y-blocks of n 64-site
+    chunks) and workgroups per CU of the tiled order (2, or 0 = as registers
+    allow) per storage, staple-force shape (1 = plane split) and link form."""
     table = db or (os.environ.get("HMC_TUNE_DB") or H.TUNE_TABLE)
     if os.path.isabs(table) and table.startswith(ROOT + os.sep):
         table = os.path.relpath(table, ROOT)
@@ -85,6 +87,8 @@ def launch_shapes(H, L, db):
         out[f"dslash_stream_{name}"] = [c, "table" if tuned else "rule"]
         c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_ORDER, p)
         out[f"dslash_order_{name}"] = [c, "table" if tuned else "rule"]
+        c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_OCC, p)
+        out[f"dslash_occupancy_{name}"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE)
     out["gauge_force_planes"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE_LINKS)
@@ -675,6 +679,7 @@ def main():
             out["roofline"]["link_reals"] = out["config"]["launch_shapes"]["dslash_links_f64"][0]
             out["roofline"]["stream"] = out["config"]["launch_shapes"]["dslash_stream_f64"][0]
             out["roofline"]["tiled_order"] = out["config"]["launch_shapes"]["dslash_order_f64"][0]
+            out["roofline"]["tiled_occupancy"] = out["config"]["launch_shapes"]["dslash_occupancy_f64"][0]
     print(json.dumps(out))
 
 

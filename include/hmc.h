@@ -368,27 +368,36 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
  *     work-item Dslash walks each XCD's t-slices z-plane by z-plane, t-slice
  *     by t-slice, so neighbour spinors are reused in that XCD's L2 (lattices
  *     with L0 L1 / 2 a multiple of 64, L3 a multiple of 8 and Vh a multiple
- *     of 2048).
+ *     of 2048); n >= 2 = the same walk over y-blocks of n 64-site chunks of
+ *     each z-plane in turn, so several z-planes are in flight at once (n
+ *     divides L0 L1 / 128, n <= 64; any other n reads as 1);
+ *   HMC_TUNE_DSLASH_OCC (per storage precision): workgroups per CU of the
+ *     tiled order, 2 = at most two (an unused LDS reservation keeps the
+ *     wavefronts in flight close together in the walk), 0 = as many as
+ *     registers allow.
  * Decision order: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES,
  * HMC_LINK_FORM = 18 / 12 / 10, HMC_LINK_STREAM = 0 / 1, HMC_DSLASH_ORDER =
- * 0 / 1) > table entry for the lattice extents > built-in rule.
+ * 0 / 1 / n, HMC_DSLASH_OCC = 0 / 2) > table entry for the lattice extents >
+ * built-in rule.
  * HMC_TUNE_DB names a table file read on first use.  Table file: text lines
  * "kind L0 L1 L2 L3 prec choice us" with kind dslash, gauge_force,
- * dslash_links, gauge_force_links, dslash_stream or dslash_order ('#'
- * lines and malformed lines are ignored).  Shapes are fixed per solve (and
- * per service request) when it starts; do not tune while solves or a
- * service run on the same lattice extents. */
+ * dslash_links, gauge_force_links, dslash_stream, dslash_order or
+ * dslash_occupancy ('#' lines and malformed lines are ignored).  Shapes are
+ * fixed per solve (and per service request) when it starts; do not tune
+ * while solves or a service run on the same lattice extents. */
 typedef enum {
   HMC_TUNE_DSLASH = 0,
   HMC_TUNE_GAUGE_FORCE = 1,
   HMC_TUNE_DSLASH_LINKS = 2,
   HMC_TUNE_GAUGE_FORCE_LINKS = 3,
   HMC_TUNE_DSLASH_STREAM = 4,
-  HMC_TUNE_DSLASH_ORDER = 5
+  HMC_TUNE_DSLASH_ORDER = 5,
+  HMC_TUNE_DSLASH_OCC = 6
 } hmc_tune_kind;
 /* Times every candidate on f's lattice and stores the fastest in the
  * table: for each storage precision the Dslash shape x link form pairs
- * (then streaming and the tiled order on and off for the best pair)
+ * (then streaming, and the site orders x workgroups per CU, for the best
+ * pair)
  * where it runs, inside a solve (CG on Mhat^dag Mhat from Gaussian noise to
  * 1e-10 or 100 iterations: FP64 CG, and with HMC_FIELDS_LOWPREC
  * mixed-precision CG with that storage inside; "us" = microseconds per

@@ -366,8 +366,9 @@ struct Lat {
   int stride;  // elements between successive components of a field (= Vh)
   // Tiled site order of the one-site-per-work-item Dslash (tiled = 0: the
   // linear order with XCD-contiguous ranges): checkerboard sites per z-plane
-  // and per t-slice, 64-site chunks per z-plane, t-slices per XCD.
-  int tiled, plane, slice, tile_r, tile_t;
+  // and per t-slice, 64-site chunks per z-plane, t-slices per XCD, chunks
+  // per y-block (tile_y = tile_r: the whole plane is one block).
+  int tiled, plane, slice, tile_r, tile_t, tile_y;
 };
 
 inline Lat to_lat(const LatArg& a) {
@@ -375,7 +376,7 @@ inline Lat to_lat(const LatArg& a) {
   for (int k = 0; k < 4; ++k) g.L[k] = a.L[k];
   g.Vh = a.Vh;
   g.stride = a.stride;
-  g.tiled = g.plane = g.slice = g.tile_r = g.tile_t = 0;
+  g.tiled = g.plane = g.slice = g.tile_r = g.tile_t = g.tile_y = 0;
   return g;
 }
 
@@ -442,20 +443,26 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // 256-site blocks; *part gets the block's partial-sum slot.  Linear order:
 // block b covers sites 256 b .. 256 b + 255, XCD-contiguous (xcd_remap).
 // Tiled order: XCD x (blocks with blockIdx.x % 8 == x) owns the t-slices
-// [x tile_t, (x + 1) tile_t) and walks its wavefronts z-plane by z-plane,
-// within a plane t-slice by t-slice, within a (z, t) row of the x-y plane
-// 64 sites at a time; the +-t neighbours of a site are then one row of
-// chunks away and the +-z neighbours tile_t rows away, both still in the
-// XCD's L2, where the linear order has the t neighbours a whole t-slice
-// (tens of MB of traffic) away.
+// [x tile_t, (x + 1) tile_t).  Each z-plane of a t-slice is cut into
+// y-blocks of tile_y 64-site chunks (consecutive checkerboard sites, so a
+// block spans whole rows of constant y but for its ends); the XCD walks its
+// wavefronts y-block by y-block, within a y-block z-plane by z-plane, then
+// t-slice by t-slice, then chunk by chunk.  The +-t neighbours of a site are
+// then tile_y wavefronts away in the walk and the +-z neighbours
+// tile_t tile_y away: with small y-blocks several z-planes are in flight at
+// once and the neighbours they share are still in the XCD's L2, where the
+// linear order has the t neighbours a whole t-slice (tens of MB of traffic)
+// away.  Only the +-y neighbours of the two edge rows of a y-block and the
+// +-t neighbours across XCDs are read a second time from beyond L2.
 __device__ __forceinline__ int dslash_site(const Lat& g, int* part) {
   if (g.tiled) {
     const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
     const int w = k * 4 + (threadIdx.x >> 6);  // wavefront of this XCD, in walk order
-    const int r = w % g.tile_r, q = w / g.tile_r;
-    const int t = xcd * g.tile_t + q % g.tile_t, z = q / g.tile_t;
+    const int c = w % g.tile_y, q = w / g.tile_y;
+    const int t = xcd * g.tile_t + q % g.tile_t, q2 = q / g.tile_t;
+    const int z = q2 % g.L[2], yb = q2 / g.L[2];
     *part = blockIdx.x;
-    return t * g.slice + z * g.plane + r * 64 + (threadIdx.x & 63);
+    return t * g.slice + z * g.plane + (yb * g.tile_y + c) * 64 + (threadIdx.x & 63);
   }
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   *part = b;

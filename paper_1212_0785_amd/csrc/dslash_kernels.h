@@ -288,22 +288,26 @@ static hipError_t launch_typed(hmc_prec prec, int dagger, int epi, const LatArg&
                                KernelEvents ev) {
   Lat g = to_lat(ga);
   const int shape = one.shape ? one.shape : dslash_shape(ga, prec);
-  if (shape == 1 && dslash_tiled_order(ga, prec)) {
+  const int order = shape == 1 ? dslash_tiled_order(ga, prec) : 0;
+  if (order) {
     g.tiled = 1;
     g.plane = ga.L[0] * ga.L[1] / 2;
     g.slice = g.plane * ga.L[2];
     g.tile_r = g.plane / 64;
     g.tile_t = ga.L[3] / 8;
+    g.tile_y = order == 1 ? g.tile_r : order;
   }
   const int ways = shape == 1 ? 0 : shape;
   const dim3 grid(dslash_shape_blocks(ga.Vh, shape), nbatch);
   const dim3 block(ways ? 64 * ways : kBlock);
-  // The tiled order reserves LDS it does not use: 54,000 bytes per block
+  // The tiled order may reserve LDS it does not use: 54,000 bytes per block
   // leave room for two blocks per CU (2 wavefronts per SIMD), so an XCD's
   // wavefronts in flight span a few (z, t) rows instead of dozens and the
-  // neighbours they share are still in its L2 (measured at 48^3x96: 1.36 ms
-  // without the cap, 1.25 ms with it, 1.30 ms for the linear order).
-  const size_t lds_cap = g.tiled ? 54000 : 0;
+  // neighbours they share are still in its L2 (measured at 48^3x96 with
+  // whole z-planes: FP64 1.36 ms without the cap, 1.24 ms with it, 1.27-1.31
+  // ms for the linear order; with y-blocks the FP32 and FP16 kernels run
+  // faster without it).
+  const size_t lds_cap = g.tiled && dslash_tiled_occupancy(ga, prec) == 2 ? 54000 : 0;
 #define HMC_LAUNCH(KERNEL) \
   hipExtLaunchKernelGGL(KERNEL, grid, block, lds_cap, st, ev.start, ev.stop, 0, g, out_par, table, one, j)
 #define HMC_DS_B(D, E, B)                                  \

@@ -1326,11 +1326,12 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
     prm.prec = prec;
     // one timed candidate: installs its table entries, returns us per
     // iteration (< 0 after a failure; status / err say which)
-    auto time_candidate = [&](int shape, int form, int stream, int order) -> double {
+    auto time_candidate = [&](int shape, int form, int stream, int order, int occ) -> double {
       tune_store(F->g.L, TUNE_DSLASH, prec, shape, 0);
       if (form) tune_store(F->g.L, TUNE_DSLASH_LINKS, prec, form, 0);
       if (form) tune_store(F->g.L, TUNE_DSLASH_STREAM, prec, stream, 0);
       tune_store(F->g.L, TUNE_DSLASH_ORDER, prec, order, 0);
+      tune_store(F->g.L, TUNE_DSLASH_OCC, prec, occ, 0);
       double us = -1;
       for (int r = 0; r <= kReps; ++r) {  // r = 0 warms up
         hmc_cg_stats cs{};
@@ -1349,28 +1350,37 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
       return us;
     };
     // shapes x link forms (linear order, no streaming), then streaming and
-    // the tiled order for the best pair
-    int best = 0, best_form = 0, best_stream = 0, best_order = 0;
+    // the tiled orders x workgroups per CU for the best pair
+    int best = 0, best_form = 0, best_stream = 0, best_order = 0, best_occ = 2;
     double best_us = 0;
     for (int form : forms) {
       for (int shape : {1, 2, 4}) {
-        const double us = time_candidate(shape, form, 0, 0);
+        const double us = time_candidate(shape, form, 0, 0, 2);
         if (us < 0) break;
         if (!best || us < best_us) best = shape, best_form = form, best_us = us;
       }
       if (status != HMC_OK) break;
     }
     if (status == HMC_OK && best_form) {
-      const double us = time_candidate(best, best_form, 1, 0);
+      const double us = time_candidate(best, best_form, 1, 0, 2);
       if (us >= 0 && us < best_us) best_stream = 1, best_us = us;
     }
     if (status == HMC_OK && best == 1 && tiled_order_valid(F->g)) {
-      const double us = time_candidate(best, best_form, best_stream, 1);
-      if (us >= 0 && us < best_us) best_order = 1, best_us = us;
+      // whole z-planes, then y-blocks of a few chunks
+      for (int order : {1, 2, 3, 4, 6}) {
+        if (!tiled_order_valid(F->g, order) || (order > 1 && order >= F->g.L[0] * F->g.L[1] / 128)) continue;
+        for (int occ : {2, 0}) {
+          const double us = time_candidate(best, best_form, best_stream, order, occ);
+          if (us < 0) break;
+          if (us < best_us) best_order = order, best_occ = occ, best_us = us;
+        }
+        if (status != HMC_OK) break;
+      }
     }
     if (status == HMC_OK) {
       tune_store(F->g.L, TUNE_DSLASH, prec, best, best_us);
       tune_store(F->g.L, TUNE_DSLASH_ORDER, prec, best_order, best_us);
+      tune_store(F->g.L, TUNE_DSLASH_OCC, prec, best_occ, best_us);
       if (best_form) {
         tune_store(F->g.L, TUNE_DSLASH_LINKS, prec, best_form, best_us);
         tune_store(F->g.L, TUNE_DSLASH_STREAM, prec, best_stream, best_us);
@@ -1447,7 +1457,7 @@ hmc_status hmc_tune_save(const char* path, int32_t* n_entries) {
 
 hmc_status hmc_tune_query(const int32_t* L, int32_t kind, int32_t prec, int32_t* choice, int32_t* tuned) {
   HMC_REQUIRE(L && choice, "null argument");
-  HMC_REQUIRE(kind >= HMC_TUNE_DSLASH && kind <= HMC_TUNE_DSLASH_ORDER, "bad kind %d", kind);
+  HMC_REQUIRE(kind >= HMC_TUNE_DSLASH && kind <= HMC_TUNE_DSLASH_OCC, "bad kind %d", kind);
   HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision %d", prec);
   hmc_geom geom;
   for (int k = 0; k < 4; ++k) geom.L[k] = L[k];
@@ -1457,14 +1467,15 @@ hmc_status hmc_tune_query(const int32_t* L, int32_t kind, int32_t prec, int32_t*
   if (s) return s;
   const int ints[4] = {L[0], L[1], L[2], L[3]};
   const bool per_prec = kind == HMC_TUNE_DSLASH || kind == HMC_TUNE_DSLASH_LINKS || kind == HMC_TUNE_DSLASH_STREAM ||
-                        kind == HMC_TUNE_DSLASH_ORDER;
+                        kind == HMC_TUNE_DSLASH_ORDER || kind == HMC_TUNE_DSLASH_OCC;
   const int t = tune_lookup(ints, kind, per_prec ? prec : HMC_F64);
   switch (kind) {
     case HMC_TUNE_DSLASH: *choice = dslash_shape(g, (hmc_prec)prec); break;
     case HMC_TUNE_GAUGE_FORCE: *choice = gauge_force_shape(g); break;
     case HMC_TUNE_DSLASH_LINKS: *choice = dslash_link_form(g, (hmc_prec)prec); break;
     case HMC_TUNE_DSLASH_STREAM: *choice = dslash_link_stream(g, (hmc_prec)prec) ? 1 : 0; break;
-    case HMC_TUNE_DSLASH_ORDER: *choice = dslash_tiled_order(g, (hmc_prec)prec) ? 1 : 0; break;
+    case HMC_TUNE_DSLASH_ORDER: *choice = dslash_tiled_order(g, (hmc_prec)prec); break;
+    case HMC_TUNE_DSLASH_OCC: *choice = dslash_tiled_occupancy(g, (hmc_prec)prec); break;
     default: *choice = staple_link_form(g); break;
   }
   if (tuned) *tuned = t >= 0 ? 1 : 0;

@@ -45,7 +45,8 @@ enum TuneKind {
   TUNE_DSLASH_LINKS = 2,
   TUNE_GFORCE_LINKS = 3,
   TUNE_DSLASH_STREAM = 4,
-  TUNE_DSLASH_ORDER = 5
+  TUNE_DSLASH_ORDER = 5,
+  TUNE_DSLASH_OCC = 6
 };
 // All nine entries; rows 0 and 1 (LkRows2); row 0 and column 2 (LkRowCol).
 // The compact forms need SU(3) links.
@@ -61,14 +62,22 @@ int staple_link_form(const LatArg& g);
 // from displacing the neighbour spinors in L2 (pays at large volumes) but
 // also from the last-level cache (costs where the fields fit in it).
 bool dslash_link_stream(const LatArg& g, hmc_prec prec);
-// Whether the one-site-per-work-item Dslash walks its sites in the tiled
-// order (dslash_site in device.h), and whether the lattice admits it: whole
-// 256-site blocks, a multiple of 8 of them, 64-site chunks per z-plane and
-// a multiple of 8 t-slices.
-bool dslash_tiled_order(const LatArg& g, hmc_prec prec);
-inline bool tiled_order_valid(const LatArg& g) {
+// Site order of the one-site-per-work-item Dslash (dslash_site in
+// device.h): 0 linear, 1 tiled with whole z-planes, n >= 2 tiled with
+// y-blocks of n 64-site chunks.  The lattice admits the tiled order with
+// whole 256-site blocks, a multiple of 8 of them, 64-site chunks per z-plane
+// and a multiple of 8 t-slices; y-blocks of n chunks need n to divide the
+// chunks per plane.
+int dslash_tiled_order(const LatArg& g, hmc_prec prec);
+constexpr int kMaxYBlock = 64;  // largest y-block, in chunks
+// Workgroups per CU of the tiled-order Dslash: 2 (an LDS reservation keeps
+// the wavefronts in flight on an XCD within a few rows of the walk) or 0 (as
+// many as registers allow).
+int dslash_tiled_occupancy(const LatArg& g, hmc_prec prec);
+inline bool tiled_order_valid(const LatArg& g, int order = 1) {
   const int plane = g.L[0] * g.L[1] / 2;
-  return g.Vh % kThreads == 0 && (g.Vh / kThreads) % 8 == 0 && plane % 64 == 0 && g.L[3] % 8 == 0;
+  if (!(g.Vh % kThreads == 0 && (g.Vh / kThreads) % 8 == 0 && plane % 64 == 0 && g.L[3] % 8 == 0)) return false;
+  return order == 1 || (order >= 2 && order <= kMaxYBlock && (plane / 64) % order == 0);
 }
 // The form a kernel reads: the compact one on SU(3) links, else all entries.
 inline int link_form_for(bool su3, int compact) { return su3 ? compact : (int)LINK_FULL; }

@@ -1,12 +1,14 @@
 // Launch-shape and link-form decisions and their persisted tuning table
 // (the auto-tuner of Sec. 4, for the choices this library offers): per
 // lattice and storage, the Dslash shape (one site per work-item, 2- or
-// 4-way direction split), the staple-force shape (one link per work-item or
-// plane split), and the compact link form of the hop and staple kernels
-// (two rows, or row 0 and column 2).
+// 4-way direction split), its link streaming, site order and workgroups per
+// CU, the staple-force shape (one link per work-item or plane split), and
+// the compact link form of the hop and staple kernels (two rows, or row 0
+// and column 2).
 //
 // Precedence: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES,
-// HMC_LINK_FORM) > tuned entry > built-in rule measured on MI355X.
+// HMC_LINK_FORM, HMC_LINK_STREAM, HMC_DSLASH_ORDER, HMC_DSLASH_OCC) > tuned
+// entry > built-in rule measured on MI355X.
 // HMC_TUNE_DB names a table file loaded on first use; hmc_autotune fills and
 // saves entries.
 #include <hip/hip_runtime.h>
@@ -46,9 +48,9 @@ Table& table() {
 
 Key make_key(const int* L, int kind, int prec) { return Key(L[0], L[1], L[2], L[3], kind, prec); }
 
-const char* const kKindNames[] = {"dslash", "gauge_force", "dslash_links", "gauge_force_links", "dslash_stream",
-                                  "dslash_order"};
-constexpr int kNumKinds = 6;
+const char* const kKindNames[] = {"dslash",        "gauge_force",  "dslash_links",    "gauge_force_links",
+                                  "dslash_stream", "dslash_order", "dslash_occupancy"};
+constexpr int kNumKinds = 7;
 
 const char* kind_name(int kind) { return kKindNames[kind]; }
 
@@ -62,8 +64,9 @@ bool valid_choice(int kind, int c) {
   switch (kind) {
     case TUNE_DSLASH: return c == 1 || c == 2 || c == 4;
     case TUNE_GFORCE:
-    case TUNE_DSLASH_STREAM:
-    case TUNE_DSLASH_ORDER: return c == 0 || c == 1;
+    case TUNE_DSLASH_STREAM: return c == 0 || c == 1;
+    case TUNE_DSLASH_ORDER: return c >= 0 && c <= kMaxYBlock;
+    case TUNE_DSLASH_OCC: return c == 0 || c == 2;
     default: return c == LINK_ROWS2 || c == LINK_ROWCOL;
   }
 }
@@ -143,7 +146,9 @@ int tune_save(const char* path) {
                "# gauge_force: choice 0 = one link per work-item, 1 = plane split; us per launch\n"
                "# dslash_links, gauge_force_links: reals read per SU(3) link, 12 = two rows, 10 = row 0 and column 2\n"
                "# dslash_stream: 1 = non-temporal link loads and output stores\n"
-               "# dslash_order: 1 = tiled site order (one site per work-item shape)\n");
+               "# dslash_order: 1 = tiled site order (one site per work-item shape), n >= 2 = tiled in y-blocks of n "
+               "64-site chunks\n"
+               "# dslash_occupancy: workgroups per CU of the tiled order, 2 = at most two, 0 = as registers allow\n");
   for (const auto& kv : merged) {
     const Key& k = kv.first;
     std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", kind_name(std::get<4>(k)), std::get<0>(k), std::get<1>(k),
@@ -155,7 +160,7 @@ int tune_save(const char* path) {
 
 bool tune_env_forced() {
   return env_int("HMC_DSLASH_SPLIT") >= 0 || env_int("HMC_GFORCE_PLANES") >= 0 || env_int("HMC_LINK_FORM") >= 0 ||
-         env_int("HMC_LINK_STREAM") >= 0 || env_int("HMC_DSLASH_ORDER") >= 0;
+         env_int("HMC_LINK_STREAM") >= 0 || env_int("HMC_DSLASH_ORDER") >= 0 || env_int("HMC_DSLASH_OCC") >= 0;
 }
 
 namespace {
@@ -188,13 +193,22 @@ bool dslash_link_stream(const LatArg& g, hmc_prec prec) {
   return g.Vh >= (1 << 20);
 }
 
-bool dslash_tiled_order(const LatArg& g, hmc_prec prec) {
-  if (!tiled_order_valid(g)) return false;
+int dslash_tiled_order(const LatArg& g, hmc_prec prec) {
+  if (!tiled_order_valid(g)) return 0;
   static const int forced = env_int("HMC_DSLASH_ORDER");
-  if (forced >= 0) return forced != 0;
+  // an order the lattice does not admit falls back to whole z-planes
+  if (forced >= 0) return forced == 0 ? 0 : tiled_order_valid(g, forced) ? forced : 1;
   const int t = tune_lookup(g.L, TUNE_DSLASH_ORDER, prec);
-  if (t >= 0) return t != 0;
-  return false;
+  if (t >= 0) return t == 0 ? 0 : tiled_order_valid(g, t) ? t : 1;
+  return 0;
+}
+
+int dslash_tiled_occupancy(const LatArg& g, hmc_prec prec) {
+  static const int forced = env_int("HMC_DSLASH_OCC");
+  if (forced >= 0) return forced == 0 ? 0 : 2;
+  const int t = tune_lookup(g.L, TUNE_DSLASH_OCC, prec);
+  if (t >= 0) return t;
+  return 2;
 }
 
 int staple_link_form(const LatArg& g) {

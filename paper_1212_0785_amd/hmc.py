@@ -398,8 +398,8 @@ def hmc_gauge_force(f, coef, stream=None):
     check(lib().hmc_gauge_force(_h(f), float(coef), _stream(stream)))
 
 
-TUNE_DSLASH, TUNE_GAUGE_FORCE, TUNE_DSLASH_LINKS, TUNE_GAUGE_FORCE_LINKS, TUNE_DSLASH_STREAM, TUNE_DSLASH_ORDER = \
-    0, 1, 2, 3, 4, 5
+(TUNE_DSLASH, TUNE_GAUGE_FORCE, TUNE_DSLASH_LINKS, TUNE_GAUGE_FORCE_LINKS, TUNE_DSLASH_STREAM, TUNE_DSLASH_ORDER,
+ TUNE_DSLASH_OCC) = 0, 1, 2, 3, 4, 5, 6
 LINK_FULL, LINK_ROWS2, LINK_ROWCOL = 18, 12, 10
 
 

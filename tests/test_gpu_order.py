@@ -1,4 +1,5 @@
-"""GPU: the tiled site order of the one-site-per-work-item Dslash.
+"""GPU: the tiled site orders of the one-site-per-work-item Dslash (whole
+z-planes, and y-blocks of a few 64-site chunks).
 
 Only the work-item that computes a site changes, not its arithmetic, so
 every output equals the linear order's bit for bit; the partial sums of
@@ -15,8 +16,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 # extents that admit the tiled order and that no other test uses (their
-# table entries leave the other tests' lattices alone)
-ORDER_L = [(16, 8, 4, 8), (16, 16, 4, 16)]
+# table entries leave the other tests' lattices alone), with the (tiled
+# order, workgroups per CU) pairs tried on each: 48 x 16 / 2 = 384 sites
+# per z-plane = 6 chunks, so y-blocks of 2 and 3 chunks
+ORDER_L = [(16, 8, 4, 8), (16, 16, 4, 16), (48, 16, 4, 8)]
+ORDERS = {(48, 16, 4, 8): ((1, 2), (2, 2), (3, 2), (3, 0))}
 
 
 @pytest.fixture(scope="module")
@@ -28,14 +32,16 @@ def H():
     return hmc
 
 
-def set_order(H, path, L, order):
+def set_order(H, path, L, order, occ=2):
     ext = " ".join(map(str, L))
-    lines = [f"dslash {ext} {p} 1 0" for p in range(4)] + [f"dslash_order {ext} {p} {order} 0" for p in range(4)]
+    lines = ([f"dslash {ext} {p} 1 0" for p in range(4)] + [f"dslash_order {ext} {p} {order} 0" for p in range(4)] +
+             [f"dslash_occupancy {ext} {p} {occ} 0" for p in range(4)])
     path.write_text("\n".join(lines) + "\n")
     H.hmc_tune_load(str(path))
     for p in range(4):
         assert H.hmc_tune_query(L, H.TUNE_DSLASH, p) == (1, True)
         assert H.hmc_tune_query(L, H.TUNE_DSLASH_ORDER, p) == (order, True)
+        assert H.hmc_tune_query(L, H.TUNE_DSLASH_OCC, p) == (occ, True)
 
 
 @pytest.mark.parametrize("L", ORDER_L)
@@ -43,8 +49,9 @@ def test_tiled_order_bit_identical_and_oracle(H, tmp_path, L):
     U = synth.gauge_field(61, L, eps=0.5)
     psi = synth.spinor(62, L)
     outs = {}
-    for order in (0, 1):
-        set_order(H, tmp_path / f"o{order}.txt", L, order)
+    orders = ORDERS.get(L, ((1, 2),))
+    for order in ((0, 2),) + orders:
+        set_order(H, tmp_path / f"o{order[0]}_{order[1]}.txt", L, *order)
         F = H.Fields(L, 5.6, 0.15, flags=H.FIELDS_LOWPREC)
         put_gauge(H, F, U)
         for prec in range(4):
@@ -54,18 +61,20 @@ def test_tiled_order_bit_identical_and_oracle(H, tmp_path, L):
                     out = F.spinor(prec=prec)
                     H.hmc_wilson_dslash(F, out, b, par, dag, prec)
                     outs[(order, prec, par, dag)] = out.clone()
-                    if prec == 0 and order == 1:
+                    if prec == 0 and order[0] > 0:
                         want = O.dslash(L, U, psi, par, dag)
                         assert rel(get_spinor(H, F, out, par), want) < 1e-14
         del F
-    for key in [k for k in outs if k[0] == 0]:
-        assert torch.equal(outs[key], outs[(1,) + key[1:]]), key
+    for key in [k for k in outs if k[0] == (0, 2)]:
+        for order in orders:
+            assert torch.equal(outs[key], outs[(order,) + key[1:]]), (order, key)
 
 
 @pytest.mark.parametrize("L", ORDER_L)
 def test_tiled_order_solves(H, tmp_path, L):
     k = 0.15
-    set_order(H, tmp_path / "o1.txt", L, 1)
+    order = ORDERS.get(L, ((1, 2),))[-1]
+    set_order(H, tmp_path / "o.txt", L, *order)
     F = H.Fields(L, 5.6, k, flags=H.FIELDS_LOWPREC)
     U = synth.gauge_field(63, L, eps=0.5)
     put_gauge(H, F, U)

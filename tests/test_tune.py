@@ -68,7 +68,7 @@ def test_link_form_entries(H, tmp_path):
     assert H.hmc_tune_query((64, 64, 64, 64), H.TUNE_DSLASH_LINKS, H.F64) == (H.LINK_ROWCOL, False)
     assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_GAUGE_FORCE_LINKS) == (H.LINK_ROWCOL, False)
     with pytest.raises(H.HmcError):
-        H.hmc_tune_query((6, 4, 2, 10), 6, H.F64)  # no such kind
+        H.hmc_tune_query((6, 4, 2, 10), 7, H.F64)  # no such kind
 
 
 def test_stream_entries(H, tmp_path):
@@ -91,8 +91,27 @@ def test_order_entries_need_an_admissible_lattice(H, tmp_path):
         pytest.skip("environment overrides the table")
     src = tmp_path / "order.txt"
     src.write_text("dslash_order 16 8 4 8 0 1 1.0\n"     # admissible
-                   "dslash_order 6 4 4 10 0 1 1.0\n")    # 6*4/2 = 12 sites per z-plane: not a multiple of 64
-    assert H.hmc_tune_load(str(src)) == 2
+                   "dslash_order 6 4 4 10 0 1 1.0\n"     # 6*4/2 = 12 sites per z-plane: not a multiple of 64
+                   "dslash_order 48 16 4 8 0 3 1.0\n"    # 384 sites per z-plane = 6 chunks: y-blocks of 3
+                   "dslash_order 48 16 4 8 1 4 1.0\n"    # 4 does not divide 6: whole z-planes
+                   "dslash_order 48 16 4 8 2 65 1.0\n")  # beyond 64 chunks: ignored
+    assert H.hmc_tune_load(str(src)) == 4
     assert H.hmc_tune_query((16, 8, 4, 8), H.TUNE_DSLASH_ORDER, H.F64) == (1, True)
     assert H.hmc_tune_query((6, 4, 4, 10), H.TUNE_DSLASH_ORDER, H.F64) == (0, True)
     assert H.hmc_tune_query((16, 8, 4, 8), H.TUNE_DSLASH_ORDER, H.F32) == (0, False)
+    assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_ORDER, H.F64) == (3, True)
+    assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_ORDER, H.F32) == (1, True)
+    assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_ORDER, H.F16) == (0, False)
+
+
+def test_occupancy_entries(H, tmp_path):
+    if os.environ.get("HMC_DSLASH_OCC"):
+        pytest.skip("environment overrides the table")
+    src = tmp_path / "occ.txt"
+    src.write_text("dslash_occupancy 48 16 4 8 0 0 1.0\n"
+                   "dslash_occupancy 48 16 4 8 1 2 1.0\n"
+                   "dslash_occupancy 48 16 4 8 2 1 1.0\n")  # not 0 / 2: ignored
+    assert H.hmc_tune_load(str(src)) == 2
+    assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_OCC, H.F64) == (0, True)
+    assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_OCC, H.F32) == (2, True)
+    assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_OCC, H.F16) == (2, False)  # rule: at most two
