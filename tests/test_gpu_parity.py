@@ -514,13 +514,15 @@ def _coords48(lex):
 
 def test_dslash_sampled_at_48c96(H):
     """The 48^3 x 96 bandwidth workload in the launch configuration the
-    benchmark times: GPU weak-field links and Gaussian spinor from their
-    seeds; ~260 even output sites recomputed by the oracle from its own
-    draws (only the links and spinors those sites touch are generated)."""
+    benchmark times (FP64, and the FP32 / FP16 / BF16 storages): GPU
+    weak-field links and Gaussian spinor from their seeds; ~260 even output
+    sites recomputed by the oracle from its own draws (only the links and
+    spinors those sites touch are generated)."""
     L = (48, 48, 48, 96)
     V = synth.volume(L)
-    F = H.Fields(L, 5.6, 0.15)
+    F = H.Fields(L, 5.6, 0.15, flags=H.FIELDS_LOWPREC)
     H.hmc_weak_field_start(F, 2, 0.3)
+    H.hmc_sync_lowprec(F)
     src = F.spinor(full=True)
     H.hmc_make_source(F, src, 0, 2, 0)
     out = F.spinor()
@@ -545,10 +547,20 @@ def test_dslash_sampled_at_48c96(H):
     O.weak_field_sites(L, 2, 0.3, need, U)
     O.gauss_source_sites(2, 0, need, psi)
     want = O.dslash_sites(L, U, psi, lex)
-    half = out.view(torch.float64).view(12, -1, 2)  # component-major [12][Vh] complex
-    gv = half[:, torch.from_numpy(lex // 2).cuda(), :].cpu().numpy()
-    got = (gv[..., 0] + 1j * gv[..., 1]).T.reshape(-1, 4, 3)
-    assert rel(got, want) < 1e-14
+    cb = torch.from_numpy(lex // 2).cuda()
+
+    def sampled(o):
+        gv = o.view(torch.float64).view(12, -1, 2)[:, cb, :].cpu().numpy()  # component-major [12][Vh]
+        return (gv[..., 0] + 1j * gv[..., 1]).T.reshape(-1, 4, 3)
+
+    assert rel(sampled(out), want) < 1e-14
+    for prec, tol in ((1, 1e-6), (2, 3e-3), (3, 2e-2)):
+        inl, outl = F.spinor(prec=prec), F.spinor(prec=prec)
+        H.hmc_convert_spinor(F, inl, prec, src[hb:], H.F64)
+        H.hmc_wilson_dslash(F, outl, inl, 0, 0, prec)
+        H.hmc_convert_spinor(F, out, H.F64, outl, prec)
+        torch.cuda.synchronize()
+        assert rel(sampled(out), want) < tol, prec
 
 
 def test_gauge_force_sampled_at_48c96(H):
