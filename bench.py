@@ -73,7 +73,9 @@ def launch_shapes(H, L, db):
     column 2), streaming (non-temporal link loads and output stores), site
     order (0 linear, 1 tiled by z-planes, n tiled by y-blocks of n 64-site
     chunks) and workgroups per CU of the tiled order (2, or 0 = as registers
-    allow) per storage, staple-force shape (1 = plane split) and link form."""
+    allow) per storage, staple-force shape (0 = one link per work-item,
+    1 = plane split, 2 = four directions of 64 sites per block) and link
+    form."""
     table = db or (os.environ.get("HMC_TUNE_DB") or H.TUNE_TABLE)
     if os.path.isabs(table) and table.startswith(ROOT + os.sep):
         table = os.path.relpath(table, ROOT)
@@ -90,7 +92,7 @@ def launch_shapes(H, L, db):
         c, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_OCC, p)
         out[f"dslash_occupancy_{name}"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE)
-    out["gauge_force_planes"] = [c, "table" if tuned else "rule"]
+    out["gauge_force_shape"] = [c, "table" if tuned else "rule"]
     c, tuned = H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE_LINKS)
     out["gauge_force_links"] = [c, "table" if tuned else "rule"]
     return out

@@ -356,7 +356,9 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
  *   HMC_TUNE_DSLASH (per storage precision): 1 = one site per work-item,
  *     2 / 4 = direction split with that many wavefronts per 64-site group;
  *   HMC_TUNE_GAUGE_FORCE (prec HMC_F64): 0 = one link per work-item,
- *     1 = plane split;
+ *     direction by direction; 1 = plane split; 2 = a block per 64 sites and
+ *     all four directions, in the tiled walk of the Dslash (y-blocks of two
+ *     chunks) where the lattice admits it;
  *   HMC_TUNE_DSLASH_LINKS (per storage precision): reals read per SU(3)
  *     link by the hopping kernels, 12 = rows 0 and 1, 10 = row 0 and
  *     column 2 (the fermion force follows the FP64 entry);
@@ -375,10 +377,10 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
  *     tiled order, 2 = at most two (an unused LDS reservation keeps the
  *     wavefronts in flight close together in the walk), 0 = as many as
  *     registers allow.
- * Decision order: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES,
- * HMC_LINK_FORM = 18 / 12 / 10, HMC_LINK_STREAM = 0 / 1, HMC_DSLASH_ORDER =
- * 0 / 1 / n, HMC_DSLASH_OCC = 0 / 2) > table entry for the lattice extents >
- * built-in rule.
+ * Decision order: environment override (HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES
+ * = 0 / 1 / 2, HMC_LINK_FORM = 18 / 12 / 10, HMC_LINK_STREAM = 0 / 1,
+ * HMC_DSLASH_ORDER = 0 / 1 / n, HMC_DSLASH_OCC = 0 / 2) > table entry for
+ * the lattice extents > built-in rule.
  * HMC_TUNE_DB names a table file read on first use.  Table file: text lines
  * "kind L0 L1 L2 L3 prec choice us" with kind dslash, gauge_force,
  * dslash_links, gauge_force_links, dslash_stream, dslash_order or

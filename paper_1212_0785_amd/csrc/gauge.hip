@@ -30,6 +30,40 @@ __device__ __forceinline__ mat3<double> link(const Lat& g, const void* U, int mu
   return LK::load(U, g.stride, mu, site_parity(st), st.lex >> 1);
 }
 
+// Walk of the site-blocked gauge kernels.  A walk unit is a 64-site chunk
+// of one parity; consecutive units alternate the parities.  Where the
+// lattice admits it (tiled != 0) XCD x (blocks with blockIdx.x % 8 == x)
+// takes units 0, 1, ... of its own t-slices in the Dslash's tiled order,
+// y-blocks of kGfYBlock chunks (dslash_site in device.h); otherwise unit u
+// covers chunk u / 2 of parity u % 2 (u from XCD-contiguous block ranges).
+// The links a site's staples or plaquettes share with its neighbours' are
+// then fetched into L1 / L2 once for all four directions and both parities,
+// where a parity-major or direction-major sweep finds the +-z and +-t
+// neighbours long evicted.  *s may be >= Vh in the linear walk (ragged
+// last chunk).
+constexpr int kGfYBlock = 2;
+
+__device__ __forceinline__ void walk_site(const Lat& g, int xcd, int u, int* par, int* s) {
+  const int lane = threadIdx.x & 63;
+  *par = u & 1;
+  const int w = u >> 1;  // 64-site chunk, in walk order
+  if (g.tiled) {
+    const int c = w % g.tile_y, q = w / g.tile_y;
+    const int t = xcd * g.tile_t + q % g.tile_t, q2 = q / g.tile_t;
+    const int z = q2 % g.L[2], yb = q2 / g.L[2];
+    *s = t * g.slice + z * g.plane + (yb * g.tile_y + c) * 64 + lane;
+  } else {
+    *s = w * 64 + lane;
+  }
+}
+
+// The XCD-local (tiled) or global (linear) walk unit of block b scaled by
+// `per`, the units per block.
+__device__ __forceinline__ int walk_unit(const Lat& g, int per) {
+  if (g.tiled) return (blockIdx.x >> 3) * per;
+  return xcd_remap(blockIdx.x, gridDim.x) * per;
+}
+
 // Re Tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
 template <class LK, int MU, int NU>
 __device__ __forceinline__ double plaq(const Lat& g, const void* U, const Site& x) {
@@ -50,11 +84,14 @@ __device__ __forceinline__ Site plane_site(Site x, double& sp) {
   return x;
 }
 
+// Plaquette partial sums: a block of four wavefronts covers four walk
+// units, one work-item per site (all six planes), one partial per block.
 template <class LK>
 __global__ void __launch_bounds__(kBlock) k_plaquette_partials(Lat g, const void* U, double* part) {
+  int par, s;
+  walk_site(g, blockIdx.x & 7, walk_unit(g, 4) + (threadIdx.x >> 6), &par, &s);
   double v[1] = {0.0};
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < 2 * g.Vh; j += gridDim.x * kBlock) {
-    int par = j >= g.Vh, s = j - par * g.Vh;
+  if (s < g.Vh) {
     Site x = cb_site(g, par, s);
     // one plane at a time: the site of each plane passes through an empty
     // asm that also takes the running sum, so the loads of a plane cannot
@@ -67,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) k_plaquette_partials(Lat g, const void
     sp += plaq<LK, 1, 2>(g, U, plane_site(x, sp));
     sp += plaq<LK, 1, 3>(g, U, plane_site(x, sp));
     sp += plaq<LK, 2, 3>(g, U, plane_site(x, sp));
-    v[0] += sp;
+    v[0] = sp;
   }
   block_sum<1>(v);
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -170,6 +207,22 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force(Lat g, const void* U, do
   }
 }
 
+// Site-blocked form: a block of four wavefronts covers 64 sites of one
+// parity, wavefront w the links U_w of those sites (walk_site with the
+// block as the walk unit).
+template <class LK>
+__global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void* U, double* P, double coef_beta) {
+  int par, s;
+  walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
+  if (s >= g.Vh) return;
+  switch (threadIdx.x >> 6) {  // wavefront-uniform
+    case 0: gauge_force_link<LK, 0>(g, U, P, coef_beta, par, s); break;
+    case 1: gauge_force_link<LK, 1>(g, U, P, coef_beta, par, s); break;
+    case 2: gauge_force_link<LK, 2>(g, U, P, coef_beta, par, s); break;
+    default: gauge_force_link<LK, 3>(g, U, P, coef_beta, par, s); break;
+  }
+}
+
 // Plane-split form: a block of three wavefronts covers 64 links of one
 // direction MU; wavefront w sums the two staples of the w-th plane (MU, NU)
 // and parks them in LDS; after a barrier the first wavefront adds the three
@@ -244,19 +297,37 @@ __global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const dou
   LkF64::store(U, g.stride, mu, par, s, u);
 }
 
-hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st,
-                                     bool su3) {
+// Lattice argument of the site-blocked walk (tiled where admitted).
+static Lat walk_lat(const LatArg& g) {
+  Lat lat = to_lat(g);
+  if (tiled_order_valid(g)) {
+    lat.tiled = 1;
+    lat.plane = g.L[0] * g.L[1] / 2;
+    lat.slice = lat.plane * g.L[2];
+    lat.tile_r = lat.plane / 64;
+    lat.tile_t = g.L[3] / 8;
+    lat.tile_y = lat.tile_r % kGfYBlock == 0 ? kGfYBlock : lat.tile_r;
+  }
+  return lat;
+}
+
+int plaquette_blocks(const LatArg& g) {
+  return tiled_order_valid(g) ? g.Vh / 128 : ceil_div(2 * ceil_div(g.Vh, 64), 4);
+}
+
+hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, hipStream_t st, bool su3) {
   const int form = link_form_for(su3, staple_link_form(g));
   const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
                                                                                      : LkF64::kBytes;
   TimedScope ts(TK_PLAQUETTE, st, 2.0 * g.Vh * 4 * lb);
-  const dim3 grid(nb), block(kBlock);
+  const dim3 grid(plaquette_blocks(g)), block(kBlock);
+  const Lat lat = walk_lat(g);
   if (form == LINK_ROWCOL)
-    hipLaunchKernelGGL(k_plaquette_partials<LkRowCol<LkF64>>, grid, block, 0, st, to_lat(g), U, part);
+    hipLaunchKernelGGL(k_plaquette_partials<LkRowCol<LkF64>>, grid, block, 0, st, lat, U, part);
   else if (form == LINK_ROWS2)
-    hipLaunchKernelGGL(k_plaquette_partials<LkRows2<LkF64>>, grid, block, 0, st, to_lat(g), U, part);
+    hipLaunchKernelGGL(k_plaquette_partials<LkRows2<LkF64>>, grid, block, 0, st, lat, U, part);
   else
-    hipLaunchKernelGGL(k_plaquette_partials<LkF64>, grid, block, 0, st, to_lat(g), U, part);
+    hipLaunchKernelGGL(k_plaquette_partials<LkF64>, grid, block, 0, st, lat, U, part);
   return hipGetLastError();
 }
 
@@ -268,7 +339,10 @@ hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* par
 
 template <class LK>
 static void gauge_force_typed(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st, int shape) {
-  if (shape == 1)
+  if (shape == 2) {
+    hipLaunchKernelGGL(k_gauge_force_sites<LK>, dim3(2 * ceil_div(g.Vh, 64)), dim3(kBlock), 0, st, walk_lat(g), U,
+                       P, coef_beta);
+  } else if (shape == 1)
     hipLaunchKernelGGL(k_gauge_force_planes<LK>, dim3(ceil_div(2LL * g.Vh, kGfSites), 4), dim3(3 * kGfSites), 0, st,
                        to_lat(g), U, P, coef_beta);
   else

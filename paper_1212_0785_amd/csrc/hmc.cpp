@@ -330,6 +330,13 @@ static hipError_t finalize_to_slot(Fields* F, const double* part, int n, int nva
   return launch_finalize(part, n, nvals, F->slots + slot, 1.0, 0, st);
 }
 
+// Sum over x, mu < nu of Re Tr U_mu nu(x) into a slot (partials in part[0]).
+static hipError_t plaquette_to_slot(Fields* F, int slot, hipStream_t st) {
+  hipError_t e = launch_plaquette_partials(F->g, F->U, F->part[0], st, F->su3);
+  if (e != hipSuccess) return e;
+  return finalize_to_slot(F, F->part[0], plaquette_blocks(F->g), 1, slot, st);
+}
+
 }  // namespace hmc
 
 using namespace hmc;
@@ -650,8 +657,7 @@ hmc_status hmc_plaquette(hmc_fields* f, double* out, void* stream) {
   HMC_REQUIRE(out, "null output");
   hipStream_t st = ST(stream);
   double sum;
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], F->nbR, 1, SL_RED, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &sum, st));
   *out = sum / (18.0 * F->V);
   return HMC_OK;
@@ -662,8 +668,7 @@ hmc_status hmc_gauge_action(hmc_fields* f, double* out, void* stream) {
   HMC_REQUIRE(out, "null output");
   hipStream_t st = ST(stream);
   double sum;
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], F->nbR, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], F->nbR, 1, SL_RED, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &sum, st));
   *out = F->beta * (6.0 * F->V - sum / 3.0);
   return HMC_OK;
@@ -911,8 +916,7 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
   const int nb = F->nbR;
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_OLD, st));
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_OLD, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_PLAQ_OLD, st));
   HMC_CHECK_HIP(launch_norm2_partials(F->g, HMC_F64, F->eta, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_ETA2, st));
 
@@ -922,8 +926,7 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
 
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_NEW, st));
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_NEW, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_PLAQ_NEW, st));
   HMC_CHECK_HIP(launch_inner_partials(F->g, F->phi, F->Xe, F->part[1], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_PHIX, st));
   HMC_CHECK_HIP(launch_metropolis(seed, traj, F->beta, (double)F->V, F->slots, st));
@@ -937,8 +940,7 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
     F->su3 = F->su3_old;
   }
   double plaq_sum;
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &plaq_sum, st));
 
   res->KE_old = sl[SL_KE_OLD];
@@ -1206,8 +1208,7 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
   const int nb = F->nbR;
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_OLD, st));
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_OLD, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_PLAQ_OLD, st));
   // S_1 + S_2 = |eta_1|^2 + |eta_2|^2 into SL_ETA2 (parts in SL_RED + 0, + 1)
   HMC_CHECK_HIP(launch_norm2_partials(F->g, HMC_F64, F->eta, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED + 0, st));
@@ -1224,8 +1225,7 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
 
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_NEW, st));
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_PLAQ_NEW, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_PLAQ_NEW, st));
   // S_1 = <phi_1, X_1>, S_2 = <chi, X_2> at the final links (SL_RED + 2.., + 4..)
   HMC_CHECK_HIP(launch_inner_partials(F->g, F->phi, F->Xe, F->part[1], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[1], nb, 2, SL_RED + 2, st));
@@ -1246,8 +1246,7 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
     F->su3 = F->su3_old;
   }
   double plaq_sum;
-  HMC_CHECK_HIP(launch_plaquette_partials(F->g, F->U, F->part[0], nb, st, F->su3));
-  HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED, st));
+  HMC_CHECK_HIP(plaquette_to_slot(F, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, &plaq_sum, st));
 
   stats->S1_old = parts[0];
@@ -1393,7 +1392,7 @@ hmc_status hmc_autotune(hmc_fields* f, const char* db_path, void* stream) {
     int best = -1, best_form = 0;
     double best_us = 0;
     for (int form : forms) {
-      for (int shape : {0, 1}) {
+      for (int shape : {0, 1, 2}) {
         auto launch = [&] {
           return launch_gauge_force(F->g, F->U, F->P, 0.0, st, F->su3, shape, form) == hipSuccess;
         };

@@ -210,10 +210,11 @@ hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStre
 
 // Gauge-field kernels.
 // su3: U is SU(3) to rounding (compact link forms allowed).
-hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, int nb, hipStream_t st,
-                                     bool su3);
+// One partial per block, plaquette_blocks(g) of them (at most Vh / 64).
+int plaquette_blocks(const LatArg& g);
+hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, hipStream_t st, bool su3);
 hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* part, int nb, hipStream_t st);
-// shape: -1 = gauge_force_shape(), 0 / 1 = fixed; form: 0 =
+// shape: -1 = gauge_force_shape(), 0 / 1 / 2 = fixed; form: 0 =
 // staple_link_form(), else a fixed compact form (used on SU(3) links only).
 hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st,
                               bool su3, int shape = -1, int form = 0);

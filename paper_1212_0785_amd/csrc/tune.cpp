@@ -2,7 +2,8 @@
 // (the auto-tuner of Sec. 4, for the choices this library offers): per
 // lattice and storage, the Dslash shape (one site per work-item, 2- or
 // 4-way direction split), its link streaming, site order and workgroups per
-// CU, the staple-force shape (one link per work-item or plane split), and
+// CU, the staple-force shape (one link per work-item, plane split, or four
+// directions of 64 sites per block in the tiled walk), and
 // the compact link form of the hop and staple kernels (two rows, or row 0
 // and column 2).
 //
@@ -63,7 +64,7 @@ int kind_of(const char* name) {
 bool valid_choice(int kind, int c) {
   switch (kind) {
     case TUNE_DSLASH: return c == 1 || c == 2 || c == 4;
-    case TUNE_GFORCE:
+    case TUNE_GFORCE: return c == 0 || c == 1 || c == 2;
     case TUNE_DSLASH_STREAM: return c == 0 || c == 1;
     case TUNE_DSLASH_ORDER: return c >= 0 && c <= kMaxYBlock;
     case TUNE_DSLASH_OCC: return c == 0 || c == 2;
@@ -143,7 +144,8 @@ int tune_save(const char* path) {
   std::fprintf(f,
                "# kind L0 L1 L2 L3 prec choice us\n"
                "# dslash: choice 1 = one site per work-item, 2|4 = direction split; us per CG iteration in a solve\n"
-               "# gauge_force: choice 0 = one link per work-item, 1 = plane split; us per launch\n"
+               "# gauge_force: choice 0 = one link per work-item, 1 = plane split, 2 = four directions of 64 sites per "
+               "block; us per launch\n"
                "# dslash_links, gauge_force_links: reals read per SU(3) link, 12 = two rows, 10 = row 0 and column 2\n"
                "# dslash_stream: 1 = non-temporal link loads and output stores\n"
                "# dslash_order: 1 = tiled site order (one site per work-item shape), n >= 2 = tiled in y-blocks of n "
@@ -234,12 +236,13 @@ int dslash_shape(const LatArg& g, hmc_prec prec) {
 
 int gauge_force_shape(const LatArg& g) {
   static const int forced = env_int("HMC_GFORCE_PLANES");
-  if (forced >= 0) return forced != 0;
+  if (forced >= 0) return forced == 0 ? 0 : forced == 2 ? 2 : 1;
   const int t = tune_lookup(g.L, TUNE_GFORCE, HMC_F64);
   if (t >= 0) return t;
-  // measured on MI355X: the plane split is 6% faster at 48^3x96 and 20%
-  // slower at 16^3x32
-  return g.Vh > (1 << 20) ? 1 : 0;
+  // measured on MI355X: four directions per block in the tiled walk are
+  // 27% faster than one link per work-item at 48^3x96 and 13% faster at
+  // 16^3x32 (the plane split: 6% slower and 20% slower)
+  return 2;
 }
 
 }  // namespace hmc

@@ -87,3 +87,41 @@ def test_tiled_order_solves(H, tmp_path, L):
         st = H.hmc_cg_solve(F, x, bb, H.cg_params(tol=1e-10, prec=prec, maxiter=20000))
         assert st["status"] == 0 and st["true_rel_res"] <= 1e-10, prec
         assert rel(get_spinor(H, F, x, 0), want) < 1e-8, prec
+
+
+# (lattice, site walk of the site-blocked staple force): 144 sites per
+# parity = two whole chunks and a ragged one (linear walk); one chunk per
+# z-plane (tiled, whole planes); six chunks per z-plane (y-blocks of two)
+GF_L = [(6, 4, 2, 6), (16, 8, 4, 8), (48, 16, 4, 8)]
+
+
+@pytest.mark.parametrize("L", GF_L)
+def test_staple_force_shapes(H, tmp_path, L):
+    """Every staple-force shape and link form against the oracle; the
+    site-blocked shape runs the per-link code of the direction-major one on
+    other work-items, so the two agree bit for bit."""
+    from tests.test_gpu_parity import get_momenta, put_momenta
+    ext = " ".join(map(str, L))
+    P0 = synth.hermitian_traceless(81, L)
+    for field, forms in (("su3", (10, 12)), ("u3", (18,))):
+        U = synth.gauge_field(82, L, eps=0.6)
+        if field == "u3":  # det != 1: all nine entries are read
+            U = U * np.exp(1j * synth.rng(83).uniform(0.3, 2.5, size=U.shape[:-2]))[..., None, None]
+        want = P0 - 0.05 * O.gauge_force(L, U, 5.7)
+        for form in forms:
+            got = {}
+            for shape in (0, 1, 2):
+                path = tmp_path / f"gf_{field}_{form}_{shape}.txt"
+                path.write_text(f"gauge_force {ext} 0 {shape} 0\n" +
+                                (f"gauge_force_links {ext} 0 {form} 0\n" if form != 18 else ""))
+                H.hmc_tune_load(str(path))
+                assert H.hmc_tune_query(L, H.TUNE_GAUGE_FORCE) == (shape, True)
+                F = H.Fields(L, 5.7, 0.15)
+                put_gauge(H, F, U)
+                assert H.hmc_links_two_row(F) == (field == "su3")
+                put_momenta(H, F, P0)
+                H.hmc_gauge_force(F, 0.05)
+                got[shape] = get_momenta(H, F)
+                assert rel(got[shape], want) < 1e-13, (field, form, shape)
+                del F
+            assert np.array_equal(got[0], got[2]), (field, form)

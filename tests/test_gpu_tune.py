@@ -55,3 +55,42 @@ def test_autotune_then_parity(H, tmp_path):
     put_momenta(H, F, P)
     H.hmc_gauge_force(F, 0.3)
     assert rel(get_momenta(H, F), P - 0.3 * O.gauge_force(L, U, 5.6)) < 1e-13
+
+
+def test_autotune_site_orders_then_parity(H, tmp_path):
+    """A lattice that admits the tiled order and y-blocks (32 x 16 / 2 = 256
+    sites per z-plane = 4 chunks: whole planes or y-blocks of 2): the tuner
+    times the orders x workgroups per CU for the one-site shape, stores its
+    choice for every storage, and the Dslash and a solve reproduce the oracle
+    under it."""
+    L = (32, 16, 4, 8)
+    k = 0.15
+    F = H.Fields(L, 5.6, k, flags=H.FIELDS_LOWPREC)
+    U = synth.gauge_field(71, L, eps=0.5)
+    put_gauge(H, F, U)
+    db = tmp_path / "tune.txt"
+    H.hmc_autotune(F, str(db))
+    kinds = {ln.split()[0] for ln in db.read_text().splitlines() if ln and not ln.startswith("#")}
+    assert {"dslash_order", "dslash_occupancy"} <= kinds
+    for prec in (0, 1, 2, 3):
+        order, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_ORDER, prec)
+        assert tuned and order in (0, 1, 2), (prec, order)
+        occ, tuned = H.hmc_tune_query(L, H.TUNE_DSLASH_OCC, prec)
+        assert tuned and occ in (0, 2), (prec, occ)
+    psi = synth.spinor(72, L)
+    for par, dag in ((0, 0), (1, 1)):
+        want = O.dslash(L, U, psi, par, dag)
+        for prec, tol in ((0, 1e-14), (1, 1e-6), (2, 3e-3), (3, 2e-2)):
+            b = put_spinor(H, F, psi, 1 - par, prec=prec)
+            out = F.spinor(prec=prec)
+            H.hmc_wilson_dslash(F, out, b, par, dag, prec)
+            assert rel(get_spinor(H, F, out, par, prec=prec), want) < tol, (prec, par, dag)
+    odd = O.parity_mask(L)
+    b = synth.spinor(73, L, odd, 0)
+    want, _ = O.cg_mhat(L, U, k, b, tol=1e-12)
+    bb = put_spinor(H, F, b, 0)
+    for prec in (0, 1, 2):
+        x = F.spinor()
+        st = H.hmc_cg_solve(F, x, bb, H.cg_params(tol=1e-10, prec=prec, maxiter=20000))
+        assert st["status"] == 0 and st["true_rel_res"] <= 1e-10, prec
+        assert rel(get_spinor(H, F, x, 0), want) < 1e-8, prec

@@ -30,10 +30,11 @@ def test_table_load_query_and_save(H, tmp_path):
     assert H.hmc_tune_query((6, 2, 2, 10), H.TUNE_DSLASH, H.F32) == (4, True)
     assert H.hmc_tune_query((6, 2, 2, 10), H.TUNE_GAUGE_FORCE) == (1, True)
     # untuned entries follow the built-in rule (small volume: F64 one site
-    # per work-item, FP32 arithmetic 4-way split, staple force unsplit)
+    # per work-item, FP32 arithmetic 4-way split, staple force four
+    # directions per block)
     assert H.hmc_tune_query((6, 2, 2, 10), H.TUNE_DSLASH, H.F16) == (4, False)
     assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_DSLASH, H.F64) == (1, False)
-    assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_GAUGE_FORCE) == (0, False)
+    assert H.hmc_tune_query((4, 4, 4, 6), H.TUNE_GAUGE_FORCE) == (2, False)
     # save merges with what the file already holds
     dst = tmp_path / "out.txt"
     dst.write_text("dslash 2 2 2 2 0 4 3.0\n")
