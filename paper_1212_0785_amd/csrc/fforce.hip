@@ -10,6 +10,7 @@
 // h_j(b)^dag, so each trace is two colour outer products.
 #include "device.h"
 #include "internal.h"
+#include "walk.h"
 
 namespace hmc {
 
@@ -63,13 +64,16 @@ __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, 
   store_compact(P, g.stride, MU, par, s, c);
 }
 
+// A block of four wavefronts covers 64 sites of one parity, wavefront w the
+// links U_w (walk_site with the block as the walk unit), so X and Y at a
+// site and its neighbours are fetched once for all four directions.
 template <class LK>
 __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, ForceVecs v, double* P,
                                                           double c_ta) {
-  int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= 2 * g.Vh) return;
-  int par = j >= g.Vh, s = j - par * g.Vh;
-  switch (blockIdx.y) {
+  int par, s;
+  walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
+  if (s >= g.Vh) return;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // the wavefront, as a scalar
     case 0: fermion_force_link<LK, 0>(g, U, v, P, c_ta, par, s); break;
     case 1: fermion_force_link<LK, 1>(g, U, v, P, c_ta, par, s); break;
     case 2: fermion_force_link<LK, 2>(g, U, v, P, c_ta, par, s); break;
@@ -93,14 +97,15 @@ hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, 
   v.X[1] = Xo;
   v.Y[0] = Ye;
   v.Y[1] = Yo;
-  const dim3 grid(ceil_div(2LL * g.Vh, kBlock), 4), block(kBlock);
+  const dim3 grid(2 * ceil_div(g.Vh, 64)), block(kBlock);
   const double c = -0.5 * coef;
+  const Lat lat = walk_lat(g);
   if (form == LINK_ROWCOL)
-    hipLaunchKernelGGL(k_fermion_force<LkRowCol<LkF64>>, grid, block, 0, st, to_lat(g), U, v, P, c);
+    hipLaunchKernelGGL(k_fermion_force<LkRowCol<LkF64>>, grid, block, 0, st, lat, U, v, P, c);
   else if (form == LINK_ROWS2)
-    hipLaunchKernelGGL(k_fermion_force<LkRows2<LkF64>>, grid, block, 0, st, to_lat(g), U, v, P, c);
+    hipLaunchKernelGGL(k_fermion_force<LkRows2<LkF64>>, grid, block, 0, st, lat, U, v, P, c);
   else
-    hipLaunchKernelGGL(k_fermion_force<LkF64>, grid, block, 0, st, to_lat(g), U, v, P, c);
+    hipLaunchKernelGGL(k_fermion_force<LkF64>, grid, block, 0, st, lat, U, v, P, c);
   return hipGetLastError();
 }
 

@@ -1,13 +1,15 @@
 // Gauge-field kernels of the HMC step list (Sec. 1): the plaquette / gauge
 // action sum, the staple force fused with the momentum update, the link
 // update exp(i eps P) U with SU(3) reunitarisation, and the kinetic sum.
-// One work-item per (site, direction) for the force and the link update
-// (direction from blockIdx.y, so the direction is uniform in a block and
-// resolved at compile time), one per site for the sums.
+// One work-item per (site, direction) for the force and the link update:
+// the direction is uniform in a wavefront and resolved at compile time
+// (from blockIdx.y in the direction-major forms, from the wavefront in the
+// site-blocked one); one work-item per site for the sums.
 #include <cstdlib>
 
 #include "device.h"
 #include "internal.h"
+#include "walk.h"
 
 namespace hmc {
 
@@ -28,40 +30,6 @@ __device__ __forceinline__ int site_parity(const Site& st) { return (st.c[0] + s
 template <class LK>
 __device__ __forceinline__ mat3<double> link(const Lat& g, const void* U, int mu, const Site& st) {
   return LK::load(U, g.stride, mu, site_parity(st), st.lex >> 1);
-}
-
-// Walk of the site-blocked gauge kernels.  A walk unit is a 64-site chunk
-// of one parity; consecutive units alternate the parities.  Where the
-// lattice admits it (tiled != 0) XCD x (blocks with blockIdx.x % 8 == x)
-// takes units 0, 1, ... of its own t-slices in the Dslash's tiled order,
-// y-blocks of kGfYBlock chunks (dslash_site in device.h); otherwise unit u
-// covers chunk u / 2 of parity u % 2 (u from XCD-contiguous block ranges).
-// The links a site's staples or plaquettes share with its neighbours' are
-// then fetched into L1 / L2 once for all four directions and both parities,
-// where a parity-major or direction-major sweep finds the +-z and +-t
-// neighbours long evicted.  *s may be >= Vh in the linear walk (ragged
-// last chunk).
-constexpr int kGfYBlock = 2;
-
-__device__ __forceinline__ void walk_site(const Lat& g, int xcd, int u, int* par, int* s) {
-  const int lane = threadIdx.x & 63;
-  *par = u & 1;
-  const int w = u >> 1;  // 64-site chunk, in walk order
-  if (g.tiled) {
-    const int c = w % g.tile_y, q = w / g.tile_y;
-    const int t = xcd * g.tile_t + q % g.tile_t, q2 = q / g.tile_t;
-    const int z = q2 % g.L[2], yb = q2 / g.L[2];
-    *s = t * g.slice + z * g.plane + (yb * g.tile_y + c) * 64 + lane;
-  } else {
-    *s = w * 64 + lane;
-  }
-}
-
-// The XCD-local (tiled) or global (linear) walk unit of block b scaled by
-// `per`, the units per block.
-__device__ __forceinline__ int walk_unit(const Lat& g, int per) {
-  if (g.tiled) return (blockIdx.x >> 3) * per;
-  return xcd_remap(blockIdx.x, gridDim.x) * per;
 }
 
 // Re Tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
@@ -215,7 +183,7 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void*
   int par, s;
   walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
   if (s >= g.Vh) return;
-  switch (threadIdx.x >> 6) {  // wavefront-uniform
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // the wavefront, as a scalar
     case 0: gauge_force_link<LK, 0>(g, U, P, coef_beta, par, s); break;
     case 1: gauge_force_link<LK, 1>(g, U, P, coef_beta, par, s); break;
     case 2: gauge_force_link<LK, 2>(g, U, P, coef_beta, par, s); break;
@@ -295,20 +263,6 @@ __global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const dou
   mat3<double> u = mmul(E, LkF64::load(U, g.stride, mu, par, s));
   reunitarise(u);
   LkF64::store(U, g.stride, mu, par, s, u);
-}
-
-// Lattice argument of the site-blocked walk (tiled where admitted).
-static Lat walk_lat(const LatArg& g) {
-  Lat lat = to_lat(g);
-  if (tiled_order_valid(g)) {
-    lat.tiled = 1;
-    lat.plane = g.L[0] * g.L[1] / 2;
-    lat.slice = lat.plane * g.L[2];
-    lat.tile_r = lat.plane / 64;
-    lat.tile_t = g.L[3] / 8;
-    lat.tile_y = lat.tile_r % kGfYBlock == 0 ? kGfYBlock : lat.tile_r;
-  }
-  return lat;
 }
 
 int plaquette_blocks(const LatArg& g) {

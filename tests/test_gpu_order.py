@@ -99,7 +99,8 @@ GF_L = [(6, 4, 2, 6), (16, 8, 4, 8), (48, 16, 4, 8)]
 def test_staple_force_shapes(H, tmp_path, L):
     """Every staple-force shape and link form against the oracle; the
     site-blocked shape runs the per-link code of the direction-major one on
-    other work-items, so the two agree bit for bit."""
+    other work-items, so the two agree bit for bit.  The plaquette sum walks
+    the sites the same way."""
     from tests.test_gpu_parity import get_momenta, put_momenta
     ext = " ".join(map(str, L))
     P0 = synth.hermitian_traceless(81, L)
@@ -108,6 +109,7 @@ def test_staple_force_shapes(H, tmp_path, L):
         if field == "u3":  # det != 1: all nine entries are read
             U = U * np.exp(1j * synth.rng(83).uniform(0.3, 2.5, size=U.shape[:-2]))[..., None, None]
         want = P0 - 0.05 * O.gauge_force(L, U, 5.7)
+        want_plaq = O.plaquette(L, U)
         for form in forms:
             got = {}
             for shape in (0, 1, 2):
@@ -123,5 +125,6 @@ def test_staple_force_shapes(H, tmp_path, L):
                 H.hmc_gauge_force(F, 0.05)
                 got[shape] = get_momenta(H, F)
                 assert rel(got[shape], want) < 1e-13, (field, form, shape)
+                assert abs(H.hmc_plaquette(F) - want_plaq) < 1e-13, (field, form)
                 del F
             assert np.array_equal(got[0], got[2]), (field, form)
