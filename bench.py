@@ -248,7 +248,8 @@ def run_hmc(args, H, torch):
     if rf:
         out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": rf["achieved"] / HBM_PEAK_GBS, "traffic": load_traffic("hmc_16c32"),
-                           "kernel": ("k_dslash F64 (half-lattice hop; plain, axpy/norm and CG-update "
+                           "kernel": ("F64 half-lattice hop, k_dslash or k_dslash_split (shape in "
+                                      "config.launch_shapes.dslash_f64; plain, axpy/norm and CG-update "
                                       "epilogues; link form in config.launch_shapes.dslash_links_f64)"),
                            "avg_launch_ms": rf["avg_ms"], "bytes_per_launch": rf["bytes_per_launch"],
                            "launches_timed": rf["launches_timed"]}
