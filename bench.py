@@ -53,15 +53,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
+# F64 Dslash launch decisions a committed counter figure depends on
+TRAFFIC_LAUNCH_KEYS = ("dslash_f64", "dslash_links_f64", "dslash_stream_f64", "dslash_order_f64",
+                       "dslash_occupancy_f64")
+
+
+def load_traffic(workload: str, launch=None):
     """HBM bytes per Dslash launch from the committed rocprofv3 counter runs,
-    or None when the kernel changed since they were taken."""
+    or None when the kernel source or (given `launch`, the choices of
+    TRAFFIC_LAUNCH_KEYS in force) the launch changed since they were taken."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     e = d.get(workload)
     if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    if launch is not None and e.get("launch") != launch:
         return None
     return e.get("bytes_per_launch")
 
@@ -683,6 +691,8 @@ def main():
             out["roofline"]["stream"] = out["config"]["launch_shapes"]["dslash_stream_f64"][0]
             out["roofline"]["tiled_order"] = out["config"]["launch_shapes"]["dslash_order_f64"][0]
             out["roofline"]["tiled_occupancy"] = out["config"]["launch_shapes"]["dslash_occupancy_f64"][0]
+            launch = {k: out["config"]["launch_shapes"][k][0] for k in TRAFFIC_LAUNCH_KEYS}
+            out["roofline"]["traffic"] = load_traffic(out["config"]["workload"], launch)
     print(json.dumps(out))
 
 
