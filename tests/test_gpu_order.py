@@ -128,3 +128,24 @@ def test_staple_force_shapes(H, tmp_path, L):
                 assert abs(H.hmc_plaquette(F) - want_plaq) < 1e-13, (field, form)
                 del F
             assert np.array_equal(got[0], got[2]), (field, form)
+
+
+@pytest.mark.parametrize("L", GF_L)
+def test_fermion_force_walk(H, L):
+    """The fermion force in the site-blocked walk (linear with a ragged
+    chunk, tiled by whole planes, tiled by y-blocks) against the oracle."""
+    from tests.test_gpu_parity import get_momenta, put_momenta
+    k = 0.13
+    U = synth.gauge_field(91, L, eps=0.6)
+    odd = O.parity_mask(L)
+    Xe, Ye = synth.spinor(92, L, odd, 0), synth.spinor(93, L, odd, 0)
+    P = synth.hermitian_traceless(94, L)
+    X, Y = Xe.copy(), Ye.copy()
+    X[odd] = O.dslash(L, U, Xe, 1)[odd]
+    Y[odd] = O.dslash(L, U, Ye, 1, dagger=True)[odd]
+    want = P - 0.37 * O.fermion_force(L, U, k ** 2, X, Y)
+    F = H.Fields(L, 5.6, 0.15)
+    put_gauge(H, F, U)
+    put_momenta(H, F, P)
+    H.hmc_fermion_force_bilinear(F, put_spinor(H, F, Xe, 0), put_spinor(H, F, Ye, 0), k, 0.37)
+    assert rel(get_momenta(H, F), want) < 1e-13
