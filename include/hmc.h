@@ -369,10 +369,12 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
  *   HMC_TUNE_DSLASH_ORDER (per storage precision): 1 = the one-site-per-
  *     work-item Dslash walks each XCD's t-slices z-plane by z-plane, t-slice
  *     by t-slice, so neighbour spinors are reused in that XCD's L2 (lattices
- *     with L0 L1 / 2 a multiple of 64, L3 a multiple of 8 and Vh a multiple
- *     of 2048); n >= 2 = the same walk over y-blocks of n 64-site chunks of
- *     each z-plane in turn, so several z-planes are in flight at once (n
- *     divides L0 L1 / 128, n <= 64; any other n reads as 1);
+ *     with L3 a multiple of 8, Vh a multiple of 2048 and L0 L1 / 2 a
+ *     multiple of 64; where only L0 L1 L2 / 2 is, the walk takes the 64-site
+ *     chunks of the t-slices, t-slice fastest); n >= 2 = the z-plane walk
+ *     over y-blocks of n 64-site chunks of each z-plane in turn, so several
+ *     z-planes are in flight at once (n divides L0 L1 / 128, n <= 64; any
+ *     other n reads as 1);
  *   HMC_TUNE_DSLASH_OCC (per storage precision): workgroups per CU of the
  *     tiled order, 2 = at most two (an unused LDS reservation keeps the
  *     wavefronts in flight close together in the walk), 0 = as many as

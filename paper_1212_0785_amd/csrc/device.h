@@ -367,7 +367,9 @@ struct Lat {
   // Tiled site order of the one-site-per-work-item Dslash (tiled = 0: the
   // linear order with XCD-contiguous ranges): checkerboard sites per z-plane
   // and per t-slice, 64-site chunks per z-plane, t-slices per XCD, chunks
-  // per y-block (tile_y = tile_r: the whole plane is one block).
+  // per y-block (tile_y = tile_r: the whole plane is one block; tile_y = 0:
+  // the z-planes are not whole chunks and the walk takes the chunks of the
+  // t-slices instead).
   int tiled, plane, slice, tile_r, tile_t, tile_y;
 };
 
@@ -453,15 +455,19 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // once and the neighbours they share are still in the XCD's L2, where the
 // linear order has the t neighbours a whole t-slice (tens of MB of traffic)
 // away.  Only the +-y neighbours of the two edge rows of a y-block and the
-// +-t neighbours across XCDs are read a second time from beyond L2.
+// +-t neighbours across XCDs are read a second time from beyond L2.  Where
+// a z-plane is not a whole number of chunks (tile_y = 0) the XCD walks the
+// 64-site chunks of its t-slices, t-slice fastest: the +-t neighbours are
+// then one wavefront away and the +-z neighbours tile_t plane / 64.
 __device__ __forceinline__ int dslash_site(const Lat& g, int* part) {
   if (g.tiled) {
     const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
     const int w = k * 4 + (threadIdx.x >> 6);  // wavefront of this XCD, in walk order
+    *part = blockIdx.x;
+    if (g.tile_y == 0) return (xcd * g.tile_t + w % g.tile_t) * g.slice + (w / g.tile_t) * 64 + (threadIdx.x & 63);
     const int c = w % g.tile_y, q = w / g.tile_y;
     const int t = xcd * g.tile_t + q % g.tile_t, q2 = q / g.tile_t;
     const int z = q2 % g.L[2], yb = q2 / g.L[2];
-    *part = blockIdx.x;
     return t * g.slice + z * g.plane + (yb * g.tile_y + c) * 64 + (threadIdx.x & 63);
   }
   const int b = xcd_remap(blockIdx.x, gridDim.x);

@@ -293,9 +293,9 @@ static hipError_t launch_typed(hmc_prec prec, int dagger, int epi, const LatArg&
     g.tiled = 1;
     g.plane = ga.L[0] * ga.L[1] / 2;
     g.slice = g.plane * ga.L[2];
-    g.tile_r = g.plane / 64;
+    g.tile_r = g.plane % 64 == 0 ? g.plane / 64 : 0;
     g.tile_t = ga.L[3] / 8;
-    g.tile_y = order == 1 ? g.tile_r : order;
+    g.tile_y = order == 1 ? g.tile_r : order;  // 0: chunks of the t-slices
   }
   const int ways = shape == 1 ? 0 : shape;
   const dim3 grid(dslash_shape_blocks(ga.Vh, shape), nbatch);

@@ -65,9 +65,10 @@ bool dslash_link_stream(const LatArg& g, hmc_prec prec);
 // Site order of the one-site-per-work-item Dslash (dslash_site in
 // device.h): 0 linear, 1 tiled with whole z-planes, n >= 2 tiled with
 // y-blocks of n 64-site chunks.  The lattice admits the tiled order with
-// whole 256-site blocks, a multiple of 8 of them, 64-site chunks per z-plane
-// and a multiple of 8 t-slices; y-blocks of n chunks need n to divide the
-// chunks per plane.
+// whole 256-site blocks, a multiple of 8 of them, a multiple of 8 t-slices
+// and 64-site chunks per z-plane, or else per t-slice (then order 1 walks
+// the chunks of the t-slices, t fastest); y-blocks of n chunks need whole
+// chunks per z-plane and n to divide their number.
 int dslash_tiled_order(const LatArg& g, hmc_prec prec);
 constexpr int kMaxYBlock = 64;  // largest y-block, in chunks
 // Workgroups per CU of the tiled-order Dslash: 2 (an LDS reservation keeps
@@ -75,9 +76,9 @@ constexpr int kMaxYBlock = 64;  // largest y-block, in chunks
 // many as registers allow).
 int dslash_tiled_occupancy(const LatArg& g, hmc_prec prec);
 inline bool tiled_order_valid(const LatArg& g, int order = 1) {
-  const int plane = g.L[0] * g.L[1] / 2;
-  if (!(g.Vh % kThreads == 0 && (g.Vh / kThreads) % 8 == 0 && plane % 64 == 0 && g.L[3] % 8 == 0)) return false;
-  return order == 1 || (order >= 2 && order <= kMaxYBlock && (plane / 64) % order == 0);
+  const int plane = g.L[0] * g.L[1] / 2, slice = plane * g.L[2];
+  if (!(g.Vh % kThreads == 0 && (g.Vh / kThreads) % 8 == 0 && slice % 64 == 0 && g.L[3] % 8 == 0)) return false;
+  return order == 1 || (order >= 2 && order <= kMaxYBlock && plane % 64 == 0 && (plane / 64) % order == 0);
 }
 // The form a kernel reads: the compact one on SU(3) links, else all entries.
 inline int link_form_for(bool su3, int compact) { return su3 ? compact : (int)LINK_FULL; }

@@ -18,8 +18,10 @@ pytestmark = pytest.mark.gpu
 # extents that admit the tiled order and that no other test uses (their
 # table entries leave the other tests' lattices alone), with the (tiled
 # order, workgroups per CU) pairs tried on each: 48 x 16 / 2 = 384 sites
-# per z-plane = 6 chunks, so y-blocks of 2 and 3 chunks
-ORDER_L = [(16, 8, 4, 8), (16, 16, 4, 16), (48, 16, 4, 8)]
+# per z-plane = 6 chunks, so y-blocks of 2 and 3 chunks; 24 x 12 / 2 = 144
+# sites per z-plane, not whole chunks, 1152 per t-slice: the walk over the
+# chunks of the t-slices
+ORDER_L = [(16, 8, 4, 8), (16, 16, 4, 16), (48, 16, 4, 8), (24, 12, 8, 16)]
 ORDERS = {(48, 16, 4, 8): ((1, 2), (2, 2), (3, 2), (3, 0))}
 
 
@@ -91,8 +93,9 @@ def test_tiled_order_solves(H, tmp_path, L):
 
 # (lattice, site walk of the site-blocked staple force): 144 sites per
 # parity = two whole chunks and a ragged one (linear walk); one chunk per
-# z-plane (tiled, whole planes); six chunks per z-plane (y-blocks of two)
-GF_L = [(6, 4, 2, 6), (16, 8, 4, 8), (48, 16, 4, 8)]
+# z-plane (tiled, whole planes); six chunks per z-plane (y-blocks of two);
+# z-planes not whole chunks (tiled, chunks of the t-slices)
+GF_L = [(6, 4, 2, 6), (16, 8, 4, 8), (48, 16, 4, 8), (24, 12, 8, 16)]
 
 
 @pytest.mark.parametrize("L", GF_L)

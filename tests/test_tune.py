@@ -92,17 +92,19 @@ def test_order_entries_need_an_admissible_lattice(H, tmp_path):
         pytest.skip("environment overrides the table")
     src = tmp_path / "order.txt"
     src.write_text("dslash_order 16 8 4 8 0 1 1.0\n"     # admissible
-                   "dslash_order 6 4 4 10 0 1 1.0\n"     # 6*4/2 = 12 sites per z-plane: not a multiple of 64
+                   "dslash_order 6 4 4 10 0 1 1.0\n"     # 6*4*4/2 = 48 sites per t-slice: not a multiple of 64
                    "dslash_order 48 16 4 8 0 3 1.0\n"    # 384 sites per z-plane = 6 chunks: y-blocks of 3
                    "dslash_order 48 16 4 8 1 4 1.0\n"    # 4 does not divide 6: whole z-planes
-                   "dslash_order 48 16 4 8 2 65 1.0\n")  # beyond 64 chunks: ignored
-    assert H.hmc_tune_load(str(src)) == 4
+                   "dslash_order 48 16 4 8 2 65 1.0\n"   # beyond 64 chunks: ignored
+                   "dslash_order 24 12 8 16 0 2 1.0\n")  # z-planes not whole chunks: the t-slice walk (1)
+    assert H.hmc_tune_load(str(src)) == 5
     assert H.hmc_tune_query((16, 8, 4, 8), H.TUNE_DSLASH_ORDER, H.F64) == (1, True)
     assert H.hmc_tune_query((6, 4, 4, 10), H.TUNE_DSLASH_ORDER, H.F64) == (0, True)
     assert H.hmc_tune_query((16, 8, 4, 8), H.TUNE_DSLASH_ORDER, H.F32) == (0, False)
     assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_ORDER, H.F64) == (3, True)
     assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_ORDER, H.F32) == (1, True)
     assert H.hmc_tune_query((48, 16, 4, 8), H.TUNE_DSLASH_ORDER, H.F16) == (0, False)
+    assert H.hmc_tune_query((24, 12, 8, 16), H.TUNE_DSLASH_ORDER, H.F64) == (1, True)
 
 
 def test_occupancy_entries(H, tmp_path):
