@@ -357,8 +357,10 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
  *     2 / 4 = direction split with that many wavefronts per 64-site group;
  *   HMC_TUNE_GAUGE_FORCE (prec HMC_F64): 0 = one link per work-item,
  *     direction by direction; 1 = plane split; 2 = a block per 64 sites and
- *     all four directions, in the tiled walk of the Dslash (y-blocks of two
- *     chunks) where the lattice admits it;
+ *     all four directions, in the tiled walk of the Dslash where the lattice
+ *     admits it (y-blocks of two chunks, or the chunks of the t-slices where
+ *     a z-plane is not a whole number of chunks), else linearly (the
+ *     plaquette sum and the fermion force always walk this way);
  *   HMC_TUNE_DSLASH_LINKS (per storage precision): reals read per SU(3)
  *     link by the hopping kernels, 12 = rows 0 and 1, 10 = row 0 and
  *     column 2 (the fermion force follows the FP64 entry);
