@@ -249,7 +249,11 @@ __global__ void __launch_bounds__(3 * kGfSites) k_gauge_force_planes(Lat g, cons
   }
 }
 
-// U <- reunit(exp(i eps P) U), one link per work-item.
+// U <- reunit(exp(i eps P) U), one link per work-item.  The reunitarisation
+// uses rows 0 and 1 of the product only, so on SU(3) links LK reads rows 0
+// and 1 of U and rebuilds row 2 (which the product needs) from them; the
+// full link is written.
+template <class LK>
 __global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const double* P, double eps) {
   int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= 2 * g.Vh) return;
@@ -260,7 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const dou
 #pragma unroll
   for (int k = 0; k < 8; ++k) c[k] *= eps;
   mat3<double> E = exp_iQ(herm_from_compact(c));
-  mat3<double> u = mmul(E, LkF64::load(U, g.stride, mu, par, s));
+  mat3<double> u = mmul(E, LK::load(U, g.stride, mu, par, s));
   reunitarise(u);
   LkF64::store(U, g.stride, mu, par, s, u);
 }
@@ -321,9 +325,15 @@ hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double 
   return hipGetLastError();
 }
 
-hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st) {
-  TimedScope ts(TK_EXP_UPDATE, st, 2.0 * g.Vh * 4 * (2 * LkF64::kBytes + 64));
-  hipLaunchKernelGGL(k_exp_update, dim3(ceil_div(2LL * g.Vh, kBlock), 4), dim3(kBlock), 0, st, to_lat(g), U, P, eps);
+hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st, bool su3) {
+  // algorithmic: link read (two rows on SU(3) links) and written, momenta read
+  const int rb = su3 ? LkRows2<LkF64>::kBytes : LkF64::kBytes;
+  TimedScope ts(TK_EXP_UPDATE, st, 2.0 * g.Vh * 4 * (rb + LkF64::kBytes + 64));
+  const dim3 grid(ceil_div(2LL * g.Vh, kBlock), 4), block(kBlock);
+  if (su3)
+    hipLaunchKernelGGL(k_exp_update<LkRows2<LkF64>>, grid, block, 0, st, to_lat(g), U, P, eps);
+  else
+    hipLaunchKernelGGL(k_exp_update<LkF64>, grid, block, 0, st, to_lat(g), U, P, eps);
   return hipGetLastError();
 }
 

@@ -709,7 +709,7 @@ hmc_status hmc_fermion_force(hmc_fields* f, const void* X_e, double coef, void* 
 
 hmc_status hmc_exp_update_reunit(hmc_fields* f, double eps, void* stream) {
   FIELDS(f);
-  HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, ST(stream)));
+  HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, ST(stream), F->su3));
   F->u_version++;
   F->su3 = true;  // third row rebuilt by the reunitarisation
   return HMC_OK;
@@ -878,7 +878,7 @@ static hmc_status leapfrog_impl(Fields* F, double tau, int nsteps, const hmc_cg_
   hmc_status s = force_kick(F, 0.5 * eps, cg, ms, st, n_chrono);
   if (s) return s;
   for (int k = 1; k <= nsteps; ++k) {
-    HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, st));
+    HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, eps, st, F->su3));
     F->u_version++;
     F->su3 = true;
     s = force_kick(F, k < nsteps ? eps : 0.5 * eps, cg, ms, st, n_chrono);
@@ -1129,7 +1129,7 @@ hmc_status mts_integrate(Fields* F, const hmc_mts_params* p, hmc_mts_stats* ms, 
       ms->gauge_forces++;
     }
     if (s.eps != 0) {
-      HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, s.eps, st));
+      HMC_CHECK_HIP(launch_exp_update(F->g, F->U, F->P, s.eps, st, F->su3));
       F->u_version++;
       F->su3 = true;
       ms->link_updates++;

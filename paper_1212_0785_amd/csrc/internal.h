@@ -219,7 +219,8 @@ hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* par
 // staple_link_form(), else a fixed compact form (used on SU(3) links only).
 hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st,
                               bool su3, int shape = -1, int form = 0);
-hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st);
+// su3: U is SU(3) to rounding (rows 0 and 1 read, row 2 rebuilt).
+hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st, bool su3);
 hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, const void* Xo, const void* Ye,
                                 const void* Yo, double* P, double coef, hipStream_t st,
                                 bool su3);

@@ -189,3 +189,21 @@ def test_compact_forms_match_oracle(H, tmp_path, L, field):
         assert rel(get_momenta(H, F), want_gf) < 1e-13, staple
         assert abs(H.hmc_plaquette(F) - want_plaq) < 1e-13, staple
         del F
+
+
+@pytest.mark.parametrize("L", SMALL)
+def test_exp_update_reads_follow_the_field(H, L):
+    """exp(i eps P) U with reunitarisation reads rows 0 and 1 of SU(3) links
+    (row 2 rebuilt) and all nine entries of any other link; both against the
+    oracle."""
+    from tests.test_gpu_parity import get_gauge, put_momenta
+    P = synth.hermitian_traceless(51, L, scale=2.0)
+    for U, su3 in ((synth.gauge_field(52, L, eps=0.7), True), (u3_field(53, L), False)):
+        F = H.Fields(L, 5.6, 0.15)
+        put_gauge(H, F, U)
+        assert H.hmc_links_two_row(F) == su3
+        put_momenta(H, F, P)
+        H.hmc_exp_update_reunit(F, 0.1)
+        assert rel(get_gauge(H, F), O.update_links(L, U, P, 0.1)) < 1e-14, su3
+        assert H.hmc_links_two_row(F)
+        del F
