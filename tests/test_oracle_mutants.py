@@ -119,6 +119,19 @@ MUTANTS = {
         "for (long k = 0; k < n; ++k) { r[k] = b[k] - q[k]; p[k] = r[k]; }",
         "for (long k = 0; k < n; ++k) { r[k] = b[k]; p[k] = r[k]; }",
         [CH.test_cg_from_the_solution_takes_no_iteration]),
+    "Z2 sign from bit 0 instead of bit 63": (
+        "double re = (w[2 * k] >> 63) ? -s : s;", "double re = (w[2 * k] & 1) ? -s : s;",
+        [lambda: P.test_z2_source(12120785, 0)]),
+    "Z2 without the 1/sqrt2": (
+        "double re = (w[2 * k] >> 63) ? -s : s;\n                double im = (w[2 * k + 1] >> 63) ? -s : s;",
+        "double re = (w[2 * k] >> 63) ? -1.0 : 1.0;\n                double im = (w[2 * k + 1] >> 63) ? -1.0 : 1.0;",
+        [lambda: P.test_z2_source(12120785, 0), P.test_z2_source_statistics]),
+    "Z2 imaginary sign from the real part's word": (
+        "double im = (w[2 * k + 1] >> 63) ? -s : s;", "double im = (w[2 * k] >> 63) ? -s : s;",
+        [lambda: P.test_z2_source(3, 17)]),
+    "point source on the last site": (
+        "b[i * 12 + k] = (i == 0 && k == 0) ? 1.0 : 0.0;", "b[i * 12 + k] = (i == V - 1 && k == 0) ? 1.0 : 0.0;",
+        [P.test_point_source]),
     "link update right-multiplies": (
         "mat_mul(E, &U[l * 9], &U[l * 9]);", "mat_mul(&U[l * 9], E, &U[l * 9]);",
         [P.test_update_links_is_left_multiplication_by_exp]),

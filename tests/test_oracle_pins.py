@@ -75,6 +75,68 @@ def test_gaussian_moments():
     assert abs(k - 3) < 4 * np.sqrt(24 / n)
 
 
+
+def _numpy_site_words(seed, site, stream, epoch, nblocks):
+    """Philox4x64-10 words of counter (block, site, stream, epoch), key
+    (seed, 0), drawn from numpy's own Philox (independent of the oracle)."""
+    out = []
+    for blk in range(nblocks):
+        # numpy increments its 256-bit counter before the first block
+        c = (blk + (site << 64) + (stream << 128) + (epoch << 192) - 1) % 2**256
+        ctr = np.array([(c >> (64 * j)) % 2**64 for j in range(4)], dtype=np.uint64)
+        bg = np.random.Philox(counter=ctr, key=np.array([seed, 0], dtype=np.uint64))
+        out.extend(int(w) for w in bg.random_raw(4))
+    return out
+
+
+@pytest.mark.parametrize("seed,epoch", [(12120785, 0), (3, 17)])
+def test_z2_source(seed, epoch):
+    """Z2 noise: each real component is +-1/sqrt2, the sign of component
+    (spin, colour, re/im) at site i being bit 63 of Philox word
+    (spin*3 + colour)*2 + re/im of that site (stream 4, epoch = source
+    index).  The words come from numpy's Philox, the magnitude from the
+    definition |b_k|^2 = 1."""
+    L = [4, 2, 2, 4]
+    b = O.source(L, O.Z2, seed, epoch)
+    V = b.shape[0]
+    comp = b.reshape(V, 12)
+    # every component is (+-1 +- i)/sqrt2: unit modulus, |re| = |im|
+    assert np.all(np.abs(comp.real) == np.abs(comp.imag))
+    assert np.abs(np.abs(comp) ** 2 - 1).max() < 1e-15
+    assert np.all(np.abs(comp.real) == 0.7071067811865476)
+    for i in range(V):
+        w = _numpy_site_words(seed, i, O.ST_SOURCE, epoch, 6)
+        signs = np.array([-1.0 if (x >> 63) else 1.0 for x in w[:24]])
+        assert np.array_equal(np.sign(comp[i].real), signs[0::2]), i
+        assert np.array_equal(np.sign(comp[i].imag), signs[1::2]), i
+    # a different epoch gives a different (independent) noise vector
+    b2 = O.source(L, O.Z2, seed, epoch + 1)
+    agree = np.mean(np.sign(b2.real) == np.sign(b.real))
+    assert 0.35 < agree < 0.65
+
+
+def test_z2_source_statistics():
+    """Z2 noise has E[b] = 0 and E[b b^dag] = 1 between components."""
+    L = [4, 4, 4, 4]
+    b = O.source(L, O.Z2, 99, 0).reshape(-1)
+    n = b.size
+    assert abs(b.real.mean()) < 4 * np.sqrt(0.5 / n) and abs(b.imag.mean()) < 4 * np.sqrt(0.5 / n)
+    assert abs(np.vdot(b, b).real / n - 1) < 1e-15
+    off = np.vdot(b[:-1], b[1:]) / (n - 1)
+    assert abs(off) < 4 / np.sqrt(n)
+
+
+def test_point_source():
+    """Point source: 1 at site 0, spin 0, colour 0; zero everywhere else,
+    whatever the seed and epoch."""
+    for L in ([4, 2, 2, 4], [2, 4, 6, 2]):
+        for seed, epoch in [(1, 0), (12120785, 9)]:
+            b = O.source(L, O.POINT, seed, epoch)
+            ref = np.zeros_like(b)
+            ref[0, 0, 0] = 1.0
+            assert np.array_equal(b, ref)
+
+
 # ------------------------------------------------------- Dirac algebra
 
 
