@@ -471,6 +471,59 @@ def test_trajectory_parity_c2_short(H):
     assert rel(get_gauge(H, F), U) < 1e-12
 
 
+@pytest.mark.timeout(900)
+def test_full_trajectory_parity_c2(H):
+    """The headline's whole 16^3x32 integration in the benchmark's launch
+    configuration (beta 5.6, kappa 0.156, weak-field start eps 0.3 seed
+    12120785, trajectory 0, tau 1 with 20 leapfrog steps: 21 force solves
+    to 1e-10) against the oracle.  Trajectory 0 is rejected (dH ~ 1.4e3), so
+    the integrated fields are compared after hmc_md_leapfrog from the same
+    refresh; the energies, the uniform and the decision of hmc_trajectory
+    against the oracle's energies of those fields.  Tolerances (relative,
+    whole field): links and momenta 1e-13, the last solve X_e 1e-12 (21
+    solves of condition ~1e3 could amplify rounding; measured on MI355X:
+    4e-16, 7e-16, 7e-16, printed by the test), every energy 1e-12, dH 1e-12
+    of H_old (measured 4e-14), plaquette 1e-12, identical decision."""
+    L = (16, 16, 16, 32)
+    seed, beta, k = 12120785, 5.6, 0.156
+    F = H.Fields(L, beta, k)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    H.hmc_refresh(F, seed, 0)
+    st = H.hmc_md_leapfrog(F, 1.0, 20, H.cg_params(tol=1e-10))
+    Ug, Pg = get_gauge(H, F), get_momenta(H, F)
+    Xg = get_spinor(H, F, F.pointer(H.FIELD_XE), 0)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    r = H.hmc_trajectory(F, seed, 0, 1.0, 20, H.cg_params(tol=1e-10))
+
+    U0 = O.weak_field(L, seed, 0.3)
+    P0 = O.refresh_momenta(L, seed, 0)
+    eta = O.eta(L, seed, 0, 0)
+    phi = O.mhat(L, U0, k, eta, dagger=True)
+    U1, P1, Xe, ost = O.leapfrog(L, U0, P0, phi, beta, k, 1.0, 20, tol=1e-10)
+    want = {"KE_old": O.kinetic(L, P0), "S_g_old": O.gauge_action(L, U0, beta), "S_f_old": O.norm2(eta),
+            "KE_new": O.kinetic(L, P1), "S_g_new": O.gauge_action(L, U1, beta), "S_f_new": O.inner(phi, Xe).real}
+    want["H_old"] = want["KE_old"] + want["S_g_old"] + want["S_f_old"]
+    want["H_new"] = want["KE_new"] + want["S_g_new"] + want["S_f_new"]
+    dH = want["H_new"] - want["H_old"]
+    u = O.accept_uniform(seed, 0)
+
+    dev = {"U": rel(Ug, U1), "P": rel(Pg, P1), "X_e": rel(Xg, Xe), "dH": abs(r["dH"] - dH) / abs(want["H_old"]),
+           "plaq_md": abs(O.plaquette(L, Ug) - O.plaquette(L, U1))}
+    dev.update({key: abs(r[key] - want[key]) / abs(want[key]) for key in want})
+    print("C2 full-trajectory deviations:", {kk: f"{v:.2e}" for kk, v in dev.items()},
+          f"dH gpu {r['dH']:.10f} oracle {dH:.10f}, CG iterations gpu {st['iters_total']} oracle {ost['iters_total']}")
+    assert st["status"] == 0 and ost["status"] == 0 and st["solves"] == ost["solves"] == 21
+    assert abs(st["iters_total"] - ost["iters_total"]) <= 21
+    assert dev["U"] < 1e-13 and dev["P"] < 1e-13 and dev["X_e"] < 1e-12
+    assert dev["plaq_md"] < 1e-12
+    for key in want:
+        assert dev[key] < 1e-12, key
+    assert dev["dH"] < 1e-12
+    assert r["u"] == u
+    assert r["accepted"] == int(dH <= 0 or u < np.exp(-dH))
+    assert abs(r["plaquette"] - O.plaquette(L, U0 if not r["accepted"] else U1)) < 1e-12
+
+
 def test_leapfrog_reversible_at_c2(H):
     """At the benchmark's 16^3x32 shape and launch configuration, with no
     oracle: leapfrog over tau = 0.2 and back over -0.2 returns to the start

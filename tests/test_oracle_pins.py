@@ -555,6 +555,16 @@ def test_trajectory_bookkeeping(c1_setup):
     if not acc:
         assert np.array_equal(U1, U)
     assert abs(r["plaquette"] - O.plaquette(L, U1)) == 0
+    # the energies are those of the refreshed fields before and of the
+    # integrated fields after the leapfrog (the assembly the full-size GPU
+    # test repeats from these primitives)
+    P0 = O.refresh_momenta(L, 12120785, 0)
+    eta = O.eta(L, 12120785, 0, 0)
+    phi = O.mhat(L, U, 0.15, eta, dagger=True)
+    U2, P2, Xe, st = O.leapfrog(L, U, P0, phi, 5.6, 0.15, 1.0, 10)
+    assert st["solves"] == 11 and st["iters_total"] == r["cg_iters_total"]
+    assert r["H_old"] == O.kinetic(L, P0) + O.gauge_action(L, U, 5.6) + O.norm2(eta)
+    assert r["H_new"] == O.kinetic(L, P2) + O.gauge_action(L, U2, 5.6) + O.inner(phi, Xe).real
 
 
 def test_site_list_functions_match_full_lattice():
