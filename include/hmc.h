@@ -76,7 +76,7 @@ typedef int32_t hmc_status;
 #define HMC_E_HIP (-3)    /* a HIP runtime call failed */
 #define HMC_E_NOCONV (-4) /* solver reached maxiter before the tolerance */
 #define HMC_E_BUSY (-5)   /* poll: request not finished yet */
-#define HMC_E_NAN (-6)    /* non-finite energy change; trajectory rejected */
+#define HMC_E_NAN (-6)    /* non-finite residual or energy change; trajectory rejected */
 
 typedef enum { HMC_F64 = 0, HMC_F32 = 1, HMC_F16 = 2, HMC_BF16 = 3 } hmc_prec;
 
@@ -104,17 +104,23 @@ const char* hmc_last_error(void);
 hmc_status hmc_get_version(int32_t* major, int32_t* minor);
 
 /* Bytes of one device field of the given kind and storage precision
- * (momenta exist in F64 only).  HMC_E_ARG on bad geometry. */
+ * (momenta exist in F64 only): one entry per lattice site and component,
+ * the site-per-thread data of Sec. 3 (Tab. 1: outer x spin x colour x
+ * reality).  HMC_E_ARG on bad geometry. */
 hmc_status hmc_field_bytes(const hmc_geom* geom, hmc_prec prec, hmc_kind kind, size_t* bytes);
 
 /* Flags of hmc_alloc_fields. */
 #define HMC_FIELDS_LOWPREC 1u /* also hold F32/F16/BF16 link copies and inner solver vectors */
 
-/* Arena bytes hmc_alloc_fields needs for this geometry and flags. */
+/* Arena bytes hmc_alloc_fields needs for this geometry and flags (all
+ * fields of a trajectory stay resident in HBM: the caller's arena takes
+ * the place of the automatic memory management of Sec. 5). */
 hmc_status hmc_fields_bytes(const hmc_geom* geom, uint32_t flags, size_t* bytes);
 
 /* Create a fields object inside the caller's device arena (at least
- * hmc_fields_bytes bytes, 256-byte aligned).  It holds: the gauge field U,
+ * hmc_fields_bytes bytes, 256-byte aligned): the lattice fields of the HMC
+ * (Sec. 1) laid out one site per work-item (Sec. 3, Tab. 1), resident for
+ * the object's lifetime (no spilling, unlike Sec. 5).  It holds: the gauge field U,
  * its backup, the momenta P, the pseudofermion noise eta_e and phi_e, the
  * solution X_e, the force vectors and the solver work space.  Nothing is
  * initialised: import or generate U before use.  The arena must outlive
@@ -122,7 +128,8 @@ hmc_status hmc_fields_bytes(const hmc_geom* geom, uint32_t flags, size_t* bytes)
  * arena_bytes is too small. */
 hmc_status hmc_alloc_fields(const hmc_geom* geom, const hmc_action* action, uint32_t flags, void* arena,
                             size_t arena_bytes, hmc_fields** out);
-/* Release the host metadata (the arena stays the caller's). */
+/* Release the host metadata (the arena stays the caller's; Sec. 5's
+ * memory manager has no counterpart here). */
 hmc_status hmc_free_fields(hmc_fields* f);
 /* Change beta and kappa of an existing fields object. */
 hmc_status hmc_set_action(hmc_fields* f, const hmc_action* action);
@@ -141,7 +148,11 @@ hmc_status hmc_field_pointer(hmc_fields* f, hmc_field_id which, void** ptr);
  * afterwards.  Fetching that pointer switches the hopping kernels to
  * full-link loads until then (see hmc_links_two_row). */
 
-/* Canonical <-> device layout conversion (both buffers in device memory).
+/* Canonical <-> device layout conversion (both buffers in device memory):
+ * site-major canonical arrays <-> the component-major structure of arrays
+ * in which consecutive work-items read consecutive addresses (the
+ * site-per-thread mapping of Sec. 3 with the coalesced layout Sec. 9 names
+ * as future work).
  * Spinors: `parity` 0 or 1 converts one half spinor (export writes zeros on
  * the other parity's sites of the canonical buffer); -1 converts a full
  * spinor.  Gauge/momenta act on the fields object's U / P.  The canonical
@@ -177,14 +188,17 @@ hmc_status hmc_sync_lowprec(hmc_fields* f, void* stream);
  * operator on SU(3) fields up to rounding. */
 hmc_status hmc_links_two_row(hmc_fields* f, int32_t* on);
 
-/* One half-lattice hop: out = D_{p <- 1-p} in (dagger: D^dag), p =
- * out_parity.  in/out are half spinors of storage `prec`; links come from U
+/* One half-lattice hop of the fermion matrix whose inversion takes most
+ * of the floating-point work (Sec. 1): out = D_{p <- 1-p} in (dagger:
+ * D^dag), p = out_parity.  in/out are half spinors of storage `prec`; links come from U
  * (F64) or its low-precision copy.  Arithmetic is FP64 for F64, else FP32. */
 hmc_status hmc_wilson_dslash(hmc_fields* f, void* out, const void* in, int32_t out_parity, int32_t dagger,
                              hmc_prec prec, void* stream);
-/* out_e = Mhat in_e (dagger: Mhat^dag), half spinors of storage `prec`. */
+/* The even-odd preconditioned fermion matrix (Sec. 1, fermion matrix):
+ * out_e = Mhat in_e (dagger: Mhat^dag), half spinors of storage `prec`. */
 hmc_status hmc_mhat(hmc_fields* f, void* out, const void* in, int32_t dagger, hmc_prec prec, void* stream);
-/* Full Wilson matrix on full F64 spinors: out = M in (dagger: M^dag). */
+/* Full Wilson fermion matrix (Sec. 1) on full F64 spinors: out = M in
+ * (dagger: M^dag). */
 hmc_status hmc_wilson_m(hmc_fields* f, void* out, const void* in, int32_t dagger, void* stream);
 
 /* Global sums (QDP++ sum / innerProduct / sumMulti, Sec. 1), deterministic:
@@ -203,7 +217,9 @@ hmc_status hmc_sum_multi(hmc_fields* f, const void* x, int32_t nhalves, const in
                          double* out, void* stream);
 
 /* Plaquette (1/18V) sum Re Tr U_munu, gauge action S_g and kinetic term
- * sum Tr P^2 of the fields object; synchronise and return host values. */
+ * sum Tr P^2 of the fields object: the gauge and momentum parts of the HMC
+ * Hamiltonian (Sec. 1), each a global sum (Sec. 1, sum); synchronise and
+ * return host values. */
 hmc_status hmc_plaquette(hmc_fields* f, double* out, void* stream);
 hmc_status hmc_gauge_action(hmc_fields* f, double* out, void* stream);
 hmc_status hmc_kinetic_energy(hmc_fields* f, double* out, void* stream);
@@ -214,7 +230,8 @@ hmc_status hmc_kinetic_energy(hmc_fields* f, double* out, void* stream);
  * A_mu the sum of the six staples. */
 hmc_status hmc_gauge_force(hmc_fields* f, double coef, void* stream);
 
-/* Momentum update with the fermion force of S_f for the solution X_e =
+/* Momentum update with the fermion force (Sec. 1 "force term", "momentum
+ * update") of S_f for the solution X_e =
  * (Mhat^dag Mhat)^-1 phi_e (even half spinor, F64): the library forms
  * X_o = D_oe X_e, Y_e = Mhat X_e, Y_o = (D^dag)_oe Y_e and applies
  *   P <- P - coef * (i kappa^2/2) [(W - W^dag) - Tr(W - W^dag)/3],
@@ -238,11 +255,14 @@ hmc_status hmc_exp_update_reunit(hmc_fields* f, double eps, void* stream);
 #define HMC_REFRESH_PF 2u
 hmc_status hmc_refresh(hmc_fields* f, uint64_t seed, uint64_t traj, uint32_t what, void* stream);
 
-/* Weak-field start U_mu(x) = reunit(exp(i eps H_mu(x))), H = sum_a h_a T^a,
- * h ~ N(0,1) from stream 0, epoch 0. */
+/* Weak-field start from the generator, exponentiation and
+ * reunitarisation of Sec. 1: U_mu(x) = reunit(exp(i eps H_mu(x))),
+ * H = sum_a h_a T^a, h ~ N(0,1) from stream 0, epoch 0. */
 hmc_status hmc_weak_field_start(hmc_fields* f, uint64_t seed, double eps, void* stream);
 
-/* Solver source on a full F64 spinor b (stream 4, epoch = source index):
+/* Solver source (right-hand side of a fermion-matrix inversion, Sec. 1;
+ * noise from the generator of Sec. 1) on a full F64 spinor b (stream 4,
+ * epoch = source index):
  * HMC_SOURCE_GAUSS unit-variance Gaussian per real component;
  * HMC_SOURCE_Z2 (+-1 +-i)/sqrt2 with signs from bit 63 of successive words;
  * HMC_SOURCE_POINT 1 at site 0, spin 0, colour 0. */
@@ -275,7 +295,9 @@ hmc_status hmc_random_gaussians(uint64_t seed, uint64_t rng_stream, uint64_t epo
  * the exit test is always on the FP64 true residual.  Needs
  * HMC_FIELDS_LOWPREC.  fixed_iters > 0 runs exactly that many (outer
  * FP64) iterations and ignores tol.  Synchronises the stream; fills
- * stats.  HMC_E_NOCONV when maxiter is reached (x holds the last iterate). */
+ * stats.  HMC_E_NOCONV when maxiter is reached (x holds the last iterate);
+ * HMC_E_NAN when |b|^2 or a residual norm is not finite (the iteration
+ * stops at the first such norm; x holds the last iterate). */
 typedef enum { HMC_CG_NORMAL_MHAT = 0, HMC_CG_WILSON_SOLVE = 1 } hmc_cg_mode;
 typedef struct {
   double tol;
@@ -298,16 +320,21 @@ typedef struct {
 hmc_status hmc_cg_solve(hmc_fields* f, void* x, const void* b, const hmc_cg_params* params, hmc_cg_stats* stats,
                         void* stream);
 
-/* Leapfrog molecular dynamics (PQP): with eps = tau/nsteps,
+/* Leapfrog molecular dynamics (the HMC integration of Sec. 1: momentum
+ * updates with the force terms, link updates by exponentiation and
+ * reunitarisation), PQP: with eps = tau/nsteps,
  *   P -= (eps/2) F(U); then nsteps times { U <- reunit(exp(i eps P) U);
  *   P -= eps_k F(U) } with eps_k = eps except eps/2 for the last step;
  * F = F_g + F_f, the fermion force from a CG solve of phi_e (FP64).
- * tau may be negative.  X_e holds the last solve.  Synchronises. */
+ * tau may be negative.  X_e holds the last solve.  Synchronises.  The
+ * integration always runs to the end; then HMC_E_NAN if a solve met a
+ * non-finite residual, else HMC_E_NOCONV if a solve stopped at maxiter. */
 typedef struct {
   int32_t solves;
   int32_t iters_total;
   int32_t iters_max;
-  int32_t nonconverged;
+  int32_t nonconverged; /* solves that did not reach tol (non-finite ones included) */
+  int32_t nonfinite;    /* solves whose residual became non-finite */
 } hmc_md_stats;
 hmc_status hmc_md_leapfrog(hmc_fields* f, double tau, int32_t nsteps, const hmc_cg_params* cg, hmc_md_stats* stats,
                            void* stream);
@@ -316,9 +343,12 @@ hmc_status hmc_md_leapfrog(hmc_fields* f, double tau, int32_t nsteps, const hmc_
  * generation): backup U; refresh momenta and pseudofermions; H_old = sum
  * Tr P^2 + S_g + eta^dag eta; leapfrog; H_new = sum Tr P^2 + S_g +
  * phi^dag X_e; accept iff dH <= 0 or u < exp(-dH), u from stream 3 at epoch
- * traj (site 0, block 0, word 0); restore U on reject.  A non-converged
- * solve or a non-finite dH forces a reject and returns HMC_E_NOCONV /
- * HMC_E_NAN with the result filled.  Synchronises. */
+ * traj (site 0, block 0, word 0); restore U on reject.  Failures force a
+ * reject (U restored bit for bit from the backup) and fill the result:
+ * a non-finite dH, or a solve that met a non-finite residual, returns
+ * HMC_E_NAN; otherwise a solve that stopped at maxiter returns
+ * HMC_E_NOCONV.  HMC_E_NAN takes precedence because a non-finite field
+ * also stops every solve that reads it.  Synchronises. */
 typedef struct {
   double tau;
   int32_t nsteps;
@@ -444,7 +474,7 @@ typedef struct {
 typedef struct {
   double S1_old, S2_old, S1_new, S2_new;
   int32_t solves_ratio, solves_heavy, gauge_forces, link_updates;
-  int32_t iters_ratio, iters_heavy, nonconverged, pad;
+  int32_t iters_ratio, iters_heavy, nonconverged, nonfinite;
 } hmc_mts_stats;
 /* P -= coef F for the Wilson-force bilinear of X = (X_e, D_oe X_e) and
  * Y = (Y_e, (D^dag)_oe Y_e) at hopping parameter kappa_c (the plain
@@ -479,8 +509,13 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
  *
  * With manual = 0 a scheduler thread runs rounds while work is pending;
  * with manual = 1 progress happens only in hmc_service_step (deterministic
- * tests).  Volume groups run on separate internal streams (default
- * priority).  Times are seconds since hmc_service_create. */
+ * tests).  The caller owns the streams as it owns the memory (Sec. 5.1:
+ * work asynchronous on streams): the k-th volume group in use runs on
+ * streams[k mod n_streams], so n_streams > 1 lets different volumes
+ * overlap on the device; the library creates and destroys no stream, and
+ * the streams must outlive the service.  Times are seconds since
+ * hmc_service_create. */
+#define HMC_SERVICE_MAX_STREAMS 8
 typedef struct {
   void* arena;            /* device memory owned by the caller */
   size_t arena_bytes;
@@ -490,7 +525,8 @@ typedef struct {
   int32_t maxiter;        /* inner iterations per request */
   int32_t manual;
   int32_t chunk;          /* iterations per round (<= 0 selects 16) */
-  int32_t pad;
+  int32_t n_streams;      /* 1..HMC_SERVICE_MAX_STREAMS entries of streams[] used */
+  void* streams[HMC_SERVICE_MAX_STREAMS]; /* hipStream_t of the caller (0 = null stream) */
 } hmc_service_params;
 typedef struct {
   int32_t L[4];
@@ -513,22 +549,33 @@ typedef struct {
 } hmc_solve_result;
 typedef struct hmc_service hmc_service;
 
-/* Device bytes one request occupies in the service arena. */
+/* Device bytes one request occupies in the service arena: its gauge
+ * field, source, solution and solver vectors, resident while it runs
+ * (the admission footprint; no spilling as in Sec. 5). */
 hmc_status hmc_request_bytes(const hmc_solve_request* req, int32_t inner_prec, size_t* bytes);
+/* Start a service on the caller's arena and streams (Sec. 5.1: device work
+ * asynchronous on streams, host progress alongside).  HMC_E_ARG on bad
+ * parameters, HMC_E_OOM if the arena cannot hold the service header. */
 hmc_status hmc_service_create(const hmc_service_params* params, hmc_service** out);
-/* Non-blocking.  HMC_E_OOM if the request can never fit the arena,
+/* Submit one Wilson solve (a fermion-matrix inversion, Sec. 1).
+ * Non-blocking.  HMC_E_OOM if the request can never fit the arena,
  * HMC_E_ARG on a bad request; otherwise it waits for memory. */
 hmc_status hmc_service_submit(hmc_service* svc, const hmc_solve_request* req, uint64_t* ticket);
-/* HMC_E_BUSY until the request has finished; then fills res and returns
- * the request's status.  A finished ticket stays queryable. */
+/* Poll a request without blocking (the host progresses beside the device,
+ * Sec. 5.1).  HMC_E_BUSY until the request has finished; then fills res and
+ * returns the request's status.  A finished ticket stays queryable. */
 hmc_status hmc_service_poll(hmc_service* svc, uint64_t ticket, hmc_solve_result* res);
-/* Blocks until the request has finished (runs rounds itself in manual mode). */
+/* Blocks until the request has finished (runs rounds itself in manual
+ * mode); the synchronising counterpart of the asynchronous calls of
+ * Sec. 5.1. */
 hmc_status hmc_service_wait(hmc_service* svc, uint64_t ticket, hmc_solve_result* res);
-/* One scheduling round (admit, advance, retire); *pending = requests not
- * yet finished.  Manual mode only. */
+/* One scheduling round (admit, advance, retire: a batch of the Sec. 1
+ * inversions advanced together); *pending = requests not yet finished.
+ * Manual mode only. */
 hmc_status hmc_service_step(hmc_service* svc, int32_t* pending);
-/* Stops the scheduler (after the current round) and releases host state;
- * unfinished requests are dropped. */
+/* Stops the scheduler (after the current round), waits for the caller's
+ * streams (Sec. 5.1) and releases host state; unfinished requests are
+ * dropped. */
 hmc_status hmc_service_destroy(hmc_service* svc);
 
 /* Kernel timing with HIP events on the launch streams.  With sample_every =

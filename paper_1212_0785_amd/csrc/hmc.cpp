@@ -860,12 +860,14 @@ static hmc_status force_kick(Fields* F, double coef, const hmc_cg_params* cg, hm
   }
   hmc_cg_stats cs;
   hmc_status s = cg_solve_impl(F, F->Xe, F->phi, &p, &cs, st);
-  if (s != HMC_OK && s != HMC_E_NOCONV) return s;
+  if (s != HMC_OK && s != HMC_E_NOCONV && s != HMC_E_NAN) return s;
+  const hmc_status solved = s;
   if (n_chrono > 0 && (s = chrono_push(F, F->Xe, n_chrono, st))) return s;
   ms->solves++;
   ms->iters_total += cs.iters;
   ms->iters_max = std::max(ms->iters_max, cs.iters);
-  if (s == HMC_E_NOCONV) ms->nonconverged++;
+  if (solved != HMC_OK) ms->nonconverged++;
+  if (solved == HMC_E_NAN) ms->nonfinite++;
   HMC_CHECK_HIP(fermion_force_impl(F, F->Xe, coef, st));
   return HMC_OK;
 }
@@ -873,7 +875,7 @@ static hmc_status force_kick(Fields* F, double coef, const hmc_cg_params* cg, hm
 static hmc_status leapfrog_impl(Fields* F, double tau, int nsteps, const hmc_cg_params* cg, hmc_md_stats* ms,
                                 hipStream_t st, int n_chrono = 0) {
   const double eps = tau / nsteps;
-  *ms = hmc_md_stats{0, 0, 0, 0};
+  *ms = hmc_md_stats{};
   F->n_hist = 0;
   hmc_status s = force_kick(F, 0.5 * eps, cg, ms, st, n_chrono);
   if (s) return s;
@@ -896,7 +898,15 @@ hmc_status hmc_md_leapfrog(hmc_fields* f, double tau, int32_t nsteps, const hmc_
   hmc_status s = leapfrog_impl(F, tau, nsteps, cg, stats, st);
   if (s) return s;
   HMC_CHECK_HIP(hipStreamSynchronize(st));
-  return stats->nonconverged ? HMC_E_NOCONV : HMC_OK;
+  if (stats->nonfinite) {
+    set_error("%d of %d solves met a non-finite residual", stats->nonfinite, stats->solves);
+    return HMC_E_NAN;
+  }
+  if (stats->nonconverged) {
+    set_error("%d of %d solves did not converge", stats->nonconverged, stats->solves);
+    return HMC_E_NOCONV;
+  }
+  return HMC_OK;
 }
 
 hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc_traj_params* params,
@@ -933,7 +943,8 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
   double sl[13];
   HMC_CHECK_HIP(read_slots(F, 0, 13, sl, st));
 
-  bool accepted = sl[SL_ACC] != 0.0 && ms.nonconverged == 0;
+  const bool finite = std::isfinite(sl[SL_DH]) && ms.nonfinite == 0;
+  bool accepted = sl[SL_ACC] != 0.0 && ms.nonconverged == 0 && finite;
   if (!accepted) {
     HMC_CHECK_HIP(launch_copy(F->U, F->U_old, ub, st));
     F->u_version++;
@@ -959,13 +970,14 @@ hmc_status hmc_trajectory(hmc_fields* f, uint64_t seed, uint64_t traj, const hmc
   res->cg_iters_max = ms.iters_max;
   res->nonconverged = ms.nonconverged;
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  // a non-finite energy change (or solve) explains any non-convergence it caused
+  if (!finite) {
+    set_error("non-finite energy change (%d of %d solves non-finite); trajectory rejected", ms.nonfinite, ms.solves);
+    return HMC_E_NAN;
+  }
   if (ms.nonconverged) {
     set_error("%d of %d solves did not converge; trajectory rejected", ms.nonconverged, ms.solves);
     return HMC_E_NOCONV;
-  }
-  if (!(res->dH == res->dH) || std::isinf(res->dH)) {
-    set_error("non-finite energy change; trajectory rejected");
-    return HMC_E_NAN;
   }
   return HMC_OK;
 }
@@ -1053,7 +1065,7 @@ hipError_t force_bilinear(Fields* F, const void* Xe, const void* Ye, double kapp
 
 // x = (Mhat^dag Mhat)^-1 b at kappa_c.
 hmc_status solve_at(Fields* F, double kappa_c, void* x, const void* b, const hmc_cg_params* cg, int* iters,
-                    int* nonconv, hipStream_t st) {
+                    int* nonconv, int* nonfinite, hipStream_t st) {
   hmc_cg_params p = *cg;
   p.mode = HMC_CG_NORMAL_MHAT;
   p.initial_guess = 0;
@@ -1062,9 +1074,10 @@ hmc_status solve_at(Fields* F, double kappa_c, void* x, const void* b, const hmc
   F->kappa = kappa_c;
   hmc_status s = cg_solve_impl(F, x, b, &p, &cs, st);
   F->kappa = k0;
-  if (s != HMC_OK && s != HMC_E_NOCONV) return s;
+  if (s != HMC_OK && s != HMC_E_NOCONV && s != HMC_E_NAN) return s;
   *iters += cs.iters;
-  if (s == HMC_E_NOCONV) ++*nonconv;
+  if (s != HMC_OK) ++*nonconv;
+  if (s == HMC_E_NAN) ++*nonfinite;
   return HMC_OK;
 }
 
@@ -1106,11 +1119,11 @@ std::vector<Stretch> mts_schedule(int n_ratio, int n_heavy, int n_gauge, double 
 
 hmc_status mts_integrate(Fields* F, const hmc_mts_params* p, hmc_mts_stats* ms, hipStream_t st) {
   const double k = F->kappa, kh = p->kappa_h;
-  int nc = 0;
+  int nc = 0, nf = 0;
   for (const Stretch& s : mts_schedule(p->n_ratio, p->n_heavy, p->n_gauge, p->tau)) {
     if (s.coef[0] != 0) {  // ratio: chi = Mhat_h^dag phi_2, X_2 = A^-1 chi
       HMC_CHECK_HIP(mhat_k(F, F->chi, F->phi2, 1, kh, st));
-      hmc_status r = solve_at(F, k, F->X2, F->chi, &p->cg, &ms->iters_ratio, &nc, st);
+      hmc_status r = solve_at(F, k, F->X2, F->chi, &p->cg, &ms->iters_ratio, &nc, &nf, st);
       if (r) return r;
       ms->solves_ratio++;
       HMC_CHECK_HIP(mhat_k(F, F->Ye, F->X2, 0, k, st));
@@ -1118,7 +1131,7 @@ hmc_status mts_integrate(Fields* F, const hmc_mts_params* p, hmc_mts_stats* ms, 
       HMC_CHECK_HIP(force_bilinear(F, F->X2, F->phi2, kh, -s.coef[0], st));
     }
     if (s.coef[1] != 0) {  // heavy: X_1 = A_h^-1 phi_1
-      hmc_status r = solve_at(F, kh, F->Xe, F->phi, &p->cg, &ms->iters_heavy, &nc, st);
+      hmc_status r = solve_at(F, kh, F->Xe, F->phi, &p->cg, &ms->iters_heavy, &nc, &nf, st);
       if (r) return r;
       ms->solves_heavy++;
       HMC_CHECK_HIP(mhat_k(F, F->Ye, F->Xe, 0, kh, st));
@@ -1136,6 +1149,7 @@ hmc_status mts_integrate(Fields* F, const hmc_mts_params* p, hmc_mts_stats* ms, 
     }
   }
   ms->nonconverged = nc;
+  ms->nonfinite = nf;
   return HMC_OK;
 }
 
@@ -1173,6 +1187,10 @@ hmc_status hmc_md_mts(hmc_fields* f, const void* phi2, const hmc_mts_params* p, 
   s = mts_integrate(F, p, stats, st);
   if (s) return s;
   HMC_CHECK_HIP(hipStreamSynchronize(st));
+  if (stats->nonfinite) {
+    set_error("%d solves met a non-finite residual", stats->nonfinite);
+    return HMC_E_NAN;
+  }
   if (stats->nonconverged) {
     set_error("%d solves did not converge", stats->nonconverged);
     return HMC_E_NOCONV;
@@ -1199,8 +1217,8 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
   HMC_CHECK_HIP(launch_eta(F->g, seed, traj, 0, F->eta2, st, 1));
   HMC_CHECK_HIP(mhat_k(F, F->phi, F->eta, 1, kh, st));
   HMC_CHECK_HIP(mhat_k(F, F->chi, F->eta2, 1, k, st));
-  int nc = 0;
-  s = solve_at(F, kh, F->Xe, F->chi, &p->cg, &stats->iters_heavy, &nc, st);
+  int nc = 0, nf = 0;
+  s = solve_at(F, kh, F->Xe, F->chi, &p->cg, &stats->iters_heavy, &nc, &nf, st);
   if (s) return s;
   stats->solves_heavy++;
   HMC_CHECK_HIP(mhat_k(F, F->phi2, F->Xe, 0, kh, st));
@@ -1217,11 +1235,10 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_RED + 1, st));
   HMC_CHECK_HIP(launch_finalize(F->part[0], nb, 1, F->slots + SL_ETA2, 1.0, 1, st));
 
-  int nc_md = 0;
   s = mts_integrate(F, p, stats, st);
   if (s) return s;
-  nc_md = stats->nonconverged;
   stats->nonconverged += nc;
+  stats->nonfinite += nf;
 
   HMC_CHECK_HIP(launch_kinetic_partials(F->g, F->P, F->part[0], nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb, 1, SL_KE_NEW, st));
@@ -1239,7 +1256,8 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
   HMC_CHECK_HIP(read_slots(F, SL_RED, 6, parts, st));
 
   const bool converged = stats->nonconverged == 0;
-  bool accepted = sl[SL_ACC] != 0.0 && converged;
+  const bool finite = std::isfinite(sl[SL_DH]) && stats->nonfinite == 0;
+  bool accepted = sl[SL_ACC] != 0.0 && converged && finite;
   if (!accepted) {
     HMC_CHECK_HIP(launch_copy(F->U, F->U_old, ub, st));
     F->u_version++;
@@ -1269,14 +1287,13 @@ hmc_status hmc_trajectory_mts(hmc_fields* f, uint64_t seed, uint64_t traj, const
   res->cg_iters_max = 0;
   res->nonconverged = stats->nonconverged;
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  (void)nc_md;
+  if (!finite) {
+    set_error("non-finite energy change (%d solves non-finite); trajectory rejected", stats->nonfinite);
+    return HMC_E_NAN;
+  }
   if (!converged) {
     set_error("%d solves did not converge; trajectory rejected", stats->nonconverged);
     return HMC_E_NOCONV;
-  }
-  if (!(res->dH == res->dH) || std::isinf(res->dH)) {
-    set_error("non-finite energy change; trajectory rejected");
-    return HMC_E_NAN;
   }
   return HMC_OK;
 }

@@ -8,8 +8,10 @@
 // requests of the group (blockIdx.y = request, per-request kappa, links and
 // vectors from a device table); (c) reads the per-request solver states in
 // one copy, performs reliable updates / convergence checks, and retires
-// finished requests, freeing their memory for the next admissions.  Groups
-// run on separate streams so that different volumes overlap on the device.
+// finished requests, freeing their memory for the next admissions.  Volume
+// groups run on the caller's streams (group slot k on stream k mod n), so
+// that different volumes overlap on the device when the caller gives
+// several.
 //
 // A request's arithmetic never reads another request's data and its
 // reductions use a grid that depends only on its volume, so the result is
@@ -154,7 +156,7 @@ struct Service {
   std::vector<std::unique_ptr<Group>> groups;
   bool group_slot_used[kMaxGroups] = {};
   int idx_used[kMaxActive] = {};
-  hipStream_t streams[kMaxGroups] = {};
+  hipStream_t streams[kMaxGroups] = {};  // the caller's, by group slot
   // shared with submitters
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -562,6 +564,9 @@ hmc_status hmc_service_create(const hmc_service_params* p, hmc_service** out) {
   HMC_REQUIRE(p->max_batch >= 1 && p->max_batch <= kMaxBatch, "max_batch must be in [1, %d]", kMaxBatch);
   HMC_REQUIRE(p->inner_prec >= HMC_F64 && p->inner_prec <= HMC_BF16, "bad precision");
   HMC_REQUIRE(p->tol > 0 && p->maxiter >= 1, "bad tolerance or maxiter");
+  HMC_REQUIRE(p->n_streams >= 1 && p->n_streams <= HMC_SERVICE_MAX_STREAMS, "n_streams must be in [1, %d]",
+              HMC_SERVICE_MAX_STREAMS);
+  static_assert(kMaxGroups == HMC_SERVICE_MAX_STREAMS, "one stream slot per volume group");
   auto S = std::make_unique<Service>();
   S->prm = *p;
   S->chunk = p->chunk > 0 ? p->chunk : 16;
@@ -584,7 +589,7 @@ hmc_status hmc_service_create(const hmc_service_params* p, hmc_service** out) {
     set_error("hipHostMalloc of the service staging buffers failed");
     return HMC_E_HIP;
   }
-  for (int k = 0; k < kMaxGroups; ++k) HMC_CHECK_HIP(hipStreamCreateWithFlags(&S->streams[k], hipStreamNonBlocking));
+  for (int k = 0; k < kMaxGroups; ++k) S->streams[k] = (hipStream_t)p->streams[k % p->n_streams];
   Service* raw = S.release();
   if (!p->manual) raw->worker = std::thread([raw] { raw->loop(); });
   *out = reinterpret_cast<hmc_service*>(raw);
@@ -674,11 +679,7 @@ hmc_status hmc_service_destroy(hmc_service* svc) {
   }
   S->cv_work.notify_all();
   if (S->worker.joinable()) S->worker.join();
-  for (int k = 0; k < kMaxGroups; ++k)
-    if (S->streams[k]) {
-      hipStreamSynchronize(S->streams[k]);
-      hipStreamDestroy(S->streams[k]);
-    }
+  for (int k = 0; k < kMaxGroups && k < S->prm.n_streams; ++k) hipStreamSynchronize(S->streams[k]);
   if (S->h_states) hipHostFree(S->h_states);
   if (S->h_slots) hipHostFree(S->h_slots);
   if (S->h_tables) hipHostFree(S->h_tables);

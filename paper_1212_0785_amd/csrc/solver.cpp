@@ -364,7 +364,9 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   SolverState stt{};
   stt.rr = rr0;
   hmc_status status = HMC_OK;
-  if (bnorm2 == 0.0 || (fixed == 0 && rr0 <= thr)) {
+  if (!std::isfinite(bnorm2) || !std::isfinite(rr0)) {
+    status = HMC_E_NAN;  // a non-finite right-hand side or operator: no iteration can help
+  } else if (bnorm2 == 0.0 || (fixed == 0 && rr0 <= thr)) {
     // x = 0 already meets the tolerance
   } else if (prec == HMC_F64) {
     if (cgls) {
@@ -378,7 +380,8 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
     CHK(run_until_stop(F, v, args, &k, limit, &stt, st, rr0, thr, &rate));
     S.iters = stt.iters;
     S.rel_res = std::sqrt(stt.rr / bnorm2);
-    if (fixed == 0 && !(stt.rr <= thr)) status = HMC_E_NOCONV;
+    if (!std::isfinite(stt.rr)) status = HMC_E_NAN;  // the device stops at a non-finite |r|^2
+    else if (fixed == 0 && !(stt.rr <= thr)) status = HMC_E_NOCONV;
   } else {
     IterArgs args;
     build_iteration(v, 0, thr, 1, delta * delta, &args);
@@ -391,7 +394,11 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
       CHK(read_slots(F, SL_SOLVER, 1, &rr64, st));
       S.reliable_updates++;
       if (rr64 <= thr) break;
-      if (!(rr64 == rr64) || k >= limit || S.reliable_updates >= kMaxReliable) {
+      if (!std::isfinite(rr64) || !std::isfinite(stt.rr)) {
+        status = HMC_E_NAN;
+        break;
+      }
+      if (k >= limit || S.reliable_updates >= kMaxReliable) {
         status = HMC_E_NOCONV;
         break;
       }
@@ -422,6 +429,7 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = S;
   if (status == HMC_E_NOCONV) set_error("solver stopped after %d iterations at |r|/|b| = %.3e", S.iters, S.rel_res);
+  if (status == HMC_E_NAN) set_error("non-finite residual after %d iterations", S.iters);
   return status;
 }
 

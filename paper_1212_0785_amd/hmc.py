@@ -55,7 +55,7 @@ class CgStats(C.Structure):
 
 class MdStats(C.Structure):
     _fields_ = [("solves", C.c_int32), ("iters_total", C.c_int32), ("iters_max", C.c_int32),
-                ("nonconverged", C.c_int32)]
+                ("nonconverged", C.c_int32), ("nonfinite", C.c_int32)]
 
 
 class TrajParams(C.Structure):
@@ -70,7 +70,7 @@ class MtsParams(C.Structure):
 class MtsStats(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("S1_old", "S2_old", "S1_new", "S2_new")] + \
         [(n, C.c_int32) for n in ("solves_ratio", "solves_heavy", "gauge_forces", "link_updates", "iters_ratio",
-                                  "iters_heavy", "nonconverged", "pad")]
+                                  "iters_heavy", "nonconverged", "nonfinite")]
 
 
 class TrajResult(C.Structure):
@@ -83,7 +83,7 @@ class TrajResult(C.Structure):
 class ServiceParams(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_batch", C.c_int32),
                 ("inner_prec", C.c_int32), ("tol", C.c_double), ("maxiter", C.c_int32), ("manual", C.c_int32),
-                ("chunk", C.c_int32), ("pad", C.c_int32)]
+                ("chunk", C.c_int32), ("n_streams", C.c_int32), ("streams", C.c_void_p * 8)]
 
 
 class SolveRequest(C.Structure):
@@ -439,7 +439,7 @@ def hmc_fermion_force_bilinear(f, X_e, Y_e, kappa_c, coef, stream=None):
 def hmc_md_mts(f, phi2, p: MtsParams, stream=None, allow_noconv=False):
     ms = MtsStats()
     status = lib().hmc_md_mts(_h(f), _ptr(phi2), C.byref(p), C.byref(ms), _stream(stream))
-    check(status, allow=(HMC_E_NOCONV,) if allow_noconv else ())
+    check(status, allow=(HMC_E_NOCONV, HMC_E_NAN) if allow_noconv else ())
     d = struct_dict(ms)
     d["status"] = status
     return d
@@ -499,7 +499,7 @@ def cg_params(tol=1e-10, maxiter=10000, mode=CG_NORMAL_MHAT, prec=F64, fixed_ite
 def hmc_cg_solve(f, x, b, params: CgParams, stream=None, allow_noconv=False):
     st = CgStats()
     status = lib().hmc_cg_solve(_h(f), _ptr(x), _ptr(b), C.byref(params), C.byref(st), _stream(stream))
-    check(status, allow=(HMC_E_NOCONV,) if allow_noconv else ())
+    check(status, allow=(HMC_E_NOCONV, HMC_E_NAN) if allow_noconv else ())
     d = struct_dict(st)
     d["status"] = status
     return d
@@ -508,7 +508,7 @@ def hmc_cg_solve(f, x, b, params: CgParams, stream=None, allow_noconv=False):
 def hmc_md_leapfrog(f, tau, nsteps, params: CgParams, stream=None, allow_noconv=False):
     st = MdStats()
     status = lib().hmc_md_leapfrog(_h(f), float(tau), int(nsteps), C.byref(params), C.byref(st), _stream(stream))
-    check(status, allow=(HMC_E_NOCONV,) if allow_noconv else ())
+    check(status, allow=(HMC_E_NOCONV, HMC_E_NAN) if allow_noconv else ())
     d = struct_dict(st)
     d["status"] = status
     return d
@@ -564,13 +564,19 @@ def hmc_request_bytes(req: SolveRequest, inner_prec: int) -> int:
 
 
 class Service:
-    """A solve service over a torch-allocated device arena."""
+    """A solve service over a torch-allocated device arena, on torch streams
+    (``streams``: torch.cuda.Stream objects, default n_streams new ones)."""
 
     def __init__(self, arena_bytes, inner_prec=F32, max_batch=64, tol=1e-10, maxiter=50000, manual=False,
-                 chunk=16, device="cuda"):
+                 chunk=16, device="cuda", streams=None, n_streams=8):
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        # default priority on purpose: streams of mixed priorities are not used
+        self.streams = list(streams) if streams is not None else [torch.cuda.Stream(device=device)
+                                                                  for _ in range(n_streams)]
         p = ServiceParams(self.arena.data_ptr(), int(arena_bytes), int(max_batch), int(inner_prec), float(tol),
-                          int(maxiter), int(bool(manual)), int(chunk), 0)
+                          int(maxiter), int(bool(manual)), int(chunk), len(self.streams))
+        for k, s in enumerate(self.streams):
+            p.streams[k] = _stream(s)
         h = C.c_void_p()
         check(lib().hmc_service_create(C.byref(p), C.byref(h)))
         self.handle = h

@@ -103,3 +103,44 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+# the boundary's entry points, each documented with the passage of the paper
+# that defines (or motivates) the operation
+BOUNDARY = ("hmc_field_bytes", "hmc_fields_bytes", "hmc_alloc_fields", "hmc_free_fields", "hmc_import_gauge",
+            "hmc_export_gauge", "hmc_import_momenta", "hmc_export_momenta", "hmc_import_spinor",
+            "hmc_export_spinor", "hmc_wilson_dslash", "hmc_mhat", "hmc_wilson_m", "hmc_norm2", "hmc_inner",
+            "hmc_sum_multi", "hmc_plaquette", "hmc_gauge_action", "hmc_kinetic_energy", "hmc_gauge_force",
+            "hmc_fermion_force", "hmc_exp_update_reunit", "hmc_refresh", "hmc_weak_field_start",
+            "hmc_make_source", "hmc_cg_solve", "hmc_md_leapfrog", "hmc_trajectory", "hmc_request_bytes",
+            "hmc_service_create", "hmc_service_submit", "hmc_service_poll", "hmc_service_wait",
+            "hmc_service_step", "hmc_service_destroy")
+
+
+def doc_block(name):
+    """The last comment block standing on its own lines before the
+    declaration of `name`."""
+    text = open(HEADER).read()
+    m = re.search(r"^hmc_status\s+%s\s*\(" % name, text, flags=re.M)
+    assert m, name
+    blocks = [b for b in re.finditer(r"^[ \t]*/\*.*?\*/[ \t]*$", text[:m.start()], flags=re.S | re.M)]
+    assert blocks, name
+    return blocks[-1].group(0)
+
+
+@pytest.mark.parametrize("name", BOUNDARY)
+def test_boundary_entry_cites_the_paper(name):
+    assert re.search(r"Sec\. \d", doc_block(name)), name
+
+
+def test_service_needs_caller_streams(H):
+    """The service runs on streams the caller owns: zero streams is an
+    argument error (checked before any device work)."""
+    buf = C.create_string_buffer(1 << 16)
+    base = (C.addressof(buf) + 255) & ~255
+    p = H.ServiceParams(base, 1 << 15, 4, H.F32, 1e-10, 100, 1, 16, 0)
+    h = C.c_void_p()
+    assert H.lib().hmc_service_create(C.byref(p), C.byref(h)) == H.HMC_E_ARG
+    assert "n_streams" in H.last_error()
+    p.n_streams = 9
+    assert H.lib().hmc_service_create(C.byref(p), C.byref(h)) == H.HMC_E_ARG

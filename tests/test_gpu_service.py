@@ -44,8 +44,8 @@ def to_canon(H, L, buf):
     return c.cpu().numpy()
 
 
-def run_manual(H, reqs, prec, arena=1 << 28, max_batch=16):
-    svc = H.Service(arena, inner_prec=prec, max_batch=max_batch, manual=True)
+def run_manual(H, reqs, prec, arena=1 << 28, max_batch=16, streams=None):
+    svc = H.Service(arena, inner_prec=prec, max_batch=max_batch, manual=True, streams=streams)
     outs, tickets = [], []
     for (L, k, gs, eps, kind, ss) in reqs:
         out = torch.zeros(full_bytes(H, L), dtype=torch.uint8, device="cuda")
@@ -80,6 +80,47 @@ def test_service_matches_oracle(H):
         want, st = O.wilson_solve(L, U, k, b, tol=1e-12)
         got = to_canon(H, L, out)
         assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-8
+
+
+# the serving workload's volumes, kappa range and source kinds (Z2, point)
+MIX_SERVE = [
+    ((8, 8, 8, 8), 0.151, 31, 0.25, 1, 40),
+    ((16, 16, 16, 32), 0.156, 32, 0.45, 2, 0),
+    ((24, 24, 24, 48), 0.157, 33, 0.5, 1, 41),
+    ((8, 8, 8, 8), 0.157, 34, 0.5, 2, 0),
+    ((16, 16, 16, 32), 0.150, 35, 0.2, 1, 42),
+    ((24, 24, 24, 48), 0.153, 36, 0.3, 2, 0),
+]
+
+
+@pytest.mark.timeout(900)
+def test_service_at_serving_volumes(H):
+    """Requests of 8^4, 16^3x32 and 24^3x48 in one mix (FP32 inner solves,
+    the tuned launch shapes of those volumes, three caller streams): every
+    result meets the FP64 true-residual tolerance, is bit-identical to the
+    same request solved alone (on the caller's current stream) and agrees
+    with the oracle's FP64 Wilson solve (1e-8: both solutions meet
+    |b - M x| <= 1e-10 |b|, the oracle's to 1e-12)."""
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    arena = 6 << 30
+    res, outs = run_manual(H, MIX_SERVE, H.F32, arena=arena, streams=streams)
+    for r in res:
+        assert r["status"] == 0 and r["true_rel_res"] <= 1e-10, r
+    assert max(r["max_group"] for r in res) == 2
+    for i, req in enumerate(MIX_SERVE):
+        alone, aout = run_manual(H, [req], H.F32, arena=arena, streams=[torch.cuda.current_stream()])
+        assert alone[0]["iters"] == res[i]["iters"], i
+        assert torch.equal(aout[0], outs[i]), i
+        del aout
+    for (L, k, gs, eps, kind, ss), out in zip(MIX_SERVE, outs):
+        U = O.weak_field(L, gs, eps)
+        b = O.source(L, kind, ss, 0)
+        want, st = O.wilson_solve(L, U, k, b, tol=1e-12, maxiter=50000)
+        assert st["status"] == 0
+        got = to_canon(H, L, out)
+        d = np.linalg.norm(got - want) / np.linalg.norm(want)
+        print(f"service {L} kappa {k} source {kind}: |x - x_oracle| / |x_oracle| = {d:.2e}")
+        assert d < 1e-8, (L, d)
 
 
 def test_admission_waits_for_memory(H):
