@@ -215,6 +215,20 @@ hmc_status hmc_norm2(hmc_fields* f, const void* x, int32_t nhalves, hmc_prec pre
 hmc_status hmc_inner(hmc_fields* f, const void* a, const void* b, int32_t nhalves, double* out, void* stream);
 hmc_status hmc_sum_multi(hmc_fields* f, const void* x, int32_t nhalves, const int32_t* subset, int32_t nsub,
                          double* out, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hmc_norm2
+ * on a spinor of lattice `geom` (layout and storage as in hmc_norm2)
+ * without a fields object.  The block partial sums go to a static device
+ * array of 4096 doubles (32 KiB) that the library holds on each GPU it runs
+ * on until the process ends; the call allocates nothing, reads nothing back
+ * and writes the sum to the device double out_dev.  Asynchronous on the
+ * stream.  The result is bit-identical to hmc_norm2's.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (different
+ * streams, or threads without ordering) race; serialise them, e.g. on one
+ * stream.  HMC_E_ARG on bad geometry or arguments, or when the partial
+ * sums (two halves x up to 2048 blocks) would exceed the array. */
+hmc_status hmc_norm2_static(const hmc_geom* geom, const void* x, int32_t nhalves, hmc_prec prec, double* out_dev,
+                            void* stream);
 
 /* Plaquette (1/18V) sum Re Tr U_munu, gauge action S_g and kinetic term
  * sum Tr P^2 of the fields object: the gauge and momentum parts of the HMC

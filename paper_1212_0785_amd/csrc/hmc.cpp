@@ -341,6 +341,39 @@ static hipError_t plaquette_to_slot(Fields* F, int slot, hipStream_t st) {
 
 using namespace hmc;
 
+// Partial sums of hmc_norm2_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, never the device array: kernels receive the address
+// hipGetSymbolAddress returns, looked up once per device on the first call.
+// Every partial is written before the final sum reads it, so the array
+// needs no clearing between calls.
+constexpr int kStaticPartials = 4096;  // two halves x the largest BLAS grid
+static __device__ __align__(256) double scratch[kStaticPartials];
+
+namespace hmc {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+hmc_status static_partials(double** out) {
+  int dev = -1;
+  HMC_CHECK_HIP(hipGetDevice(&dev));
+  HMC_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HMC_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    HMC_REQUIRE(p != nullptr, "no device address for the static partial-sum array");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return HMC_OK;
+}
+}  // namespace
+}  // namespace hmc
+
 #define ST(s) reinterpret_cast<hipStream_t>(s)
 #define FIELDS(f)                                 \
   HMC_REQUIRE((f) != nullptr, "null fields");     \
@@ -611,6 +644,28 @@ hmc_status hmc_norm2(hmc_fields* f, const void* x, int32_t nhalves, hmc_prec pre
     HMC_CHECK_HIP(launch_norm2_partials(F->g, prec, (const char*)x + h * hb, F->part[0] + h * nb, nb, st));
   HMC_CHECK_HIP(finalize_to_slot(F, F->part[0], nb * nhalves, 1, SL_RED, st));
   HMC_CHECK_HIP(read_slots(F, SL_RED, 1, out, st));
+  return HMC_OK;
+}
+
+hmc_status hmc_norm2_static(const hmc_geom* geom, const void* x, int32_t nhalves, hmc_prec prec, double* out_dev,
+                            void* stream) {
+  LatArg g;
+  long long V;
+  hmc_status s = check_geom(geom, &g, &V);
+  if (s) return s;
+  HMC_REQUIRE(x && out_dev, "null argument");
+  HMC_REQUIRE(nhalves == 1 || nhalves == 2, "nhalves must be 1 or 2");
+  HMC_REQUIRE(prec >= HMC_F64 && prec <= HMC_BF16, "bad precision");
+  const int nb = blas_blocks(g.Vh);
+  HMC_REQUIRE(nb * nhalves <= kStaticPartials, "%d partial sums exceed the static array of %d", nb * nhalves,
+              kStaticPartials);
+  double* part = nullptr;
+  if ((s = static_partials(&part))) return s;
+  hipStream_t st = ST(stream);
+  const size_t hb = half_bytes(g.Vh, prec);
+  for (int h = 0; h < nhalves; ++h)
+    HMC_CHECK_HIP(launch_norm2_partials(g, prec, (const char*)x + h * hb, part + h * nb, nb, st));
+  HMC_CHECK_HIP(launch_finalize(part, nb * nhalves, 1, out_dev, 1.0, 0, st));
   return HMC_OK;
 }
 

@@ -138,6 +138,7 @@ _SIGNATURES = {
     "hmc_wilson_m": (_I32, [_P, _P, _P, _I32, _P]),
     "hmc_norm2": (_I32, [_P, _P, _I32, _I32, C.POINTER(_D), _P]),
     "hmc_inner": (_I32, [_P, _P, _P, _I32, C.POINTER(_D), _P]),
+    "hmc_norm2_static": (_I32, [C.POINTER(Geom), _P, _I32, _I32, _P, _P]),
     "hmc_sum_multi": (_I32, [_P, _P, _I32, _P, _I32, C.POINTER(_D), _P]),
     "hmc_plaquette": (_I32, [_P, C.POINTER(_D), _P]),
     "hmc_gauge_action": (_I32, [_P, C.POINTER(_D), _P]),
@@ -362,6 +363,11 @@ def hmc_norm2(f, x, nhalves=1, prec=F64, stream=None) -> float:
     out = C.c_double()
     check(lib().hmc_norm2(_h(f), _ptr(x), nhalves, prec, C.byref(out), _stream(stream)))
     return out.value
+
+
+def hmc_norm2_static(L, x, nhalves, prec, out_dev, stream=None):
+    """Asynchronous: the sum lands in the device double out_dev."""
+    check(lib().hmc_norm2_static(C.byref(geom(L)), _ptr(x), nhalves, prec, _ptr(out_dev), _stream(stream)))
 
 
 def hmc_inner(f, a, b, nhalves=1, stream=None) -> complex:
