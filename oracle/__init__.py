@@ -25,19 +25,26 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1: build and load an AddressSanitizer + UBSan build of the
+# oracle (the process must preload libasan; see tests/test_oracle_sanitized.py)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 
 GAUSSIAN, Z2, POINT = 0, 1, 2
 ST_WEAKFIELD, ST_MOMENTA, ST_ETA, ST_ACCEPT, ST_SOURCE = 0, 1, 2, 3, 4
 
 
-def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (in-tree)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (in-tree); with
+    sanitize, an AddressSanitizer + UBSan build ``liboracle_san.so``."""
+    lib = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fcx-limited-range", "-fPIC", "-shared",
-               "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-Wall", *(_SAN_FLAGS if sanitize else []), "-o", lib + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(lib + ".tmp", lib)
+    return lib
 
 
 class CgStats(C.Structure):
@@ -86,9 +93,10 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build(force=True)
-    _lib = bind(_LIB)
+    lib = _SAN_LIB if _SANITIZE else _LIB
+    if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        build(force=True, sanitize=_SANITIZE)
+    _lib = bind(lib)
     return _lib
 
 
