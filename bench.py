@@ -25,8 +25,13 @@ Inputs are synthetic (weak-field gauge fields and sources drawn on the device
 from seeds) and resident in HBM when the timed region starts.  The roofline
 object reports the dominant kernel's algorithmic bytes per launch over its
 average duration, measured with HIP events on the launch stream inside the
-timed region.  The CPU baseline times the FP64 oracle on a bounded sample of
-the same workload on the host cores.
+timed region.  Algorithmic bytes count each datum of the operation read once
+and each output written once, an SU(3) link as its nine complex entries (the
+half Dslash: 1536 / 1728 / 1920 B per output site in FP64 for the plain, axpy
+and CG-update forms); the `implemented` entry gives the same launches with
+the bytes the kernel as implemented must move (compact links).  The CPU
+baseline times the FP64 oracle on a bounded sample of the same workload on
+the host cores (and, smaller, on one core).
 """
 from __future__ import annotations
 
@@ -144,27 +149,58 @@ def triad_ceiling(H, torch, mib=512, reps=10):
 
 
 def timed_kernel_roofline(H, name="dslash", timing=None):
+    """Average launch time and rates of a timed kernel family: `achieved`
+    on the algorithmic bytes, `achieved_moved` on the bytes as implemented."""
     t = (timing if timing is not None else H.hmc_timing_read()).get(name)
     if not t or not t["launches"]:
         return None
     avg_ms = t["total_ms"] / t["launches"]
     bytes_per_launch = t["bytes"] / t["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return {"avg_ms": avg_ms, "bytes_per_launch": bytes_per_launch, "achieved": achieved,
-            "launches_timed": t["launches"]}
+    moved_per_launch = t["bytes_moved"] / t["launches"]
+    return {"avg_ms": avg_ms, "bytes_per_launch": bytes_per_launch,
+            "achieved": bytes_per_launch / (avg_ms * 1e-3) / 1e9, "moved_per_launch": moved_per_launch,
+            "achieved_moved": moved_per_launch / (avg_ms * 1e-3) / 1e9, "launches_timed": t["launches"]}
+
+
+def implemented(rf):
+    """The same launches' rate on the bytes the kernel as implemented moves."""
+    return {"bytes_per_launch": rf["moved_per_launch"], "achieved": rf["achieved_moved"],
+            "frac": rf["achieved_moved"] / HBM_PEAK_GBS}
+
+
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 # ------------------------------------------------------------------- HMC
 
 
-def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sample=400, n_rep=3):
+def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sample=400, n_rep=3, threads=0):
     """Time the oracle's pieces of one trajectory (forces and link update
     n_rep times each, the CG over a fixed n_cg_sample iterations; about 15 s
     on 16 host cores) and project seconds per trajectory with the measured
-    GPU iteration count per solve (same algorithm, same count)."""
+    GPU iteration count per solve (same algorithm, same count).  threads > 0
+    runs the oracle's site loops on that many threads."""
     import numpy as np  # noqa: F401
 
     import oracle as O
+    prev = O.set_threads(threads)
+    try:
+        return _oracle_hmc_sample(O, L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sample, n_rep)
+    finally:
+        O.set_threads(prev)
+
+
+def _oracle_hmc_sample(O, L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sample, n_rep):
     t0 = time.perf_counter()
     U = O.weak_field(L, seed, 0.3)
     ta = time.perf_counter()
@@ -196,13 +232,26 @@ def oracle_hmc_sample(L, seed, beta, kappa, nsteps, cg_iters_per_solve, n_cg_sam
     sample = time.perf_counter() - t0
     n_force = nsteps + 1
     proj = 2 * t_refresh + n_force * (t_gf + t_ff + cg_iters_per_solve * t_cg) + nsteps * t_up
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = O.set_threads(0)
     return {"value": proj, "unit": "s/traj", "cores": cores, "kind": "oracle",
             "sample": (f"FP64 oracle on 16^3x32, trajectory 0 pieces: refresh + actions once, gauge force, "
                        f"fermion force and link update {n_rep} times each, {n_cg_sample} CG iterations; "
                        f"projected to {n_force} force evaluations x {cg_iters_per_solve:.0f} CG iterations "
                        f"(the GPU's mean per solve) + {nsteps} link updates; sample wall {sample:.1f} s"),
-            "per_cg_iter_s": t_cg, "force_eval_s": t_gf + t_ff}
+            "per_kernel_s": {"cg_iteration": t_cg, "gauge_force": t_gf, "fermion_force": t_ff,
+                             "exp_update_reunit": t_up, "refresh_and_actions": t_refresh}}
+
+
+def oracle_hmc_trajectory(L, seed, beta, kappa, nsteps):
+    """One whole oracle trajectory (trajectory 0 of the chain), timed: the
+    measured counterpart of the projected baseline (about a minute on 16
+    host cores, so only on request)."""
+    import oracle as O
+    U = O.weak_field(L, seed, 0.3)
+    t0 = time.perf_counter()
+    _, r = O.hmc_trajectory(L, U, beta, kappa, seed, 0, 1.0, nsteps, tol=1e-10)
+    return {"seconds": time.perf_counter() - t0, "cores": O.set_threads(0), "dH": r["dH"],
+            "cg_iters_total": r["cg_iters_total"]}
 
 
 def run_hmc(args, H, torch):
@@ -247,7 +296,9 @@ def run_hmc(args, H, torch):
         "cg_iters_per_solve": iters / solves,
         "kernels_sampled": {k: {"launches_timed": v["launches"], "launches_all": v["calls"],
                                 "avg_ms": v["total_ms"] / v["launches"],
-                                "GBps": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9 if v["bytes"] else None}
+                                "GBps": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9 if v["bytes"] else None,
+                                "GBps_implemented": (v["bytes_moved"] / (v["total_ms"] * 1e-3) / 1e9
+                                                     if v["bytes_moved"] else None)}
                             for k, v in timing.items() if v["launches"]},
         # per kernel family: sampled average x all launches, per trajectory
         "time_split_ms_per_traj": {k: v["total_ms"] / v["launches"] * v["calls"] / args.steps
@@ -259,8 +310,10 @@ def run_hmc(args, H, torch):
                            "kernel": ("F64 half-lattice hop, k_dslash or k_dslash_split (shape in "
                                       "config.launch_shapes.dslash_f64; plain, axpy/norm and CG-update "
                                       "epilogues; link form in config.launch_shapes.dslash_links_f64)"),
+                           "bytes": ("algorithmic: 1536 / 1728 / 1920 B per output site (8 links of 144 B, "
+                                     "spinors of 192 B) for the plain, axpy and CG-update hops"),
                            "avg_launch_ms": rf["avg_ms"], "bytes_per_launch": rf["bytes_per_launch"],
-                           "launches_timed": rf["launches_timed"]}
+                           "launches_timed": rf["launches_timed"], "implemented": implemented(rf)}
     return out, iters / solves, L, seed, beta, kappa, nsteps
 
 
@@ -328,7 +381,8 @@ def run_dslash(args, H, torch):
         H.hmc_timing_enable(0)
         rf = timed_kernel_roofline(H, "dslash")
         res[name] = {"avg_ms": rf["avg_ms"], "GBps": rf["achieved"], "frac": rf["achieved"] / HBM_PEAK_GBS,
-                     "wall_ms": 1e3 * wall, "bytes_per_launch": rf["bytes_per_launch"]}
+                     "wall_ms": 1e3 * wall, "bytes_per_launch": rf["bytes_per_launch"],
+                     "implemented": implemented(rf)}
     # other field kernels (FP64); flops per site (all four links) are the
     # approximate counts of the kernels' arithmetic, for the FP64 fraction
     # of the kernels near the ridge
@@ -349,7 +403,8 @@ def run_dslash(args, H, torch):
         torch.cuda.synchronize()
         H.hmc_timing_enable(0)
         rf = timed_kernel_roofline(H, kern)
-        res[name] = {"avg_ms": rf["avg_ms"], "GBps": rf["achieved"], "frac": rf["achieved"] / HBM_PEAK_GBS}
+        res[name] = {"avg_ms": rf["avg_ms"], "GBps": rf["achieved"], "frac": rf["achieved"] / HBM_PEAK_GBS,
+                     "bytes_per_launch": rf["bytes_per_launch"], "implemented": implemented(rf)}
         if flops_site:
             tf = flops_site * V / (rf["avg_ms"] * 1e-3) / 1e12
             res[name].update({"TFLOPs_approx": tf, "fp64_frac_approx": tf / FP64_PEAK_TFLOPS})
@@ -364,9 +419,60 @@ def run_dslash(args, H, torch):
         "roofline": {"bound": "hbm", "achieved": best["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": best["frac"], "traffic": load_traffic("dslash_48c96"),
                      "kernel": f"k_dslash F64 plain, {best['bytes_per_launch'] / (synth_vh(L)):.0f} B/site",
-                     "avg_launch_ms": best["avg_ms"]},
+                     "bytes": "algorithmic: 8 links of 144 B + in and out spinors of 192 B per output site",
+                     "avg_launch_ms": best["avg_ms"], "bytes_per_launch": best["bytes_per_launch"],
+                     "implemented": best["implemented"]},
     }
-    return out
+    return out, L, {k: v["avg_ms"] for k, v in res.items()}
+
+
+def _slab_sample(L, t_lo, t_hi):
+    """Lexicographic sites of the t-slices t_lo..t_hi (inclusive)."""
+    import numpy as np
+    slab = L[0] * L[1] * L[2]
+    return np.arange(t_lo * slab, (t_hi + 1) * slab, dtype=np.int64)
+
+
+def oracle_field_kernel_sample(L, gpu_ms, threads=0, reps=64):
+    """The oracle's Dslash and staple force on a slab of the 48^3x96 field
+    (the even sites, resp. all sites, of t-slices 10 and 11, with the links
+    and spinors they read drawn from the same seeds as the GPU's), timed and
+    projected to one whole-lattice launch."""
+    import numpy as np
+
+    import oracle as O
+    prev = O.set_threads(threads)
+    try:
+        V = L[0] * L[1] * L[2] * L[3]
+        t0 = time.perf_counter()
+        need = _slab_sample(L, 9, 12)
+        U = np.zeros((V, 4, 3, 3), np.complex128)  # lazily zero pages: only the slab is touched
+        psi = np.zeros((V, 4, 3), np.complex128)
+        O.weak_field_sites(L, 2, 0.3, need, U)
+        O.gauss_source_sites(2, 0, need, psi)
+        sites = _slab_sample(L, 10, 11)
+        c = np.stack([sites % L[0], (sites // L[0]) % L[1], (sites // (L[0] * L[1])) % L[2],
+                      sites // (L[0] * L[1] * L[2])], 1)
+        even = sites[c.sum(1) % 2 == 0]
+        ta = time.perf_counter()
+        for _ in range(reps):
+            O.dslash_sites(L, U, psi, even)
+        t_ds = (time.perf_counter() - ta) / reps * (V // 2) / len(even)
+        ta = time.perf_counter()
+        for _ in range(reps):
+            O.gauge_force_sites(L, U, 5.6, sites)
+        t_gf = (time.perf_counter() - ta) / reps * V / len(sites)
+        wall = time.perf_counter() - t0
+        cores = O.set_threads(0)
+    finally:
+        O.set_threads(prev)
+    alg = 1536.0 * (V // 2)
+    return {"value": alg / t_ds / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle Dslash on the {len(even)} even sites and staple force on the {len(sites)} "
+                       f"sites of t-slices 10-11 of 48^3x96 ({reps} passes each), projected to one launch over "
+                       f"the lattice; algorithmic bytes 1536 B per output site; sample wall {wall:.1f} s"),
+            "per_kernel_ms": {"dslash": 1e3 * t_ds, "gauge_force": 1e3 * t_gf},
+            "gpu_speedup": {"dslash": 1e3 * t_ds / gpu_ms["f64"], "gauge_force": 1e3 * t_gf / gpu_ms["gauge_force"]}}
 
 
 # ------------------------------------------------------------------- triad
@@ -629,6 +735,8 @@ def main():
                           "launches of a CG iteration count as one, bracketed by one event pair; each sampled "
                           "launch costs the GPU a few us)"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="hmc: also time one whole oracle trajectory (about a minute on 16 host cores)")
     ap.add_argument("--kappa-h", type=float, default=0.10, help="mts: heavy hopping parameter")
     ap.add_argument("--chrono", type=int, default=0,
                     help="hmc: start each force solve from the chronological guess over the last N solutions")
@@ -661,10 +769,23 @@ def main():
         out, iters_per_solve, L, seed, beta, kappa, nsteps = run_hmc(args, H, torch)
         if not args.no_cpu_baseline:
             cb = oracle_hmc_sample(L, seed, beta, kappa, nsteps, iters_per_solve)
-            out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+            out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "per_kernel_s")}
+            out["cpu_baseline"].update(cpu_info())
             out["cpu_baseline"]["gpu_speedup"] = cb["value"] / out["value"]
+            c1 = oracle_hmc_sample(L, seed, beta, kappa, nsteps, iters_per_solve, n_cg_sample=16, n_rep=1,
+                                   threads=1)
+            out["cpu_baseline"]["single_thread"] = {k: c1[k] for k in ("value", "unit", "cores", "sample",
+                                                                       "per_kernel_s")}
+            if args.cpu_full:
+                out["cpu_baseline"]["measured_trajectory"] = oracle_hmc_trajectory(L, seed, beta, kappa, nsteps)
     elif args.workload == "dslash":
-        out = run_dslash(args, H, torch)
+        out, L, gpu_ms = run_dslash(args, H, torch)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = oracle_field_kernel_sample(L, gpu_ms)
+            out["cpu_baseline"].update(cpu_info())
+            c1 = oracle_field_kernel_sample(L, gpu_ms, threads=1, reps=2)
+            out["cpu_baseline"]["single_thread"] = {k: c1[k] for k in ("value", "unit", "cores", "sample",
+                                                                       "per_kernel_ms")}
     elif args.workload == "serve":
         out = run_serve(args, H, torch)
     elif args.workload == "copy":

@@ -592,20 +592,27 @@ hmc_status hmc_service_step(hmc_service* svc, int32_t* pending);
  * dropped. */
 hmc_status hmc_service_destroy(hmc_service* svc);
 
-/* Kernel timing with HIP events on the launch streams.  With sample_every =
- * n > 0 every n-th launch of each kernel family is bracketed by a pair of
- * events (up to a fixed pool; later launches go untimed); 0 disables.
+/* Kernel timing with HIP events on the launch streams (the measurement
+ * behind the performance figures of Sec. 7).  With sample_every = n > 0
+ * every n-th launch of each kernel family is bracketed by a pair of events
+ * (up to a fixed pool; later launches go untimed); 0 disables.
  * hmc_timing_read synchronises the recorded events and returns, per family,
- * the number of timed launches, their summed milliseconds and summed
- * algorithmic bytes, and the number of all launches (timed or not), so that
- * average x calls estimates the family's total time.  Process-wide, not thread-safe against concurrent
- * launches. */
+ * the number of timed launches, their summed milliseconds, their summed
+ * bytes in two conventions, and the number of all launches (timed or not),
+ * so that average x calls estimates the family's total time.  `bytes` are
+ * the operation's algorithmic bytes: each datum it reads once, each output
+ * written once, an SU(3) link as its nine complex entries (144 B in FP64),
+ * a half spinor site as its twelve (192 B).  `bytes_moved` are the bytes
+ * of what the kernel as implemented must move: on SU(3) fields the compact
+ * links it reads (96 B for two rows, 80 B for row 0 and column 2).
+ * Process-wide, not thread-safe against concurrent launches. */
 typedef struct {
   char name[32];
   int64_t launches;
   double total_ms;
-  double bytes;
-  int64_t calls; /* all launches of the family while timing was enabled */
+  double bytes;       /* algorithmic */
+  int64_t calls;      /* all launches of the family while timing was enabled */
+  double bytes_moved; /* as implemented */
 } hmc_timing_entry;
 hmc_status hmc_timing_enable(int32_t sample_every);
 hmc_status hmc_timing_reset(void);

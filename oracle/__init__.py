@@ -104,6 +104,7 @@ def bind(path):
     """Load a compiled oracle library and declare its signatures."""
     lib = C.CDLL(path)
     sig = {
+        "or_set_threads": (C.c_int, [C.c_int]),
         "or_lex_index": (C.c_long, [_I, C.c_int, C.c_int, C.c_int, C.c_int]),
         "or_site_parity": (C.c_int, [_I, C.c_long]),
         "or_neighbor_table": (None, [_I, _P]),
@@ -183,6 +184,12 @@ def _dims(L):
 def _ptr(a: np.ndarray):
     assert a.flags.c_contiguous
     return a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's site loops; returns the previous count
+    (n <= 0 only queries)."""
+    return _load().or_set_threads(int(n))
 
 
 def volume(L):

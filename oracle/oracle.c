@@ -26,11 +26,22 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 typedef double complex cplx;
+
+/* Threads of the site loops (the CPU baseline is timed at several counts);
+ * returns the previous count.  Results do not depend on it: every global
+ * sum is serial. */
+int or_set_threads(int n)
+{
+    int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
+}
 
 /* ------------------------------------------------------------------ */
 /* Geometry: lexicographic sites, parity, periodic neighbours.         */

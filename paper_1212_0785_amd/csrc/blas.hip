@@ -264,14 +264,67 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
   using XR = typename SX::R;
   constexpr int NC = 12 / NP;  // components per work-item
   const int cur = k & 1, nxt = cur ^ 1;
+  const void* src = a.cgls ? a.s : a.r;
+  // XCD x (hardware blocks b with b % 8 == x; gridDim.x is a multiple of
+  // 8) updates the sites [x Vh / 8, (x + 1) Vh / 8), the range the Dslash's
+  // XCD-aware block order gives the same XCD, so p, r and x stay in the L2
+  // of the XCD that reads them next.
+  const int xcd = blockIdx.x & 7, nbx = gridDim.x >> 3;
+  const int lo = (int)((long long)g.Vh * xcd / 8), nsx = (int)((long long)g.Vh * (xcd + 1) / 8) - lo;
+  const int nwork = nsx * NP;
+  cx<R> p[NC], q[NC];
+  cx<XR> x[NC];
+  auto load = [&](int i) {
+    const int part = NP == 1 ? 0 : i / nsx;
+    const int s = lo + i - part * nsx;
+    if constexpr (NP == 1) {
+      SP::load(a.p, g.stride, s, p);
+      if (a.fused) SX::load(a.x, g.stride, s, x);
+      SP::load(src, g.stride, s, q);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) p[c] = SP::load_one(a.p, g.stride, s, NC * part + c);
+      if (a.fused)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = SX::load_one(a.x, g.stride, s, NC * part + c);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) q[c] = SP::load_one(src, g.stride, s, NC * part + c);
+    }
+  };
+  // The first element's loads do not depend on the sums: issued before the
+  // reduction, their latency overlaps it.
+  const int i0 = (blockIdx.x >> 3) * kBlock + threadIdx.x;
+  if (i0 < nwork) load(i0);
   // the three sums of this step in one block reduction (same order, hence
   // the same bits, in every block)
   __shared__ double bc[3];
   {
+    // each work-item adds its partials in index order; the loads of up to
+    // eight of them are issued together
+    constexpr int U = 8;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < a.n_pp; i += kBlock) v[0] += a.pp[nxt][i], v[1] += a.pp[cur][i];
+    for (int base = threadIdx.x; base < a.n_pp; base += U * kBlock) {
+      double t0[U], t1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = base + u * kBlock;
+        t0[u] = i < a.n_pp ? a.pp[nxt][i] : 0.0;
+        t1[u] = i < a.n_pp ? a.pp[cur][i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[0] += t0[u], v[1] += t1[u];
+    }
     if (a.cgls)
-      for (int i = threadIdx.x; i < a.n_pr; i += kBlock) v[2] += a.pr[i];
+      for (int base = threadIdx.x; base < a.n_pr; base += U * kBlock) {
+        double t2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = base + u * kBlock;
+          t2[u] = i < a.n_pr ? a.pr[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[2] += t2[u];
+      }
     block_sum<3>(v);
     if (threadIdx.x == 0) bc[0] = v[0], bc[1] = v[1], bc[2] = v[2];
     __syncthreads();
@@ -299,33 +352,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
   const bool p_done = conv && !a.mixed;  // converged: the search direction is not needed
   if (p_done && !a.fused) return;
   const R beta = (R)(nw / old);
-  const void* src = a.cgls ? a.s : a.r;
-  // XCD x (hardware blocks b with b % 8 == x; gridDim.x is a multiple of
-  // 8) updates the sites [x Vh / 8, (x + 1) Vh / 8), the range the Dslash's
-  // XCD-aware block order gives the same XCD, so p, r and x stay in the L2
-  // of the XCD that reads them next.
-  const int xcd = blockIdx.x & 7, nbx = gridDim.x >> 3;
-  const int lo = (int)((long long)g.Vh * xcd / 8), nsx = (int)((long long)g.Vh * (xcd + 1) / 8) - lo;
-  const int nwork = nsx * NP;
-  for (int i = (blockIdx.x >> 3) * kBlock + threadIdx.x; i < nwork; i += nbx * kBlock) {
+  for (int i = i0; i < nwork; i += nbx * kBlock) {
     const int part = NP == 1 ? 0 : i / nsx;
     const int s = lo + i - part * nsx;
-    cx<R> p[NC], q[NC];
-    cx<XR> x[NC];
-    if constexpr (NP == 1) {
-      SP::load(a.p, g.stride, s, p);
-      if (a.fused) SX::load(a.x, g.stride, s, x);
-      if (!p_done) SP::load(src, g.stride, s, q);
-    } else {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) p[c] = SP::load_one(a.p, g.stride, s, NC * part + c);
-      if (a.fused)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) x[c] = SX::load_one(a.x, g.stride, s, NC * part + c);
-      if (!p_done)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = SP::load_one(src, g.stride, s, NC * part + c);
-    }
+    if (i != i0) load(i);
     if (a.fused) {  // x += alpha p with the p of this iteration
 #pragma unroll
       for (int m = 0; m < NC; ++m) {
@@ -497,9 +527,19 @@ hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x
   return hipGetLastError();
 }
 
+// Bytes of a solver-vector update per site: x read and written in its own
+// storage, `nsp` reads or writes of vectors of the iteration's storage.
+static double cg_vec_bytes(hmc_prec prec, bool with_x, int nsp) {
+  const double sp = prec == HMC_F64 ? SpF64::kBytes : prec == HMC_F32 ? SpF32::kBytes
+                    : prec == HMC_F16 ? SpF16::kBytes : SpBF16::kBytes;
+  const double sx = prec == HMC_F64 ? SpF64::kBytes : SpF32::kBytes;
+  return (with_x ? 2 * sx : 0.0) + nsp * sp;
+}
+
 hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
                             int nbatch, int j, hipStream_t st) {
-  TimedScope ts(TK_CG_BLAS, st, 0);
+  // x += alpha p, r -= alpha q: x read + written, p and q read, r read + written
+  TimedScope ts(TK_CG_BLAS, st, cg_vec_bytes(prec, true, 4) * g.Vh * nbatch);
   const dim3 grid(nb, nbatch), block(kBlock);
   auto go = [&](auto kernel_single, auto kernel_batch) {
     if (table)
@@ -518,7 +558,8 @@ hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int
 
 hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
                              int nbatch, int j, hipStream_t st) {
-  TimedScope ts(TK_CG_BLAS, st, 0);
+  // p = r + beta p: p read + written, r read (fused: x += alpha p as well)
+  TimedScope ts(TK_CG_BLAS, st, cg_vec_bytes(prec, a.fused != 0, 3) * g.Vh * nbatch);
   (void)nb;  // the update writes no partial sums: its grid is its own
   // multiples of 8 blocks (one share per XCD)
   const int nb4 = std::min(8 * ceil_div(4LL * g.Vh, 8 * kBlock), 2048);

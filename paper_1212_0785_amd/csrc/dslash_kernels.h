@@ -355,11 +355,13 @@ hipError_t launch_links(hmc_prec prec, int dagger, int epi, const LatArg& g, int
   const bool stream = form != LINK_FULL && dslash_link_stream(g, prec);
   const int link_bytes = form == LINK_ROWCOL ? LkRowCol<LK>::kBytes : form == LINK_ROWS2 ? LkRows2<LK>::kBytes
                                                                                           : LK::kBytes;
-  // algorithmic bytes: 8 links + 1 input + 1 output spinor per site (+1 for
-  // y, +1 more for the residual read by the CG epilogue)
-  const double site_bytes =
-      8.0 * link_bytes + 2 * SP::kBytes + (epi ? SP::kBytes : 0) + (epi == EPI_CG ? SP::kBytes : 0);
-  const KernelEvents ev = timing_kernel_events(TK_DSLASH, site_bytes * g.Vh * nbatch);
+  // bytes per site: 8 links + 1 input + 1 output spinor (+1 for y, +1 more
+  // for the residual read by the CG epilogue); algorithmic with whole links,
+  // moved with the stored reals of the link form
+  const double spinor_bytes = 2 * SP::kBytes + (epi ? SP::kBytes : 0) + (epi == EPI_CG ? SP::kBytes : 0);
+  const double alg = (8.0 * LK::kBytes + spinor_bytes) * g.Vh * nbatch;
+  const double moved = (8.0 * link_bytes + spinor_bytes) * g.Vh * nbatch;
+  const KernelEvents ev = timing_kernel_events(TK_DSLASH, alg, moved);
   if (form == LINK_ROWCOL) {
     if (stream)
       return launch_typed<SP, LkRowCol<LK, true>>(prec, dagger, epi, g, out_par, table, nbatch, one, st, j, ev);

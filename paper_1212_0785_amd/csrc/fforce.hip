@@ -90,8 +90,9 @@ hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, 
   const int form = link_form_for(su3, dslash_link_form(g, HMC_F64));
   const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
                                                                                      : LkF64::kBytes;
-  // algorithmic: 4 links, X and Y (both read once), momenta read + written
-  TimedScope ts(TK_FERMION_FORCE, st, 2.0 * g.Vh * (4 * lb + 2 * SpF64::kBytes + 2 * 4 * 64));
+  // per site: 4 links, X and Y (both read once), momenta read + written
+  TimedScope ts(TK_FERMION_FORCE, st, 2.0 * g.Vh * (4 * LkF64::kBytes + 2 * SpF64::kBytes + 2 * 4 * 64),
+                2.0 * g.Vh * (4 * lb + 2 * SpF64::kBytes + 2 * 4 * 64));
   ForceVecs v;
   v.X[0] = Xe;
   v.X[1] = Xo;

@@ -277,7 +277,7 @@ hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* par
   const int form = link_form_for(su3, staple_link_form(g));
   const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
                                                                                      : LkF64::kBytes;
-  TimedScope ts(TK_PLAQUETTE, st, 2.0 * g.Vh * 4 * lb);
+  TimedScope ts(TK_PLAQUETTE, st, 2.0 * g.Vh * 4 * LkF64::kBytes, 2.0 * g.Vh * 4 * lb);
   const dim3 grid(plaquette_blocks(g)), block(kBlock);
   const Lat lat = walk_lat(g);
   if (form == LINK_ROWCOL)
@@ -314,8 +314,8 @@ hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double 
   form = link_form_for(su3, form ? form : staple_link_form(g));
   const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
                                                                                      : LkF64::kBytes;
-  // algorithmic: 4 links read, momenta read + written, per site
-  TimedScope ts(TK_GAUGE_FORCE, st, 2.0 * g.Vh * (4 * lb + 2 * 4 * 64));
+  // per site: 4 links read, momenta read + written
+  TimedScope ts(TK_GAUGE_FORCE, st, 2.0 * g.Vh * (4 * LkF64::kBytes + 2 * 4 * 64), 2.0 * g.Vh * (4 * lb + 2 * 4 * 64));
   if (form == LINK_ROWCOL)
     gauge_force_typed<LkRowCol<LkF64>>(g, U, P, coef_beta, st, shape);
   else if (form == LINK_ROWS2)
@@ -326,9 +326,9 @@ hipError_t launch_gauge_force(const LatArg& g, const void* U, double* P, double 
 }
 
 hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double eps, hipStream_t st, bool su3) {
-  // algorithmic: link read (two rows on SU(3) links) and written, momenta read
+  // per link: read (two rows on SU(3) links) and written, momenta read
   const int rb = su3 ? LkRows2<LkF64>::kBytes : LkF64::kBytes;
-  TimedScope ts(TK_EXP_UPDATE, st, 2.0 * g.Vh * 4 * (rb + LkF64::kBytes + 64));
+  TimedScope ts(TK_EXP_UPDATE, st, 2.0 * g.Vh * 4 * (2 * LkF64::kBytes + 64), 2.0 * g.Vh * 4 * (rb + LkF64::kBytes + 64));
   const dim3 grid(ceil_div(2LL * g.Vh, kBlock), 4), block(kBlock);
   if (su3)
     hipLaunchKernelGGL(k_exp_update<LkRows2<LkF64>>, grid, block, 0, st, to_lat(g), U, P, eps);

@@ -39,7 +39,8 @@ namespace {
 struct TimingRec {
   int kernel;
   int pair;
-  double bytes;
+  double bytes;  // algorithmic
+  double moved;  // as implemented
   int launches;  // launches the pair brackets (a group shares one pair)
 };
 struct Timing {
@@ -52,6 +53,7 @@ struct Timing {
   long long calls[TK_COUNT] = {};  // every launch while enabled
   double ms[TK_COUNT] = {};
   double bytes[TK_COUNT] = {};
+  double moved[TK_COUNT] = {};
   int open_pair = -1;
   // open group: family, launches still to come, its record (-1: unsampled)
   int group_kernel = -1, group_left = 0, group_rec = -1;
@@ -69,7 +71,7 @@ const char* timed_kernel_name(int k) {
   return (k >= 0 && k < TK_COUNT) ? names[k] : "?";
 }
 
-bool timing_begin(int kernel, hipStream_t st, double bytes) {
+bool timing_begin(int kernel, hipStream_t st, double bytes, double moved) {
   Timing& T = timing();
   if (T.sample_every <= 0) return false;
   std::lock_guard<std::mutex> lk(T.mu);
@@ -83,7 +85,7 @@ bool timing_begin(int kernel, hipStream_t st, double bytes) {
     T.events.push_back(e);
   }
   if (hipEventRecord(T.events[2 * pair], st) != hipSuccess) return false;
-  T.recs.push_back({kernel, pair, bytes, 1});
+  T.recs.push_back({kernel, pair, bytes, moved < 0 ? bytes : moved, 1});
   T.open_pair = pair;
   return true;
 }
@@ -100,8 +102,9 @@ static int new_pair(Timing& T) {
   return pair;
 }
 
-KernelEvents timing_kernel_events(int kernel, double bytes) {
+KernelEvents timing_kernel_events(int kernel, double bytes, double moved) {
   KernelEvents ev;
+  if (moved < 0) moved = bytes;
   Timing& T = timing();
   if (T.sample_every <= 0) return ev;
   std::lock_guard<std::mutex> lk(T.mu);
@@ -114,7 +117,7 @@ KernelEvents timing_kernel_events(int kernel, double bytes) {
       if (T.counter[kernel]++ % T.sample_every == 0) {
         const int pair = new_pair(T);
         if (pair >= 0) {
-          T.recs.push_back({kernel, pair, 0.0, 0});
+          T.recs.push_back({kernel, pair, 0.0, 0.0, 0});
           T.group_rec = (int)T.recs.size() - 1;
           ev.start = T.events[2 * pair];
         }
@@ -123,6 +126,7 @@ KernelEvents timing_kernel_events(int kernel, double bytes) {
     if (T.group_rec >= 0) {
       TimingRec& r = T.recs[T.group_rec];
       r.bytes += bytes;
+      r.moved += moved;
       r.launches += 1;
       if (last) ev.stop = T.events[2 * r.pair + 1];
     }
@@ -132,7 +136,7 @@ KernelEvents timing_kernel_events(int kernel, double bytes) {
   if (T.counter[kernel]++ % T.sample_every) return ev;
   const int pair = new_pair(T);
   if (pair < 0) return ev;
-  T.recs.push_back({kernel, pair, bytes, 1});
+  T.recs.push_back({kernel, pair, bytes, moved, 1});
   ev.start = T.events[2 * pair];
   ev.stop = T.events[2 * pair + 1];
   return ev;
@@ -1055,6 +1059,7 @@ hmc_status hmc_timing_reset(void) {
     T.calls[k] = 0;
     T.ms[k] = 0;
     T.bytes[k] = 0;
+    T.moved[k] = 0;
   }
   return HMC_OK;
 }
@@ -1077,6 +1082,7 @@ hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* 
     T.launches[r.kernel] += r.launches;
     T.ms[r.kernel] += ms;
     T.bytes[r.kernel] += r.bytes;
+    T.moved[r.kernel] += r.moved;
   }
   T.recs.clear();
   int n = 0;
@@ -1088,6 +1094,7 @@ hmc_status hmc_timing_read(hmc_timing_entry* out, int32_t max_entries, int32_t* 
       out[n].total_ms = T.ms[k];
       out[n].bytes = T.bytes[k];
       out[n].calls = T.calls[k];
+      out[n].bytes_moved = T.moved[k];
     }
     ++n;
   }

@@ -280,8 +280,13 @@ enum TimedKernel {
   TK_COUNT
 };
 const char* timed_kernel_name(int k);
+// Byte counts of a timed launch: `bytes` are the method's algorithmic bytes
+// (every datum of the operation read once and every output written once,
+// SU(3) links as their nine complex entries), `moved` the bytes of the data
+// the kernel as implemented must move (compact links: the stored reals it
+// reads); moved < 0 means the same as bytes.
 // Returns true and records a start event when this launch is sampled.
-bool timing_begin(int kernel, hipStream_t st, double bytes);
+bool timing_begin(int kernel, hipStream_t st, double bytes, double moved = -1.0);
 void timing_end(int kernel, hipStream_t st);
 
 // Event pair for a sampled launch of `kernel` (both null when this launch is
@@ -291,7 +296,7 @@ void timing_end(int kernel, hipStream_t st);
 struct KernelEvents {
   hipEvent_t start = nullptr, stop = nullptr;
 };
-KernelEvents timing_kernel_events(int kernel, double bytes);
+KernelEvents timing_kernel_events(int kernel, double bytes, double moved = -1.0);
 // The next n launches of `kernel` (consecutive on one stream, nothing of
 // another family between them) form one sample: one event pair from the
 // start of the first to the end of the last, so the pair's own cost is
@@ -309,7 +314,8 @@ struct TimedScope {
   int k;
   hipStream_t st;
   bool on;
-  TimedScope(int kernel, hipStream_t s, double bytes) : k(kernel), st(s), on(timing_begin(kernel, s, bytes)) {}
+  TimedScope(int kernel, hipStream_t s, double bytes, double moved = -1.0)
+      : k(kernel), st(s), on(timing_begin(kernel, s, bytes, moved)) {}
   ~TimedScope() {
     if (on) timing_end(k, st);
   }

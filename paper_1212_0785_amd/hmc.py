@@ -100,7 +100,7 @@ class SolveResult(C.Structure):
 
 class TimingEntry(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
-                ("calls", C.c_int64)]
+                ("calls", C.c_int64), ("bytes_moved", C.c_double)]
 
 
 def struct_dict(s) -> dict:
@@ -547,7 +547,8 @@ def hmc_timing_read() -> dict:
     buf = (TimingEntry * 16)()
     check(lib().hmc_timing_read(buf, 16, C.byref(n)))
     return {buf[k].name.decode(): {"launches": buf[k].launches, "total_ms": buf[k].total_ms,
-                                   "bytes": buf[k].bytes, "calls": buf[k].calls} for k in range(min(n.value, 16))}
+                                   "bytes": buf[k].bytes, "calls": buf[k].calls, "bytes_moved": buf[k].bytes_moved}
+            for k in range(min(n.value, 16))}
 
 
 # ------------------------------------------------------- solve service

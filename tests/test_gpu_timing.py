@@ -2,7 +2,8 @@
 
 With every launch sampled, a fused CG solve of n iterations is timed as n
 groups of four Dslash launches; the algorithmic bytes per Dslash launch lie
-between the plain hop's and the CG-epilogue hop's; the probe's empty
+between the plain hop's and the CG-epilogue hop's, and exceed the bytes as
+implemented by the compact links' saving; the probe's empty
 kernels are timed under "other"; disabled sampling records nothing."""
 import pytest
 
@@ -42,8 +43,15 @@ def test_cg_iterations_timed_in_groups(H):
     # 12 iterations of four hops, plus the set-up and final-residual hops
     assert ds["launches"] >= 4 * 12
     assert ds["calls"] == ds["launches"]  # every launch sampled
+    # algorithmic bytes count whole links (144 B); the bytes as implemented
+    # count the two stored rows (96 B); spinors 192 B: in + out, + y, + r
     per_site = ds["bytes"] / ds["launches"] / Vh
-    assert 8 * 96 + 2 * 192 <= per_site <= 8 * 96 + 4 * 192
+    assert 8 * 144 + 2 * 192 <= per_site <= 8 * 144 + 4 * 192
+    moved = ds["bytes_moved"] / ds["launches"] / Vh
+    assert abs((per_site - moved) - 8 * (144 - 96)) < 1e-9
+    # the p-update: x read + written, p read + written, r read (5 x 192 B per site)
+    cg = t["cg_blas"]
+    assert cg["launches"] == 12 and cg["bytes"] == cg["bytes_moved"] == 12 * 5 * 192 * Vh
     assert ds["total_ms"] > 0
     H.hmc_timing_reset()
     H.hmc_timing_enable(0)

@@ -585,3 +585,24 @@ def test_site_list_functions_match_full_lattice():
     b = np.zeros_like(psi)
     O.gauss_source_sites(7, 2, sites, b)
     assert np.array_equal(b[sites], O.source(L, 0, 7, 2)[sites])
+
+
+def test_results_do_not_depend_on_thread_count():
+    """The CPU baseline is timed at several thread counts: the oracle's
+    results are bit-identical at each (site loops write disjoint outputs,
+    global sums are serial)."""
+    L = (4, 4, 4, 4)
+    U = synth.gauge_field(5, L, eps=0.5)
+    b = synth.spinor(6, L, O.parity_mask(L), 0)
+    got = []
+    prev = O.set_threads(0)
+    try:
+        for n in (1, 3):
+            O.set_threads(n)
+            x, st = O.cg_mhat(L, U, 0.15, b, tol=1e-10)
+            assert st["status"] == 0
+            got.append((O.plaquette(L, U), O.gauge_force(L, U, 5.6), x, st["iters"], O.dslash(L, U, b, -1, 0)))
+    finally:
+        O.set_threads(prev)
+    for a, c in zip(got[0], got[1]):
+        assert np.array_equal(a, c)
