@@ -260,7 +260,7 @@ def run_hmc(args, H, torch):
     cg_prec = H.PREC_NAMES[args.cg_prec]
     F = H.Fields(L, beta, kappa, flags=H.FIELDS_LOWPREC if cg_prec != H.F64 else 0)
     stream = torch.cuda.current_stream()
-    prm = H.cg_params(tol=1e-10, maxiter=10000, prec=cg_prec)
+    prm = H.cg_params(tol=1e-10, maxiter=10000, prec=cg_prec, reliable_delta=args.reliable_delta)
     H.hmc_weak_field_start(F, seed, 0.3)
     for w in range(args.warmup):
         H.hmc_trajectory(F, seed, w, tau, nsteps, prm, n_chrono=args.chrono)
@@ -288,7 +288,8 @@ def run_hmc(args, H, torch):
                    "trajectories": f"0..{args.steps - 1}", "initial_guess": (
                        f"chronological, last {args.chrono} solutions" if args.chrono else "zero"),
                    "force_solves": ("FP64 CG" if cg_prec == H.F64 else
-                                    f"mixed-precision CG, {args.cg_prec} inner storage, FP64 reliable updates"),
+                                    f"mixed-precision CG, {args.cg_prec} inner storage, FP64 reliable updates "
+                                    f"(delta {args.reliable_delta})"),
                    "parallelism": "1 GPU"},
         "trajectories": [{"traj": k, "seconds": r["seconds"], "dH": r["dH"], "accepted": r["accepted"],
                           "plaquette": r["plaquette"], "cg_iters": r["cg_iters_total"]}
@@ -743,6 +744,8 @@ def main():
     ap.add_argument("--mts-steps", default="5,2,2", help="mts: ratio,heavy,gauge steps per enclosing step")
     ap.add_argument("--cg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"],
                     help="hmc: storage of the force solves' inner iteration (default f64: the plain FP64 HMC)")
+    ap.add_argument("--reliable-delta", type=float, default=0.1,
+                    help="hmc with --cg-prec other than f64: reliable-update threshold delta")
     ap.add_argument("--tune-db", default=None,
                     help=("extra launch-shape table to load (hmc_tune_load) before the run; the binding "
                           "already loads paper_1212_0785_amd/tune/mi355x.txt unless HMC_TUNE_DB is set "

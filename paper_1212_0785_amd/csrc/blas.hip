@@ -22,8 +22,15 @@ namespace hmc {
 
 // ------------------------------------------------------------- sums
 
+// Longest run of inner iterations between two device-driven reliable updates.
+constexpr int kMaxInner = 48;
+
+// The kernels taking `gate` do nothing while *gate == 0 (gate may be null).
+__device__ __forceinline__ bool gate_closed(const int* gate) { return gate && *gate == 0; }
+
 template <class SP>
-__global__ void __launch_bounds__(kBlock) k_norm2_partials(Lat g, const void* x, double* part) {
+__global__ void __launch_bounds__(kBlock) k_norm2_partials(Lat g, const void* x, double* part, const int* gate) {
+  if (gate_closed(gate)) return;
   double v[1] = {0.0};
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
     cx<typename SP::R> a[12];
@@ -52,7 +59,8 @@ __global__ void __launch_bounds__(kBlock) k_inner_partials(Lat g, const double2*
 }
 
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* part, int n, int nvals, double* out, double scale,
-                                                     int accumulate) {
+                                                     int accumulate, const int* gate) {
+  if (gate_closed(gate)) return;
   for (int v = 0; v < nvals; ++v) {
     double s = sum_partials(part + (size_t)v * n, n);
     if (threadIdx.x == 0) out[v] = (accumulate ? out[v] : 0.0) + scale * s;
@@ -137,7 +145,8 @@ __global__ void __launch_bounds__(kBlock) k_triad(void* a, const void* b, const 
 }
 
 __global__ void __launch_bounds__(kBlock) k_xmy_norm(Lat g, const double2* b, const double2* q, double2* r,
-                                                    double* part) {
+                                                    double* part, const int* gate) {
+  if (gate_closed(gate)) return;
   double v[1] = {0.0};
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
 #pragma unroll
@@ -211,7 +220,7 @@ __device__ __forceinline__ const CgArgs& cg_args(const CgArgs* table, const CgAr
 template <class SP, class SX, bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table, CgArgs one, int j) {
   const CgArgs& a = cg_args<BATCH>(table, one);
-  const int k = a.iter0 + j;
+  const int k = a.iter0 + a.state->base + j;
   if (k >= a.state->stop_at) return;
   using R = typename SP::R;
   const int cur = k & 1;
@@ -258,7 +267,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
   static_assert(NP == 1 || (NP == 4 && !SP::kScaled), "parts need an unscaled storage");
   const CgArgs& a = cg_args<BATCH>(table, one);
   SolverState* stt = a.state;
-  const int k = a.iter0 + j;
+  const int k = a.iter0 + stt->base + j;
   if (k >= stt->stop_at) return;
   using R = typename SP::R;
   using XR = typename SX::R;
@@ -298,6 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
   // the three sums of this step in one block reduction (same order, hence
   // the same bits, in every block)
   __shared__ double bc[3];
+  __shared__ int fold_sh;
   {
     // each work-item adds its partials in index order; the loads of up to
     // eight of them are issued together
@@ -326,13 +336,24 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
         for (int u = 0; u < U; ++u) v[2] += t2[u];
       }
     block_sum<3>(v);
-    if (threadIdx.x == 0) bc[0] = v[0], bc[1] = v[1], bc[2] = v[2];
+    if (threadIdx.x == 0) {
+      bc[0] = v[0], bc[1] = v[1], bc[2] = v[2];
+      // mixed precision with device-driven updates: does this iteration ask
+      // for one?  (Block 0 may already have raised maxrr to max(maxrr, rr):
+      // every block gets the same answer.)
+      const double r2 = a.cgls ? v[2] : v[0];
+      fold_sh = a.x64 && (r2 <= stt->thr || r2 < a.delta2 * fmax(stt->maxrr, r2) || !(r2 == r2) ||
+                          k + 1 - stt->ru_label >= kMaxInner);
+    }
     __syncthreads();
   }
   const double nw = bc[0], old = bc[1];
   const double rr = a.cgls ? bc[2] : nw;
-  const bool conv = rr <= a.thr;
+  const bool conv = rr <= stt->thr;
   const double alpha = a.fused ? stt->alpha : 0.0;
+  // the iteration that asks for an update folds the inner solution into
+  // the FP64 one (x64 += xl, xl = 0) for the update that follows
+  const bool fold = fold_sh != 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     stt->iters += 1;
     stt->last = k;
@@ -340,9 +361,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
     if (a.mixed) {
       double mx = fmax(stt->maxrr, rr);
       stt->maxrr = mx;
-      if (conv || rr < a.delta2 * mx || !(rr == rr)) {
+      // device-driven updates also come every kMaxInner iterations, so a
+      // low-precision recursion that stagnates cannot run away
+      if (conv || rr < a.delta2 * mx || !(rr == rr) || (a.x64 && k + 1 - stt->ru_label >= kMaxInner)) {
         stt->reason = 2;
         stt->stop_at = k + 1;
+        stt->ru_gate = INT_MAX;  // a device-driven solve updates next
       }
     } else if (conv || !(rr == rr)) {
       stt->reason = conv ? 1 : 3;
@@ -362,6 +386,23 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
         x[m].re = fma((XR)alpha, (XR)p[m].re, x[m].re);
         x[m].im = fma((XR)alpha, (XR)p[m].im, x[m].im);
       }
+    } else if (fold) {  // CGLS: x was updated by the update kernel
+      if constexpr (NP == 1)
+        SX::load(a.x, g.stride, s, x);
+      else
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = SX::load_one(a.x, g.stride, s, NC * part + c);
+    }
+    if (fold) {
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        double2* h = (double2*)a.x64 + (size_t)(NP == 1 ? m : NC * part + m) * g.stride + s;
+        const double2 v = *h;
+        *h = make_double2(v.x + (double)x[m].re, v.y + (double)x[m].im);
+        x[m] = {(XR)0, (XR)0};
+      }
+    }
+    if (a.fused || fold) {
       if constexpr (NP == 1)
         SX::store(a.x, g.stride, s, x);
       else
@@ -380,23 +421,110 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
   }
 }
 
-// Start or resume a solve: stop_at = INT_MAX, reason = 0, maxrr from a
-// device slot (null -> 0); the iteration count is cleared on request.
-__global__ void k_state_reset(SolverState* st, const double* maxrr, int nbatch, int reset_iters) {
+// Start or resume a solve: stop_at = INT_MAX, reason = 0, no reliable
+// update pending, maxrr from a device slot (null -> 0), threshold thr; a
+// start also clears the counts and the label base.
+__global__ void k_state_reset(SolverState* st, const double* maxrr, int nbatch, int reset_iters, double thr) {
   int k = blockIdx.x * kBlock + threadIdx.x;
   if (k >= nbatch) return;
   st[k].stop_at = INT_MAX;
   st[k].reason = 0;
+  st[k].ru_gate = 0;
+  st[k].thr = thr;
   if (reset_iters) {
     st[k].iters = 0;
     st[k].last = -1;
     st[k].rr = 0.0;
+    st[k].base = 0;
+    st[k].done = 0;
+    st[k].nru = 0;
+    st[k].ru_iter = 0;
+    st[k].ru_label = 0;
+    st[k].rr64 = 0.0;
   }
   st[k].maxrr = maxrr ? maxrr[k] : 0.0;
 }
 
+// dst = src over n doubles while *gate != 0.
+__global__ void k_copy_doubles_gated(double* dst, const double* src, int n, const int* gate) {
+  if (*gate == 0) return;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[i];
+}
+
+__global__ void k_advance_base(SolverState* st, int n) {
+  if (threadIdx.x == 0) st->base += n;
+}
+
+__global__ void k_ru_request(SolverState* st) {
+  if (threadIdx.x != 0) return;
+  st->ru_gate = INT_MAX;
+  st->stop_at = min(st->stop_at, st->base);
+}
+
+// The end of a device-driven reliable update (see launch_ru_finish).  One
+// block; every thread reads the gate before thread 0 clears it (the sum
+// synchronises the block in between).
+__global__ void __launch_bounds__(kBlock) k_ru_finish(SolverState* st, const double* part64, int n, double* slot,
+                                                     int max_ru, int max_iters) {
+  if (st->ru_gate == 0) return;
+  const double rr64 = sum_partials(part64, n);
+  if (threadIdx.x != 0) return;
+  *slot = rr64;
+  st->nru += 1;
+  st->ru_iter = st->iters;
+  st->ru_label = st->base;
+  st->rr64 = rr64;
+  if (rr64 <= st->thr) {
+    st->done = 1;
+  } else if (!isfinite(rr64)) {
+    st->done = 3;
+  } else if (st->nru >= max_ru || st->iters >= max_iters) {
+    st->done = 4;
+  } else {  // resume: the iterations of the next chunk run
+    st->stop_at = INT_MAX;
+    st->reason = 0;
+    st->maxrr = rr64;
+  }
+  st->ru_gate = 0;
+}
+
+// Device-driven reliable update after q = A x (see launch_ru_residual).  The
+// |r|^2 of the stored low-precision r is summed from its stored values, as
+// the norm of a freshly converted vector is.
+template <class SP>
+__global__ void __launch_bounds__(kBlock) k_ru_residual(Lat g, const double2* rhs, const double2* q, double2* r64,
+                                                        void* rlow, double* part64, double* pp0, double* pp1,
+                                                        const int* gate) {
+  if (*gate == 0) return;
+  using R = typename SP::R;
+  double v[2] = {0.0, 0.0};
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {
+    cx<R> a[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const size_t j = (size_t)k * g.stride + s;
+      const double2 d = make_double2(rhs[j].x - q[j].x, rhs[j].y - q[j].y);
+      r64[j] = d;
+      v[0] += d.x * d.x + d.y * d.y;
+      a[k] = {(R)d.x, (R)d.y};
+    }
+    SP::store(rlow, g.stride, s, a);
+    if (pp0) {
+      SP::load(rlow, g.stride, s, a);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[1] += (double)a[k].re * a[k].re + (double)a[k].im * a[k].im;
+    }
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    part64[blockIdx.x] = v[0];
+    if (pp0) pp0[blockIdx.x] = v[1], pp1[blockIdx.x] = v[1];
+  }
+}
+
 // x64 += x32; x32 = 0 (mixed precision accumulator hand-over).
-__global__ void k_add_low_to_f64(Lat g, double2* x64, float2* x32) {
+__global__ void k_add_low_to_f64(Lat g, double2* x64, float2* x32, const int* gate) {
+  if (gate_closed(gate)) return;
   const size_t n = (size_t)12 * g.stride;
   for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)gridDim.x * kBlock) {
     float2 l = x32[j];
@@ -429,14 +557,14 @@ hipError_t launch_triad(void* a, const void* b, const void* c, double sc, size_t
 }
 
 hipError_t launch_norm2_partials(const LatArg& g, hmc_prec prec, const void* x, double* part, int nb,
-                                 hipStream_t st) {
+                                 hipStream_t st, const int* gate) {
   const double kb[4] = {SpF64::kBytes, SpF32::kBytes, SpF16::kBytes, SpBF16::kBytes};
   TimedScope ts(TK_REDUCE, st, kb[prec] * g.Vh);
   switch (prec) {
-    case HMC_F64: hipLaunchKernelGGL(k_norm2_partials<SpF64>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
-    case HMC_F32: hipLaunchKernelGGL(k_norm2_partials<SpF32>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
-    case HMC_F16: hipLaunchKernelGGL(k_norm2_partials<SpF16>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
-    case HMC_BF16: hipLaunchKernelGGL(k_norm2_partials<SpBF16>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part); break;
+    case HMC_F64: hipLaunchKernelGGL(k_norm2_partials<SpF64>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part, gate); break;
+    case HMC_F32: hipLaunchKernelGGL(k_norm2_partials<SpF32>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part, gate); break;
+    case HMC_F16: hipLaunchKernelGGL(k_norm2_partials<SpF16>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part, gate); break;
+    case HMC_BF16: hipLaunchKernelGGL(k_norm2_partials<SpBF16>, dim3(nb), dim3(kBlock), 0, st, to_lat(g), x, part, gate); break;
   }
   return hipGetLastError();
 }
@@ -450,8 +578,8 @@ hipError_t launch_inner_partials(const LatArg& g, const void* a, const void* b, 
 }
 
 hipError_t launch_finalize(const double* part, int n, int nvals, double* out, double scale, int accumulate,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, part, n, nvals, out, scale, accumulate);
+                           hipStream_t st, const int* gate) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, part, n, nvals, out, scale, accumulate, gate);
   return hipGetLastError();
 }
 
@@ -498,9 +626,9 @@ hipError_t launch_lincomb(const LatArg& g, const void* const* y, const double* c
 }
 
 hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* r, double* part, int nb,
-                           hipStream_t st) {
+                           hipStream_t st, const int* gate) {
   hipLaunchKernelGGL(k_xmy_norm, dim3(nb), dim3(kBlock), 0, st, to_lat(g), (const double2*)b, (const double2*)q,
-                     (double2*)r, part);
+                     (double2*)r, part, gate);
   return hipGetLastError();
 }
 
@@ -581,15 +709,55 @@ hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, in
   return hipGetLastError();
 }
 
-hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, hipStream_t st) {
+hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, double thr,
+                              hipStream_t st) {
   hipLaunchKernelGGL(k_state_reset, dim3(ceil_div(nbatch, kBlock)), dim3(kBlock), 0, st, st_dev, maxrr, nbatch,
-                     reset_iters);
+                     reset_iters, thr);
   return hipGetLastError();
 }
 
-hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st) {
+hipError_t launch_advance_base(SolverState* st_dev, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance_base, dim3(1), dim3(64), 0, st, st_dev, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_doubles_gated(double* dst, const double* src, int n, const int* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_doubles_gated, dim3(std::max(1, std::min(ceil_div(n, kBlock), 64))), dim3(kBlock), 0, st,
+                     dst, src, n, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_ru_request(SolverState* st_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_ru_request, dim3(1), dim3(64), 0, st, st_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_ru_finish(SolverState* st_dev, const double* part64, int n, double* rr64_slot, int max_ru,
+                            int max_iters, hipStream_t st) {
+  hipLaunchKernelGGL(k_ru_finish, dim3(1), dim3(kBlock), 0, st, st_dev, part64, n, rr64_slot, max_ru, max_iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_ru_residual(const LatArg& g, hmc_prec prec, const void* rhs, const void* q, void* r64, void* rlow,
+                              double* part64, double* pp0, double* pp1, int nb, const int* gate, hipStream_t st) {
+  const dim3 grid(nb), block(kBlock);
+  const Lat lat = to_lat(g);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, lat, (const double2*)rhs, (const double2*)q, (double2*)r64, rlow,
+                       part64, pp0, pp1, gate);
+  };
+  switch (prec) {
+    case HMC_F64: return hipErrorInvalidValue;  // FP64 solves need no update
+    case HMC_F32: go(k_ru_residual<SpF32>); break;
+    case HMC_F16: go(k_ru_residual<SpF16>); break;
+    case HMC_BF16: go(k_ru_residual<SpBF16>); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st, const int* gate) {
   hipLaunchKernelGGL(k_add_low_to_f64, dim3(blas_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), (double2*)x64,
-                     (float2*)xlow);
+                     (float2*)xlow, gate);
   return hipGetLastError();
 }
 

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(kBlock) HMC_DSLASH_WAVES k_dslash(Lat g, int o
   else
     ep = &one;
   const DslashArgs& e = *ep;
-  const int label = e.iter0 + j;
+  const int label = e.iter0 + j + (e.label_base ? *(const HMC_GLOBAL int*)e.label_base : 0);
   if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
   alpha_prologue(e, label);
   int b;
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(NW * 64) k_dslash_split(Lat g, int out_par, co
   else
     ep = &one;
   const DslashArgs& e = *ep;
-  const int label = e.iter0 + j;
+  const int label = e.iter0 + j + (e.label_base ? *(const HMC_GLOBAL int*)e.label_base : 0);
   if (e.stop_at && label >= *(const HMC_GLOBAL int*)e.stop_at) return;
   alpha_prologue<NW>(e, label);
   const int b = xcd_remap(blockIdx.x, gridDim.x);

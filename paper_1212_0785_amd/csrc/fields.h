@@ -4,6 +4,8 @@
 
 #include <climits>
 #include <cstdint>
+#include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -77,7 +79,19 @@ struct Fields {
   // kept by the reunitarised updates).  su3_old: the same for U_old.
   bool su3, su3_old;
   double* pinned;  // host, hipHostMalloc'ed, SL_COUNT + 64 doubles
-  hipEvent_t state_ev[2];  // solver-state read-backs in flight (pinned + SL_COUNT + 8 * i)
+  hipEvent_t state_ev[2];  // solver-state read-backs in flight (pinned + SL_COUNT + 16 * i)
+  // Recorded chunks of solver iterations (HIP graphs replayed on the
+  // caller's stream), keyed by everything their launches depend on, and the
+  // stream they are recorded on (no work ever runs there).
+  struct Recorded {
+    std::string key;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  std::vector<Recorded> recorded;
+  hipStream_t record_stream = nullptr;
+  uint64_t record_clock = 0;
+  bool record_failed = false;
 };
 
 inline Fields* as_fields(hmc_fields* f) { return reinterpret_cast<Fields*>(f); }

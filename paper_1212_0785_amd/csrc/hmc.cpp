@@ -63,7 +63,24 @@ Timing& timing() {
   return t;
 }
 constexpr int kMaxPairs = 8192;
+// Launches recorded into a graph on this thread take no timing events;
+// while t_every is set, every launch of this thread is sampled.
+thread_local bool t_recording = false;
+thread_local bool t_every = false;
 }  // namespace
+
+void timing_set_recording(bool on) { t_recording = on; }
+void timing_sample_all(bool on) { t_every = on; }
+int timing_sample_every() { return timing().sample_every; }
+
+void timing_count(int kernel, long long n) {
+  Timing& T = timing();
+  if (T.sample_every <= 0 || n <= 0) return;
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.calls[kernel] += n;
+}
+
+bool timing_enabled() { return timing().sample_every > 0; }
 
 const char* timed_kernel_name(int k) {
   static const char* names[TK_COUNT] = {"dslash", "cg_blas", "reduce", "gauge_force", "fermion_force",
@@ -73,10 +90,10 @@ const char* timed_kernel_name(int k) {
 
 bool timing_begin(int kernel, hipStream_t st, double bytes, double moved) {
   Timing& T = timing();
-  if (T.sample_every <= 0) return false;
+  if (T.sample_every <= 0 || t_recording) return false;
   std::lock_guard<std::mutex> lk(T.mu);
   ++T.calls[kernel];
-  if (T.counter[kernel]++ % T.sample_every) return false;
+  if (T.counter[kernel]++ % T.sample_every && !t_every) return false;
   int pair = (int)T.recs.size();
   if (pair >= kMaxPairs) return false;
   while ((int)T.events.size() < 2 * (pair + 1)) {
@@ -106,7 +123,7 @@ KernelEvents timing_kernel_events(int kernel, double bytes, double moved) {
   KernelEvents ev;
   if (moved < 0) moved = bytes;
   Timing& T = timing();
-  if (T.sample_every <= 0) return ev;
+  if (T.sample_every <= 0 || t_recording) return ev;
   std::lock_guard<std::mutex> lk(T.mu);
   ++T.calls[kernel];
   if (T.group_left > 0 && T.group_kernel == kernel) {  // inside a group
@@ -114,7 +131,7 @@ KernelEvents timing_kernel_events(int kernel, double bytes, double moved) {
     --T.group_left;
     if (first) {  // the group's sampling decision, on its first launch
       T.group_rec = -1;
-      if (T.counter[kernel]++ % T.sample_every == 0) {
+      if (T.counter[kernel]++ % T.sample_every == 0 || t_every) {
         const int pair = new_pair(T);
         if (pair >= 0) {
           T.recs.push_back({kernel, pair, 0.0, 0.0, 0});
@@ -133,7 +150,7 @@ KernelEvents timing_kernel_events(int kernel, double bytes, double moved) {
     if (last) T.group_kernel = -1;
     return ev;
   }
-  if (T.counter[kernel]++ % T.sample_every) return ev;
+  if (T.counter[kernel]++ % T.sample_every && !t_every) return ev;
   const int pair = new_pair(T);
   if (pair < 0) return ev;
   T.recs.push_back({kernel, pair, bytes, moved, 1});
@@ -155,7 +172,7 @@ void timing_group_end() {
 void timing_group_begin(int kernel, int n) {
   Timing& T = timing();
   std::lock_guard<std::mutex> lk(T.mu);
-  if (T.sample_every <= 0 || n <= 0) return;
+  if (T.sample_every <= 0 || n <= 0 || t_recording) return;
   T.group_kernel = kernel;
   T.group_left = n;
   T.group_rec = -2;  // decided on the first launch
@@ -470,6 +487,8 @@ hmc_status hmc_alloc_fields(const hmc_geom* geom, const hmc_action* action, uint
 
 hmc_status hmc_free_fields(hmc_fields* f) {
   FIELDS(f);
+  for (Fields::Recorded& r : F->recorded) hipGraphExecDestroy(r.exec);
+  if (F->record_stream) hipStreamDestroy(F->record_stream);
   if (F->pinned) hipHostFree(F->pinned);
   for (hipEvent_t e : F->state_ev)
     if (e) hipEventDestroy(e);

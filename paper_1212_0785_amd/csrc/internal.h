@@ -91,6 +91,8 @@ int tune_lookup(const int* L, int kind, int prec);
 void tune_store(const int* L, int kind, int prec, int choice, double us);
 int tune_load(const char* path);
 int tune_save(const char* path);
+// Changes whenever a table entry may have changed.
+uint64_t tune_generation();
 // True when HMC_DSLASH_SPLIT, HMC_GFORCE_PLANES, HMC_LINK_FORM,
 // HMC_LINK_STREAM or HMC_DSLASH_ORDER forces a decision.
 bool tune_env_forced();
@@ -104,14 +106,25 @@ struct SolverState {
   int reason;    // 1 converged, 2 reliable update requested, 3 non-finite
   int iters;     // iterations completed
   int last;      // label of the last completed iteration
+  int base;      // label base: added to every iteration label (advanced on the device)
+  int ru_gate;   // mixed precision: INT_MAX while a reliable update is pending, else 0
+  int done;      // device-driven mixed solve ended: 1 converged, 3 non-finite, 4 limit
+  int nru;       // device-driven reliable updates performed
+  int ru_iter;   // iterations completed at the last device-driven update
+  int ru_label;  // label of the first iteration after the last device-driven update
   double rr;     // last residual norm^2 seen by the p-update
   double maxrr;  // mixed precision: max inner |r|^2 since the last update
   double alpha;  // CG step length of the current iteration (fused form)
+  double thr;    // stop threshold on |r|^2 (< 0: never)
+  double rr64;   // FP64 |r|^2 of the last device-driven reliable update
 };
 
-// Iteration labels: a solver iteration carries the label iter0 + j, where
-// iter0 is fixed per solve (per batch entry) and j is passed with each
-// launch.  Ping-pong partial buffers are chosen by the parity of the label.
+// Iteration labels: a solver iteration carries the label iter0 + base + j,
+// where iter0 is fixed per solve (per batch entry), base is read from the
+// solver state when the kernel runs (so a recorded chunk of iterations,
+// followed by a kernel that advances base, can be replayed) and j is passed
+// with each launch.  Ping-pong partial buffers are chosen by the parity of
+// the label.
 
 // One Dslash application (one batch entry).
 struct DslashArgs {
@@ -123,6 +136,7 @@ struct DslashArgs {
   double* partial;      // per-block |out|^2 for the NORM epilogue
   double* partial_pp[2];  // if set: partial_pp[(label + 1) & 1] instead
   const int* stop_at;   // solver control (may be null)
+  const int* label_base;  // added to the label when set (the solver state's base)
   int iter0;            // label offset compared with *stop_at
   int su3;              // host dispatch: links are SU(3) (compact link forms allowed)
   int shape;            // host dispatch: 0 = dslash_shape(), else a fixed Dslash shape (1, 2, 4)
@@ -154,17 +168,21 @@ hipError_t launch_unpack_momenta(const LatArg& g, const double* P, void* canon, 
 // Per-block counts of links whose third row is not conj(row0 x row1) to `tol`.
 hipError_t launch_su3_check(const LatArg& g, const void* U, double tol, double* part, int nb, hipStream_t st);
 hipError_t launch_convert_gauge(const LatArg& g, const void* U64, void* Ulow, hmc_prec prec, hipStream_t st);
+// Launchers taking `gate`: when it is set the kernel does nothing while
+// *gate == 0 (the device-driven reliable update of the mixed-precision
+// solver runs them only when the inner iteration asked for one).
 hipError_t launch_convert_spinor(const LatArg& g, const void* in, hmc_prec pin, void* out, hmc_prec pout,
-                                 int nbatch, const void* const* tab_in, void* const* tab_out, hipStream_t st);
+                                 int nbatch, const void* const* tab_in, void* const* tab_out, hipStream_t st,
+                                 const int* gate = nullptr);
 
 // Reductions: per-block partials of one half-field (or several), then a
 // fixed-order finalisation into a device slot.
 hipError_t launch_norm2_partials(const LatArg& g, hmc_prec prec, const void* x, double* part, int nb,
-                                 hipStream_t st);
+                                 hipStream_t st, const int* gate = nullptr);
 hipError_t launch_inner_partials(const LatArg& g, const void* a, const void* b, double* part, int nb,
                                  hipStream_t st);  // FP64 only; part holds [re..., im...]
 hipError_t launch_finalize(const double* part, int n, int nvals, double* out, double scale, int accumulate,
-                           hipStream_t st);
+                           hipStream_t st, const int* gate = nullptr);
 hipError_t launch_sum_multi(const LatArg& g, const void* x, int nhalves, const int* subset, int nsub, double* part,
                             int nb, double* out, hipStream_t st);
 
@@ -172,7 +190,7 @@ hipError_t launch_sum_multi(const LatArg& g, const void* x, int nhalves, const i
 // out = sum_k (c[2k] + i c[2k+1]) y[k], n in 1..4 F64 half spinors.
 hipError_t launch_lincomb(const LatArg& g, const void* const* y, const double* c, int n, void* out, hipStream_t st);
 hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* r, double* part, int nb,
-                           hipStream_t st);  // r = b - q, partials of |r|^2
+                           hipStream_t st, const int* gate = nullptr);  // r = b - q, partials of |r|^2
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 
@@ -189,10 +207,11 @@ struct CgArgs {
   double* pr;      // CGLS |r|^2 written by the update (blas blocks)
   int n_pp, n_pq, n_pr;
   SolverState* state;
-  int iter0;       // label offset
+  int iter0;       // label offset (the state's base is added)
   int cgls;
-  double thr;      // convergence threshold on |r|^2
   double delta2;   // mixed precision: reliable-update trigger (delta^2)
+  void* x64;       // mixed precision with device-driven updates: the FP64 solution, into which the
+                   // iteration that asks for an update folds the inner solution (null: the host does)
   int mixed;       // 1: never declare convergence, pause instead
   int fused;       // CG with the residual update in the Dslash epilogue: the p-update also does x += alpha p
 };
@@ -202,12 +221,35 @@ hipError_t launch_cg_update(const LatArg& g, hmc_prec prec, const CgArgs& a, int
                             int nbatch, int j, hipStream_t st);
 hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, int nb, const CgArgs* table,
                              int nbatch, int j, hipStream_t st);
-// state[k].stop_at = INT_MAX, reason = 0; iters kept unless reset_iters;
-// maxrr from maxrr[k] (may be null -> 0).
-hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, hipStream_t st);
+// Start (reset_iters: counts, base and the device-driven fields cleared) or
+// resume a solve: stop_at = INT_MAX, reason = 0, maxrr from a device slot
+// (null -> 0), stop threshold thr.
+hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, double thr,
+                              hipStream_t st);
+// base += n (one solve): closes a chunk of n iterations launched with j = 0..n-1.
+hipError_t launch_advance_base(SolverState* st_dev, int n, hipStream_t st);
 // STREAM triad a = b + sc * c over n2 double2 elements (nt: non-temporal).
 hipError_t launch_triad(void* a, const void* b, const void* c, double sc, size_t n2, bool nt, hipStream_t st);
-hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st);  // x += xl; xl = 0
+hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStream_t st,
+                                 const int* gate = nullptr);  // x += xl; xl = 0
+// Ends a device-driven reliable update (when st->ru_gate is set): sums the n
+// |r64|^2 partials into *rr64_slot, counts the update and either ends the
+// solve (converged, non-finite, max_ru updates or max_iters iterations
+// reached) or resumes the inner iteration (stop_at = INT_MAX, maxrr =
+// |r64|^2); clears the gate.
+hipError_t launch_ru_finish(SolverState* st_dev, const double* part64, int n, double* rr64_slot, int max_ru,
+                            int max_iters, hipStream_t st);
+// Device-driven reliable update after q = A x (gated): r64 = rhs - q with
+// |r64|^2 partials (nb blocks), r = r64 in storage prec; with pp0 set also
+// the |r|^2 partials of the stored r into pp0 and pp1 (nb = the iteration's
+// partial count).
+hipError_t launch_ru_residual(const LatArg& g, hmc_prec prec, const void* rhs, const void* q, void* r64, void* rlow,
+                              double* part64, double* pp0, double* pp1, int nb, const int* gate, hipStream_t st);
+// dst = src over n doubles while *gate != 0.
+hipError_t launch_copy_doubles_gated(double* dst, const double* src, int n, const int* gate, hipStream_t st);
+// Asks for a reliable update from the host: opens the gate and stops the
+// iterations still queued.
+hipError_t launch_ru_request(SolverState* st_dev, hipStream_t st);
 
 // Gauge-field kernels.
 // su3: U is SU(3) to rounding (compact link forms allowed).
@@ -304,6 +346,14 @@ KernelEvents timing_kernel_events(int kernel, double bytes, double moved = -1.0)
 void timing_group_begin(int kernel, int n);
 // Closes the group (drops its sample if fewer than n launches happened).
 void timing_group_end();
+// While on, launches of this thread are being recorded into a graph: they
+// take no events and are not counted (timing_count counts them per replay).
+void timing_set_recording(bool on);
+void timing_count(int kernel, long long n);
+bool timing_enabled();
+int timing_sample_every();
+// While on, every launch of this thread is sampled.
+void timing_sample_all(bool on);
 // An empty one-wavefront kernel launched with the event pair of the "other"
 // family (sampled like any launch).
 hipError_t launch_empty_timed(hipStream_t st);

@@ -121,7 +121,9 @@ __global__ void __launch_bounds__(kBlock) k_su3_check(Lat g, const void* U, doub
 }
 
 template <class SI, class SO>
-__global__ void k_convert_spinor(Lat g, const void* in, void* out, const void* const* tin, void* const* tout) {
+__global__ void k_convert_spinor(Lat g, const void* in, void* out, const void* const* tin, void* const* tout,
+                                 const int* gate) {
+  if (gate && *gate == 0) return;  // gated: a device-driven reliable update that was not requested
   int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.Vh) return;
   const void* src = tin ? tin[blockIdx.y] : in;
@@ -183,24 +185,25 @@ hipError_t launch_convert_gauge(const LatArg& g, const void* U64, void* Ulow, hm
 
 template <class SI>
 static hipError_t conv_out(const LatArg& g, const void* in, void* out, hmc_prec pout, int nbatch,
-                           const void* const* tin, void* const* tout, hipStream_t st) {
+                           const void* const* tin, void* const* tout, hipStream_t st, const int* gate) {
   dim3 grid(site_blocks(g.Vh), nbatch), block(kBlock);
   switch (pout) {
-    case HMC_F64: hipLaunchKernelGGL((k_convert_spinor<SI, SpF64>), grid, block, 0, st, to_lat(g), in, out, tin, tout); break;
-    case HMC_F32: hipLaunchKernelGGL((k_convert_spinor<SI, SpF32>), grid, block, 0, st, to_lat(g), in, out, tin, tout); break;
-    case HMC_F16: hipLaunchKernelGGL((k_convert_spinor<SI, SpF16>), grid, block, 0, st, to_lat(g), in, out, tin, tout); break;
-    case HMC_BF16: hipLaunchKernelGGL((k_convert_spinor<SI, SpBF16>), grid, block, 0, st, to_lat(g), in, out, tin, tout); break;
+    case HMC_F64: hipLaunchKernelGGL((k_convert_spinor<SI, SpF64>), grid, block, 0, st, to_lat(g), in, out, tin, tout, gate); break;
+    case HMC_F32: hipLaunchKernelGGL((k_convert_spinor<SI, SpF32>), grid, block, 0, st, to_lat(g), in, out, tin, tout, gate); break;
+    case HMC_F16: hipLaunchKernelGGL((k_convert_spinor<SI, SpF16>), grid, block, 0, st, to_lat(g), in, out, tin, tout, gate); break;
+    case HMC_BF16: hipLaunchKernelGGL((k_convert_spinor<SI, SpBF16>), grid, block, 0, st, to_lat(g), in, out, tin, tout, gate); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_convert_spinor(const LatArg& g, const void* in, hmc_prec pin, void* out, hmc_prec pout,
-                                 int nbatch, const void* const* tab_in, void* const* tab_out, hipStream_t st) {
+                                 int nbatch, const void* const* tab_in, void* const* tab_out, hipStream_t st,
+                                 const int* gate) {
   switch (pin) {
-    case HMC_F64: return conv_out<SpF64>(g, in, out, pout, nbatch, tab_in, tab_out, st);
-    case HMC_F32: return conv_out<SpF32>(g, in, out, pout, nbatch, tab_in, tab_out, st);
-    case HMC_F16: return conv_out<SpF16>(g, in, out, pout, nbatch, tab_in, tab_out, st);
-    case HMC_BF16: return conv_out<SpBF16>(g, in, out, pout, nbatch, tab_in, tab_out, st);
+    case HMC_F64: return conv_out<SpF64>(g, in, out, pout, nbatch, tab_in, tab_out, st, gate);
+    case HMC_F32: return conv_out<SpF32>(g, in, out, pout, nbatch, tab_in, tab_out, st, gate);
+    case HMC_F16: return conv_out<SpF16>(g, in, out, pout, nbatch, tab_in, tab_out, st, gate);
+    case HMC_BF16: return conv_out<SpBF16>(g, in, out, pout, nbatch, tab_in, tab_out, st, gate);
   }
   return hipErrorInvalidValue;
 }

@@ -267,7 +267,7 @@ struct Service {
       // s = Mhat^dag r (|s|^2 -> pp[k&1]), p = s
       if ((e = mhat64(v, v.s, v.r, 1, v.pp[k & 1], st))) return e;
       if ((e = launch_copy(v.p, v.s, half_bytes(v.g.Vh, HMC_F64), st))) return e;
-      return launch_state_reset(v.state, nullptr, 1, 1, st);
+      return launch_state_reset(v.state, nullptr, 1, 1, r->thr, st);
     }
     e = inner_restart(v, k, r->fresh, st);
     r->fresh = false;
@@ -336,8 +336,7 @@ struct Service {
     for (int i = 0; i < n; ++i) {
       Req* r = gr->members[i];
       IterArgs a;
-      build_iteration(r->v, r->iter0, r->thr, r->v.prec == HMC_F64 ? 0 : 1,
-                      r->v.prec == HMC_F64 ? 0.0 : 0.01, &a);
+      build_iteration(r->v, r->iter0, r->v.prec == HMC_F64 ? 0 : 1, r->v.prec == HMC_F64 ? 0.0 : 0.01, &a);
       for (int k = 0; k < 4; ++k) hd[k * kMaxBatch + i] = a.d[k];
       for (int k = 0; k < 2; ++k) hc[k * kMaxBatch + i] = a.c[k];
       r->max_group = std::max(r->max_group, n);
@@ -410,6 +409,7 @@ struct Service {
       for (auto& [r, gr] : admitted) {
         r->bnorm2 = h_slots[2 * r->idx];
         r->thr = prm.tol * prm.tol * r->bnorm2;
+        r->v.thr = r->thr;
         double rr0 = h_slots[2 * r->idx + 1];
         gr->members.push_back(r);
         gr->dirty = true;
@@ -417,7 +417,7 @@ struct Service {
         r->phase = Phase::Running;
         if (r->bnorm2 == 0.0 || rr0 <= r->thr) {
           r->fresh = false;
-          HMC_CHECK_HIP(launch_state_reset(r->v.state, nullptr, 1, 1, gr->stream));
+          HMC_CHECK_HIP(launch_state_reset(r->v.state, nullptr, 1, 1, r->thr, gr->stream));
           HMC_CHECK_HIP(finalize_enqueue(r, gr->stream));
           r->phase = Phase::Setup;  // finished below without iterating
         } else {
@@ -441,7 +441,7 @@ struct Service {
       IterTables t = device_tables(gr.get());
       Req* r0 = gr->members[0];
       IterArgs one;
-      build_iteration(r0->v, 0, 0, 0, 0, &one);
+      build_iteration(r0->v, 0, 0, 0, &one);
       for (int j = 0; j < chunk; ++j)
         HMC_CHECK_HIP(launch_iteration(gr->g, (hmc_prec)prm.inner_prec, 1, &t, one, (int)gr->members.size(),
                                        r0->v.nbD, r0->v.nbR, gr->J + j, gr->stream));
@@ -679,10 +679,10 @@ hmc_status hmc_service_destroy(hmc_service* svc) {
   }
   S->cv_work.notify_all();
   if (S->worker.joinable()) S->worker.join();
-  for (int k = 0; k < kMaxGroups && k < S->prm.n_streams; ++k) hipStreamSynchronize(S->streams[k]);
-  if (S->h_states) hipHostFree(S->h_states);
-  if (S->h_slots) hipHostFree(S->h_slots);
-  if (S->h_tables) hipHostFree(S->h_tables);
+  for (int k = 0; k < kMaxGroups && k < S->prm.n_streams; ++k) (void)hipStreamSynchronize(S->streams[k]);
+  if (S->h_states) (void)hipHostFree(S->h_states);
+  if (S->h_slots) (void)hipHostFree(S->h_slots);
+  if (S->h_tables) (void)hipHostFree(S->h_tables);
   delete S;
   return HMC_OK;
 }

@@ -14,14 +14,24 @@
 //
 // An iteration is six launches on one stream (four Dslash, two vector
 // kernels) with alpha, beta and the stop test computed on the device.  The
-// host enqueues chunks of iterations and reads the 32-byte solver state once
-// per chunk; iterations enqueued after the stop exit at once.
+// host enqueues chunks of iterations and reads the solver state once per
+// chunk; iterations enqueued after the stop exit at once.  A chunk of n
+// iterations is launched with j = 0..n-1 and closed by a kernel that
+// advances the state's label base by n, so the same launches serve every
+// chunk of that length: they are recorded once into a HIP graph and
+// replayed, which takes the per-launch host cost (several us for these
+// argument sizes, more than a low-precision hop at 16^3x32 takes on the
+// GPU) off the critical path.  In mixed precision the reliable update is
+// part of the chunk too, gated on the device (it runs only when the inner
+// iteration asked for it), so a solve needs no host round trip until it
+// ends.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "fields.h"
@@ -32,15 +42,19 @@ namespace hmc {
 namespace {
 constexpr int kChunk = 16;
 constexpr int kMaxReliable = 2000;  // a solve that needs more has stagnated
+constexpr int kMaxRecorded = 64;    // recorded chunks kept per fields object
+constexpr int kStateSlot = 16;      // doubles per solver-state read-back slot
 }  // namespace
 
-void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, double delta2, IterArgs* o) {
+void build_iteration(const SolveVecs& v, int iter0, int mixed, double delta2, IterArgs* o, bool device_updates) {
+  std::memset(o, 0, sizeof *o);  // the recorded-launch key compares these bytes
   const double k2 = v.kappa * v.kappa;
   DslashArgs b{};
   b.U = v.Ulow;
   b.su3 = v.su3;
   b.shape = v.shape;
   b.stop_at = &v.state->stop_at;
+  b.label_base = &v.state->base;
   b.iter0 = iter0;
   b.a = 1.0;
   b.b = 1.0;
@@ -83,8 +97,8 @@ void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, doubl
   c.state = v.state;
   c.iter0 = iter0;
   c.cgls = v.cgls;
-  c.thr = thr;
   c.delta2 = delta2;
+  c.x64 = mixed && device_updates ? v.x : nullptr;
   c.mixed = mixed;
   c.fused = v.cgls ? 0 : 1;
   o->c[0] = c;
@@ -117,8 +131,10 @@ hipError_t launch_iteration(const LatArg& g, hmc_prec prec, int cgls, const Iter
   return PUP(1);
 }
 
+// One FP64 hop of a solve; with `gate` set it runs only while *gate != 0
+// (label 0 against the gate as stop_at).
 static hipError_t ds64(const SolveVecs& v, void* out, const void* in, int out_par, int dag, int epi, const void* y,
-                       double a, double b, double* partial, hipStream_t st) {
+                       double a, double b, double* partial, hipStream_t st, const int* gate = nullptr) {
   DslashArgs d{};
   d.U = v.U64;
   d.su3 = v.su3;
@@ -129,26 +145,35 @@ static hipError_t ds64(const SolveVecs& v, void* out, const void* in, int out_pa
   d.a = a;
   d.b = b;
   d.partial = partial;
+  d.stop_at = gate;
   return launch_dslash(HMC_F64, dag, epi, v.g, out_par, nullptr, 1, d, st, 0);
 }
 
-hipError_t mhat64(const SolveVecs& v, void* out, const void* in, int dag, double* partial, hipStream_t st) {
-  hipError_t e = ds64(v, v.t64, in, 1, dag, EPI_PLAIN, nullptr, 0.0, 1.0, nullptr, st);
+static hipError_t mhat64_gated(const SolveVecs& v, void* out, const void* in, int dag, double* partial,
+                               hipStream_t st, const int* gate) {
+  hipError_t e = ds64(v, v.t64, in, 1, dag, EPI_PLAIN, nullptr, 0.0, 1.0, nullptr, st, gate);
   if (e != hipSuccess) return e;
-  return ds64(v, out, v.t64, 0, dag, partial ? EPI_AXPY_NORM : EPI_AXPY, in, 1.0, -v.kappa * v.kappa, partial, st);
+  return ds64(v, out, v.t64, 0, dag, partial ? EPI_AXPY_NORM : EPI_AXPY, in, 1.0, -v.kappa * v.kappa, partial, st,
+              gate);
 }
 
-hipError_t true_residual(const SolveVecs& v, hipStream_t st) {
+hipError_t mhat64(const SolveVecs& v, void* out, const void* in, int dag, double* partial, hipStream_t st) {
+  return mhat64_gated(v, out, in, dag, partial, st, nullptr);
+}
+
+static hipError_t true_residual_gated(const SolveVecs& v, hipStream_t st, const int* gate) {
   hipError_t e;
   if (v.cgls) {
-    if ((e = mhat64(v, v.q64, v.x, 0, nullptr, st))) return e;
+    if ((e = mhat64_gated(v, v.q64, v.x, 0, nullptr, st, gate))) return e;
   } else {
-    if ((e = mhat64(v, v.s64, v.x, 0, nullptr, st))) return e;
-    if ((e = mhat64(v, v.q64, v.s64, 1, nullptr, st))) return e;
+    if ((e = mhat64_gated(v, v.s64, v.x, 0, nullptr, st, gate))) return e;
+    if ((e = mhat64_gated(v, v.q64, v.s64, 1, nullptr, st, gate))) return e;
   }
-  if ((e = launch_xmy_norm(v.g, v.rhs, v.q64, v.r64, v.red, v.nbR, st))) return e;
-  return launch_finalize(v.red, v.nbR, 1, v.slot, 1.0, 0, st);
+  if ((e = launch_xmy_norm(v.g, v.rhs, v.q64, v.r64, v.red, v.nbR, st, gate))) return e;
+  return launch_finalize(v.red, v.nbR, 1, v.slot, 1.0, 0, st, gate);
 }
+
+hipError_t true_residual(const SolveVecs& v, hipStream_t st) { return true_residual_gated(v, st, nullptr); }
 
 hipError_t reliable_update(const SolveVecs& v, hipStream_t st) {
   hipError_t e = launch_add_low_to_f64(v.g, v.x, v.xl, st);
@@ -156,34 +181,64 @@ hipError_t reliable_update(const SolveVecs& v, hipStream_t st) {
   return true_residual(v, st);
 }
 
+// r = low(r64) (unless already converted) and the inner |r|^2 (CG) or
+// s = Mhat^dag r with |s|^2 (CGLS) into `part`, optionally gated.
+static hipError_t restart_vectors(const SolveVecs& v, double* part, hipStream_t st, const int* gate,
+                                  bool convert = true) {
+  hipError_t e;
+  if (convert && (e = launch_convert_spinor(v.g, v.r64, HMC_F64, v.r, v.prec, 1, nullptr, nullptr, st, gate)))
+    return e;
+  if (!v.cgls) return launch_norm2_partials(v.g, v.prec, v.r, part, v.nbD, st, gate);
+  DslashArgs d{};
+  d.U = v.Ulow;
+  d.su3 = v.su3;
+  d.shape = v.shape;
+  d.in = v.r;
+  d.out = v.t;
+  d.a = 1.0;
+  d.b = 1.0;
+  d.stop_at = gate;
+  if ((e = launch_dslash(v.prec, 1, EPI_PLAIN, v.g, 1, nullptr, 1, d, st, 0))) return e;
+  d.in = v.t;
+  d.out = v.s;
+  d.y = v.r;
+  d.b = -v.kappa * v.kappa;
+  d.partial = part;
+  return launch_dslash(v.prec, 1, EPI_AXPY_NORM, v.g, 0, nullptr, 1, d, st, 0);
+}
+
 hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st) {
   hipError_t e;
   const size_t lowbytes = (size_t)v.g.Vh * (v.prec == HMC_F32 ? 96 : v.prec == HMC_F16 ? 52 : 48);
-  if ((e = launch_convert_spinor(v.g, v.r64, HMC_F64, v.r, v.prec, 1, nullptr, nullptr, st))) return e;
-  double* part = v.pp[k & 1];
-  if (v.cgls) {
-    DslashArgs d{};
-    d.U = v.Ulow;
-    d.su3 = v.su3;
-    d.shape = v.shape;
-    d.in = v.r;
-    d.out = v.t;
-    d.a = 1.0;
-    d.b = 1.0;
-    if ((e = launch_dslash(v.prec, 1, EPI_PLAIN, v.g, 1, nullptr, 1, d, st, 0))) return e;
-    d.in = v.t;
-    d.out = v.s;
-    d.y = v.r;
-    d.b = -v.kappa * v.kappa;
-    d.partial = part;
-    if ((e = launch_dslash(v.prec, 1, EPI_AXPY_NORM, v.g, 0, nullptr, 1, d, st, 0))) return e;
-    if (first && (e = launch_copy(v.p, v.s, lowbytes, st))) return e;
-  } else {
-    if ((e = launch_norm2_partials(v.g, v.prec, v.r, part, v.nbD, st))) return e;
-    if (first && (e = launch_copy(v.p, v.r, lowbytes, st))) return e;
-  }
+  if ((e = restart_vectors(v, v.pp[k & 1], st, nullptr))) return e;
+  if (first && (e = launch_copy(v.p, v.cgls ? v.s : v.r, lowbytes, st))) return e;
   if (first && (e = launch_zero(v.xl, (size_t)v.g.Vh * 96, st))) return e;
-  return launch_state_reset(v.state, v.slot, 1, first ? 1 : 0, st);
+  return launch_state_reset(v.state, v.slot, 1, first ? 1 : 0, v.thr, st);
+}
+
+// The device-driven reliable update closing a mixed-precision chunk: every
+// launch is gated on the state's ru_gate, set by the p-update that asked
+// for it (which has also folded the inner solution into x).  q = A x in
+// FP64, r64 = rhs - q and r = low(r64) in one pass, the restarted |r|^2
+// (CG) or s = Mhat^dag r with |s|^2 (CGLS) into both ping-pong buffers (so
+// the next iteration finds it whatever the parity of its label; the other
+// buffer is rewritten before it is read), then the decision.
+static hipError_t reliable_update_block(const SolveVecs& v, int max_ru, int max_iters, hipStream_t st) {
+  const int* gate = &v.state->ru_gate;
+  hipError_t e;
+  if (v.cgls) {
+    if ((e = mhat64_gated(v, v.q64, v.x, 0, nullptr, st, gate))) return e;
+    if ((e = launch_ru_residual(v.g, v.prec, v.rhs, v.q64, v.r64, v.r, v.red, nullptr, nullptr, v.nbD, gate, st)))
+      return e;
+    if ((e = restart_vectors(v, v.pp[0], st, gate, false))) return e;
+    if ((e = launch_copy_doubles_gated(v.pp[1], v.pp[0], v.nbD, gate, st))) return e;
+  } else {
+    if ((e = mhat64_gated(v, v.s64, v.x, 0, nullptr, st, gate))) return e;
+    if ((e = mhat64_gated(v, v.q64, v.s64, 1, nullptr, st, gate))) return e;
+    if ((e = launch_ru_residual(v.g, v.prec, v.rhs, v.q64, v.r64, v.r, v.red, v.pp[0], v.pp[1], v.nbD, gate, st)))
+      return e;
+  }
+  return launch_ru_finish(v.state, v.red, v.nbD, v.slot, max_ru, max_iters, st);
 }
 
 namespace {
@@ -196,19 +251,152 @@ hipError_t read_state(Fields* F, SolverState* out, hipStream_t st) {
   return hipSuccess;
 }
 
+// What a chunk of a solve launches besides its iterations.
+struct ChunkExtra {
+  bool ru = false;  // the gated reliable update (mixed precision)
+  int max_ru = 0, max_iters = 0;
+};
+
+// The launches of one chunk: iterations j = 0..n-1, the label advance and
+// (mixed precision) the gated reliable update.
+hipError_t chunk_launches(const SolveVecs& v, const IterArgs& args, int n, const ChunkExtra& x, hipStream_t st) {
+  for (int j = 0; j < n; ++j) {
+    hipError_t e = launch_iteration(v.g, v.prec, v.cgls, nullptr, args, 1, v.nbD, v.nbR, j, st);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_advance_base(v.state, n, st);
+  if (e != hipSuccess || !x.ru) return e;
+  return reliable_update_block(v, x.max_ru, x.max_iters, st);
+}
+
+// Which chunks are replayed from recordings.  Measured on MI355X (ROCm
+// 7.2), direct launches win everywhere: a replayed launch that exits at
+// once (an iteration queued past a stop, an update gate with no request)
+// occupies the GPU for several microseconds, more than issued directly, and
+// the host issues these launches fast enough once no reliable update waits
+// for it (16^3x32 trajectories: FP64 0.1187 direct / 0.1211 replayed; with
+// FP32 / FP16 / BF16 force solves 0.1027 / 0.0950 / 0.0867 direct against
+// 0.1065 / 0.0990 / 0.0916 replayed).  So chunks launch directly unless
+// HMC_SOLVER_GRAPHS asks otherwise: =mixed replays the mixed-precision
+// chunks, =all every chunk, =strict every chunk with a failed recording an
+// error instead of a fall-back to direct launches (for tests).
+enum GraphMode { GRAPHS_NONE = 0, GRAPHS_MIXED = 1, GRAPHS_ALL = 2, GRAPHS_STRICT = 3 };
+int graphs_mode() {
+  const char* e = std::getenv("HMC_SOLVER_GRAPHS");
+  if (!e || e[0] == '0') return GRAPHS_NONE;
+  if (std::strcmp(e, "mixed") == 0) return GRAPHS_MIXED;
+  if (std::strcmp(e, "all") == 0) return GRAPHS_ALL;
+  return std::strcmp(e, "strict") == 0 ? GRAPHS_STRICT : GRAPHS_NONE;
+}
+
+// The recorded form of a chunk: everything its launches depend on goes
+// into the key (the launch arguments, the buffers of the gated update, the
+// launch decisions in force), so a replay issues exactly the launches a
+// direct chunk would.
+hipError_t recorded_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, int n, const ChunkExtra& x,
+                          hipGraphExec_t* out) {
+  struct KeyData {
+    IterArgs args;
+    SolveVecs v;
+    int ru, max_ru, max_iters, n;
+    uint64_t tune;
+  } kd;
+  std::memset(&kd, 0, sizeof kd);
+  std::memcpy(&kd.args, &args, sizeof args);
+  std::memcpy(&kd.v, &v, sizeof v);
+  kd.v.thr = 0.0;  // read from the solver state, not recorded
+  kd.ru = x.ru ? 1 : 0;
+  kd.max_ru = x.max_ru;
+  kd.max_iters = x.max_iters;
+  kd.n = n;
+  kd.tune = tune_generation();
+  std::string key(reinterpret_cast<const char*>(&kd), sizeof kd);
+  ++F->record_clock;
+  for (Fields::Recorded& r : F->recorded)
+    if (r.key == key) {
+      r.last_use = F->record_clock;
+      *out = r.exec;
+      return hipSuccess;
+    }
+  hipError_t e;
+  if (!F->record_stream && (e = hipStreamCreateWithFlags(&F->record_stream, hipStreamNonBlocking))) return e;
+  if ((e = hipStreamBeginCapture(F->record_stream, hipStreamCaptureModeThreadLocal))) return e;
+  timing_set_recording(true);
+  hipError_t le = chunk_launches(v, args, n, x, F->record_stream);
+  timing_set_recording(false);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(F->record_stream, &graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return le != hipSuccess ? le : e;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  if ((int)F->recorded.size() >= kMaxRecorded) {  // drop the least recently used
+    auto old = std::min_element(F->recorded.begin(), F->recorded.end(),
+                                [](const Fields::Recorded& a, const Fields::Recorded& b) {
+                                  return a.last_use < b.last_use;
+                                });
+    hipGraphExecDestroy(old->exec);
+    F->recorded.erase(old);
+  }
+  F->recorded.push_back(Fields::Recorded{key, exec, F->record_clock});
+  *out = exec;
+  return hipSuccess;
+}
+
+// Launches a chunk of n iterations: replayed from its recording, or
+// directly (see graphs_mode).  While the kernel timing samples every m-th
+// launch, every m-th chunk that would be replayed runs directly with all
+// its launches timed, so the sampled durations are those of the launches a
+// replay issues.
+hipError_t launch_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, int n, const ChunkExtra& x,
+                        hipStream_t st) {
+  static thread_local unsigned counter = 0;
+  const int mode = graphs_mode();
+  const bool record = mode == GRAPHS_ALL || mode == GRAPHS_STRICT || (mode == GRAPHS_MIXED && x.ru);
+  if (!record || (F->record_failed && mode != GRAPHS_STRICT)) return chunk_launches(v, args, n, x, st);
+  const int every = timing_sample_every();
+  if (every > 0 && counter++ % every == 0) {
+    timing_sample_all(true);
+    hipError_t e = chunk_launches(v, args, n, x, st);
+    timing_sample_all(false);
+    return e;
+  }
+  hipGraphExec_t exec;
+  hipError_t e = recorded_chunk(F, v, args, n, x, &exec);
+  if (e != hipSuccess) {
+    if (mode == GRAPHS_STRICT) return e;
+    (void)hipGetLastError();  // a runtime that cannot record these launches: launch them directly from now on
+    F->record_failed = true;
+    return chunk_launches(v, args, n, x, st);
+  }
+  timing_count(TK_DSLASH, 4LL * n);
+  timing_count(TK_CG_BLAS, (v.cgls ? 2LL : 1LL) * n);
+  return hipGraphLaunch(exec, st);
+}
+
 // A chunk of enqueued iterations whose solver state is being copied back
 // into pinned slot `slot` (completion marked by F->state_ev[slot]).
 struct Chunk {
   int k, n, slot;
 };
 
-hipError_t enqueue_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, const Chunk& c, hipStream_t st) {
-  for (int j = 0; j < c.n; ++j) {
-    hipError_t e = launch_iteration(v.g, v.prec, v.cgls, nullptr, args, 1, v.nbD, v.nbR, c.k + j, st);
-    if (e != hipSuccess) return e;
-  }
-  static_assert(sizeof(SolverState) <= 8 * sizeof(double), "state slot");
-  hipError_t e = hipMemcpyAsync(F->pinned + SL_COUNT + 8 * c.slot, F->state, sizeof(SolverState),
+// F64 chunks: lengths taken as sums of powers of two, so at most five
+// recordings per solve configuration serve every length.
+hipError_t enqueue_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, const Chunk& c, hipStream_t st,
+                         const ChunkExtra& x = ChunkExtra{}) {
+  int left = c.n;
+  for (int p = kChunk; p >= 1; p >>= 1)
+    while (left >= p) {
+      hipError_t e = launch_chunk(F, v, args, p, x, st);
+      if (e != hipSuccess) return e;
+      left -= p;
+    }
+  static_assert(sizeof(SolverState) <= kStateSlot * sizeof(double), "state slot");
+  hipError_t e = hipMemcpyAsync(F->pinned + SL_COUNT + kStateSlot * c.slot, F->state, sizeof(SolverState),
                                 hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   return hipEventRecord(F->state_ev[c.slot], st);
@@ -217,11 +405,11 @@ hipError_t enqueue_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, co
 hipError_t wait_chunk(Fields* F, const Chunk& c, SolverState* out) {
   hipError_t e = hipEventSynchronize(F->state_ev[c.slot]);
   if (e != hipSuccess) return e;
-  std::memcpy(out, F->pinned + SL_COUNT + 8 * c.slot, sizeof(SolverState));
+  std::memcpy(out, F->pinned + SL_COUNT + kStateSlot * c.slot, sizeof(SolverState));
   return hipSuccess;
 }
 
-// Runs iterations with labels *k.. until the device stops or `limit` is
+// Runs F64 iterations with labels *k.. until the device stops or `limit` is
 // reached; leaves the next label in *k.  The chunk length follows the
 // observed convergence rate toward `target` (|r|^2 at which the device will
 // stop), so few iterations are enqueued past the stop; while the host waits
@@ -273,6 +461,89 @@ hipError_t run_until_stop(Fields* F, const SolveVecs& v, const IterArgs& args, i
     cur = Chunk{next, std::min({kChunk, limit - next, std::max(1, (int)std::ceil(predict(rr_now)))}), cur.slot ^ 1};
     if ((e = enqueue_chunk(F, v, args, cur, st))) return e;
     next += cur.n;
+  }
+}
+
+// Mixed precision with the reliable updates on the device: chunks of inner
+// iterations, each closed by the gated update, until the device marks the
+// solve done (FP64 true residual <= thr, non-finite, or a limit).  The host
+// reads the state of one chunk while the next is queued and sizes the chunk
+// after it so that it ends at the iteration predicted to ask for the next
+// update: the spacing of the last two updates (inner iterations), or before
+// two updates the decrease of the inner |r|^2 toward max(thr, delta^2
+// maxrr) at the observed rate.  An iteration queued past the request exits
+// at once, an update gate that finds no request does nothing; both cost a
+// few microseconds of dispatch.  The host stops queueing when the last
+// update read implies that the next one ends the solve.  Returns the final
+// state in *stt.
+hipError_t run_mixed(Fields* F, const SolveVecs& v, const IterArgs& args, int limit, double rr0, double thr,
+                     double delta2, SolverState* stt, hipStream_t st) {
+  ChunkExtra x;
+  x.ru = true;
+  x.max_ru = kMaxReliable;
+  x.max_iters = limit;
+  double rate = std::log(delta2) / 8;  // log |r|^2 per inner iteration (a first guess)
+  auto iterations_to = [&](double ratio) {  // inner iterations until |r|^2 falls by `ratio`
+    if (!(rate < 0)) return kChunk;
+    const double m = std::log(ratio) / rate;
+    if (!(m > 1)) return 1;
+    return m >= kChunk ? kChunk : (int)std::ceil(m - 1e-9);
+  };
+  int spacing = 0;  // inner iterations between the last two updates (0: not seen yet)
+  int labels = 0;
+  Chunk cur{labels, iterations_to(std::max(thr / rr0, delta2)), 0};
+  hipError_t e;
+  if ((e = enqueue_chunk(F, v, args, cur, st, x))) return e;
+  labels += cur.n;
+  int queued = iterations_to(delta2);  // length of the next chunk to queue
+  bool last_expected = false;
+  SolverState prev{};
+  prev.maxrr = prev.rr = rr0;
+  while (true) {
+    Chunk nxt{labels, 0, cur.slot ^ 1};
+    if (!last_expected && labels < limit + kChunk) {
+      nxt.n = queued;
+      if ((e = enqueue_chunk(F, v, args, nxt, st, x))) return e;
+      labels += nxt.n;
+    }
+    if ((e = wait_chunk(F, cur, stt))) return e;
+    if (stt->done) return hipSuccess;
+    const bool updated = stt->nru > prev.nru;
+    if (updated && prev.nru > 0) spacing = stt->ru_iter - prev.ru_iter;
+    if (!updated && stt->iters > prev.iters && stt->rr > 0 && prev.rr > 0 && stt->rr < prev.rr)
+      rate = std::log(stt->rr / prev.rr) / (stt->iters - prev.iters);
+    // inner iterations from the end of `cur` to the next request, and what
+    // the chunk already queued (nxt) takes of them
+    int per_update = spacing > 0 ? std::min(spacing, kChunk) : iterations_to(delta2);
+    int m;
+    if (spacing > 0)
+      m = std::max(1, stt->ru_iter + spacing - stt->iters);
+    else
+      m = updated ? iterations_to(std::max(thr / stt->rr64, delta2))
+                  : iterations_to(std::max(thr, delta2 * stt->maxrr) / stt->rr);
+    if (nxt.n > 0)
+      queued = m > nxt.n ? m - nxt.n : per_update;
+    else
+      queued = m;
+    queued = std::max(1, std::min(kChunk, queued));
+    if (updated) last_expected = stt->rr64 * delta2 <= thr;
+    prev = *stt;
+    if (nxt.n > 0) {
+      cur = nxt;
+      continue;
+    }
+    if (labels >= limit + kChunk) {
+      // no update was asked for within the iteration limit: force one,
+      // which ends the solve (max_iters 0: converged or at the limit)
+      if ((e = launch_ru_request(v.state, st))) return e;
+      if ((e = launch_add_low_to_f64(v.g, v.x, v.xl, st))) return e;
+      if ((e = reliable_update_block(v, x.max_ru, 0, st))) return e;
+      return read_state(F, stt, st);
+    }
+    cur = Chunk{labels, queued, cur.slot ^ 1};
+    last_expected = false;  // nothing is queued: queue one and look again
+    if ((e = enqueue_chunk(F, v, args, cur, st, x))) return e;
+    labels += cur.n;
   }
 }
 
@@ -359,6 +630,7 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   CHK(read_slots(F, SL_SOLVER, 1, &rr0, st));
   if (!cgls && !guess) bnorm2 = rr0;
   const double thr = fixed > 0 ? -1.0 : prm->tol * prm->tol * bnorm2;
+  v.thr = thr;
 
   int k = 0;
   SolverState stt{};
@@ -373,9 +645,9 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
       CHK(mhat64(v, v.s, v.r, 1, v.pp[0], st));  // s = Mhat^dag r, |s|^2 into pp[0]
       CHK(launch_copy(v.p, v.s, F->half64, st));
     }
-    CHK(launch_state_reset(v.state, nullptr, 1, 1, st));
+    CHK(launch_state_reset(v.state, nullptr, 1, 1, thr, st));
     IterArgs args;
-    build_iteration(v, 0, thr, 0, 0.0, &args);
+    build_iteration(v, 0, 0, 0.0, &args);
     double rate = 0;
     CHK(run_until_stop(F, v, args, &k, limit, &stt, st, rr0, thr, &rate));
     S.iters = stt.iters;
@@ -384,29 +656,14 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
     else if (fixed == 0 && !(stt.rr <= thr)) status = HMC_E_NOCONV;
   } else {
     IterArgs args;
-    build_iteration(v, 0, thr, 1, delta * delta, &args);
+    build_iteration(v, 0, 1, delta * delta, &args, true);
     CHK(inner_restart(v, 0, true, st));  // the slot holds |r64|^2 = rr0
-    double rr64 = rr0, rate = 0;
-    while (true) {
-      // the inner iteration pauses once |r|^2 < delta^2 max|r|^2 (or <= thr)
-      CHK(run_until_stop(F, v, args, &k, limit, &stt, st, rr64, std::max(thr, delta * delta * rr64), &rate));
-      CHK(reliable_update(v, st));
-      CHK(read_slots(F, SL_SOLVER, 1, &rr64, st));
-      S.reliable_updates++;
-      if (rr64 <= thr) break;
-      if (!std::isfinite(rr64) || !std::isfinite(stt.rr)) {
-        status = HMC_E_NAN;
-        break;
-      }
-      if (k >= limit || S.reliable_updates >= kMaxReliable) {
-        status = HMC_E_NOCONV;
-        break;
-      }
-      CHK(inner_restart(v, k, false, st));
-    }
-    CHK(read_state(F, &stt, st));
+    CHK(run_mixed(F, v, args, limit, rr0, thr, delta * delta, &stt, st));
     S.iters = stt.iters;
-    S.rel_res = std::sqrt(rr64 / bnorm2);
+    S.reliable_updates = stt.nru;
+    S.rel_res = std::sqrt(stt.rr64 / bnorm2);
+    if (stt.done == 3) status = HMC_E_NAN;
+    else if (stt.done != 1) status = HMC_E_NOCONV;
   }
 
   // ---- odd half and FP64 true residual

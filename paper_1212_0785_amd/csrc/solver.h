@@ -32,6 +32,7 @@ struct SolveVecs {
   double* red;       // scratch partials for FP64 reductions (>= 2 * nbR)
   double* slot;      // device scalar (FP64 reductions land here)
   SolverState* state;
+  double thr;        // stop threshold on |r|^2 of the solve
   int nbD, nbR;
 };
 
@@ -41,7 +42,11 @@ struct IterArgs {
   CgArgs c[2];
 };
 
-void build_iteration(const SolveVecs& v, int iter0, double thr, int mixed, double delta2, IterArgs* out);
+// device_updates: mixed precision with the reliable updates decided and
+// performed on the device (the iteration that asks for one folds the inner
+// solution into the FP64 one).
+void build_iteration(const SolveVecs& v, int iter0, int mixed, double delta2, IterArgs* out,
+                     bool device_updates = false);
 
 // Device copies of the per-entry arguments of a batch (each an array of
 // nbatch entries), or nullptrs for a single solve taken from `one`.

@@ -14,6 +14,7 @@
 // saves entries.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -41,6 +42,10 @@ struct Table {
   std::map<Key, Entry> map;
   bool env_loaded = false;
 };
+
+// Bumped whenever an entry may have changed (recorded solver launches
+// depend on the decisions in force when they were recorded).
+std::atomic<uint64_t> g_generation{1};
 
 Table& table() {
   static Table t;
@@ -119,14 +124,18 @@ void tune_store(const int* L, int kind, int prec, int choice, double us) {
   std::lock_guard<std::mutex> lk(t.mu);
   ensure_env_loaded(t);
   t.map[make_key(L, kind, prec)] = Entry{choice, us};
+  ++g_generation;
 }
 
 int tune_load(const char* path) {
   Table& t = table();
   std::lock_guard<std::mutex> lk(t.mu);
   ensure_env_loaded(t);
+  ++g_generation;
   return load_locked(t, path);
 }
+
+uint64_t tune_generation() { return g_generation.load(); }
 
 int tune_save(const char* path) {
   Table& t = table();

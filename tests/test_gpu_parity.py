@@ -652,3 +652,32 @@ def test_gauge_force_sampled_at_48c96(H):
     want = -np.stack([Fo[..., 0, 0].real, Fo[..., 1, 1].real, Fo[..., 0, 1].real, Fo[..., 0, 1].imag,
                       Fo[..., 0, 2].real, Fo[..., 0, 2].imag, Fo[..., 1, 2].real, Fo[..., 1, 2].imag], -1)
     assert rel(dP, want) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_trajectory_with_mixed_precision_solves_c1(H, prec):
+    """The 4^4 chain with the force solves in mixed precision (FP32 / FP16 /
+    BF16 inner storage, device-driven FP64 reliable updates, the same 1e-10
+    FP64 true-residual stop) against the FP64 oracle: every energy within
+    1e-10 of H_old (the solves differ from the oracle's by their residual
+    tolerance, not by rounding), the same Metropolis decision, links after
+    the integration within 1e-9."""
+    L = (4, 4, 4, 4)
+    seed, beta, k = 12120785, 5.6, 0.15
+    F = H.Fields(L, beta, k, flags=H.FIELDS_LOWPREC)
+    H.hmc_weak_field_start(F, seed, 0.3)
+    U = O.weak_field(L, seed, 0.3)
+    prm = H.cg_params(tol=1e-10, prec=prec)
+    for traj in range(2):
+        r = H.hmc_trajectory(F, seed, traj, 1.0, 10, prm)
+        U_md = O.leapfrog(L, U, O.refresh_momenta(L, seed, traj),
+                          O.mhat(L, U, k, O.eta(L, seed, traj, 0), dagger=True), beta, k, 1.0, 10, tol=1e-10)[0]
+        U, o = O.hmc_trajectory(L, U, beta, k, seed, traj, 1.0, 10, tol=1e-10)
+        assert r["status"] == 0 and r["accepted"] == o["accepted"] and r["u"] == o["u"]
+        dev = {key: abs(r[key] - o[key]) / abs(o["H_old"]) for key in ("H_old", "H_new", "dH", "S_f_new")}
+        print(f"prec {prec} trajectory {traj}: deviations relative to H_old", {kk: f"{v:.1e}" for kk, v in dev.items()})
+        assert max(dev.values()) < 1e-10, dev
+        if not r["accepted"]:
+            assert rel(get_gauge(H, F), U) < 1e-14  # restored start
+        else:
+            assert rel(get_gauge(H, F), U_md) < 1e-9

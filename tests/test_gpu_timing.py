@@ -5,6 +5,8 @@ groups of four Dslash launches; the algorithmic bytes per Dslash launch lie
 between the plain hop's and the CG-epilogue hop's, and exceed the bytes as
 implemented by the compact links' saving; the probe's empty
 kernels are timed under "other"; disabled sampling records nothing."""
+import os
+
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -20,7 +22,17 @@ def H():
     return hmc
 
 
-def test_cg_iterations_timed_in_groups(H):
+@pytest.fixture
+def direct():
+    """The timed launches are those issued directly (a chunk replayed from
+    its recording takes no events); HMC_SOLVER_GRAPHS=0 issues all of them
+    directly."""
+    os.environ["HMC_SOLVER_GRAPHS"] = "0"
+    yield
+    os.environ.pop("HMC_SOLVER_GRAPHS", None)
+
+
+def test_cg_iterations_timed_in_groups(H, direct):
     L = (8, 8, 8, 16)   # two-row links by the built-in rule at this volume
     F = H.Fields(L, 5.6, 0.15)
     H.hmc_weak_field_start(F, 5, 0.3)
@@ -67,6 +79,17 @@ def test_cg_iterations_timed_in_groups(H):
     H.hmc_timing_enable(0)
     H.hmc_timing_reset()
     assert ds5["calls"] == ds["calls"] and 0 < ds5["launches"] < ds["launches"]
+    # replayed recordings: every launch still counted; every second chunk
+    # runs directly with all its launches timed
+    os.environ["HMC_SOLVER_GRAPHS"] = "strict"
+    H.hmc_timing_reset()
+    H.hmc_timing_enable(2)
+    H.hmc_cg_solve(F, x, b, prm)
+    torch.cuda.synchronize()
+    dsg = H.hmc_timing_read()["dslash"]
+    H.hmc_timing_enable(0)
+    H.hmc_timing_reset()
+    assert dsg["calls"] == ds["calls"] and 0 < dsg["launches"] < ds["launches"]
 
 
 def test_probe(H):
