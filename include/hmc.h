@@ -305,11 +305,15 @@ hmc_status hmc_random_gaussians(uint64_t seed, uint64_t rng_stream, uint64_t epo
  * iteration on vectors and links stored in that format with FP32
  * arithmetic and FP64 global sums, and replace the residual by the FP64
  * true residual b - A x whenever the inner residual fell by
- * reliable_delta (Clark et al., Comput. Phys. Commun. 181 (2010) 1517);
- * the exit test is always on the FP64 true residual.  Needs
- * HMC_FIELDS_LOWPREC.  fixed_iters > 0 runs exactly that many (outer
- * FP64) iterations and ignores tol.  Synchronises the stream; fills
- * stats.  HMC_E_NOCONV when maxiter is reached (x holds the last iterate);
+ * reliable_delta (Clark et al., Comput. Phys. Commun. 181 (2010) 1517),
+ * and at least every 48 inner iterations; an update keeps the search
+ * direction unless the FP64 residual exceeds twice the inner one or did
+ * not fall since the previous update, when it restarts it from the new
+ * residual (BF16 storage with delta <= 0.01 needs this); the exit test is
+ * always on the FP64 true residual.  Needs HMC_FIELDS_LOWPREC.
+ * fixed_iters > 0 (F64 only) runs exactly that many iterations and ignores
+ * tol.  Synchronises the stream; fills stats.  HMC_E_NOCONV when maxiter
+ * is reached (after exactly maxiter iterations; x holds the last iterate);
  * HMC_E_NAN when |b|^2 or a residual norm is not finite (the iteration
  * stops at the first such norm; x holds the last iterate). */
 typedef enum { HMC_CG_NORMAL_MHAT = 0, HMC_CG_WILSON_SOLVE = 1 } hmc_cg_mode;

@@ -168,7 +168,8 @@ __global__ void k_zero(uint4* p, size_t n16, unsigned char* tail, size_t ntail) 
 }
 
 __global__ void k_copy(uint4* d, const uint4* s, size_t n16, unsigned char* dt, const unsigned char* st,
-                       size_t ntail) {
+                       size_t ntail, const int* gate) {
+  if (gate && *gate == 0) return;
   for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n16; j += (size_t)gridDim.x * kBlock) d[j] = s[j];
   if (blockIdx.x == 0 && threadIdx.x < ntail) dt[threadIdx.x] = st[threadIdx.x];
 }
@@ -342,8 +343,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
       // for one?  (Block 0 may already have raised maxrr to max(maxrr, rr):
       // every block gets the same answer.)
       const double r2 = a.cgls ? v[2] : v[0];
+      // (ru_iter and ru_label change only between chunks, so every block
+      // counts the same iterations.)
+      const int done_after = stt->ru_iter + (k + 1 - stt->ru_label);
       fold_sh = a.x64 && (r2 <= stt->thr || r2 < a.delta2 * fmax(stt->maxrr, r2) || !(r2 == r2) ||
-                          k + 1 - stt->ru_label >= kMaxInner);
+                          k + 1 - stt->ru_label >= kMaxInner || (a.max_iters > 0 && done_after >= a.max_iters));
     }
     __syncthreads();
   }
@@ -362,8 +366,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
       double mx = fmax(stt->maxrr, rr);
       stt->maxrr = mx;
       // device-driven updates also come every kMaxInner iterations, so a
-      // low-precision recursion that stagnates cannot run away
-      if (conv || rr < a.delta2 * mx || !(rr == rr) || (a.x64 && k + 1 - stt->ru_label >= kMaxInner)) {
+      // low-precision recursion that stagnates cannot run away, and at the
+      // iteration limit
+      if (a.x64 ? fold : (conv || rr < a.delta2 * mx || !(rr == rr))) {
         stt->reason = 2;
         stt->stop_at = k + 1;
         stt->ru_gate = INT_MAX;  // a device-driven solve updates next
@@ -466,10 +471,20 @@ __global__ void k_ru_request(SolverState* st) {
 // synchronises the block in between).
 __global__ void __launch_bounds__(kBlock) k_ru_finish(SolverState* st, const double* part64, int n, double* slot,
                                                      int max_ru, int max_iters) {
-  if (st->ru_gate == 0) return;
+  if (st->ru_gate == 0) {
+    if (threadIdx.x == 0) st->restart = 0;
+    return;
+  }
   const double rr64 = sum_partials(part64, n);
   if (threadIdx.x != 0) return;
   *slot = rr64;
+  // The reliable update keeps the search direction p, which is conjugate
+  // for the recursive residual it replaces.  Where the two differ by more
+  // than a factor 2 in |r|^2, or a whole cycle of inner iterations did not
+  // lower the FP64 residual, the low-precision recursion has lost track
+  // (BF16 storage with a small delta does this) and keeping p makes the
+  // iteration diverge: p restarts from the new residual instead.
+  st->restart = rr64 > 2.0 * st->rr || (st->nru > 0 && rr64 >= st->rr64);
   st->nru += 1;
   st->ru_iter = st->iters;
   st->ru_label = st->base;
@@ -639,12 +654,16 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+hipError_t launch_copy_gated(void* dst, const void* src, size_t bytes, const int* gate, hipStream_t st) {
   size_t n16 = bytes / 16, nt = bytes % 16;
   int nb = (int)std::min<size_t>(std::max<size_t>((n16 + kBlock - 1) / kBlock, 1), 4096);
   hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kBlock), 0, st, (uint4*)dst, (const uint4*)src, n16,
-                     (unsigned char*)dst + n16 * 16, (const unsigned char*)src + n16 * 16, nt);
+                     (unsigned char*)dst + n16 * 16, (const unsigned char*)src + n16 * 16, nt, gate);
   return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  return launch_copy_gated(dst, src, bytes, nullptr, st);
 }
 
 hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x, void* r, void* p, double* part,

@@ -112,6 +112,7 @@ struct SolverState {
   int nru;       // device-driven reliable updates performed
   int ru_iter;   // iterations completed at the last device-driven update
   int ru_label;  // label of the first iteration after the last device-driven update
+  int restart;   // the last device-driven update restarts the search direction (p = r, or s for CGLS)
   double rr;     // last residual norm^2 seen by the p-update
   double maxrr;  // mixed precision: max inner |r|^2 since the last update
   double alpha;  // CG step length of the current iteration (fused form)
@@ -193,6 +194,8 @@ hipError_t launch_xmy_norm(const LatArg& g, const void* b, const void* q, void* 
                            hipStream_t st, const int* gate = nullptr);  // r = b - q, partials of |r|^2
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+// dst = src (bytes a multiple of 8) while *gate != 0.
+hipError_t launch_copy_gated(void* dst, const void* src, size_t bytes, const int* gate, hipStream_t st);
 
 // Krylov solver kernels.  `prec` is the storage of p/r/q/s; x is FP64 for
 // HMC_F64 and FP32 (inner accumulator) otherwise.
@@ -214,6 +217,7 @@ struct CgArgs {
                    // iteration that asks for an update folds the inner solution (null: the host does)
   int mixed;       // 1: never declare convergence, pause instead
   int fused;       // CG with the residual update in the Dslash epilogue: the p-update also does x += alpha p
+  int max_iters;   // device-driven updates: the iteration that completes this many asks for the last one (0: none)
 };
 hipError_t launch_cg_init(const LatArg& g, hmc_prec prec, const void* b, void* x, void* r, void* p, double* part,
                           int nb, hipStream_t st);
@@ -236,7 +240,10 @@ hipError_t launch_add_low_to_f64(const LatArg& g, void* x64, void* xlow, hipStre
 // |r64|^2 partials into *rr64_slot, counts the update and either ends the
 // solve (converged, non-finite, max_ru updates or max_iters iterations
 // reached) or resumes the inner iteration (stop_at = INT_MAX, maxrr =
-// |r64|^2); clears the gate.
+// |r64|^2); sets st->restart when the search direction must restart (the
+// FP64 residual exceeds twice the inner one that asked for the update, or
+// did not fall below the previous update's), else clears it (also when no
+// update was pending); clears the gate.
 hipError_t launch_ru_finish(SolverState* st_dev, const double* part64, int n, double* rr64_slot, int max_ru,
                             int max_iters, hipStream_t st);
 // Device-driven reliable update after q = A x (gated): r64 = rhs - q with

@@ -116,6 +116,7 @@ struct Req {
   double bnorm2 = 0, thr = 0;
   int iter0 = 0;
   int reliable = 0;
+  double last_rr64 = 0;  // FP64 |r|^2 of the previous reliable update
   int max_group = 0;
   bool fresh = true;  // first inner start pending
   hmc_solve_result res{};
@@ -260,7 +261,7 @@ struct Service {
   }
 
   // Start (first) or resume the inner iteration at label k.
-  hipError_t start_inner(Req* r, int k, hipStream_t st) {
+  hipError_t start_inner(Req* r, int k, hipStream_t st, bool restart_p = false) {
     SolveVecs& v = r->v;
     hipError_t e;
     if (v.prec == HMC_F64) {
@@ -269,7 +270,7 @@ struct Service {
       if ((e = launch_copy(v.p, v.s, half_bytes(v.g.Vh, HMC_F64), st))) return e;
       return launch_state_reset(v.state, nullptr, 1, 1, r->thr, st);
     }
-    e = inner_restart(v, k, r->fresh, st);
+    e = inner_restart(v, k, r->fresh, st, restart_p);
     r->fresh = false;
     return e;
   }
@@ -481,7 +482,12 @@ struct Service {
         fstatus.push_back(conv ? HMC_OK : HMC_E_NOCONV);
         HMC_CHECK_HIP(finalize_enqueue(r, gr->stream));
       } else {
-        HMC_CHECK_HIP(start_inner(r, gr->J + r->iter0, gr->stream));
+        // the search direction restarts as in the single solve's device-driven
+        // update: the recursion lost track of the FP64 residual, or a cycle
+        // made no progress
+        const bool restart_p = rr64 > 2.0 * s.rr || (r->reliable > 1 && rr64 >= r->last_rr64);
+        r->last_rr64 = rr64;
+        HMC_CHECK_HIP(start_inner(r, gr->J + r->iter0, gr->stream, restart_p));
       }
     }
     if (!finishing.empty()) {

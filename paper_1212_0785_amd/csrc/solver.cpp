@@ -207,11 +207,14 @@ static hipError_t restart_vectors(const SolveVecs& v, double* part, hipStream_t 
   return launch_dslash(v.prec, 1, EPI_AXPY_NORM, v.g, 0, nullptr, 1, d, st, 0);
 }
 
-hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st) {
+static size_t low_half_bytes(const SolveVecs& v) {
+  return (size_t)v.g.Vh * (v.prec == HMC_F32 ? 96 : v.prec == HMC_F16 ? 52 : 48);
+}
+
+hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st, bool restart_p) {
   hipError_t e;
-  const size_t lowbytes = (size_t)v.g.Vh * (v.prec == HMC_F32 ? 96 : v.prec == HMC_F16 ? 52 : 48);
   if ((e = restart_vectors(v, v.pp[k & 1], st, nullptr))) return e;
-  if (first && (e = launch_copy(v.p, v.cgls ? v.s : v.r, lowbytes, st))) return e;
+  if ((first || restart_p) && (e = launch_copy(v.p, v.cgls ? v.s : v.r, low_half_bytes(v), st))) return e;
   if (first && (e = launch_zero(v.xl, (size_t)v.g.Vh * 96, st))) return e;
   return launch_state_reset(v.state, v.slot, 1, first ? 1 : 0, v.thr, st);
 }
@@ -222,7 +225,8 @@ hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st) 
 // FP64, r64 = rhs - q and r = low(r64) in one pass, the restarted |r|^2
 // (CG) or s = Mhat^dag r with |s|^2 (CGLS) into both ping-pong buffers (so
 // the next iteration finds it whatever the parity of its label; the other
-// buffer is rewritten before it is read), then the decision.
+// buffer is rewritten before it is read), then the decision, and p = r
+// (CG) or s (CGLS) where the decision restarts the search direction.
 static hipError_t reliable_update_block(const SolveVecs& v, int max_ru, int max_iters, hipStream_t st) {
   const int* gate = &v.state->ru_gate;
   hipError_t e;
@@ -238,7 +242,8 @@ static hipError_t reliable_update_block(const SolveVecs& v, int max_ru, int max_
     if ((e = launch_ru_residual(v.g, v.prec, v.rhs, v.q64, v.r64, v.r, v.red, v.pp[0], v.pp[1], v.nbD, gate, st)))
       return e;
   }
-  return launch_ru_finish(v.state, v.red, v.nbD, v.slot, max_ru, max_iters, st);
+  if ((e = launch_ru_finish(v.state, v.red, v.nbD, v.slot, max_ru, max_iters, st))) return e;
+  return launch_copy_gated(v.p, v.cgls ? v.s : v.r, low_half_bytes(v), &v.state->restart, st);
 }
 
 namespace {
@@ -657,6 +662,7 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   } else {
     IterArgs args;
     build_iteration(v, 0, 1, delta * delta, &args, true);
+    args.c[0].max_iters = args.c[1].max_iters = limit;  // the update at the limit ends the solve
     CHK(inner_restart(v, 0, true, st));  // the slot holds |r64|^2 = rr0
     CHK(run_mixed(F, v, args, limit, rr0, thr, delta * delta, &stt, st));
     S.iters = stt.iters;

@@ -67,7 +67,8 @@ hipError_t true_residual(const SolveVecs& v, hipStream_t st);
 hipError_t reliable_update(const SolveVecs& v, hipStream_t st);
 // Restart the inner iteration from the FP64 residual at label k: r = low(r64),
 // CGLS s = Mhat^dag r (partials into pp[k&1]) / CG |r|^2 into pp[k&1]; on the
-// first start also p = s (CGLS) or r (CG); state reset with maxrr = |r64|^2.
-hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st);
+// first start, or with restart_p, also p = s (CGLS) or r (CG); state reset
+// with maxrr = |r64|^2.
+hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st, bool restart_p = false);
 
 }  // namespace hmc
