@@ -254,6 +254,14 @@ def oracle_hmc_trajectory(L, seed, beta, kappa, nsteps):
             "cg_iters_total": r["cg_iters_total"]}
 
 
+def effective_delta(args):
+    """The reliable-update delta the solves use (the library picks it when
+    --reliable-delta is not given)."""
+    if args.reliable_delta > 0:
+        return args.reliable_delta
+    return 0.01 if args.cg_prec == "f32" else 0.1
+
+
 def run_hmc(args, H, torch):
     L = (16, 16, 16, 32)
     seed, beta, kappa, tau, nsteps = 12120785, 5.6, 0.156, 1.0, 20
@@ -289,7 +297,7 @@ def run_hmc(args, H, torch):
                        f"chronological, last {args.chrono} solutions" if args.chrono else "zero"),
                    "force_solves": ("FP64 CG" if cg_prec == H.F64 else
                                     f"mixed-precision CG, {args.cg_prec} inner storage, FP64 reliable updates "
-                                    f"(delta {args.reliable_delta})"),
+                                    f"(delta {effective_delta(args)})"),
                    "parallelism": "1 GPU"},
         "trajectories": [{"traj": k, "seconds": r["seconds"], "dH": r["dH"], "accepted": r["accepted"],
                           "plaquette": r["plaquette"], "cg_iters": r["cg_iters_total"]}
@@ -744,8 +752,9 @@ def main():
     ap.add_argument("--mts-steps", default="5,2,2", help="mts: ratio,heavy,gauge steps per enclosing step")
     ap.add_argument("--cg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"],
                     help="hmc: storage of the force solves' inner iteration (default f64: the plain FP64 HMC)")
-    ap.add_argument("--reliable-delta", type=float, default=0.1,
-                    help="hmc with --cg-prec other than f64: reliable-update threshold delta")
+    ap.add_argument("--reliable-delta", type=float, default=0.0,
+                    help=("hmc with --cg-prec other than f64: reliable-update threshold delta (default: the "
+                          "library's, 0.01 for f32 and 0.1 for f16 / bf16)"))
     ap.add_argument("--tune-db", default=None,
                     help=("extra launch-shape table to load (hmc_tune_load) before the run; the binding "
                           "already loads paper_1212_0785_amd/tune/mi355x.txt unless HMC_TUNE_DB is set "

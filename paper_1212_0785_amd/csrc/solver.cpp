@@ -7,10 +7,13 @@
 //    Schur complement bhat_e = b_e + kappa D_eo b_o, x_o = b_o + kappa D_oe x_e.
 //  * Mixed precision: the same iteration on FP32 / FP16 / BF16 storage with
 //    FP32 arithmetic and FP64 global sums; whenever the inner residual has
-//    fallen by reliable_delta since the last update, the inner solution is
-//    folded into the FP64 solution and the residual replaced by the FP64
-//    true residual (reliable updates, Clark et al., Comput. Phys. Commun.
-//    181 (2010) 1517); the search direction is kept.
+//    fallen by reliable_delta since the last update (or 48 inner iterations
+//    have passed), the inner solution is folded into the FP64 solution and
+//    the residual replaced by the FP64 true residual (reliable updates,
+//    Clark et al., Comput. Phys. Commun. 181 (2010) 1517).  The search
+//    direction is kept unless the update finds the recursion off track
+//    (FP64 |r|^2 above twice the inner one, or no decrease over a cycle),
+//    when it restarts from the new residual.
 //
 // An iteration is six launches on one stream (four Dslash, two vector
 // kernels) with alpha, beta and the stop test computed on the device.  The
@@ -18,13 +21,11 @@
 // chunk; iterations enqueued after the stop exit at once.  A chunk of n
 // iterations is launched with j = 0..n-1 and closed by a kernel that
 // advances the state's label base by n, so the same launches serve every
-// chunk of that length: they are recorded once into a HIP graph and
-// replayed, which takes the per-launch host cost (several us for these
-// argument sizes, more than a low-precision hop at 16^3x32 takes on the
-// GPU) off the critical path.  In mixed precision the reliable update is
-// part of the chunk too, gated on the device (it runs only when the inner
-// iteration asked for it), so a solve needs no host round trip until it
-// ends.
+// chunk of that length (and can be recorded once into a HIP graph and
+// replayed; see graphs_mode).  In mixed precision the reliable update is
+// part of the chunk too, decided and gated on the device (it runs only
+// when the inner iteration asked for it), so a solve needs no host round
+// trip until it ends.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -569,7 +570,9 @@ hmc_status cg_solve_impl(Fields* F, void* x, const void* b, const hmc_cg_params*
   const int cgls = prm->mode == HMC_CG_WILSON_SOLVE;
   const int fixed = prm->fixed_iters;
   const int limit = fixed > 0 ? fixed : prm->maxiter;
-  const double delta = prm->reliable_delta > 0 ? prm->reliable_delta : 0.1;
+  // default delta: FP32 storage tracks the FP64 residual over a hundredfold
+  // decrease (fewer updates, measured faster); FP16 / BF16 over tenfold
+  const double delta = prm->reliable_delta > 0 ? prm->reliable_delta : prec == HMC_F32 ? 0.01 : 0.1;
   if (prec != HMC_F64) CHK(ensure_lowprec(F, prec, st));
 
   SolveVecs v{};

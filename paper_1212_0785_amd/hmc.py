@@ -497,7 +497,7 @@ def hmc_random_gaussians(seed, rng_stream, epoch, sites, n, stream=None):
     return out
 
 
-def cg_params(tol=1e-10, maxiter=10000, mode=CG_NORMAL_MHAT, prec=F64, fixed_iters=0, reliable_delta=0.1,
+def cg_params(tol=1e-10, maxiter=10000, mode=CG_NORMAL_MHAT, prec=F64, fixed_iters=0, reliable_delta=0.0,
               initial_guess=0):
     return CgParams(tol, maxiter, mode, prec, fixed_iters, reliable_delta, initial_guess, 0)
 

@@ -83,10 +83,10 @@ def test_iteration_limit_is_exact(H, setup, mode, prec, maxiter):
 
 
 def test_default_delta_keeps_the_search_direction(H, setup):
-    """At the default delta the FP32 recursion tracks the FP64 residual:
-    no update restarts the search direction, so the mixed solve takes the
-    FP64 solve's iteration count (43 here) with one update per tenfold
-    decrease of |r|."""
+    """At the default delta (0.01 for FP32 storage) the FP32 recursion
+    tracks the FP64 residual: no update restarts the search direction, so
+    the mixed solve takes the FP64 solve's iteration count (43 here) with
+    about one update per hundredfold decrease of |r|."""
     F, rhs, _ = setup
     x64 = F.spinor()
     s64 = H.hmc_cg_solve(F, x64, rhs[0], H.cg_params(tol=1e-10))
