@@ -754,6 +754,10 @@ struct LkRows2 {
     third_row(u);
     return u;
   }
+  // rows 0 and 1 only (row 2 not set)
+  __device__ static mat3<R> load2(const void* base, int stride, int mu, int par, int s) {
+    return LK::template load<6, NT>(base, stride, mu, par, s);
+  }
 };
 
 // Row 0 and column 2 of any of the link formats above (components 0, 1, 2,
@@ -770,6 +774,12 @@ struct LkRowCol {
   static constexpr int kBytes = LK::kBytes / 9 * 5;
   static constexpr bool kStream = NT;  // non-temporal link loads (and output stores)
   __device__ static mat3<R> load(const void* base, int stride, int mu, int par, int s) {
+    mat3<R> u = load2(base, stride, mu, par, s);
+    third_row(u);
+    return u;
+  }
+  // rows 0 and 1 only (row 2 not set)
+  __device__ static mat3<R> load2(const void* base, int stride, int mu, int par, int s) {
     mat3<R> u;
     u.m[0] = LK::template one<0, NT>(base, stride, mu, par, s);
     u.m[1] = LK::template one<1, NT>(base, stride, mu, par, s);
@@ -788,9 +798,23 @@ struct LkRowCol {
       u.m[3] = (-inv) * (u.m[0] * w + conj(u.m[1]) * conj(u.m[8]));
       u.m[4] = inv * (conj(u.m[0]) * conj(u.m[8]) - u.m[1] * w);
     }
-    third_row(u);
     return u;
   }
+};
+
+// Link forms that hold only SU(3) fields and can hand out rows 0 and 1
+// alone (load2): products of such links can skip what SU(3) fixes.
+template <class LK>
+struct CompactLinks {
+  static constexpr bool value = false;
+};
+template <class LK, bool NT>
+struct CompactLinks<LkRows2<LK, NT>> {
+  static constexpr bool value = true;
+};
+template <class LK, bool NT>
+struct CompactLinks<LkRowCol<LK, NT>> {
+  static constexpr bool value = true;
 };
 
 // Compact momenta / forces: double [mu][parity][8][stride].

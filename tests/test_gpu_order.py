@@ -100,10 +100,11 @@ GF_L = [(6, 4, 2, 6), (16, 8, 4, 8), (48, 16, 4, 8), (24, 12, 8, 16)]
 
 @pytest.mark.parametrize("L", GF_L)
 def test_staple_force_shapes(H, tmp_path, L):
-    """Every staple-force shape and link form against the oracle; the
-    site-blocked shape runs the per-link code of the direction-major one on
-    other work-items, so the two agree bit for bit.  The plaquette sum walks
-    the sites the same way."""
+    """Every staple-force shape and link form against the oracle, and the
+    shapes against each other to rounding (the site-blocked shape takes a
+    block's own links from LDS, the others from memory: the same values
+    through differently scheduled arithmetic).  The plaquette sum walks the
+    sites the same way."""
     from tests.test_gpu_parity import get_momenta, put_momenta
     ext = " ".join(map(str, L))
     P0 = synth.hermitian_traceless(81, L)
@@ -130,7 +131,7 @@ def test_staple_force_shapes(H, tmp_path, L):
                 assert rel(got[shape], want) < 1e-13, (field, form, shape)
                 assert abs(H.hmc_plaquette(F) - want_plaq) < 1e-13, (field, form)
                 del F
-            assert np.array_equal(got[0], got[2]), (field, form)
+            assert rel(got[2], got[0]) < 1e-15, (field, form)
 
 
 @pytest.mark.parametrize("L", GF_L)
