@@ -177,18 +177,26 @@ __device__ __forceinline__ cx<double> acc_conj_cross(cx<double> acc, cx<double> 
   return acc;
 }
 
-// Rows 0 and 1 of the four links U_mu(x) of a block's 64 sites, parked in
-// LDS by the site-blocked staple force: the wavefront of direction mu needs
-// U_nu(x) of the other three directions in its upper staples (and its own
-// link at the end), which the block has then read from memory once.
+// Rows 0 and 1 of the links U_mu(x) and U_mu(x-mu) of a block's 64 sites,
+// parked in LDS by the site-blocked staple force: the wavefront of
+// direction mu needs U_nu(x) of the other three directions in its upper
+// staples (and its own link at the end) and U_nu(x-nu) in its lower ones,
+// which the block has then read from memory once instead of three times.
 struct OwnLinks {
-  cx<double> m[4][6][64];
+  cx<double> m[4][6][64];     // U_mu(x)
+  cx<double> back[4][6][64];  // U_mu(x - mu)
 };
 
 __device__ __forceinline__ mat3<double> own_link(const OwnLinks& o, int mu, int lane) {
   mat3<double> u;
 #pragma unroll
   for (int k = 0; k < 6; ++k) u.m[k] = o.m[mu][k][lane];
+  return u;
+}
+__device__ __forceinline__ mat3<double> back_link(const OwnLinks& o, int mu, int lane) {
+  mat3<double> u;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) u.m[k] = o.back[mu][k][lane];
   return u;
 }
 
@@ -224,7 +232,11 @@ __device__ __forceinline__ void add_staples_su3(const Lat& g, const void* U, Sit
     mul_r01(link2<LK>(g, U, MU, xn), link<LK>(g, U, NU, xmn), H);
     third_row(H);
     chain_site(xn, H);
-    mat3<double> G = link2<LK>(g, U, NU, xn);
+    mat3<double> G;
+    if constexpr (OWN)
+      G = back_link(*own, NU, lane);
+    else
+      G = link2<LK>(g, U, NU, xn);
     G.m[6] = conj(G.m[1] * G.m[5] - G.m[2] * G.m[4]);  // row 2, columns 0 and 1
     G.m[7] = conj(G.m[2] * G.m[3] - G.m[0] * G.m[5]);
     mat3<double> S;
@@ -317,9 +329,9 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force(Lat g, const void* U, do
 // Site-blocked form: a block of four wavefronts covers 64 sites of one
 // parity, wavefront w the links U_w of those sites (walk_site with the
 // block as the walk unit).  With compact (SU(3)) links the block first
-// parks rows 0 and 1 of its 256 own links in LDS (24 KB), which the
-// wavefronts read for their upper staples and for the final product
-// instead of loading them again: at 48^3x96 5.08 -> 4.82 ms.
+// parks rows 0 and 1 of its 256 own links and of the 256 links U_mu(x-mu)
+// in LDS (48 KB), which the wavefronts read for their staples and for the
+// final product instead of loading each three times.
 template <class LK>
 __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void* U, double* P, double coef_beta) {
   int par, s;
@@ -331,9 +343,21 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void*
     __shared__ OwnLinks own;
     const int lane = threadIdx.x & 63;
     if (s < g.Vh) {
+      const Site x = cb_site(g, par, s);
       const mat3<double> u = LK::load2(U, g.stride, w, par, s);
+      Site xb;
+      switch (w) {
+        case 0: xb = shift<0, -1>(g, x); break;
+        case 1: xb = shift<1, -1>(g, x); break;
+        case 2: xb = shift<2, -1>(g, x); break;
+        default: xb = shift<3, -1>(g, x); break;
+      }
+      const mat3<double> ub = link2<LK>(g, U, w, xb);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) own.m[w][k][lane] = u.m[k];
+      for (int k = 0; k < 6; ++k) {
+        own.m[w][k][lane] = u.m[k];
+        own.back[w][k][lane] = ub.m[k];
+      }
     }
     __syncthreads();
     if (s >= g.Vh) return;
