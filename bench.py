@@ -691,7 +691,8 @@ def run_serve(args, H, torch):
     base = {"throughput": len(reqs) / (done - arr[0]), "p50": float(np.percentile(lat_base, 50)),
             "p99": float(np.percentile(lat_base, 99)), "mean_service_s": 1.0 / mu1}
     # continuous-batching service, real-time Poisson submissions
-    svc = H.Service(args.arena_gb * (1 << 30), inner_prec=H.PREC_NAMES[args.inner], max_batch=64)
+    svc = H.Service(args.arena_gb * (1 << 30), inner_prec=H.PREC_NAMES[args.inner], max_batch=64,
+                    chunk=args.serve_chunk, reliable_delta=args.reliable_delta)
     tickets = [None] * len(reqs)
 
     def submitter():
@@ -721,6 +722,9 @@ def run_serve(args, H, torch):
         "config": {"workload": "serve_mix", "volumes": ["8^4", "16^3x32", "24^3x48"], "kappa": [0.150, 0.157],
                    "gauge_eps": [0.2, 0.5], "sources": "Z2 or point, p=1/2", "master_seed": 3,
                    "rho": args.rho, "arrival_rate_per_s": lam, "tol": 1e-10, "arena_gb": args.arena_gb,
+                   "inner": args.inner, "chunk": args.serve_chunk,
+                   "reliable_delta": args.reliable_delta if args.reliable_delta > 0 else (
+                       0.01 if args.inner == "f32" else 0.1),
                    "parallelism": "1 GPU"},
         "service": serv,
         "fifo_fp64_baseline": base,
@@ -739,6 +743,7 @@ def main():
     ap.add_argument("--rho", type=float, default=0.9, help="serve: offered load relative to FP64 FIFO capacity")
     ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"], help="serve: inner precision")
     ap.add_argument("--arena-gb", type=int, default=16, help="serve: arena for request state")
+    ap.add_argument("--serve-chunk", type=int, default=16, help="serve: solver iterations per service round")
     ap.add_argument("--sample-every", type=int, default=31,
                     help=("time every n-th launch of each kernel kind with HIP events (the four Dslash "
                           "launches of a CG iteration count as one, bracketed by one event pair; each sampled "
@@ -753,8 +758,8 @@ def main():
     ap.add_argument("--cg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"],
                     help="hmc: storage of the force solves' inner iteration (default f64: the plain FP64 HMC)")
     ap.add_argument("--reliable-delta", type=float, default=0.0,
-                    help=("hmc with --cg-prec other than f64: reliable-update threshold delta (default: the "
-                          "library's, 0.01 for f32 and 0.1 for f16 / bf16)"))
+                    help=("hmc with --cg-prec other than f64, and serve: reliable-update threshold delta "
+                          "(default: the library's, 0.01 for f32 and 0.1 for f16 / bf16)"))
     ap.add_argument("--tune-db", default=None,
                     help=("extra launch-shape table to load (hmc_tune_load) before the run; the binding "
                           "already loads paper_1212_0785_amd/tune/mi355x.txt unless HMC_TUNE_DB is set "

@@ -545,6 +545,7 @@ typedef struct {
   int32_t chunk;          /* iterations per round (<= 0 selects 16) */
   int32_t n_streams;      /* 1..HMC_SERVICE_MAX_STREAMS entries of streams[] used */
   void* streams[HMC_SERVICE_MAX_STREAMS]; /* hipStream_t of the caller (0 = null stream) */
+  double reliable_delta;  /* as in hmc_cg_params (<= 0: 0.01 for F32, 0.1 for F16 / BF16) */
 } hmc_service_params;
 typedef struct {
   int32_t L[4];

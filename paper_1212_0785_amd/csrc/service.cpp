@@ -139,6 +139,7 @@ bool same_volume(const LatArg& a, const LatArg& b) {
 
 struct Service {
   hmc_service_params prm{};
+  double delta2 = 0.01;  // reliable-update threshold delta^2 of the inner iteration
   int chunk = 16;
   std::chrono::steady_clock::time_point t0;
   // device header
@@ -337,7 +338,7 @@ struct Service {
     for (int i = 0; i < n; ++i) {
       Req* r = gr->members[i];
       IterArgs a;
-      build_iteration(r->v, r->iter0, r->v.prec == HMC_F64 ? 0 : 1, r->v.prec == HMC_F64 ? 0.0 : 0.01, &a);
+      build_iteration(r->v, r->iter0, r->v.prec == HMC_F64 ? 0 : 1, r->v.prec == HMC_F64 ? 0.0 : delta2, &a);
       for (int k = 0; k < 4; ++k) hd[k * kMaxBatch + i] = a.d[k];
       for (int k = 0; k < 2; ++k) hc[k * kMaxBatch + i] = a.c[k];
       r->max_group = std::max(r->max_group, n);
@@ -576,6 +577,9 @@ hmc_status hmc_service_create(const hmc_service_params* p, hmc_service** out) {
   auto S = std::make_unique<Service>();
   S->prm = *p;
   S->chunk = p->chunk > 0 ? p->chunk : 16;
+  // the single solve's default delta (0.01 for FP32 storage, 0.1 for FP16 / BF16)
+  const double delta = p->reliable_delta > 0 ? p->reliable_delta : p->inner_prec == HMC_F32 ? 0.01 : 0.1;
+  S->delta2 = delta * delta;
   S->t0 = std::chrono::steady_clock::now();
   S->table_region = a256(4 * kMaxBatch * sizeof(DslashArgs) + 2 * kMaxBatch * sizeof(CgArgs));
   Carve c((char*)p->arena);

@@ -83,7 +83,8 @@ class TrajResult(C.Structure):
 class ServiceParams(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_batch", C.c_int32),
                 ("inner_prec", C.c_int32), ("tol", C.c_double), ("maxiter", C.c_int32), ("manual", C.c_int32),
-                ("chunk", C.c_int32), ("n_streams", C.c_int32), ("streams", C.c_void_p * 8)]
+                ("chunk", C.c_int32), ("n_streams", C.c_int32), ("streams", C.c_void_p * 8),
+                ("reliable_delta", C.c_double)]
 
 
 class SolveRequest(C.Structure):
@@ -575,7 +576,7 @@ class Service:
     (``streams``: torch.cuda.Stream objects, default n_streams new ones)."""
 
     def __init__(self, arena_bytes, inner_prec=F32, max_batch=64, tol=1e-10, maxiter=50000, manual=False,
-                 chunk=16, device="cuda", streams=None, n_streams=8):
+                 chunk=16, device="cuda", streams=None, n_streams=8, reliable_delta=0.0):
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         # default priority on purpose: streams of mixed priorities are not used
         self.streams = list(streams) if streams is not None else [torch.cuda.Stream(device=device)
@@ -584,6 +585,7 @@ class Service:
                           int(maxiter), int(bool(manual)), int(chunk), len(self.streams))
         for k, s in enumerate(self.streams):
             p.streams[k] = _stream(s)
+        p.reliable_delta = float(reliable_delta)
         h = C.c_void_p()
         check(lib().hmc_service_create(C.byref(p), C.byref(h)))
         self.handle = h
