@@ -225,9 +225,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Lat g, const CgArgs* table
   if (k >= a.state->stop_at) return;
   using R = typename SP::R;
   const int cur = k & 1;
-  const double num = sum_partials(a.pp[cur], a.n_pp);
-  const double den = sum_partials(a.pq, a.n_pq);
-  const double alpha = num / den;
+  const double* part[2] = {a.pp[cur], a.pq};
+  const int n[2] = {a.n_pp, a.n_pq};
+  double sums[2];
+  sum_partials_n<kBlock / 64, 2>(part, n, sums);
+  const double alpha = sums[0] / sums[1];
   const R al = (R)alpha;
   double v[1] = {0.0};
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < g.Vh; s += gridDim.x * kBlock) {

@@ -897,17 +897,48 @@ __device__ __forceinline__ void block_sum(double* v) {
 
 // Every block (of W wavefronts) sums the same n partials in the same order
 // and gets the same bit pattern; the result is broadcast to all threads of
-// the block.
+// the block.  Work-item t adds elements t, t + 64 W, t + 128 W, ... in that
+// order; their loads are issued eight at a time, so the sum waits for one
+// memory round trip per eight elements instead of one per element.
+template <int W = kBlock / 64, int N = 1>
+__device__ __forceinline__ void sum_partials_n(const double* const* part, const int* n, double* out) {
+  constexpr int S = 64 * W, U = 8;
+  __shared__ double bc[N];
+  double v[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = 0.0;
+  int nmax = 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) nmax = max(nmax, n[q]);
+  for (int base = threadIdx.x; base < nmax; base += U * S) {
+    double t[N][U];
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = base + u * S;
+        t[q][u] = k < n[q] ? part[q][k] : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (base + u * S < n[q]) v[q] += t[q][u];
+  }
+  block_sum<N, W>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < N; ++q) bc[q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = bc[q];
+  __syncthreads();
+}
+
 template <int W = kBlock / 64>
 __device__ __forceinline__ double sum_partials(const double* part, int n) {
-  __shared__ double bc;
-  double v[1] = {0.0};
-  for (int k = threadIdx.x; k < n; k += 64 * W) v[0] += part[k];
-  block_sum<1, W>(v);
-  if (threadIdx.x == 0) bc = v[0];
-  __syncthreads();
-  double r = bc;
-  __syncthreads();
+  double r;
+  sum_partials_n<W, 1>(&part, &n, &r);
   return r;
 }
 

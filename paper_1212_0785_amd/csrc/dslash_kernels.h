@@ -96,9 +96,11 @@ __device__ __forceinline__ void hop_dir(const Lat& g, const Site& st, int out_pa
 template <int W = kBlock / 64>
 __device__ __forceinline__ void alpha_prologue(const DslashArgs& e, int label) {
   if (!e.alpha_out || blockIdx.x != 0) return;
-  const double num = sum_partials<W>(e.alpha_pp[label & 1], e.alpha_n_pp);
-  const double den = sum_partials<W>(e.alpha_den, e.alpha_n_den);
-  if (threadIdx.x == 0) *(HMC_GLOBAL double*)e.alpha_out = num / den;
+  const double* part[2] = {e.alpha_pp[label & 1], e.alpha_den};
+  const int n[2] = {e.alpha_n_pp, e.alpha_n_den};
+  double s[2];
+  sum_partials_n<W, 2>(part, n, s);
+  if (threadIdx.x == 0) *(HMC_GLOBAL double*)e.alpha_out = s[0] / s[1];
 }
 
 // BATCH: blockIdx.y selects an entry of `table` (same-volume requests share
