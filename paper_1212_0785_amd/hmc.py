@@ -263,6 +263,7 @@ class Fields:
         for v in self.L:
             self.V *= v
         self.flags = flags
+        self.beta, self.kappa = float(beta), float(kappa)
         nbytes = hmc_fields_bytes(self.L, flags)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
         h = C.c_void_p()
@@ -300,6 +301,8 @@ def _h(f):
 def hmc_set_action(f, beta, kappa):
     a = Action(beta, kappa)
     check(lib().hmc_set_action(_h(f), C.byref(a)))
+    if isinstance(f, Fields):
+        f.beta, f.kappa = float(beta), float(kappa)
 
 
 def hmc_import_gauge(f, canon, stream=None):
@@ -674,3 +677,47 @@ def canon_gauge_zeros(L, device="cuda"):
 def canon_spinor_zeros(L, device="cuda"):
     V = L[0] * L[1] * L[2] * L[3]
     return torch.zeros((V, 4, 3), dtype=torch.complex128, device=device)
+
+
+# --------------------------------------------------- checkpoints
+
+
+def save_checkpoint(f: Fields, path, seed: int, next_traj: int, stream=None):
+    """Write a chain's state to `path` (numpy .npz, no pickled objects): the
+    gauge field in the canonical layout (hmc_export_gauge) and the chain's
+    position (lattice, beta, kappa, seed, next trajectory, plaquette).  The
+    random numbers of a trajectory come from the counter-based generator
+    keyed by (seed, trajectory), so a chain resumed from this file with
+    load_checkpoint repeats the uninterrupted chain bit for bit."""
+    import json
+
+    import numpy as np
+    U = canon_gauge_zeros(f.L)
+    hmc_export_gauge(f, U, stream)
+    torch.cuda.synchronize()
+    meta = {"format": 1, "lattice": list(f.L), "beta": f.beta, "kappa": f.kappa, "seed": int(seed),
+            "next_traj": int(next_traj), "plaquette": hmc_plaquette(f, stream)}
+    with open(path, "wb") as fh:
+        np.savez(fh, gauge=U.cpu().numpy(), meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load_checkpoint(f: Fields, path, stream=None) -> dict:
+    """Resume a chain saved by save_checkpoint into a fields object of the
+    same lattice: sets beta and kappa, imports the gauge field and checks
+    its plaquette against the saved one; returns the saved position
+    (``seed``, ``next_traj``, ...).  Raises ValueError on a lattice or
+    plaquette mismatch."""
+    import json
+
+    import numpy as np
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(bytes(z["meta"]).decode())
+        U = z["gauge"]
+    if meta.get("format") != 1 or tuple(meta["lattice"]) != f.L:
+        raise ValueError(f"checkpoint of lattice {meta.get('lattice')} does not fit {f.L}")
+    hmc_set_action(f, meta["beta"], meta["kappa"])
+    hmc_import_gauge(f, to_device_c128(U), stream)
+    p = hmc_plaquette(f, stream)
+    if not abs(p - meta["plaquette"]) <= 1e-12:
+        raise ValueError(f"plaquette {p!r} of the loaded field differs from the saved {meta['plaquette']!r}")
+    return meta
