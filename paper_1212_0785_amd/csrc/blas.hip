@@ -367,10 +367,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
     if (a.mixed) {
       double mx = fmax(stt->maxrr, rr);
       stt->maxrr = mx;
-      // device-driven updates also come every kMaxInner iterations, so a
-      // low-precision recursion that stagnates cannot run away, and at the
-      // iteration limit
-      if (a.x64 ? fold : (conv || rr < a.delta2 * mx || !(rr == rr))) {
+      // updates also come every kMaxInner iterations, so a low-precision
+      // recursion that stagnates cannot run away (the host-driven updates
+      // of the solve service: since the restart at ru_label), and, device
+      // driven, at the iteration limit
+      if (a.x64 ? fold : (conv || rr < a.delta2 * mx || !(rr == rr) || k + 1 - stt->ru_label >= kMaxInner)) {
         stt->reason = 2;
         stt->stop_at = k + 1;
         stt->ru_gate = INT_MAX;  // a device-driven solve updates next
@@ -431,7 +432,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(Lat g, const CgArgs* tabl
 // Start or resume a solve: stop_at = INT_MAX, reason = 0, no reliable
 // update pending, maxrr from a device slot (null -> 0), threshold thr; a
 // start also clears the counts and the label base.
-__global__ void k_state_reset(SolverState* st, const double* maxrr, int nbatch, int reset_iters, double thr) {
+__global__ void k_state_reset(SolverState* st, const double* maxrr, int nbatch, int reset_iters, double thr,
+                              int label) {
   int k = blockIdx.x * kBlock + threadIdx.x;
   if (k >= nbatch) return;
   st[k].stop_at = INT_MAX;
@@ -450,6 +452,7 @@ __global__ void k_state_reset(SolverState* st, const double* maxrr, int nbatch, 
     st[k].rr64 = 0.0;
   }
   st[k].maxrr = maxrr ? maxrr[k] : 0.0;
+  if (label >= 0) st[k].ru_label = label;
 }
 
 // dst = src over n doubles while *gate != 0.
@@ -731,9 +734,9 @@ hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, in
 }
 
 hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, double thr,
-                              hipStream_t st) {
+                              hipStream_t st, int label) {
   hipLaunchKernelGGL(k_state_reset, dim3(ceil_div(nbatch, kBlock)), dim3(kBlock), 0, st, st_dev, maxrr, nbatch,
-                     reset_iters, thr);
+                     reset_iters, thr, label);
   return hipGetLastError();
 }
 

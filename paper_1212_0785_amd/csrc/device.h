@@ -566,11 +566,19 @@ struct SpF16 {
       v[k] = {t.x * f, t.y * f};
     }
   }
+  // A site whose largest component is below the smallest normal float is
+  // stored as zero: 1/m would overflow to infinity.  Such sites arise where
+  // a field spreads from a point: each hop onto a new site carries the
+  // half-precision remainders of its neighbours, so the scales of the front
+  // shrink by ~1e-8 per hop and reach the float denormals within a few
+  // applications of the operator; they are ~1e-38 of the field's norm.
+  __device__ static float live_scale(float m) { return m >= __FLT_MIN__ ? m : 0.f; }
   template <bool NT = false>
   __device__ static void store(void* base, int stride, int s, const cx<R>* v) {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+    m = live_scale(m);
     float inv = m > 0.f ? 1.f / m : 0.f;
     gput<NT>(base, 12 * stride + s, m);
 #pragma unroll
@@ -586,6 +594,7 @@ struct SpF16 {
   // m computed by the caller over all 12 components (part 0 writes it)
   template <bool NT = false>
   __device__ static void store_part_scaled(void* base, int stride, int s, int part, const cx<R>* v, float m) {
+    m = live_scale(m);
     const float inv = m > 0.f ? 1.f / m : 0.f;
     if (part == 0) gput<NT>(base, 12 * stride + s, m);
 #pragma unroll

@@ -227,9 +227,10 @@ hipError_t launch_cg_pupdate(const LatArg& g, hmc_prec prec, const CgArgs& a, in
                              int nbatch, int j, hipStream_t st);
 // Start (reset_iters: counts, base and the device-driven fields cleared) or
 // resume a solve: stop_at = INT_MAX, reason = 0, maxrr from a device slot
-// (null -> 0), stop threshold thr.
+// (null -> 0), stop threshold thr; label >= 0 sets ru_label, the label of the
+// first iteration of a host-driven restart.
 hipError_t launch_state_reset(SolverState* st_dev, const double* maxrr, int nbatch, int reset_iters, double thr,
-                              hipStream_t st);
+                              hipStream_t st, int label = -1);
 // base += n (one solve): closes a chunk of n iterations launched with j = 0..n-1.
 hipError_t launch_advance_base(SolverState* st_dev, int n, hipStream_t st);
 // STREAM triad a = b + sc * c over n2 double2 elements (nt: non-temporal).

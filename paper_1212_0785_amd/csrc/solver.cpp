@@ -217,7 +217,7 @@ hipError_t inner_restart(const SolveVecs& v, int k, bool first, hipStream_t st, 
   if ((e = restart_vectors(v, v.pp[k & 1], st, nullptr))) return e;
   if ((first || restart_p) && (e = launch_copy(v.p, v.cgls ? v.s : v.r, low_half_bytes(v), st))) return e;
   if (first && (e = launch_zero(v.xl, (size_t)v.g.Vh * 96, st))) return e;
-  return launch_state_reset(v.state, v.slot, 1, first ? 1 : 0, v.thr, st);
+  return launch_state_reset(v.state, v.slot, 1, first ? 1 : 0, v.thr, st, k);
 }
 
 // The device-driven reliable update closing a mixed-precision chunk: every

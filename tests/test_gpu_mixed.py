@@ -9,6 +9,11 @@ single-precision production mode of Sec. 7).
   solve's configuration).  The update restarts the search direction in that
   case; every such solve now converges to the FP64 tolerance and agrees with
   the FP64 solve.
+* FP16 storage of a field that spreads from a point source: the per-site
+  scales of the spreading front shrink by ~1e-8 per hop and reached the
+  float denormals within four operator applications, whose reciprocal
+  overflowed (non-finite residual after three iterations at 12^3x24 and
+  16^3x32).  Such sites are now stored as zero; the solves converge.
 * The iteration limit is exact: the iteration that reaches maxiter asks for
   the last reliable update, which ends the solve with HMC_E_NOCONV after
   exactly maxiter iterations (it ran up to one update cycle past it).
@@ -94,3 +99,20 @@ def test_default_delta_keeps_the_search_direction(H, setup):
     st = H.hmc_cg_solve(F, x, rhs[0], H.cg_params(tol=1e-10, prec=H.F32))
     assert st["status"] == 0 and st["iters"] == s64["iters"]
     assert st["reliable_updates"] <= s64["iters"] // 4
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("L", [(12, 12, 12, 24), (16, 16, 16, 32)])
+def test_fp16_point_source_converges(H, mode, L):
+    F = H.Fields(L, 5.6, 0.156, flags=H.FIELDS_LOWPREC)
+    H.hmc_weak_field_start(F, 32, 0.45)
+    b = F.spinor(full=True)
+    H.hmc_make_source(F, b, H.SOURCE_POINT, 0, 0)
+    rhs = b if mode == H.CG_WILSON_SOLVE else b[: H.hmc_field_bytes(L, H.F64, H.KIND_HALF_SPINOR)].clone()
+    x = F.spinor(full=mode == H.CG_WILSON_SOLVE)
+    st = H.hmc_cg_solve(F, x, rhs, H.cg_params(tol=1e-10, mode=mode, prec=H.F16, maxiter=3000), allow_noconv=True)
+    assert st["status"] == 0 and st["true_rel_res"] <= 1e-10, st
+    x64 = F.spinor(full=mode == H.CG_WILSON_SOLVE)
+    s64 = H.hmc_cg_solve(F, x64, rhs, H.cg_params(tol=1e-12, mode=mode))
+    assert s64["status"] == 0
+    assert rel(x.view(torch.float64), x64.view(torch.float64)) < 1e-7

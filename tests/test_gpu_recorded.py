@@ -45,25 +45,26 @@ def solve(H, F, b, prm, full):
     return x, st
 
 
-CASES = [  # lattice, mode, storage, fixed iterations
-    ((8, 6, 6, 10), 0, 0, 37),        # FP64 CG, a length that takes every power of two
-    ((8, 6, 6, 10), 0, 0, 0),         # FP64 CG to 1e-10
-    ((16, 16, 16, 32), 0, 0, 0),      # the HMC force solve's shape
-    ((8, 6, 6, 10), 1, 0, 0),         # FP64 CGLS (Wilson solve)
-    ((8, 6, 6, 10), 0, 1, 0),         # mixed FP32 CG with device reliable updates
-    ((16, 16, 16, 32), 0, 1, 0),
-    ((16, 16, 16, 32), 1, 2, 0),      # mixed FP16 CGLS
-    ((8, 8, 8, 8), 1, 3, 0),          # mixed BF16 CGLS
+CASES = [  # lattice, mode, storage, fixed iterations, reliable-update delta (0: default)
+    ((8, 6, 6, 10), 0, 0, 37, 0),        # FP64 CG, a length that takes every power of two
+    ((8, 6, 6, 10), 0, 0, 0, 0),         # FP64 CG to 1e-10
+    ((16, 16, 16, 32), 0, 0, 0, 0),      # the HMC force solve's shape
+    ((8, 6, 6, 10), 1, 0, 0, 0),         # FP64 CGLS (Wilson solve)
+    ((8, 6, 6, 10), 0, 1, 0, 0),         # mixed FP32 CG with device reliable updates
+    ((16, 16, 16, 32), 0, 1, 0, 0),
+    ((16, 16, 16, 32), 1, 2, 0, 0),      # mixed FP16 CGLS
+    ((8, 8, 8, 8), 1, 3, 0, 0),          # mixed BF16 CGLS
+    ((16, 16, 16, 32), 0, 3, 0, 0.01),   # BF16 CG whose updates restart the search direction
 ]
 
 
-@pytest.mark.parametrize("L,mode,prec,fixed", CASES)
-def test_recorded_chunks_match_direct_launches(H, direct, L, mode, prec, fixed):
+@pytest.mark.parametrize("L,mode,prec,fixed,delta", CASES)
+def test_recorded_chunks_match_direct_launches(H, direct, L, mode, prec, fixed, delta):
     F = H.Fields(L, 5.6, 0.156, flags=H.FIELDS_LOWPREC)
     H.hmc_weak_field_start(F, 7, 0.4)
     full = mode == H.CG_WILSON_SOLVE
     b = source(H, F, 3, full)
-    prm = H.cg_params(tol=1e-10, mode=mode, prec=prec, fixed_iters=fixed, maxiter=20000)
+    prm = H.cg_params(tol=1e-10, mode=mode, prec=prec, fixed_iters=fixed, maxiter=20000, reliable_delta=delta)
     direct(True)
     x0, s0 = solve(H, F, b, prm, full)
     direct(False)

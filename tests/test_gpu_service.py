@@ -44,8 +44,9 @@ def to_canon(H, L, buf):
     return c.cpu().numpy()
 
 
-def run_manual(H, reqs, prec, arena=1 << 28, max_batch=16, streams=None):
-    svc = H.Service(arena, inner_prec=prec, max_batch=max_batch, manual=True, streams=streams)
+def run_manual(H, reqs, prec, arena=1 << 28, max_batch=16, streams=None, reliable_delta=0.0):
+    svc = H.Service(arena, inner_prec=prec, max_batch=max_batch, manual=True, streams=streams,
+                    reliable_delta=reliable_delta)
     outs, tickets = [], []
     for (L, k, gs, eps, kind, ss) in reqs:
         out = torch.zeros(full_bytes(H, L), dtype=torch.uint8, device="cuda")
@@ -70,6 +71,20 @@ def test_service_mix_converges_and_matches_alone(H, prec):
         alone, aout = run_manual(H, [MIX[i]], prec)
         assert alone[0]["iters"] == res[i]["iters"]
         assert torch.equal(aout[0], outs[i])
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_service_small_delta_low_storage(H, prec):
+    """FP16 / BF16 inner solves with reliable-update delta 0.01, where BF16
+    needs the search-direction restarts (the single solve diverged there
+    without them): every request of a mix with a 16^3x32 one converges to
+    the FP64 tolerance, bit-identical alone and in the mix."""
+    reqs = MIX[:3] + [((16, 16, 16, 32), 0.156, 32, 0.45, 2, 0)]
+    res, outs = run_manual(H, reqs, prec, arena=1 << 30, reliable_delta=0.01)
+    for r in res:
+        assert r["status"] == 0 and r["true_rel_res"] <= 1e-10, r
+    alone, aout = run_manual(H, [reqs[3]], prec, arena=1 << 30, reliable_delta=0.01)
+    assert alone[0]["iters"] == res[3]["iters"] and torch.equal(aout[0], outs[3])
 
 
 def test_service_matches_oracle(H):
