@@ -144,3 +144,43 @@ def test_service_needs_caller_streams(H):
     assert "n_streams" in H.last_error()
     p.n_streams = 9
     assert H.lib().hmc_service_create(C.byref(p), C.byref(h)) == H.HMC_E_ARG
+
+
+# ctypes mirrors of the header's structs: every field at the C offset
+STRUCTS = {"hmc_geom": "Geom", "hmc_action": "Action", "hmc_cg_params": "CgParams", "hmc_cg_stats": "CgStats",
+           "hmc_md_stats": "MdStats", "hmc_traj_params": "TrajParams", "hmc_traj_result": "TrajResult",
+           "hmc_mts_params": "MtsParams", "hmc_mts_stats": "MtsStats", "hmc_service_params": "ServiceParams",
+           "hmc_solve_request": "SolveRequest", "hmc_solve_result": "SolveResult",
+           "hmc_timing_entry": "TimingEntry"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The C compiler's sizeof and offsetof of every struct of include/hmc.h
+    against the binding's ctypes layouts (a field added on one side only
+    would shift every later field)."""
+    import ctypes
+    import subprocess
+
+    from paper_1212_0785_amd import hmc as Hm
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "hmc.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(Hm, pyname)
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, field, value = line.split()
+            got[(cname, field)] = int(value)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(Hm, pyname)
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
