@@ -572,7 +572,8 @@ struct SpF16 {
   // half-precision remainders of its neighbours, so the scales of the front
   // shrink by ~1e-8 per hop and reach the float denormals within a few
   // applications of the operator; they are ~1e-38 of the field's norm.
-  __device__ static float live_scale(float m) { return m >= __FLT_MIN__ ? m : 0.f; }
+  // (A NaN or infinite m passes, so a non-finite site stays non-finite.)
+  __device__ static float live_scale(float m) { return m < __FLT_MIN__ ? 0.f : m; }
   template <bool NT = false>
   __device__ static void store(void* base, int stride, int s, const cx<R>* v) {
     float m = 0.f;

@@ -116,3 +116,29 @@ def test_fp16_point_source_converges(H, mode, L):
     s64 = H.hmc_cg_solve(F, x64, rhs, H.cg_params(tol=1e-12, mode=mode))
     assert s64["status"] == 0
     assert rel(x.view(torch.float64), x64.view(torch.float64)) < 1e-7
+
+
+def test_fp16_storage_flushes_denormal_sites_and_keeps_nonfinite_ones(H):
+    L = (4, 4, 4, 4)
+    Vh = 128
+    F = H.Fields(L, 5.6, 0.15, flags=H.FIELDS_LOWPREC)
+    x = F.spinor()
+    v = x.view(torch.float64)
+    v.normal_(generator=torch.Generator(device="cuda").manual_seed(5))
+    comp = lambda k, s: 2 * (k * Vh + s)  # real part of component k of site s (component-major)
+    v[comp(0, 5)] = float("nan")
+    for k in range(12):  # site 7: every component 1e-40 (a float denormal)
+        v[comp(k, 7)] = 1e-40
+        v[comp(k, 7) + 1] = 1e-40
+    h = F.spinor(prec=H.F16)
+    H.hmc_convert_spinor(F, h, H.F16, x, H.F64)
+    back = F.spinor()
+    H.hmc_convert_spinor(F, back, H.F64, h, H.F16)
+    torch.cuda.synchronize()
+    b = back.view(torch.float64)
+    assert torch.isnan(b[comp(0, 5)])                      # a non-finite site stays non-finite
+    assert all(b[comp(k, 7) + i] == 0 for k in range(12) for i in (0, 1))  # the denormal site is zero
+    other = [s for s in range(Vh) if s not in (5, 7)]
+    idx = torch.tensor([comp(k, s) + i for s in other for k in range(12) for i in (0, 1)], device="cuda")
+    assert torch.isfinite(b[idx]).all()
+    assert ((b[idx] - v[idx]).abs() <= 1e-3 * v[idx].abs().max()).all()  # half precision of the site scale
