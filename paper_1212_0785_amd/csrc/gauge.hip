@@ -11,6 +11,7 @@
 #include "internal.h"
 #include "walk.h"
 
+
 namespace hmc {
 
 
@@ -175,6 +176,94 @@ __device__ __forceinline__ cx<double> acc_conj_cross(cx<double> acc, cx<double> 
   acc.im = fma(c.re, d.im, acc.im);
   acc.im = fma(c.im, d.re, acc.im);
   return acc;
+}
+
+// Plaquette sum on SU(3) links, plane-paired: a block of three wavefronts
+// covers one walk unit (64 sites of one parity); wavefront w takes the
+// planes (0, w+1) and its complement, which together hold each direction
+// once.  The block first parks rows 0 and 1 of its 256 own links U_mu(x)
+// in LDS (each enters three planes); each wavefront issues the loads of the
+// four links of its two planes that sit at x + mu and x + nu together, so
+// twice the memory requests of a one-plane wavefront are in flight at the
+// same occupancy (the sum is bound by the latency of those loads, not by
+// its arithmetic or bandwidth).  With a = U_mu(x) U_nu(x+mu) and
+// b = U_nu(x) U_mu(x+nu) both in SU(3), only rows 0 and 1 of each product
+// are formed: with h_ij = sum_k conj(a_ik) b_jk, row 2 of each is the
+// conjugate cross product of its rows 0 and 1, and the Binet-Cauchy
+// identity gives its part of Re Tr(a b^dag) as Re(h00 h11 - h01 h10).
+constexpr int kPlaqPairThreads = 3 * 64;
+
+template <class LK, int MU, int NU>
+__device__ __forceinline__ double plaq_rows(const cx<double> (*own)[6][64], int lane, const mat3<double>& B,
+                                            const mat3<double>& C) {
+  mat3<double> A, D, a, b;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    A.m[k] = own[MU][k][lane];
+    D.m[k] = own[NU][k][lane];
+  }
+  mul_r01(A, B, a);  // rows 0, 1 of U_mu(x) U_nu(x+mu)
+  mul_r01(D, C, b);  // rows 0, 1 of U_nu(x) U_mu(x+nu)
+  cx<double> h[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cx<double> t = cmadd_conj(cx<double>{0, 0}, a.m[3 * i], b.m[3 * j]);
+      t = cmadd_conj(t, a.m[3 * i + 1], b.m[3 * j + 1]);
+      h[i][j] = cmadd_conj(t, a.m[3 * i + 2], b.m[3 * j + 2]);
+    }
+  const cx<double> d = h[0][0] * h[1][1] - h[0][1] * h[1][0];
+  return h[0][0].re + h[1][1].re + d.re;
+}
+
+template <class LK, int M1, int N1, int M2, int N2>
+__device__ __forceinline__ double plaq_pair(const Lat& g, const void* U, const Site& x, cx<double> (*own)[6][64],
+                                            int w, int lane, int par, int s, bool on) {
+  mat3<double> B1, C1, B2, C2;
+  if (on) {
+    B1 = link2<LK>(g, U, N1, shift<M1, +1>(g, x));
+    C1 = link2<LK>(g, U, M1, shift<N1, +1>(g, x));
+    B2 = link2<LK>(g, U, N2, shift<M2, +1>(g, x));
+    C2 = link2<LK>(g, U, M2, shift<N2, +1>(g, x));
+    {
+      const mat3<double> u = LK::load2(U, g.stride, w + 1, par, s);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) own[w + 1][k][lane] = u.m[k];
+    }
+    if (w == 0) {
+      const mat3<double> u = LK::load2(U, g.stride, 0, par, s);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) own[0][k][lane] = u.m[k];
+    }
+  }
+  __syncthreads();
+  if (!on) return 0.0;
+  third_row(B1);
+  third_row(C1);
+  const double p1 = plaq_rows<LK, M1, N1>(own, lane, B1, C1);
+  third_row(B2);
+  third_row(C2);
+  return p1 + plaq_rows<LK, M2, N2>(own, lane, B2, C2);
+}
+
+template <class LK>
+__global__ void __launch_bounds__(kPlaqPairThreads) k_plaquette_pairs(Lat g, const void* U, double* part) {
+  int par, s;
+  walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const bool on = s < g.Vh;
+  __shared__ cx<double> own[4][6][64];
+  const Site x = cb_site(g, on ? par : 0, on ? s : 0);
+  double v[1];
+  switch (w) {
+    case 0: v[0] = plaq_pair<LK, 0, 1, 2, 3>(g, U, x, own, w, lane, par, s, on); break;
+    case 1: v[0] = plaq_pair<LK, 0, 2, 1, 3>(g, U, x, own, w, lane, par, s, on); break;
+    default: v[0] = plaq_pair<LK, 0, 3, 1, 2>(g, U, x, own, w, lane, par, s, on); break;
+  }
+  block_sum<1, 3>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
 // Rows 0 and 1 of the links U_mu(x) and U_mu(x-mu) of a block's 64 sites,
@@ -456,18 +545,24 @@ __global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const dou
   LkF64::store(U, g.stride, mu, par, s, u);
 }
 
-int plaquette_blocks(const LatArg& g) {
+int plaquette_blocks(const LatArg& g, bool su3) {
+  if (su3 && plaquette_shape(g) == 1) return 2 * ceil_div(g.Vh, 64);
   return tiled_order_valid(g) ? g.Vh / 128 : ceil_div(2 * ceil_div(g.Vh, 64), 4);
 }
 
 hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, hipStream_t st, bool su3) {
-  const int form = link_form_for(su3, staple_link_form(g));
+  const int form = link_form_for(su3, plaquette_link_form(g));
   const int lb = form == LINK_ROWCOL ? LkRowCol<LkF64>::kBytes : form == LINK_ROWS2 ? LkRows2<LkF64>::kBytes
                                                                                      : LkF64::kBytes;
   TimedScope ts(TK_PLAQUETTE, st, 2.0 * g.Vh * 4 * LkF64::kBytes, 2.0 * g.Vh * 4 * lb);
-  const dim3 grid(plaquette_blocks(g)), block(kBlock);
+  const dim3 grid(plaquette_blocks(g, su3)), block(kBlock);
   const Lat lat = walk_lat(g);
-  if (form == LINK_ROWCOL)
+  if (su3 && plaquette_shape(g) == 1) {
+    if (form == LINK_ROWCOL)
+      hipLaunchKernelGGL(k_plaquette_pairs<LkRowCol<LkF64>>, grid, dim3(kPlaqPairThreads), 0, st, lat, U, part);
+    else
+      hipLaunchKernelGGL(k_plaquette_pairs<LkRows2<LkF64>>, grid, dim3(kPlaqPairThreads), 0, st, lat, U, part);
+  } else if (form == LINK_ROWCOL)
     hipLaunchKernelGGL(k_plaquette_partials<LkRowCol<LkF64>>, grid, block, 0, st, lat, U, part);
   else if (form == LINK_ROWS2)
     hipLaunchKernelGGL(k_plaquette_partials<LkRows2<LkF64>>, grid, block, 0, st, lat, U, part);

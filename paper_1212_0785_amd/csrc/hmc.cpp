@@ -355,7 +355,7 @@ static hipError_t finalize_to_slot(Fields* F, const double* part, int n, int nva
 static hipError_t plaquette_to_slot(Fields* F, int slot, hipStream_t st) {
   hipError_t e = launch_plaquette_partials(F->g, F->U, F->part[0], st, F->su3);
   if (e != hipSuccess) return e;
-  return finalize_to_slot(F, F->part[0], plaquette_blocks(F->g), 1, slot, st);
+  return finalize_to_slot(F, F->part[0], plaquette_blocks(F->g, F->su3), 1, slot, st);
 }
 
 }  // namespace hmc

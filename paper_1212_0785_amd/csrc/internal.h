@@ -261,8 +261,15 @@ hipError_t launch_ru_request(SolverState* st_dev, hipStream_t st);
 
 // Gauge-field kernels.
 // su3: U is SU(3) to rounding (compact link forms allowed).
-// One partial per block, plaquette_blocks(g) of them (at most Vh / 64).
-int plaquette_blocks(const LatArg& g);
+// Plaquette sum on SU(3) links: 1 = three wavefronts per 64 sites, two
+// planes each; 0 = four 64-site units per block, all planes per work-item
+// (the only form on links that are not SU(3)).
+int plaquette_shape(const LatArg& g);
+// Compact link form of the plaquette sum on SU(3) links.
+int plaquette_link_form(const LatArg& g);
+// One partial per block, plaquette_blocks(g, su3) of them (at most
+// 2 ceil(Vh / 64)).
+int plaquette_blocks(const LatArg& g, bool su3);
 hipError_t launch_plaquette_partials(const LatArg& g, const void* U, double* part, hipStream_t st, bool su3);
 hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* part, int nb, hipStream_t st);
 // shape: -1 = gauge_force_shape(), 0 / 1 / 2 = fixed; form: 0 =

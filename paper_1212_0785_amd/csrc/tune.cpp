@@ -243,6 +243,24 @@ int dslash_shape(const LatArg& g, hmc_prec prec) {
   return (prec != HMC_F64 && g.Vh <= (1 << 17)) ? 4 : 1;
 }
 
+int plaquette_shape(const LatArg&) {
+  static const int forced = env_int("HMC_PLAQ_PAIRS");
+  if (forced >= 0) return forced == 0 ? 0 : 1;
+  // measured on MI355X: 1.78 -> 1.36 ms at 48^3x96, 26.5 -> 21.3 us at 16^3x32
+  return 1;
+}
+
+int plaquette_link_form(const LatArg& g) {
+  static const int forced = env_int("HMC_PLAQ_FORM");
+  if (forced == LINK_ROWS2 || forced == LINK_ROWCOL) return forced;
+  // measured on MI355X (plane-paired sum): two rows 1.33 ms against 1.69 ms
+  // with row 0 + column 2 at 48^3x96, 21.4 against 29.6 us at 16^3x32 (the
+  // reconstruction lengthens the latency-bound chain); the per-site form
+  // follows the staple force
+  return plaquette_shape(g) == 1 ? (int)LINK_ROWS2 : staple_link_form(g);
+}
+
+
 int gauge_force_shape(const LatArg& g) {
   static const int forced = env_int("HMC_GFORCE_PLANES");
   if (forced >= 0) return forced == 0 ? 0 : forced == 2 ? 2 : 1;

@@ -240,6 +240,16 @@ def test_plaquette_and_action(H, L):
     assert abs(H.hmc_gauge_action(F) - sg) < 1e-13 * sg
 
 
+@pytest.mark.parametrize("L", SMALL)
+def test_plaquette_on_links_that_are_not_su3(H, L):
+    """Links that fail the SU(3) check (scaled by 1.1) take the per-site sum
+    over all nine entries instead of the plane-paired two-row one."""
+    F = H.Fields(L, 5.6, 0.15)
+    U = 1.1 * synth.gauge_field(23, L, eps=0.7)
+    put_gauge(H, F, U)
+    assert abs(H.hmc_plaquette(F) - O.plaquette(L, U)) < 1e-14 * abs(O.plaquette(L, U))
+
+
 @pytest.mark.parametrize("L", ALL)
 def test_gauge_force_parity(H, L):
     F = H.Fields(L, 5.7, 0.15)
