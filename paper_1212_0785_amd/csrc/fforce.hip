@@ -7,7 +7,9 @@
 //   F  = (i kappa^2/2) TA(U_mu(x) M1 - M2 U_mu(x)^dag).
 // Because P = 1 +- gamma_mu is Hermitian with P^2 = 2P, the spin trace
 // tr[P a b^dag] equals sum over the two projected components h_j(a)
-// h_j(b)^dag, so each trace is two colour outer products.
+// h_j(b)^dag, so each trace is two colour outer products, and
+// U M1 - M2 U^dag is assembled from the colour vectors U h_j without
+// forming M1, M2 or a 3x3 product.
 #include "device.h"
 #include "internal.h"
 #include "walk.h"
@@ -20,64 +22,100 @@ struct ForceVecs {
   const void* Y[2];
 };
 
-// sg * sum_{j=0,1} h_j(a) h_j(b)^dag for projected half spinors ha, hb.
-__device__ __forceinline__ mat3<double> proj_outer(const cx<double>* ha, const cx<double>* hb, double sg) {
-  mat3<double> m;
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      cx<double> v = ha[r] * conj(hb[c]);
-      v = cmadd(v, ha[3 + r], conj(hb[3 + c]));
-      m.m[3 * r + c] = sg * v;
-    }
-  return m;
-}
+// X and Y at the block's own 64 sites, parked in LDS once for the four
+// direction wavefronts.
+struct OwnSpinors {
+  cx<double> X[12][64];
+  cx<double> Y[12][64];
+};
 
 template <class LK, int MU>
 __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, const ForceVecs& v, double* P,
-                                                   double c_ta, int par, int s) {
-  Site x = cb_site(g, par, s);
-  bool w;
-  const int sf = neighbour_lex<MU, +1>(g, x, &w) >> 1;
-  const double sg = (MU == 3 && w) ? -1.0 : 1.0;
-  cx<double> a[12], b[12], ha[6], hb[6];
-  // M1 from X(x+mu) and Y(x), projector (1 - gamma_mu)
-  SpF64::load(v.X[par ^ 1], g.stride, sf, a);
-  SpF64::load(v.Y[par], g.stride, s, b);
-  spin_project<MU, -1>(a, ha);
-  spin_project<MU, -1>(b, hb);
-  mat3<double> M1 = proj_outer(ha, hb, sg);
-  // M2 from X(x) and Y(x+mu), projector (1 + gamma_mu)
-  SpF64::load(v.X[par], g.stride, s, a);
-  SpF64::load(v.Y[par ^ 1], g.stride, sf, b);
-  spin_project<MU, +1>(a, ha);
-  spin_project<MU, +1>(b, hb);
-  mat3<double> M2 = proj_outer(ha, hb, sg);
-  mat3<double> u = LK::load(U, g.stride, MU, par, s);
-  mat3<double> W = msub(mmul(u, M1), mmul_nd(M2, u));
-  double f[8], c[8];
-  i_ta_compact(W, c_ta, f);
+                                                   double c_ta, int par, int s, bool on, OwnSpinors& own) {
+  const int w = MU, lane = threadIdx.x & 63;
+  Site x = cb_site(g, on ? par : 0, on ? s : 0);
+  bool wr;
+  const int sf = neighbour_lex<MU, +1>(g, x, &wr) >> 1;
+  const double sg = (MU == 3 && wr) ? -1.0 : 1.0;
+  cx<double> xn[12], yn[12], ha[6], hb[6], t[12];
+  mat3<double> u;
+  double c[8];
+  if (on) {
+    // X and Y at x + mu and this wavefront's quarter of the block's X and Y,
+    // issued together (the link and the momenta follow the barrier)
+    SpF64::load(v.X[par ^ 1], g.stride, sf, xn);
+    SpF64::load(v.Y[par ^ 1], g.stride, sf, yn);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      own.X[3 * w + k][lane] = SpF64::load_one(v.X[par], g.stride, s, 3 * w + k);
+      own.Y[3 * w + k][lane] = SpF64::load_one(v.Y[par], g.stride, s, 3 * w + k);
+    }
+  }
+  __syncthreads();
+  if (!on) return;
+  // the neighbour spinors projected first (half the registers)
+  cx<double> hx[6], hy[6];
+  spin_project<MU, -1>(xn, hx);
+  spin_project<MU, +1>(yn, hy);
+  // the link and the momenta: issuing them before the barrier as well
+  // raises the registers past three wavefronts per SIMD (measured slower)
+  u = LK::load(U, g.stride, MU, par, s);
   load_compact(P, g.stride, MU, par, s, c);
+  // U M1 - M2 U^dag = sg sum_j [(U hx_j) hb_j^dag - ha_j (U hy_j)^dag]
+  // (M1, M2 of rank two: no 3x3 product is formed)
+  cx<double> ux[6], uy[6];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      cx<double> p = u.m[3 * r] * hx[3 * j];
+      p = cmadd(p, u.m[3 * r + 1], hx[3 * j + 1]);
+      ux[3 * j + r] = cmadd(p, u.m[3 * r + 2], hx[3 * j + 2]);
+      cx<double> q = u.m[3 * r] * hy[3 * j];
+      q = cmadd(q, u.m[3 * r + 1], hy[3 * j + 1]);
+      uy[3 * j + r] = cmadd(q, u.m[3 * r + 2], hy[3 * j + 2]);
+    }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) t[k] = own.Y[k][lane];
+  spin_project<MU, -1>(t, hb);  // Y(x), projector (1 - gamma_mu)
+#pragma unroll
+  for (int k = 0; k < 12; ++k) t[k] = own.X[k][lane];
+  spin_project<MU, +1>(t, ha);  // X(x), projector (1 + gamma_mu)
+  mat3<double> W;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      cx<double> e = ux[r] * conj(hb[q]);
+      e = cmadd(e, ux[3 + r], conj(hb[3 + q]));
+      e = e - ha[r] * conj(uy[q]);
+      e = e - ha[3 + r] * conj(uy[3 + q]);
+      W.m[3 * r + q] = sg * e;
+    }
+  double f[8];
+  i_ta_compact(W, c_ta, f);
 #pragma unroll
   for (int k = 0; k < 8; ++k) c[k] += f[k];
   store_compact(P, g.stride, MU, par, s, c);
 }
 
 // A block of four wavefronts covers 64 sites of one parity, wavefront w the
-// links U_w (walk_site with the block as the walk unit), so X and Y at a
-// site and its neighbours are fetched once for all four directions.
+// links U_w (walk_site with the block as the walk unit): X and Y at the
+// block's sites are read from memory once into LDS, those at the
+// neighbours once per direction.
 template <class LK>
 __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, ForceVecs v, double* P,
                                                           double c_ta) {
+  __shared__ OwnSpinors own;
   int par, s;
   walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
-  if (s >= g.Vh) return;
-  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // the wavefront, as a scalar
-    case 0: fermion_force_link<LK, 0>(g, U, v, P, c_ta, par, s); break;
-    case 1: fermion_force_link<LK, 1>(g, U, v, P, c_ta, par, s); break;
-    case 2: fermion_force_link<LK, 2>(g, U, v, P, c_ta, par, s); break;
-    default: fermion_force_link<LK, 3>(g, U, v, P, c_ta, par, s); break;
+  const bool on = s < g.Vh;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // the wavefront, as a scalar; every work-item
+                                                              // reaches the barrier inside
+    case 0: fermion_force_link<LK, 0>(g, U, v, P, c_ta, par, s, on, own); break;
+    case 1: fermion_force_link<LK, 1>(g, U, v, P, c_ta, par, s, on, own); break;
+    case 2: fermion_force_link<LK, 2>(g, U, v, P, c_ta, par, s, on, own); break;
+    default: fermion_force_link<LK, 3>(g, U, v, P, c_ta, par, s, on, own); break;
   }
 }
 
