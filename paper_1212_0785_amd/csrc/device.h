@@ -655,6 +655,17 @@ struct LkF64 {
     }
     return u;
   }
+  // Component K of the link at checkerboard site s of parity par, where mu
+  // and par are uniform over the wavefront: the array's base is then a
+  // scalar and the lane's byte offset voff = 16 s is shared by all
+  // components, so a load costs no vector address arithmetic.
+  template <int K>
+  __device__ static cx<R> one_u(const void* base, int stride, int mu, int par, unsigned voff) {
+    const HMC_GLOBAL char* p =
+        (const HMC_GLOBAL char*)base + ((size_t)((mu * 2 + par) * 9 + K) * (size_t)stride) * sizeof(v2d);
+    v2d t = *(const HMC_GLOBAL v2d*)(p + voff);
+    return {t.x, t.y};
+  }
   __device__ static void store(void* base, int stride, int mu, int par, int s, const mat3<R>& u) {
     void* p = (char*)base + (size_t)(mu * 2 + par) * 9 * stride * sizeof(v2d);
 #pragma unroll
@@ -768,6 +779,24 @@ struct LkRows2 {
   __device__ static mat3<R> load2(const void* base, int stride, int mu, int par, int s) {
     return LK::template load<6, NT>(base, stride, mu, par, s);
   }
+  // the same with mu and par uniform over the wavefront (LK::one_u)
+  __device__ static mat3<R> load2_u(const void* base, int stride, int mu, int par, int s) {
+    static_assert(!NT, "uniform-parity loads are not streamed");
+    const unsigned v = (unsigned)s * 16u;
+    mat3<R> u;
+    u.m[0] = LK::template one_u<0>(base, stride, mu, par, v);
+    u.m[1] = LK::template one_u<1>(base, stride, mu, par, v);
+    u.m[2] = LK::template one_u<2>(base, stride, mu, par, v);
+    u.m[3] = LK::template one_u<3>(base, stride, mu, par, v);
+    u.m[4] = LK::template one_u<4>(base, stride, mu, par, v);
+    u.m[5] = LK::template one_u<5>(base, stride, mu, par, v);
+    return u;
+  }
+  __device__ static mat3<R> load_u(const void* base, int stride, int mu, int par, int s) {
+    mat3<R> u = load2_u(base, stride, mu, par, s);
+    third_row(u);
+    return u;
+  }
 };
 
 // Row 0 and column 2 of any of the link formats above (components 0, 1, 2,
@@ -801,14 +830,41 @@ struct LkRowCol {
       u.m[3] = LK::template one<3, NT>(base, stride, mu, par, s);
       u.m[4] = LK::template one<4, NT>(base, stride, mu, par, s);
     } else {
-      // u10 = -(u00 conj(u02) u12 + conj(u01) conj(u22)) / D
-      // u11 = (conj(u00) conj(u22) - u01 conj(u02) u12) / D
-      const R inv = R(1) / d;
-      const cx<R> w = conj(u.m[2]) * u.m[5];
-      u.m[3] = (-inv) * (u.m[0] * w + conj(u.m[1]) * conj(u.m[8]));
-      u.m[4] = inv * (conj(u.m[0]) * conj(u.m[8]) - u.m[1] * w);
+      solve_row1(u, d);
     }
     return u;
+  }
+  // the same with mu and par uniform over the wavefront (LK::one_u)
+  __device__ static mat3<R> load2_u(const void* base, int stride, int mu, int par, int s) {
+    static_assert(!NT, "uniform-parity loads are not streamed");
+    const unsigned v = (unsigned)s * 16u;
+    mat3<R> u;
+    u.m[0] = LK::template one_u<0>(base, stride, mu, par, v);
+    u.m[1] = LK::template one_u<1>(base, stride, mu, par, v);
+    u.m[2] = LK::template one_u<2>(base, stride, mu, par, v);
+    u.m[5] = LK::template one_u<5>(base, stride, mu, par, v);
+    u.m[8] = LK::template one_u<8>(base, stride, mu, par, v);
+    const R d = norm2(u.m[0]) + norm2(u.m[1]);
+    if (d < R(0.0625)) {
+      u.m[3] = LK::template one_u<3>(base, stride, mu, par, v);
+      u.m[4] = LK::template one_u<4>(base, stride, mu, par, v);
+    } else {
+      solve_row1(u, d);
+    }
+    return u;
+  }
+  __device__ static mat3<R> load_u(const void* base, int stride, int mu, int par, int s) {
+    mat3<R> u = load2_u(base, stride, mu, par, s);
+    third_row(u);
+    return u;
+  }
+  // u10 = -(u00 conj(u02) u12 + conj(u01) conj(u22)) / D
+  // u11 = (conj(u00) conj(u22) - u01 conj(u02) u12) / D
+  __device__ static void solve_row1(mat3<R>& u, R d) {
+    const R inv = R(1) / d;
+    const cx<R> w = conj(u.m[2]) * u.m[5];
+    u.m[3] = (-inv) * (u.m[0] * w + conj(u.m[1]) * conj(u.m[8]));
+    u.m[4] = inv * (conj(u.m[0]) * conj(u.m[8]) - u.m[1] * w);
   }
 };
 

@@ -289,9 +289,29 @@ __device__ __forceinline__ mat3<double> back_link(const OwnLinks& o, int mu, int
   return u;
 }
 
+// A link of the site-blocked walk, whose sites of one parity make the
+// parity of every neighbour uniform over the wavefront (scalar array
+// bases, LK::load_u); the other forms take it from the site.
+template <class LK, bool UNI>
+__device__ __forceinline__ mat3<double> slink(const Lat& g, const void* U, int mu, const Site& st, int par) {
+  if constexpr (UNI)
+    return LK::load_u(U, g.stride, mu, par, st.lex >> 1);
+  else
+    return link<LK>(g, U, mu, st);
+}
+template <class LK, bool UNI>
+__device__ __forceinline__ mat3<double> slink2(const Lat& g, const void* U, int mu, const Site& st, int par) {
+  if constexpr (UNI)
+    return LK::load2_u(U, g.stride, mu, par, st.lex >> 1);
+  else
+    return link2<LK>(g, U, mu, st);
+}
+
+// par: the parity of x (used where OWN: the site-blocked walk)
 template <class LK, int MU, int NU, bool OWN>
 __device__ __forceinline__ void add_staples_su3(const Lat& g, const void* U, Site x, Site xm, mat3<double>& A,
-                                                const OwnLinks* own, int lane) {
+                                                const OwnLinks* own, int lane, int par) {
+  const int po = par ^ 1;
   chain_sites(x, xm, A);
   {
     // upper: U_nu(x+mu) (U_nu(x) U_mu(x+nu))^dag
@@ -302,11 +322,11 @@ __device__ __forceinline__ void add_staples_su3(const Lat& g, const void* U, Sit
     else
       C = link2<LK>(g, U, NU, x);
     mat3<double> D;
-    mul_r01(C, link<LK>(g, U, MU, xn), D);
+    mul_r01(C, slink<LK, OWN>(g, U, MU, xn, po), D);
     third_row(D);
     chain_site(xm, D);
     mat3<double> S;
-    mul_r01_nd(link2<LK>(g, U, NU, xm), D, S);
+    mul_r01_nd(slink2<LK, OWN>(g, U, NU, xm, po), D, S);
 #pragma unroll
     for (int k = 0; k < 6; ++k) A.m[k] = A.m[k] + S.m[k];
     A.m[6] = acc_conj_cross(A.m[6], S.m[1], S.m[5], S.m[2], S.m[4]);
@@ -318,7 +338,7 @@ __device__ __forceinline__ void add_staples_su3(const Lat& g, const void* U, Sit
     // lower: (U_mu(x-nu) U_nu(x+mu-nu))^dag U_nu(x-nu)
     Site xmn = shift<NU, -1>(g, xm), xn = shift<NU, -1>(g, x);
     mat3<double> H;
-    mul_r01(link2<LK>(g, U, MU, xn), link<LK>(g, U, NU, xmn), H);
+    mul_r01(slink2<LK, OWN>(g, U, MU, xn, po), slink<LK, OWN>(g, U, NU, xmn, par), H);
     third_row(H);
     chain_site(xn, H);
     mat3<double> G;
@@ -343,9 +363,9 @@ __device__ __forceinline__ void add_staples_su3(const Lat& g, const void* U, Sit
 
 template <class LK, int MU, int NU, bool OWN = false>
 __device__ __forceinline__ void add_staples(const Lat& g, const void* U, Site x, Site xm, mat3<double>& A,
-                                            const OwnLinks* own = nullptr, int lane = 0) {
+                                            const OwnLinks* own = nullptr, int lane = 0, int par = 0) {
   if constexpr (CompactLinks<LK>::value) {
-    add_staples_su3<LK, MU, NU, OWN>(g, U, x, xm, A, own, lane);
+    add_staples_su3<LK, MU, NU, OWN>(g, U, x, xm, A, own, lane, par);
     return;
   }
   chain_sites(x, xm, A);
@@ -395,10 +415,10 @@ __device__ __forceinline__ void gauge_force_link(const Lat& g, const void* U, do
   mat3<double> A;
 #pragma unroll
   for (int k = 0; k < 9; ++k) A.m[k] = {0.0, 0.0};
-  if (MU != 0) add_staples<LK, MU, 0, OWN>(g, U, x, xm, A, own, lane);
-  if (MU != 1) add_staples<LK, MU, 1, OWN>(g, U, x, xm, A, own, lane);
-  if (MU != 2) add_staples<LK, MU, 2, OWN>(g, U, x, xm, A, own, lane);
-  if (MU != 3) add_staples<LK, MU, 3, OWN>(g, U, x, xm, A, own, lane);
+  if (MU != 0) add_staples<LK, MU, 0, OWN>(g, U, x, xm, A, own, lane, par);
+  if (MU != 1) add_staples<LK, MU, 1, OWN>(g, U, x, xm, A, own, lane, par);
+  if (MU != 2) add_staples<LK, MU, 2, OWN>(g, U, x, xm, A, own, lane, par);
+  if (MU != 3) add_staples<LK, MU, 3, OWN>(g, U, x, xm, A, own, lane, par);
   gauge_force_finish<LK, MU, OWN>(g, U, P, coef_beta, par, s, A, own, lane);
 }
 
@@ -425,6 +445,7 @@ template <class LK>
 __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void* U, double* P, double coef_beta) {
   int par, s;
   walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
+  par = __builtin_amdgcn_readfirstlane(par);  // one parity per walk unit
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wavefront (direction), as a scalar
   if constexpr (CompactLinks<LK>::value) {
     // each wavefront parks rows 0 and 1 of its own links; every work-item
@@ -433,7 +454,7 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void*
     const int lane = threadIdx.x & 63;
     if (s < g.Vh) {
       const Site x = cb_site(g, par, s);
-      const mat3<double> u = LK::load2(U, g.stride, w, par, s);
+      const mat3<double> u = LK::load2_u(U, g.stride, w, par, s);
       Site xb;
       switch (w) {
         case 0: xb = shift<0, -1>(g, x); break;
@@ -441,7 +462,7 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void*
         case 2: xb = shift<2, -1>(g, x); break;
         default: xb = shift<3, -1>(g, x); break;
       }
-      const mat3<double> ub = link2<LK>(g, U, w, xb);
+      const mat3<double> ub = LK::load2_u(U, g.stride, w, par ^ 1, xb.lex >> 1);
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         own.m[w][k][lane] = u.m[k];
