@@ -396,8 +396,10 @@ def run_dslash(args, H, torch):
     # approximate counts of the kernels' arithmetic, for the FP64 fraction
     # of the kernels near the ridge
     V = 2 * synth_vh(L)
+    xe = inp[H.F64]  # a Gaussian half spinor as X_e of the fermion force
     for name, fn, kern, flops_site in (
             ("gauge_force", lambda: H.hmc_gauge_force(F, 1e-3), "gauge_force", 11500),
+            ("fermion_force", lambda: H.hmc_fermion_force(F, xe, 1e-3), "fermion_force", 2800),
             ("exp_update", lambda: H.hmc_exp_update_reunit(F, 1e-3), "exp_update", 2800),
             ("plaquette", lambda: H.hmc_plaquette(F), "plaquette", 3600),
             ("norm2", lambda: H.hmc_norm2(F, inp[H.F64], 1), "reduce", None),
