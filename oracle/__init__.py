@@ -132,6 +132,7 @@ def bind(path):
         "or_hmc_trajectory_mts": (C.c_int, [_I, _P, _P, C.c_uint64, C.c_uint64, C.c_double, _P, _P]),
         "or_ratio_action": (C.c_double, [_I, _P, _P, _P]),
         "or_gauge_force_sites": (None, [_I, _P, C.c_double, _P, C.c_long, _P]),
+        "or_fermion_force_sites": (None, [_I, _P, C.c_double, _P, _P, _P, C.c_long, _P]),
         "or_fermion_force": (None, [_I, _P, C.c_double, _P, _P, _P]),
         "or_mat_exp": (None, [_P, _P]),
         "or_reunit": (None, [_P]),
@@ -333,6 +334,18 @@ def fermion_force(L, U, coef, X, Y):
     F = gauge_zeros(L)
     _load().or_fermion_force(_dims(L), _ptr(_c128(U)), float(coef), _ptr(_c128(X)), _ptr(_c128(Y)), _ptr(F))
     return F
+
+
+def fermion_force_sites(L, U, coef, X, Y, sites):
+    """Fermion force at the listed lexicographic sites only -> (n, 4, 3, 3);
+    X and Y full-size arrays, read at those sites and their +mu neighbours."""
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    for a in (U, X, Y):
+        assert a.flags.c_contiguous and a.dtype == np.complex128
+    out = np.zeros((sites.size, 4, 3, 3), np.complex128)
+    _load().or_fermion_force_sites(_dims(L), _ptr(U), float(coef), _ptr(X), _ptr(Y), _ptr(sites), sites.size,
+                                   _ptr(out))
+    return out
 
 
 def mat_exp(A):

@@ -455,38 +455,52 @@ void or_gauge_force_sites(const int *L, const cplx *U, double beta, const long *
  *   W  = U_mu(x) M1 - M2 U_mu(x)^dag,   F_f = (i coef / 2) TA(W),
  * where coef = kappa^2 for the even/odd preconditioned action (and kappa
  * for the unpreconditioned one, with X = (M^dag M)^-1 phi, Y = M X). */
+/* The force on the link (site i, direction mu), nine entries. */
+static void fermion_force_link(const int *L, const cplx *U, double coef, const cplx *X, const cplx *Y, long i,
+                               int mu, cplx *Fl)
+{
+    int c[4];
+    coords_of(L, i, c);
+    int wraps;
+    long j = hop(L, c, mu, +1, &wraps);
+    double s = wraps ? -1.0 : 1.0;
+    cplx M1[9], M2[9];
+    for (int k = 0; k < 9; ++k) M1[k] = M2[k] = 0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            cplx pm = proj_el(mu, -1, a, b), pp = proj_el(mu, +1, a, b);
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q) {
+                    M1[3 * r + q] += s * pm * X[(j * 4 + b) * 3 + r] * conj(Y[(i * 4 + a) * 3 + q]);
+                    M2[3 * r + q] += s * pp * X[(i * 4 + b) * 3 + r] * conj(Y[(j * 4 + a) * 3 + q]);
+                }
+        }
+    cplx W[9], t[9], Ud[9], Z[9];
+    const cplx *Ul = &U[(i * 4 + mu) * 9];
+    mat_mul(Ul, M1, W);
+    mat_dag(Ul, Ud);
+    mat_mul(M2, Ud, t);
+    for (int k = 0; k < 9; ++k) W[k] -= t[k];
+    traceless_antiherm(W, Z);
+    for (int k = 0; k < 9; ++k) Fl[k] = I * coef / 2.0 * Z[k];
+}
+
 void or_fermion_force(const int *L, const cplx *U, double coef, const cplx *X, const cplx *Y, cplx *F)
 {
     long V = vol4(L);
 #pragma omp parallel for schedule(static)
-    for (long i = 0; i < V; ++i) {
-        int c[4];
-        coords_of(L, i, c);
-        for (int mu = 0; mu < 4; ++mu) {
-            int wraps;
-            long j = hop(L, c, mu, +1, &wraps);
-            double s = wraps ? -1.0 : 1.0;
-            cplx M1[9], M2[9];
-            for (int k = 0; k < 9; ++k) M1[k] = M2[k] = 0;
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b) {
-                    cplx pm = proj_el(mu, -1, a, b), pp = proj_el(mu, +1, a, b);
-                    for (int r = 0; r < 3; ++r)
-                        for (int q = 0; q < 3; ++q) {
-                            M1[3 * r + q] += s * pm * X[(j * 4 + b) * 3 + r] * conj(Y[(i * 4 + a) * 3 + q]);
-                            M2[3 * r + q] += s * pp * X[(i * 4 + b) * 3 + r] * conj(Y[(j * 4 + a) * 3 + q]);
-                        }
-                }
-            cplx W[9], t[9], Ud[9], Z[9];
-            const cplx *Ul = &U[(i * 4 + mu) * 9];
-            mat_mul(Ul, M1, W);
-            mat_dag(Ul, Ud);
-            mat_mul(M2, Ud, t);
-            for (int k = 0; k < 9; ++k) W[k] -= t[k];
-            traceless_antiherm(W, Z);
-            for (int k = 0; k < 9; ++k) F[(i * 4 + mu) * 9 + k] = I * coef / 2.0 * Z[k];
-        }
-    }
+    for (long i = 0; i < V; ++i)
+        for (int mu = 0; mu < 4; ++mu) fermion_force_link(L, U, coef, X, Y, i, mu, &F[(i * 4 + mu) * 9]);
+}
+
+/* The same at the listed sites only (X and Y needed at those sites and
+ * their forward neighbours): F is (n, 4, 3, 3). */
+void or_fermion_force_sites(const int *L, const cplx *U, double coef, const cplx *X, const cplx *Y, const long *sites,
+                            long n, cplx *F)
+{
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k)
+        for (int mu = 0; mu < 4; ++mu) fermion_force_link(L, U, coef, X, Y, sites[k], mu, &F[(k * 4 + mu) * 9]);
 }
 
 /* ------------------------------------------------------------------ */

@@ -664,6 +664,88 @@ def test_gauge_force_sampled_at_48c96(H):
     assert rel(dP, want) < 1e-12
 
 
+def _ball48(lex, r):
+    """The lexicographic sites within lattice (L1) distance r of the listed
+    ones on the 48^3 x 96 torus."""
+    L = np.array([48, 48, 48, 96])
+    offs = [np.array(o) - r for o in np.ndindex(*(2 * r + 1,) * 4) if sum(abs(v - r) for v in o) <= r]
+    c = _coords48(np.asarray(lex))
+    out = set()
+    for o in offs:
+        y = (c + o) % L
+        out.update((y[:, 0] + 48 * (y[:, 1] + 48 * (y[:, 2] + 48 * y[:, 3]))).tolist())
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def test_plaquette_at_48c96(H):
+    """The plaquette sum over the whole 48^3 x 96 lattice in the launch
+    configuration the benchmark times: exactly 1 on the unit gauge, and the
+    GPU's weak-field start (seed 2, eps 0.3) against the oracle's plaquette
+    of its own draws of the same field."""
+    L = (48, 48, 48, 96)
+    F = H.Fields(L, 5.6, 0.15)
+    put_gauge(H, F, O.unit_gauge(L))
+    assert H.hmc_plaquette(F) == 1.0
+    H.hmc_weak_field_start(F, 2, 0.3)
+    p = H.hmc_plaquette(F)
+    want = O.plaquette(L, O.weak_field(L, 2, 0.3))
+    assert abs(p - want) < 1e-12 * abs(want)
+
+
+def test_fermion_force_sampled_at_48c96(H):
+    """The fermion force at 48^3 x 96 (the launch configuration the
+    benchmark times): P_after - P_before = -F_f at ~70 sites of both
+    parities, all four directions.  The oracle builds X = (X_e, D_oe X_e)
+    and Y = (Mhat X_e, D^dag_oe Mhat X_e) at the sites the force reads from
+    its own draws of the links and of the Gaussian X_e, on the ball of
+    radius four around the samples that those hops reach."""
+    L = (48, 48, 48, 96)
+    V = synth.volume(L)
+    Vh = V // 2
+    k = 0.15
+    F = H.Fields(L, 5.6, k)
+    H.hmc_weak_field_start(F, 2, 0.3)
+    H.hmc_refresh(F, 5, 0, H.REFRESH_MOM)
+    src = F.spinor(full=True)
+    H.hmc_make_source(F, src, 0, 2, 0)
+    hb = H.hmc_field_bytes(L, 0, H.KIND_HALF_SPINOR)
+    P = F.arena[F.pointer(H.FIELD_MOMENTA) - F.arena.data_ptr():].view(torch.float64)[: 4 * 2 * 8 * Vh]
+    P = P.view(4, 2, 8, Vh)
+    lex = np.random.default_rng(4).integers(0, V, 64)
+    lex = np.unique(np.concatenate([lex, [O.lex_index(L, 0, 0, 0, 0), O.lex_index(L, 47, 47, 47, 95),
+                                          O.lex_index(L, 47, 0, 0, 95)]])).astype(np.int64)
+    c = _coords48(lex)
+    par = torch.from_numpy(c.sum(1) % 2).cuda()
+    cb = torch.from_numpy(lex // 2).cuda()
+    before = P[:, par, :, cb].clone()  # (n, 4, 8)
+    H.hmc_fermion_force(F, src[:hb], 1.0)  # X_e: the even half of the Gaussian source
+    torch.cuda.synchronize()
+    dP = (P[:, par, :, cb] - before).cpu().numpy()
+
+    def even(s):
+        return s[_coords48(s).sum(1) % 2 == 0]
+
+    def odd(s):
+        return s[_coords48(s).sum(1) % 2 == 1]
+
+    ball = _ball48(lex, 4)
+    U = np.zeros((V, 4, 3, 3), np.complex128)  # lazily zero pages: only the ball is touched
+    O.weak_field_sites(L, 2, 0.3, ball, U)
+    X = np.zeros((V, 4, 3), np.complex128)
+    Y = np.zeros((V, 4, 3), np.complex128)
+    O.gauss_source_sites(2, 0, even(ball), X)  # X_e on the even sites of the ball
+    o3 = odd(_ball48(lex, 3))
+    X[o3] = O.dslash_sites(L, U, X, o3)  # X_o = D_oe X_e
+    e2 = even(_ball48(lex, 2))
+    Y[e2] = X[e2] - k * k * O.dslash_sites(L, U, X, e2)  # Y_e = Mhat X_e
+    o1 = odd(_ball48(lex, 1))
+    Y[o1] = O.dslash_sites(L, U, Y, o1, dagger=True)  # Y_o = D^dag_oe Y_e
+    Fo = O.fermion_force_sites(L, U, k * k, X, Y, lex)  # (n, 4, 3, 3), Hermitian traceless
+    want = -np.stack([Fo[..., 0, 0].real, Fo[..., 1, 1].real, Fo[..., 0, 1].real, Fo[..., 0, 1].imag,
+                      Fo[..., 0, 2].real, Fo[..., 0, 2].imag, Fo[..., 1, 2].real, Fo[..., 1, 2].imag], -1)
+    assert rel(dP, want) < 1e-12
+
+
 @pytest.mark.parametrize("prec", [1, 2, 3])
 def test_trajectory_with_mixed_precision_solves_c1(H, prec):
     """The 4^4 chain with the force solves in mixed precision (FP32 / FP16 /

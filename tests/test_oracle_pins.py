@@ -579,6 +579,9 @@ def test_site_list_functions_match_full_lattice():
     assert np.array_equal(O.dslash_sites(L, U, psi, sites), full[sites])
     fg = O.gauge_force(L, U, 5.6)
     assert np.array_equal(O.gauge_force_sites(L, U, 5.6, sites), fg[sites])
+    chi = synth.spinor(43, L)
+    ff = O.fermion_force(L, U, 0.02, psi, chi)
+    assert np.array_equal(O.fermion_force_sites(L, U, 0.02, psi, chi, sites), ff[sites])
     Uw = np.zeros_like(U)
     O.weak_field_sites(L, 3, 0.3, sites, Uw)
     assert np.array_equal(Uw[sites], O.weak_field(L, 3, 0.3)[sites])
