@@ -39,19 +39,27 @@ __device__ __forceinline__ void algebra_compact(const double* w, double* c) {
   c[7] = -0.5 * w[6];
 }
 
+// One work-item per link (blockIdx.y = mu): the eight Gaussians of
+// direction mu are the words of Philox blocks 2 mu and 2 mu + 1 of the
+// site's stream, so every value is the one a whole-site work-item would
+// draw, with a quarter of its registers.
 __global__ void __launch_bounds__(kBlock) k_refresh_momenta(Lat g, uint64_t seed, uint64_t epoch, double* P) {
   int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= 2 * g.Vh) return;
   int par = j >= g.Vh, s = j - par * g.Vh;
+  const int mu = blockIdx.y;
   Site x = cb_site(g, par, s);
-  double gs[32];
-  site_gaussians<32>(seed, (uint64_t)x.lex, ST_MOMENTA, epoch, gs);
+  double gs[8];
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    double c[8];
-    algebra_compact(&gs[8 * mu], c);
-    store_compact(P, g.stride, mu, par, s, c);
+  for (int b = 0; b < 2; ++b) {
+    uint64_t w[4];
+    philox4x64_10(2 * mu + b, (uint64_t)x.lex, ST_MOMENTA, epoch, seed, 0, w);
+    box_muller(w[0], w[1], &gs[4 * b], &gs[4 * b + 1]);
+    box_muller(w[2], w[3], &gs[4 * b + 2], &gs[4 * b + 3]);
   }
+  double c[8];
+  algebra_compact(gs, c);
+  store_compact(P, g.stride, mu, par, s, c);
 }
 
 __global__ void __launch_bounds__(kBlock) k_weak_field(Lat g, uint64_t seed, double eps, void* U) {
@@ -74,16 +82,27 @@ __global__ void __launch_bounds__(kBlock) k_weak_field(Lat g, uint64_t seed, dou
 }
 
 // eta on the sites of parity par: complex Gaussian with E|eta_k|^2 = 1.
+// Three work-items per site (blockIdx.y = q): components 4q .. 4q+3 from
+// Philox blocks 2q and 2q + 1 of the site's stream, the values a
+// whole-site work-item would draw.
 __global__ void __launch_bounds__(kBlock) k_eta(Lat g, uint64_t seed, uint64_t epoch, int par, double2* half,
                                                 int rng_stream) {
   int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.Vh) return;
+  const int q = blockIdx.y;
   Site x = cb_site(g, par, s);
-  double gs[24];
-  site_gaussians<24>(seed, (uint64_t)x.lex, rng_stream, epoch, gs);
+  double gs[8];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    uint64_t w[4];
+    philox4x64_10(2 * q + b, (uint64_t)x.lex, rng_stream, epoch, seed, 0, w);
+    box_muller(w[0], w[1], &gs[4 * b], &gs[4 * b + 1]);
+    box_muller(w[2], w[3], &gs[4 * b + 2], &gs[4 * b + 3]);
+  }
   const double r = 0.70710678118654752440;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) half[(size_t)k * g.stride + s] = make_double2(r * gs[2 * k], r * gs[2 * k + 1]);
+  for (int k = 0; k < 4; ++k)
+    half[(size_t)(4 * q + k) * g.stride + s] = make_double2(r * gs[2 * k], r * gs[2 * k + 1]);
 }
 
 // Sources on both parities (blockIdx.y = parity).
@@ -175,7 +194,7 @@ __global__ void k_metropolis(uint64_t seed, uint64_t traj, double beta, double V
 
 hipError_t launch_refresh_momenta(const LatArg& g, uint64_t seed, uint64_t epoch, double* P, hipStream_t st) {
   TimedScope ts(TK_REFRESH, st, 2.0 * g.Vh * 4 * 64);
-  hipLaunchKernelGGL(k_refresh_momenta, dim3(ceil_div(2LL * g.Vh, kBlock)), dim3(kBlock), 0, st, to_lat(g), seed,
+  hipLaunchKernelGGL(k_refresh_momenta, dim3(ceil_div(2LL * g.Vh, kBlock), 4), dim3(kBlock), 0, st, to_lat(g), seed,
                      epoch, P);
   return hipGetLastError();
 }
@@ -186,7 +205,7 @@ hipError_t launch_weak_field(const LatArg& g, uint64_t seed, double eps, void* U
 hipError_t launch_eta(const LatArg& g, uint64_t seed, uint64_t epoch, int par, void* half, hipStream_t st,
                       int second) {
   TimedScope ts(TK_REFRESH, st, (double)g.Vh * SpF64::kBytes);
-  hipLaunchKernelGGL(k_eta, dim3(site_blocks(g.Vh)), dim3(kBlock), 0, st, to_lat(g), seed, epoch, par,
+  hipLaunchKernelGGL(k_eta, dim3(site_blocks(g.Vh), 3), dim3(kBlock), 0, st, to_lat(g), seed, epoch, par,
                      (double2*)half, second ? (int)ST_ETA2 : (int)ST_ETA);
   return hipGetLastError();
 }
