@@ -413,7 +413,8 @@ hmc_status hmc_stream_triad(void* a, const void* b, const void* c, double s, uin
  *     link by the hopping kernels, 12 = rows 0 and 1, 10 = row 0 and
  *     column 2 (the fermion force follows the FP64 entry);
  *   HMC_TUNE_GAUGE_FORCE_LINKS (prec HMC_F64): the same for the staple
- *     force and the plaquette;
+ *     force (the plaquette sum on SU(3) links reads two rows, measured
+ *     fastest there; on other links all nine entries);
  *   HMC_TUNE_DSLASH_STREAM (per storage precision): 1 = the Dslash reads its
  *     compact links and writes its output with non-temporal hints;
  *   HMC_TUNE_DSLASH_ORDER (per storage precision): 1 = the one-site-per-
