@@ -66,7 +66,7 @@ MUTANTS = {
         "mat_mul(a, &U[(xmnu * 4 + nu) * 9], a);", "mat_mul(&U[(xmnu * 4 + nu) * 9], a, a);",
         [P.test_gauge_force_finite_difference, P.test_forces_gauge_covariant]),
     "fermion force boundary sign dropped": (
-        "double s = wraps ? -1.0 : 1.0;\n            cplx M1[9]", "double s = 1.0;\n            cplx M1[9]",
+        "double s = wraps ? -1.0 : 1.0;\n    cplx M1[9]", "double s = 1.0;\n    cplx M1[9]",
         [P.test_fermion_force_finite_difference]),
     "fermion force projectors swapped": (
         "cplx pm = proj_el(mu, -1, a, b), pp = proj_el(mu, +1, a, b);",
