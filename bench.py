@@ -39,6 +39,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -302,6 +303,7 @@ def run_hmc(args, H, torch):
         "trajectories": [{"traj": k, "seconds": r["seconds"], "dH": r["dH"], "accepted": r["accepted"],
                           "plaquette": r["plaquette"], "cg_iters": r["cg_iters_total"]}
                          for k, r in enumerate(results)],
+        "s_per_traj_median": statistics.median(r["seconds"] for r in results),
         "cg_iters_per_solve": iters / solves,
         "kernels_sampled": {k: {"launches_timed": v["launches"], "launches_all": v["calls"],
                                 "avg_ms": v["total_ms"] / v["launches"],
