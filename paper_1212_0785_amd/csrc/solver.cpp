@@ -358,11 +358,17 @@ hipError_t recorded_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, i
 // launch, every m-th chunk that would be replayed runs directly with all
 // its launches timed, so the sampled durations are those of the launches a
 // replay issues.
+// Whether the chunks of this kind are replayed from recordings.
+bool chunk_records(const ChunkExtra& x) {
+  const int mode = graphs_mode();
+  return mode == GRAPHS_ALL || mode == GRAPHS_STRICT || (mode == GRAPHS_MIXED && x.ru);
+}
+
 hipError_t launch_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, int n, const ChunkExtra& x,
                         hipStream_t st) {
   static thread_local unsigned counter = 0;
   const int mode = graphs_mode();
-  const bool record = mode == GRAPHS_ALL || mode == GRAPHS_STRICT || (mode == GRAPHS_MIXED && x.ru);
+  const bool record = chunk_records(x);
   if (!record || (F->record_failed && mode != GRAPHS_STRICT)) return chunk_launches(v, args, n, x, st);
   const int every = timing_sample_every();
   if (every > 0 && counter++ % every == 0) {
@@ -392,15 +398,25 @@ struct Chunk {
 
 // F64 chunks: lengths taken as sums of powers of two, so at most five
 // recordings per solve configuration serve every length.
+// A chunk with no reliable update that is not replayed takes its labels
+// from the launch arguments instead (c.k + j on a base that stays at its
+// reset value 0), which spares the label advance after every chunk.
 hipError_t enqueue_chunk(Fields* F, const SolveVecs& v, const IterArgs& args, const Chunk& c, hipStream_t st,
                          const ChunkExtra& x = ChunkExtra{}) {
-  int left = c.n;
-  for (int p = kChunk; p >= 1; p >>= 1)
-    while (left >= p) {
-      hipError_t e = launch_chunk(F, v, args, p, x, st);
+  if (!x.ru && !chunk_records(x)) {
+    for (int j = 0; j < c.n; ++j) {
+      hipError_t e = launch_iteration(v.g, v.prec, v.cgls, nullptr, args, 1, v.nbD, v.nbR, c.k + j, st);
       if (e != hipSuccess) return e;
-      left -= p;
     }
+  } else {
+    int left = c.n;
+    for (int p = kChunk; p >= 1; p >>= 1)
+      while (left >= p) {
+        hipError_t e = launch_chunk(F, v, args, p, x, st);
+        if (e != hipSuccess) return e;
+        left -= p;
+      }
+  }
   static_assert(sizeof(SolverState) <= kStateSlot * sizeof(double), "state slot");
   hipError_t e = hipMemcpyAsync(F->pinned + SL_COUNT + kStateSlot * c.slot, F->state, sizeof(SolverState),
                                 hipMemcpyDeviceToHost, st);
