@@ -110,8 +110,9 @@ __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, 
   int par, s;
   walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
   const bool on = s < g.Vh;
-  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // the wavefront, as a scalar; every work-item
-                                                              // reaches the barrier inside
+  // the wavefront, as a scalar: each case holds exactly one barrier, which
+  // every wavefront (and every work-item, on or off the lattice) reaches once
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
     case 0: fermion_force_link<LK, 0>(g, U, v, P, c_ta, par, s, on, own); break;
     case 1: fermion_force_link<LK, 1>(g, U, v, P, c_ta, par, s, on, own); break;
     case 2: fermion_force_link<LK, 2>(g, U, v, P, c_ta, par, s, on, own); break;

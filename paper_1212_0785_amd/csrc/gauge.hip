@@ -257,6 +257,9 @@ __global__ void __launch_bounds__(kPlaqPairThreads) k_plaquette_pairs(Lat g, con
   __shared__ cx<double> own[4][6][64];
   const Site x = cb_site(g, on ? par : 0, on ? s : 0);
   double v[1];
+  // w is uniform over a wavefront; each case holds exactly one barrier,
+  // which every wavefront (and every work-item, on or off the lattice)
+  // reaches once
   switch (w) {
     case 0: v[0] = plaq_pair<LK, 0, 1, 2, 3>(g, U, x, own, w, lane, par, s, on); break;
     case 1: v[0] = plaq_pair<LK, 0, 2, 1, 3>(g, U, x, own, w, lane, par, s, on); break;
