@@ -552,21 +552,29 @@ __global__ void __launch_bounds__(3 * kGfSites) k_gauge_force_planes(Lat g, cons
 // U <- reunit(exp(i eps P) U), one link per work-item.  The reunitarisation
 // uses rows 0 and 1 of the product only, so on SU(3) links LK reads rows 0
 // and 1 of U and rebuilds row 2 (which the product needs) from them; the
-// full link is written.
-template <class LK>
+// full link is written.  NT: non-temporal loads of P and U and stores of U
+// (each touched once; on large lattices they would only displace other
+// data from the caches).
+template <class LK, bool NT>
 __global__ void __launch_bounds__(kBlock) k_exp_update(Lat g, void* U, const double* P, double eps) {
   int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= 2 * g.Vh) return;
   int par = j >= g.Vh, s = j - par * g.Vh;
   int mu = blockIdx.y;
   double c[8];
-  load_compact(P, g.stride, mu, par, s, c);
+  {
+    const double* p = P + (size_t)(mu * 2 + par) * 8 * g.stride;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = gld_link<double, NT>(p, k * g.stride + s);
+  }
 #pragma unroll
   for (int k = 0; k < 8; ++k) c[k] *= eps;
   mat3<double> E = exp_iQ(herm_from_compact(c));
   mat3<double> u = mmul(E, LK::load(U, g.stride, mu, par, s));
   reunitarise(u);
-  LkF64::store(U, g.stride, mu, par, s, u);
+  void* q = (char*)U + (size_t)(mu * 2 + par) * 9 * g.stride * sizeof(v2d);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gput<NT>(q, k * g.stride + s, v2d{u.m[k].re, u.m[k].im});
 }
 
 int plaquette_blocks(const LatArg& g, bool su3) {
@@ -636,10 +644,13 @@ hipError_t launch_exp_update(const LatArg& g, void* U, const double* P, double e
   const int rb = su3 ? LkRows2<LkF64>::kBytes : LkF64::kBytes;
   TimedScope ts(TK_EXP_UPDATE, st, 2.0 * g.Vh * 4 * (2 * LkF64::kBytes + 64), 2.0 * g.Vh * 4 * (rb + LkF64::kBytes + 64));
   const dim3 grid(ceil_div(2LL * g.Vh, kBlock), 4), block(kBlock);
-  if (su3)
-    hipLaunchKernelGGL(k_exp_update<LkRows2<LkF64>>, grid, block, 0, st, to_lat(g), U, P, eps);
+  const bool nt = exp_update_stream(g);
+  if (su3 && nt)
+    hipLaunchKernelGGL((k_exp_update<LkRows2<LkF64, true>, true>), grid, block, 0, st, to_lat(g), U, P, eps);
+  else if (su3)
+    hipLaunchKernelGGL((k_exp_update<LkRows2<LkF64>, false>), grid, block, 0, st, to_lat(g), U, P, eps);
   else
-    hipLaunchKernelGGL(k_exp_update<LkF64>, grid, block, 0, st, to_lat(g), U, P, eps);
+    hipLaunchKernelGGL((k_exp_update<LkF64, false>), grid, block, 0, st, to_lat(g), U, P, eps);
   return hipGetLastError();
 }
 
