@@ -29,7 +29,7 @@ struct OwnSpinors {
   cx<double> Y[12][64];
 };
 
-template <class LK, int MU>
+template <class LK, int MU, bool NT>
 __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, const ForceVecs& v, double* P,
                                                    double c_ta, int par, int s, bool on, OwnSpinors& own) {
   const int w = MU, lane = threadIdx.x & 63;
@@ -60,7 +60,9 @@ __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, 
   // the link and the momenta: issuing them before the barrier as well
   // raises the registers past three wavefronts per SIMD (measured slower)
   u = LK::load(U, g.stride, MU, par, s);
-  load_compact(P, g.stride, MU, par, s, c);
+  double* pm = P + (size_t)(MU * 2 + par) * 8 * g.stride;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c[k] = gld_link<double, NT>(pm, k * g.stride + s);
   // U M1 - M2 U^dag = sg sum_j [(U hx_j) hb_j^dag - ha_j (U hy_j)^dag]
   // (M1, M2 of rank two: no 3x3 product is formed)
   cx<double> ux[6], uy[6];
@@ -95,15 +97,14 @@ __device__ __forceinline__ void fermion_force_link(const Lat& g, const void* U, 
   double f[8];
   i_ta_compact(W, c_ta, f);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) c[k] += f[k];
-  store_compact(P, g.stride, MU, par, s, c);
+  for (int k = 0; k < 8; ++k) gput<NT>(pm, k * g.stride + s, c[k] + f[k]);
 }
 
 // A block of four wavefronts covers 64 sites of one parity, wavefront w the
 // links U_w (walk_site with the block as the walk unit): X and Y at the
 // block's sites are read from memory once into LDS, those at the
 // neighbours once per direction.
-template <class LK>
+template <class LK, bool NT>
 __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, ForceVecs v, double* P,
                                                           double c_ta) {
   __shared__ OwnSpinors own;
@@ -113,10 +114,10 @@ __global__ void __launch_bounds__(kBlock) k_fermion_force(Lat g, const void* U, 
   // the wavefront, as a scalar: each case holds exactly one barrier, which
   // every wavefront (and every work-item, on or off the lattice) reaches once
   switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-    case 0: fermion_force_link<LK, 0>(g, U, v, P, c_ta, par, s, on, own); break;
-    case 1: fermion_force_link<LK, 1>(g, U, v, P, c_ta, par, s, on, own); break;
-    case 2: fermion_force_link<LK, 2>(g, U, v, P, c_ta, par, s, on, own); break;
-    default: fermion_force_link<LK, 3>(g, U, v, P, c_ta, par, s, on, own); break;
+    case 0: fermion_force_link<LK, 0, NT>(g, U, v, P, c_ta, par, s, on, own); break;
+    case 1: fermion_force_link<LK, 1, NT>(g, U, v, P, c_ta, par, s, on, own); break;
+    case 2: fermion_force_link<LK, 2, NT>(g, U, v, P, c_ta, par, s, on, own); break;
+    default: fermion_force_link<LK, 3, NT>(g, U, v, P, c_ta, par, s, on, own); break;
   }
 }
 
@@ -140,12 +141,19 @@ hipError_t launch_fermion_force(const LatArg& g, const void* U, const void* Xe, 
   const dim3 grid(2 * ceil_div(g.Vh, 64)), block(kBlock);
   const double c = -0.5 * coef;
   const Lat lat = walk_lat(g);
-  if (form == LINK_ROWCOL)
-    hipLaunchKernelGGL(k_fermion_force<LkRowCol<LkF64>>, grid, block, 0, st, lat, U, v, P, c);
+  // non-temporal link and momentum accesses (each used once) where the
+  // fields outgrow the last-level cache
+  const bool nt = fermion_force_stream(g);
+  if (form == LINK_ROWCOL && nt)
+    hipLaunchKernelGGL((k_fermion_force<LkRowCol<LkF64, true>, true>), grid, block, 0, st, lat, U, v, P, c);
+  else if (form == LINK_ROWCOL)
+    hipLaunchKernelGGL((k_fermion_force<LkRowCol<LkF64>, false>), grid, block, 0, st, lat, U, v, P, c);
+  else if (form == LINK_ROWS2 && nt)
+    hipLaunchKernelGGL((k_fermion_force<LkRows2<LkF64, true>, true>), grid, block, 0, st, lat, U, v, P, c);
   else if (form == LINK_ROWS2)
-    hipLaunchKernelGGL(k_fermion_force<LkRows2<LkF64>>, grid, block, 0, st, lat, U, v, P, c);
+    hipLaunchKernelGGL((k_fermion_force<LkRows2<LkF64>, false>), grid, block, 0, st, lat, U, v, P, c);
   else
-    hipLaunchKernelGGL(k_fermion_force<LkF64>, grid, block, 0, st, lat, U, v, P, c);
+    hipLaunchKernelGGL((k_fermion_force<LkF64, false>), grid, block, 0, st, lat, U, v, P, c);
   return hipGetLastError();
 }
 

@@ -265,8 +265,10 @@ hipError_t launch_ru_request(SolverState* st_dev, hipStream_t st);
 // planes each; 0 = four 64-site units per block, all planes per work-item
 // (the only form on links that are not SU(3)).
 int plaquette_shape(const LatArg& g);
-// Non-temporal loads and stores in the link update (large lattices).
+// Non-temporal loads and stores of the once-used data in the link update
+// and in the fermion force (large lattices).
 bool exp_update_stream(const LatArg& g);
+bool fermion_force_stream(const LatArg& g);
 // Compact link form of the plaquette sum on SU(3) links.
 int plaquette_link_form(const LatArg& g);
 // One partial per block, plaquette_blocks(g, su3) of them (at most
