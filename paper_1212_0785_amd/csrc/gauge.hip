@@ -390,7 +390,7 @@ __device__ __forceinline__ void add_staples(const Lat& g, const void* U, Site x,
 
 // P_mu(x) += (i coef beta / 12) TA(U_mu(x) A), A the staple sum: with
 // F = -(i beta / 12) TA(W) this is P <- P - coef F.
-template <class LK, int MU, bool OWN = false>
+template <class LK, int MU, bool OWN = false, bool NT = false>
 __device__ __forceinline__ void gauge_force_finish(const Lat& g, const void* U, double* P, double coef_beta, int par,
                                                    int s, const mat3<double>& A, const OwnLinks* own = nullptr,
                                                    int lane = 0) {
@@ -404,13 +404,15 @@ __device__ __forceinline__ void gauge_force_finish(const Lat& g, const void* U, 
   mat3<double> W = mmul(u, A);
   double f[8], c[8];
   i_ta_compact(W, coef_beta / 12.0, f);
-  load_compact(P, g.stride, MU, par, s, c);
+  // NT: non-temporal momentum accesses (each read and written once)
+  double* pm = P + (size_t)(MU * 2 + par) * 8 * g.stride;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) c[k] += f[k];
-  store_compact(P, g.stride, MU, par, s, c);
+  for (int k = 0; k < 8; ++k) c[k] = gld_link<double, NT>(pm, k * g.stride + s);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) gput<NT>(pm, k * g.stride + s, c[k] + f[k]);
 }
 
-template <class LK, int MU, bool OWN = false>
+template <class LK, int MU, bool OWN = false, bool NT = false>
 __device__ __forceinline__ void gauge_force_link(const Lat& g, const void* U, double* P, double coef_beta, int par,
                                                  int s, const OwnLinks* own = nullptr, int lane = 0) {
   Site x = cb_site(g, par, s);
@@ -422,7 +424,7 @@ __device__ __forceinline__ void gauge_force_link(const Lat& g, const void* U, do
   if (MU != 1) add_staples<LK, MU, 1, OWN>(g, U, x, xm, A, own, lane, par);
   if (MU != 2) add_staples<LK, MU, 2, OWN>(g, U, x, xm, A, own, lane, par);
   if (MU != 3) add_staples<LK, MU, 3, OWN>(g, U, x, xm, A, own, lane, par);
-  gauge_force_finish<LK, MU, OWN>(g, U, P, coef_beta, par, s, A, own, lane);
+  gauge_force_finish<LK, MU, OWN, NT>(g, U, P, coef_beta, par, s, A, own, lane);
 }
 
 template <class LK>
@@ -444,7 +446,7 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force(Lat g, const void* U, do
 // parks rows 0 and 1 of its 256 own links and of the 256 links U_mu(x-mu)
 // in LDS (48 KB), which the wavefronts read for their staples and for the
 // final product instead of loading each three times.
-template <class LK>
+template <class LK, bool NT>
 __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void* U, double* P, double coef_beta) {
   int par, s;
   walk_site(g, blockIdx.x & 7, walk_unit(g, 1), &par, &s);
@@ -475,10 +477,10 @@ __global__ void __launch_bounds__(kBlock) k_gauge_force_sites(Lat g, const void*
     __syncthreads();
     if (s >= g.Vh) return;
     switch (w) {
-      case 0: gauge_force_link<LK, 0, true>(g, U, P, coef_beta, par, s, &own, lane); break;
-      case 1: gauge_force_link<LK, 1, true>(g, U, P, coef_beta, par, s, &own, lane); break;
-      case 2: gauge_force_link<LK, 2, true>(g, U, P, coef_beta, par, s, &own, lane); break;
-      default: gauge_force_link<LK, 3, true>(g, U, P, coef_beta, par, s, &own, lane); break;
+      case 0: gauge_force_link<LK, 0, true, NT>(g, U, P, coef_beta, par, s, &own, lane); break;
+      case 1: gauge_force_link<LK, 1, true, NT>(g, U, P, coef_beta, par, s, &own, lane); break;
+      case 2: gauge_force_link<LK, 2, true, NT>(g, U, P, coef_beta, par, s, &own, lane); break;
+      default: gauge_force_link<LK, 3, true, NT>(g, U, P, coef_beta, par, s, &own, lane); break;
     }
     return;
   }
@@ -612,8 +614,12 @@ hipError_t launch_kinetic_partials(const LatArg& g, const double* P, double* par
 template <class LK>
 static void gauge_force_typed(const LatArg& g, const void* U, double* P, double coef_beta, hipStream_t st, int shape) {
   if (shape == 2) {
-    hipLaunchKernelGGL(k_gauge_force_sites<LK>, dim3(2 * ceil_div(g.Vh, 64)), dim3(kBlock), 0, st, walk_lat(g), U,
-                       P, coef_beta);
+    if (gauge_force_stream(g))
+      hipLaunchKernelGGL((k_gauge_force_sites<LK, true>), dim3(2 * ceil_div(g.Vh, 64)), dim3(kBlock), 0, st,
+                         walk_lat(g), U, P, coef_beta);
+    else
+      hipLaunchKernelGGL((k_gauge_force_sites<LK, false>), dim3(2 * ceil_div(g.Vh, 64)), dim3(kBlock), 0, st,
+                         walk_lat(g), U, P, coef_beta);
   } else if (shape == 1)
     hipLaunchKernelGGL(k_gauge_force_planes<LK>, dim3(ceil_div(2LL * g.Vh, kGfSites), 4), dim3(3 * kGfSites), 0, st,
                        to_lat(g), U, P, coef_beta);

@@ -269,6 +269,8 @@ int plaquette_shape(const LatArg& g);
 // and in the fermion force (large lattices).
 bool exp_update_stream(const LatArg& g);
 bool fermion_force_stream(const LatArg& g);
+// The same for the momenta of the site-blocked staple force.
+bool gauge_force_stream(const LatArg& g);
 // Compact link form of the plaquette sum on SU(3) links.
 int plaquette_link_form(const LatArg& g);
 // One partial per block, plaquette_blocks(g, su3) of them (at most
